@@ -1,0 +1,260 @@
+"""FP64 CPU oracle of the SAC/SMAUG+ MHD scheme -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library neither imports nor
+links it, and the two share no code: the oracle is a plain C program
+(``sacx_oracle.c``) built with gcc -O2 -ffp-contract=off, driven from here
+through ctypes.  Inputs come from the neutral ``workloads`` package.
+
+Parity status: every function is pinned by the CPU test-suite against closed
+forms, invariants and brute force, except the hyper-diffusion constants and
+the Brio-Wu solution beyond self-consistency ("parity unpinned": no values
+exist outside this oracle).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sacx_oracle.c")
+_LIB = os.path.join(_HERE, "libsacx_oracle.so")
+
+FIELDS = ("rho", "mx", "my", "e", "bx", "by")
+BACKGROUND_FIELDS = ("rho_b", "e_b", "bx_b", "by_b")
+
+OK = 0
+EINVAL = -1
+ENONPHYS = -4
+ENOMEM = -7
+
+PERIODIC = 0
+OPEN = 1
+
+# Hyper-diffusion constants (our choice; the paper gives none).  Order of the
+# classes: density, thermal energy, velocity, magnetic field.
+DEFAULT_C2 = (0.02, 0.02, 0.2, 0.02)
+DEFAULT_CSHK = (0.5, 0.5, 0.5, 0.5)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C11, OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-fPIC", "-shared", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+        ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+        ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+        ("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("hd_on", ctypes.c_int), ("hd_cross_on", ctypes.c_int),
+        ("c2", ctypes.c_double * 4), ("cshk", ctypes.c_double * 4),
+        ("bc", ctypes.c_int * 4),
+        ("background_on", ctypes.c_int),
+    ]
+
+
+_lib = None
+_lock = threading.Lock()
+_P = ctypes.POINTER(ctypes.c_double)
+_PP = ctypes.POINTER(_P)
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build(force=False)
+            lib = ctypes.CDLL(_LIB)
+            lib.orc_advance.argtypes = [ctypes.POINTER(_Cfg), _PP, _PP, ctypes.c_int, ctypes.c_double,
+                                        _P, ctypes.POINTER(ctypes.c_int), _P]
+            lib.orc_wavespeed.argtypes = [ctypes.POINTER(_Cfg), _PP, _PP, _P]
+            lib.orc_rhs.argtypes = [ctypes.POINTER(_Cfg), _PP, _PP, ctypes.c_double, _PP]
+            lib.orc_step_patch.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, ctypes.c_int, _PP, _PP,
+                                           ctypes.c_double, ctypes.c_double, _PP]
+            lib.orc_sums.argtypes = [ctypes.POINTER(_Cfg), _PP, _P]
+            lib.orc_deriv_line.argtypes = [ctypes.c_int, _P, ctypes.c_double, _P]
+            lib.orc_hd_ratio_line.argtypes = [ctypes.c_int, _P, _P]
+            for name in ("orc_advance", "orc_wavespeed", "orc_rhs", "orc_step_patch", "orc_sums",
+                         "orc_deriv_line", "orc_hd_ratio_line", "orc_abi_version"):
+                getattr(lib, name).restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what} failed with code {code}")
+        self.code = code
+
+
+def _ptrs(arrs: Sequence[np.ndarray]):
+    arr_t = _P * len(arrs)
+    return arr_t(*[a.ctypes.data_as(_P) for a in arrs])
+
+
+def _c64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def make_cfg(prob, cfl: float = 0.3, hd_on: bool = True, hd_cross_on: bool = True,
+             c2: Sequence[float] = DEFAULT_C2, cshk: Sequence[float] = DEFAULT_CSHK,
+             gamma: Optional[float] = None) -> _Cfg:
+    c = _Cfg()
+    c.nx, c.ny = prob.nx, prob.ny
+    c.x0, c.x1, c.y0, c.y1 = prob.x0, prob.x1, prob.y0, prob.y1
+    c.gamma = prob.gamma if gamma is None else gamma
+    c.cfl = cfl
+    c.hd_on = int(bool(hd_on))
+    c.hd_cross_on = int(bool(hd_cross_on))
+    c.c2 = (ctypes.c_double * 4)(*c2)
+    c.cshk = (ctypes.c_double * 4)(*cshk)
+    c.bc = (ctypes.c_int * 4)(*prob.bc)
+    c.background_on = int(prob.background is not None)
+    return c
+
+
+class State:
+    """An oracle run: the problem, the scheme constants and the current state."""
+
+    def __init__(self, prob, cfl: float = 0.3, hd_on: bool = True, hd_cross_on: bool = True,
+                 c2: Sequence[float] = DEFAULT_C2, cshk: Sequence[float] = DEFAULT_CSHK):
+        self.prob = prob
+        self.cfg = make_cfg(prob, cfl, hd_on, hd_cross_on, c2, cshk)
+        self.f = [_c64(prob.fields[k]).copy() for k in FIELDS]
+        self.bg = None
+        if prob.background is not None:
+            self.bg = [_c64(prob.background[k]).copy() for k in BACKGROUND_FIELDS]
+        self.t = float(prob.t0)
+        self.steps = 0
+        self.last = np.zeros(4)
+
+    def _bgp(self):
+        return _ptrs(self.bg) if self.bg is not None else None
+
+    def advance(self, nsteps: int, t_end: float = 0.0) -> int:
+        lib = _load()
+        t = ctypes.c_double(self.t)
+        done = ctypes.c_int(0)
+        info = np.zeros(4)
+        rc = lib.orc_advance(ctypes.byref(self.cfg), _ptrs(self.f), self._bgp(), int(nsteps),
+                             float(t_end), ctypes.byref(t), ctypes.byref(done), info.ctypes.data_as(_P))
+        self.t = t.value
+        self.steps += done.value
+        self.last = info
+        if rc not in (OK, ENONPHYS):
+            raise OracleError(rc, "orc_advance")
+        return rc, done.value
+
+    def run(self, nsteps: int, t_end: float = 0.0) -> int:
+        rc, done = self.advance(nsteps, t_end)
+        if rc != OK:
+            raise OracleError(rc, "orc_advance")
+        return done
+
+    def fields(self) -> Dict[str, np.ndarray]:
+        return {k: a.copy() for k, a in zip(FIELDS, self.f)}
+
+    def stacked(self) -> np.ndarray:
+        return np.stack(self.f)
+
+    def wavespeed(self):
+        return wavespeed(self.cfg, self.f, self.bg)
+
+    def rhs(self, cmax: Optional[float] = None) -> np.ndarray:
+        if cmax is None:
+            cmax = self.wavespeed()[2]
+        return rhs(self.cfg, self.f, self.bg, cmax)
+
+    def sums(self) -> np.ndarray:
+        return sums(self.cfg, self.f)
+
+
+def wavespeed(cfg: _Cfg, f: Sequence[np.ndarray], bg=None, check: bool = True):
+    """(c_x, c_y, c_max, dt) of a state; raises OracleError on a non-physical state."""
+    lib = _load()
+    f = [_c64(a) for a in f]
+    bgp = _ptrs([_c64(a) for a in bg]) if bg is not None else None
+    out = np.zeros(4)
+    rc = lib.orc_wavespeed(ctypes.byref(cfg), _ptrs(f), bgp, out.ctypes.data_as(_P))
+    if rc != OK and check:
+        raise OracleError(rc, "orc_wavespeed")
+    return tuple(float(v) for v in out)
+
+
+def rhs(cfg: _Cfg, f: Sequence[np.ndarray], bg, cmax: float) -> np.ndarray:
+    lib = _load()
+    f = [_c64(a) for a in f]
+    bgp = _ptrs([_c64(a) for a in bg]) if bg is not None else None
+    K = [np.zeros_like(f[0]) for _ in range(6)]
+    rc = lib.orc_rhs(ctypes.byref(cfg), _ptrs(f), bgp, float(cmax), _ptrs(K))
+    if rc != OK:
+        raise OracleError(rc, "orc_rhs")
+    return np.stack(K)
+
+
+def step_patch(cfg: _Cfg, patch: Sequence[np.ndarray], bg_patch, dt: float, cmax: float) -> np.ndarray:
+    """One RK4 step on a patch with a 12-cell supplied margin; returns (6, py-24, px-24)."""
+    lib = _load()
+    patch = [_c64(a) for a in patch]
+    py, px = patch[0].shape
+    bgp = _ptrs([_c64(a) for a in bg_patch]) if bg_patch is not None else None
+    out = [np.zeros((py - 24, px - 24)) for _ in range(6)]
+    rc = lib.orc_step_patch(ctypes.byref(cfg), px, py, _ptrs(patch), bgp, float(dt), float(cmax), _ptrs(out))
+    if rc != OK:
+        raise OracleError(rc, "orc_step_patch")
+    return np.stack(out)
+
+
+def sums(cfg: _Cfg, f: Sequence[np.ndarray]) -> np.ndarray:
+    lib = _load()
+    f = [_c64(a) for a in f]
+    out = np.zeros(6)
+    rc = lib.orc_sums(ctypes.byref(cfg), _ptrs(f), out.ctypes.data_as(_P))
+    if rc != OK:
+        raise OracleError(rc, "orc_sums")
+    return out
+
+
+def deriv_line(q: np.ndarray, h: float) -> np.ndarray:
+    lib = _load()
+    q = _c64(q)
+    out = np.zeros_like(q)
+    rc = lib.orc_deriv_line(q.size, q.ctypes.data_as(_P), float(h), out.ctypes.data_as(_P))
+    if rc != OK:
+        raise OracleError(rc, "orc_deriv_line")
+    return out
+
+
+def hd_ratio_line(q: np.ndarray) -> np.ndarray:
+    """R on faces i+1/2 of a periodic line."""
+    lib = _load()
+    q = _c64(q)
+    out = np.zeros_like(q)
+    rc = lib.orc_hd_ratio_line(q.size, q.ctypes.data_as(_P), out.ctypes.data_as(_P))
+    if rc != OK:
+        raise OracleError(rc, "orc_hd_ratio_line")
+    return out
+
+
+def rel_l2(a: np.ndarray, b: np.ndarray) -> float:
+    """||a - b||_2 / ||b||_2 (absolute when ||b|| = 0)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    nb = float(np.sqrt(np.sum(b * b)))
+    d = float(np.sqrt(np.sum((a - b) ** 2)))
+    return d / nb if nb > 0 else d

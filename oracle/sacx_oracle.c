@@ -1,0 +1,765 @@
+/*
+ * sacx_oracle.c -- plain FP64 CPU oracle of the SAC/SMAUG+ MHD scheme.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  The product path
+ * (the HIP library) never calls it, links it or shares code with it.
+ *
+ * It is written for obviousness, not speed: every stage of the scheme is a
+ * full-array pass with plain loops, in the order the scheme is defined.
+ * Build with -O2 -ffp-contract=off (no fast-math) so every operation rounds
+ * exactly as written.  OpenMP only distributes independent rows; reductions
+ * are maxima (order free) or serial pairwise sums, so results do not depend
+ * on the thread count.
+ *
+ * What is computed (paper section 2 and our reading of what it defers to the
+ * SAC/SMAUG papers; every reading is listed in the design notes):
+ *
+ *  - ideal compressible MHD in conservative form (section 2, the governing
+ *    equations), with the closure p_t = p_k + B^2/2,
+ *    p_k = (gamma-1)(e - rho v^2/2 - B^2/2) (section 2, the two pressure
+ *    definitions), written for static background + perturbation split
+ *    variables (rho = rho_b + rho~, e = e_b + e~, B = B_b + B~, v_b = 0);
+ *    the stray "+ grad p_t" of the printed energy equation is dropped;
+ *  - spatial derivatives by fourth-order central differences (section 2);
+ *  - hyper-diffusion / hyper-viscosity / hyper-resistivity whose coefficient
+ *    is the ratio of third- to first-order differences of the variable and
+ *    scales with the maximum wave speed, plus a term that grows with
+ *    compression (section 2);
+ *  - classic fourth-order Runge-Kutta in time (section 2);
+ *  - a CFL time step from the maximum fast speed;
+ *  - halo (ghost) cells filled from periodic images or by zero-gradient
+ *    copies (section 3, halo exchange; section 5 boundary conditions).
+ *
+ * Grid: cell centred, G = 3 ghost cells on every side, arrays row-major with
+ * x fastest.  Field order: rho~, m_x, m_y, e~, B~_x, B~_y; background order:
+ * rho_b, e_b, B_bx, B_by.
+ */
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define G 3
+#define NF 6
+#define NB 4
+
+enum { F_RHO = 0, F_MX = 1, F_MY = 2, F_E = 3, F_BX = 4, F_BY = 5 };
+enum { B_RHO = 0, B_E = 1, B_BX = 2, B_BY = 3 };
+/* hyper-diffusion constant classes */
+enum { C_RHO = 0, C_EPS = 1, C_V = 2, C_B = 3 };
+
+enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENONPHYS = -4, ORC_ENOMEM = -7 };
+enum { ORC_PERIODIC = 0, ORC_OPEN = 1 };
+
+typedef struct {
+    int nx, ny;
+    double x0, x1, y0, y1;
+    double gamma, cfl;
+    int hd_on, hd_cross_on;
+    double c2[4];   /* rho, eps, v, B */
+    double cshk[4]; /* rho, eps, v, B */
+    int bc[4];      /* x-, x+, y-, y+ */
+    int background_on;
+} orc_cfg;
+
+int orc_abi_version(void) { return 1; }
+
+/* ------------------------------------------------------------------ */
+/* small helpers                                                       */
+/* ------------------------------------------------------------------ */
+
+static double dmax(double a, double b) { return a > b ? a : b; }
+static double dmin(double a, double b) { return a < b ? a : b; }
+
+static int imod(int i, int n) { int r = i % n; return r < 0 ? r + n : r; }
+static int iclamp(int i, int n) { return i < 0 ? 0 : (i >= n ? n - 1 : i); }
+
+static double *alloc0(size_t n) { return (double *)calloc(n ? n : 1, sizeof(double)); }
+
+typedef struct {
+    int nxe, nye;          /* extended dims */
+    double *f[NF];         /* evolved fields (ext layout) */
+} block;
+
+static int block_alloc(block *b, int nxe, int nye) {
+    b->nxe = nxe; b->nye = nye;
+    for (int k = 0; k < NF; ++k) b->f[k] = NULL;
+    for (int k = 0; k < NF; ++k) {
+        b->f[k] = alloc0((size_t)nxe * nye);
+        if (!b->f[k]) return ORC_ENOMEM;
+    }
+    return ORC_OK;
+}
+
+static void block_free(block *b) {
+    for (int k = 0; k < NF; ++k) { free(b->f[k]); b->f[k] = NULL; }
+}
+
+static int cfg_ok(const orc_cfg *c) {
+    if (!c || c->nx < 1 || c->ny < 1) return 0;
+    if (c->nx < 2 && c->ny < 2) return 0;
+    if (!(c->x1 > c->x0) || !(c->y1 > c->y0)) return 0;
+    if (!(c->gamma > 1.0) || !(c->cfl > 0.0)) return 0;
+    for (int s = 0; s < 4; ++s)
+        if (c->bc[s] != ORC_PERIODIC && c->bc[s] != ORC_OPEN) return 0;
+    if ((c->bc[0] == ORC_PERIODIC) != (c->bc[1] == ORC_PERIODIC)) return 0;
+    if ((c->bc[2] == ORC_PERIODIC) != (c->bc[3] == ORC_PERIODIC)) return 0;
+    return 1;
+}
+
+/* ------------------------------------------------------------------ */
+/* halo fill: periodic images or zero-gradient copies                  */
+/* (the state is extended by G cells before every right-hand side;     */
+/* x first over the interior rows, then y over the padded width, which */
+/* also fills the corners)                                             */
+/* ------------------------------------------------------------------ */
+
+static void fill_ghosts_one(double *a, int nx, int ny, const int bc[4]) {
+    const int nxe = nx + 2 * G;
+#define A(i, j) a[(size_t)((i) + G) + (size_t)((j) + G) * nxe]
+    for (int j = 0; j < ny; ++j) {
+        for (int i = -G; i < 0; ++i) {
+            int s = bc[0] == ORC_PERIODIC ? imod(i, nx) : iclamp(i, nx);
+            A(i, j) = A(s, j);
+        }
+        for (int i = nx; i < nx + G; ++i) {
+            int s = bc[1] == ORC_PERIODIC ? imod(i, nx) : iclamp(i, nx);
+            A(i, j) = A(s, j);
+        }
+    }
+    for (int i = -G; i < nx + G; ++i) {
+        for (int j = -G; j < 0; ++j) {
+            int s = bc[2] == ORC_PERIODIC ? imod(j, ny) : iclamp(j, ny);
+            A(i, j) = A(i, s);
+        }
+        for (int j = ny; j < ny + G; ++j) {
+            int s = bc[3] == ORC_PERIODIC ? imod(j, ny) : iclamp(j, ny);
+            A(i, j) = A(i, s);
+        }
+    }
+#undef A
+}
+
+/* ------------------------------------------------------------------ */
+/* the fourth-order central difference (section 2)                     */
+/*   D f_i = [8 (f_{i+1} - f_{i-1}) - (f_{i+2} - f_{i-2})] / (12 h)     */
+/* ------------------------------------------------------------------ */
+
+static double d4(const double *f, ptrdiff_t i, ptrdiff_t st, double h) {
+    return (8.0 * (f[i + st] - f[i - st]) - (f[i + 2 * st] - f[i - 2 * st])) / (12.0 * h);
+}
+
+/* ------------------------------------------------------------------ */
+/* hyper-diffusion coefficient ratio at the face between q[0] and      */
+/* q[st] (section 2: ratio of the third- to the first-order forward    */
+/* difference of the variable).  Our reading: third differences on the */
+/* three faces around the face, first differences on the five faces    */
+/* around it, R = max|d3| / max|d1|, R = 0 when max|d1| = 0; R <= 4.   */
+/* ------------------------------------------------------------------ */
+
+static double d1_at(const double *q, ptrdiff_t i, ptrdiff_t st) {   /* face i+1/2 */
+    return q[i + st] - q[i];
+}
+
+static double d3_at(const double *q, ptrdiff_t i, ptrdiff_t st) {   /* face i+1/2 */
+    return (q[i + 2 * st] - q[i - st]) - 3.0 * (q[i + st] - q[i]);
+}
+
+static double hd_ratio(const double *q, ptrdiff_t i, ptrdiff_t st) {
+    double n = 0.0, m = 0.0;
+    for (int k = -1; k <= 1; ++k) n = dmax(n, fabs(d3_at(q, i + k * st, st)));
+    for (int k = -2; k <= 2; ++k) m = dmax(m, fabs(d1_at(q, i + k * st, st)));
+    return m > 0.0 ? n / m : 0.0;
+}
+
+/* ------------------------------------------------------------------ */
+/* right-hand side L(S) on an extended block                            */
+/* K is written on [G, nxe-G) x [G, nye-G); every other entry is zero.  */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double dx, dy, gamma;
+    int hd_on, hd_cross_on, bg_on;
+    double c2[4], cshk[4];
+} rhs_par;
+
+static int rhs_block(int nxe, int nye, double *const S[NF], double *const BG[NB],
+                     const rhs_par *P, double cmax, double *const K[NF]) {
+    const size_t n = (size_t)nxe * nye;
+    const double gm1 = P->gamma - 1.0;
+    const double dx = P->dx, dy = P->dy;
+    int rc = ORC_OK;
+
+    /* primitive / derived quantities on every cell of the block */
+    double *rho = alloc0(n), *vx = alloc0(n), *vy = alloc0(n), *bxT = alloc0(n), *byT = alloc0(n);
+    double *pkt = alloc0(n), *ptt = alloc0(n), *epst = alloc0(n), *ptb = alloc0(n);
+    double *Fx[NF], *Fy[NF];
+    for (int k = 0; k < NF; ++k) { Fx[k] = alloc0(n); Fy[k] = alloc0(n); }
+    double *s = NULL, *Gx[5] = {0}, *Gy[5] = {0}, *Hx[NF] = {0}, *Hy[NF] = {0};
+    int ok = rho && vx && vy && bxT && byT && pkt && ptt && epst && ptb;
+    for (int k = 0; k < NF; ++k) ok = ok && Fx[k] && Fy[k];
+    if (P->hd_on) {
+        s = alloc0(n);
+        ok = ok && s;
+        for (int k = 0; k < 5; ++k) { Gx[k] = alloc0(n); Gy[k] = alloc0(n); ok = ok && Gx[k] && Gy[k]; }
+        for (int k = 0; k < NF; ++k) { Hx[k] = alloc0(n); Hy[k] = alloc0(n); ok = ok && Hx[k] && Hy[k]; }
+    }
+    if (!ok) { rc = ORC_ENOMEM; goto done; }
+
+    /* 1. totals and derived quantities (closure of section 2, split form) */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < nye; ++j) {
+        for (int i = 0; i < nxe; ++i) {
+            size_t c = (size_t)i + (size_t)j * nxe;
+            double rb = 0.0, eb = 0.0, bxb = 0.0, byb = 0.0;
+            if (P->bg_on) { rb = BG[B_RHO][c]; eb = BG[B_E][c]; bxb = BG[B_BX][c]; byb = BG[B_BY][c]; }
+            double rt = S[F_RHO][c], mx = S[F_MX][c], my = S[F_MY][c], et = S[F_E][c];
+            double bxt = S[F_BX][c], byt = S[F_BY][c];
+            double r = rb + rt;
+            double ux = mx / r, uy = my / r;
+            double kin = 0.5 * (mx * ux + my * uy);          /* rho v^2 / 2 */
+            double bbdot = bxb * bxt + byb * byt;            /* B_b . B~ */
+            double bt2 = bxt * bxt + byt * byt;              /* |B~|^2 */
+            double pk = gm1 * (((et - kin) - bbdot) - 0.5 * bt2);   /* p~_k */
+            rho[c] = r; vx[c] = ux; vy[c] = uy;
+            bxT[c] = bxb + bxt; byT[c] = byb + byt;
+            pkt[c] = pk;
+            ptt[c] = (pk + 0.5 * bt2) + bbdot;                /* p~_t */
+            epst[c] = pk / gm1;                               /* thermal energy perturbation */
+            if (P->bg_on) {
+                double b2b = bxb * bxb + byb * byb;
+                double pkb = gm1 * (eb - 0.5 * b2b);
+                ptb[c] = pkb + 0.5 * b2b;                     /* p_tb */
+            }
+
+            /* 2. ideal fluxes of the split system (section 2 equations) */
+            double bv_t = bxt * ux + byt * uy;                /* B~ . v */
+            double bv_b = bxb * ux + byb * uy;                /* B_b . v */
+            double eflux = et + eb + ptt[c];
+            Fx[F_RHO][c] = mx;
+            Fx[F_MX][c] = (ux * mx - (bxt * bxt + 2.0 * bxt * bxb)) + ptt[c];
+            Fx[F_MY][c] = ux * my - (bxt * byt + bxt * byb + bxb * byt);
+            Fx[F_E][c] = ((ux * eflux - bxt * bv_t) - bxt * bv_b) - bxb * bv_t;
+            Fx[F_BX][c] = 0.0;
+            Fx[F_BY][c] = ux * byT[c] - bxT[c] * uy;
+            Fy[F_RHO][c] = my;
+            Fy[F_MX][c] = uy * mx - (byt * bxt + byt * bxb + byb * bxt);
+            Fy[F_MY][c] = (uy * my - (byt * byt + 2.0 * byt * byb)) + ptt[c];
+            Fy[F_E][c] = ((uy * eflux - byt * bv_t) - byt * bv_b) - byb * bv_t;
+            Fy[F_BX][c] = uy * bxT[c] - byT[c] * ux;
+            Fy[F_BY][c] = 0.0;
+        }
+    }
+
+    /* 3. K_ideal = -(D_x F_x + D_y F_y) (+ background terms of e~) */
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < nye; ++j) {
+        for (int i = 0; i < nxe; ++i) {
+            size_t c = (size_t)i + (size_t)j * nxe;
+            if (i < G || i >= nxe - G || j < G || j >= nye - G) {
+                for (int k = 0; k < NF; ++k) K[k][c] = 0.0;
+                continue;
+            }
+            for (int k = 0; k < NF; ++k) {
+                double ddx = d4(Fx[k], (ptrdiff_t)c, 1, dx);
+                double ddy = d4(Fy[k], (ptrdiff_t)c, nxe, dy);
+                K[k][c] = -(ddx + ddy);
+            }
+            if (P->bg_on) {
+                /* e~ gets -p_tb div v + sum_kl B_bk B_bl d_k v_l (non-conservative) */
+                double dxvx = d4(vx, (ptrdiff_t)c, 1, dx), dyvy = d4(vy, (ptrdiff_t)c, nxe, dy);
+                double dxvy = d4(vy, (ptrdiff_t)c, 1, dx), dyvx = d4(vx, (ptrdiff_t)c, nxe, dy);
+                double bxb = BG[B_BX][c], byb = BG[B_BY][c];
+                double bb = (bxb * bxb * dxvx + byb * byb * dyvy) + (bxb * byb * dxvy + byb * bxb * dyvx);
+                K[F_E][c] = K[F_E][c] + (bb - ptb[c] * (dxvx + dyvy));
+            }
+        }
+    }
+
+    if (!P->hd_on) goto done;
+
+    /* 4a. compression indicator s = max(0, -div v) (2nd-order centred) */
+#pragma omp parallel for schedule(static)
+    for (int j = 1; j < nye - 1; ++j) {
+        for (int i = 1; i < nxe - 1; ++i) {
+            size_t c = (size_t)i + (size_t)j * nxe;
+            double dv = (vx[c + 1] - vx[c - 1]) / (2.0 * dx) + (vy[c + nxe] - vy[c - nxe]) / (2.0 * dy);
+            s[c] = dmax(0.0, -dv);
+        }
+    }
+
+    /* 4b. face diffusion fluxes G_d(q) = nu_f(q) d1_f(q) / h_d,
+     *     nu_f(q) = c2(q) h c_max R_f(q) + cshk(q) h^2 s_f.
+     * x-face sets {rho~, eps~, v_x, v_y, B~_y}; y-face sets {rho~, eps~, v_x, v_y, B~_x}.
+     * Faces are indexed by their lower cell. */
+    {
+        double *qx[5] = {S[F_RHO], epst, vx, vy, S[F_BY]};
+        double *qy[5] = {S[F_RHO], epst, vx, vy, S[F_BX]};
+        const int cls[5] = {C_RHO, C_EPS, C_V, C_V, C_B};
+#pragma omp parallel for schedule(static)
+        for (int j = 1; j < nye - 1; ++j) {
+            for (int i = 2; i <= nxe - 4; ++i) {
+                size_t c = (size_t)i + (size_t)j * nxe;
+                double sf = dmax(s[c], s[c + 1]);
+                for (int k = 0; k < 5; ++k) {
+                    double R = hd_ratio(qx[k], (ptrdiff_t)c, 1);
+                    double nu = P->c2[cls[k]] * dx * cmax * R + P->cshk[cls[k]] * dx * dx * sf;
+                    Gx[k][c] = nu * d1_at(qx[k], (ptrdiff_t)c, 1) / dx;
+                }
+            }
+        }
+#pragma omp parallel for schedule(static)
+        for (int j = 2; j <= nye - 4; ++j) {
+            for (int i = 1; i < nxe - 1; ++i) {
+                size_t c = (size_t)i + (size_t)j * nxe;
+                double sf = dmax(s[c], s[c + nxe]);
+                for (int k = 0; k < 5; ++k) {
+                    double R = hd_ratio(qy[k], (ptrdiff_t)c, nxe);
+                    double nu = P->c2[cls[k]] * dy * cmax * R + P->cshk[cls[k]] * dy * dy * sf;
+                    Gy[k][c] = nu * d1_at(qy[k], (ptrdiff_t)c, nxe) / dy;
+                }
+            }
+        }
+    }
+    /* index of each quantity inside the G arrays */
+    enum { Q_RHO = 0, Q_EPS = 1, Q_VX = 2, Q_VY = 3, Q_B = 4 };
+
+    /* 4c. face fluxes: mass diffusion, hyper-viscous stress, hyper-resistive
+     * e.m.f. and the matching energy fluxes (all in flux form).
+     * A4_x[g] averages the four y-face values around an x-face and A4_y the
+     * four x-face values around a y-face. */
+#pragma omp parallel for schedule(static)
+    for (int j = 3; j <= nye - 4; ++j) {
+        for (int i = 2; i <= nxe - 4; ++i) {
+            size_t c = (size_t)i + (size_t)j * nxe;          /* x-face (i+1/2, j) */
+            double a4_vx = 0.0, a4_bx = 0.0;
+            if (P->hd_cross_on) {
+                a4_vx = ((Gy[Q_VX][c - nxe] + Gy[Q_VX][c]) + (Gy[Q_VX][c + 1 - nxe] + Gy[Q_VX][c + 1])) / 4.0;
+                a4_bx = ((Gy[Q_B][c - nxe] + Gy[Q_B][c]) + (Gy[Q_B][c + 1 - nxe] + Gy[Q_B][c + 1])) / 4.0;
+            }
+            double rf = 0.5 * (rho[c] + rho[c + 1]);
+            double vxf = 0.5 * (vx[c] + vx[c + 1]);
+            double vyf = 0.5 * (vy[c] + vy[c + 1]);
+            double byf = 0.5 * (byT[c] + byT[c + 1]);
+            double txx = rf * Gx[Q_VX][c];
+            double txy = 0.5 * rf * (Gx[Q_VY][c] + a4_vx);
+            double ez = Gx[Q_B][c] - a4_bx;
+            Hx[F_RHO][c] = Gx[Q_RHO][c];
+            Hx[F_MX][c] = txx;
+            Hx[F_MY][c] = txy;
+            Hx[F_E][c] = (Gx[Q_EPS][c] + (vxf * txx + vyf * txy)) + byf * ez;
+            Hx[F_BX][c] = 0.0;
+            Hx[F_BY][c] = ez;
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int j = 2; j <= nye - 4; ++j) {
+        for (int i = 3; i <= nxe - 4; ++i) {
+            size_t c = (size_t)i + (size_t)j * nxe;          /* y-face (i, j+1/2) */
+            double a4_vy = 0.0, a4_by = 0.0;
+            if (P->hd_cross_on) {
+                a4_vy = ((Gx[Q_VY][c - 1] + Gx[Q_VY][c]) + (Gx[Q_VY][c - 1 + nxe] + Gx[Q_VY][c + nxe])) / 4.0;
+                a4_by = ((Gx[Q_B][c - 1] + Gx[Q_B][c]) + (Gx[Q_B][c - 1 + nxe] + Gx[Q_B][c + nxe])) / 4.0;
+            }
+            double rf = 0.5 * (rho[c] + rho[c + nxe]);
+            double vxf = 0.5 * (vx[c] + vx[c + nxe]);
+            double vyf = 0.5 * (vy[c] + vy[c + nxe]);
+            double bxf = 0.5 * (bxT[c] + bxT[c + nxe]);
+            double tyy = rf * Gy[Q_VY][c];
+            double tyx = 0.5 * rf * (Gy[Q_VX][c] + a4_vy);
+            double ez = a4_by - Gy[Q_B][c];
+            Hy[F_RHO][c] = Gy[Q_RHO][c];
+            Hy[F_MX][c] = tyx;
+            Hy[F_MY][c] = tyy;
+            Hy[F_E][c] = (Gy[Q_EPS][c] + (vyf * tyy + vxf * tyx)) - bxf * ez;
+            Hy[F_BX][c] = -ez;
+            Hy[F_BY][c] = 0.0;
+        }
+    }
+
+    /* 4d. K_HD = divergence of the face fluxes; L = K_ideal + K_HD */
+#pragma omp parallel for schedule(static)
+    for (int j = G; j < nye - G; ++j) {
+        for (int i = G; i < nxe - G; ++i) {
+            size_t c = (size_t)i + (size_t)j * nxe;
+            for (int k = 0; k < NF; ++k) {
+                double hd = (Hx[k][c] - Hx[k][c - 1]) / dx + (Hy[k][c] - Hy[k][c - nxe]) / dy;
+                K[k][c] = K[k][c] + hd;
+            }
+        }
+    }
+
+done:
+    free(rho); free(vx); free(vy); free(bxT); free(byT); free(pkt); free(ptt); free(epst); free(ptb);
+    for (int k = 0; k < NF; ++k) { free(Fx[k]); free(Fy[k]); free(Hx[k]); free(Hy[k]); }
+    free(s);
+    for (int k = 0; k < 5; ++k) { free(Gx[k]); free(Gy[k]); }
+    return rc;
+}
+
+static void make_rhs_par(const orc_cfg *c, rhs_par *P) {
+    P->dx = (c->x1 - c->x0) / c->nx;
+    P->dy = (c->y1 - c->y0) / c->ny;
+    P->gamma = c->gamma;
+    P->hd_on = c->hd_on;
+    P->hd_cross_on = c->hd_cross_on;
+    P->bg_on = c->background_on;
+    for (int k = 0; k < 4; ++k) { P->c2[k] = c->c2[k]; P->cshk[k] = c->cshk[k]; }
+}
+
+/* ------------------------------------------------------------------ */
+/* wave speeds, CFL time step, physicality check                        */
+/*   c_f = sqrt((gamma p_k + |B|^2) / rho)  (upper bound of fast speed) */
+/*   c_d = max_cells (|v_d| + c_f); c_max = max over active d            */
+/*   dt  = CFL min_d (h_d / c_d) over active d                           */
+/* ------------------------------------------------------------------ */
+
+static int wavespeed_ext(const orc_cfg *cfg, double *const U[NF], double *const BG[NB],
+                         int nxe, int i0, int i1, int j0, int j1, double out[3]) {
+    const double gm1 = cfg->gamma - 1.0;
+    double cx = 0.0, cy = 0.0;
+    int bad = 0;
+#pragma omp parallel for schedule(static) reduction(max : cx, cy) reduction(| : bad)
+    for (int j = j0; j < j1; ++j) {
+        for (int i = i0; i < i1; ++i) {
+            size_t c = (size_t)i + (size_t)j * nxe;
+            double rb = 0.0, eb = 0.0, bxb = 0.0, byb = 0.0;
+            if (cfg->background_on) { rb = BG[B_RHO][c]; eb = BG[B_E][c]; bxb = BG[B_BX][c]; byb = BG[B_BY][c]; }
+            double rt = U[F_RHO][c], mx = U[F_MX][c], my = U[F_MY][c], et = U[F_E][c];
+            double bxt = U[F_BX][c], byt = U[F_BY][c];
+            double r = rb + rt;
+            double ux = mx / r, uy = my / r;
+            double kin = 0.5 * (mx * ux + my * uy);
+            double bbdot = bxb * bxt + byb * byt;
+            double bt2 = bxt * bxt + byt * byt;
+            double pkt = gm1 * (((et - kin) - bbdot) - 0.5 * bt2);
+            double b2b = bxb * bxb + byb * byb;
+            double pkb = gm1 * (eb - 0.5 * b2b);
+            double pk = pkb + pkt;
+            double bx = bxb + bxt, by = byb + byt;
+            double cf = sqrt((cfg->gamma * pk + (bx * bx + by * by)) / r);
+            int finite = isfinite(rt) && isfinite(mx) && isfinite(my) && isfinite(et) &&
+                         isfinite(bxt) && isfinite(byt) && isfinite(cf);
+            if (!(r > 0.0) || !(pk > 0.0) || !finite) { bad = 1; continue; }
+            cx = dmax(cx, fabs(ux) + cf);
+            cy = dmax(cy, fabs(uy) + cf);
+        }
+    }
+    out[0] = cx; out[1] = cy;
+    {
+        int ax = cfg->nx > 1, ay = cfg->ny > 1;
+        out[2] = (ax && ay) ? dmax(cx, cy) : (ax ? cx : cy);
+    }
+    return bad ? ORC_ENONPHYS : ORC_OK;
+}
+
+static double cfl_dt(const orc_cfg *cfg, const double c[3]) {
+    double dx = (cfg->x1 - cfg->x0) / cfg->nx, dy = (cfg->y1 - cfg->y0) / cfg->ny;
+    int ax = cfg->nx > 1, ay = cfg->ny > 1;
+    double h;
+    if (ax && ay) h = dmin(dx / c[0], dy / c[1]);
+    else if (ax) h = dx / c[0];
+    else h = dy / c[1];
+    return cfg->cfl * h;
+}
+
+/* ------------------------------------------------------------------ */
+/* full-domain state                                                    */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    orc_cfg cfg;
+    rhs_par par;
+    int nx, ny, nxe, nye;
+    block U, S, K[4];
+    double *BG[NB];
+} dom;
+
+static void dom_free(dom *d) {
+    block_free(&d->U); block_free(&d->S);
+    for (int k = 0; k < 4; ++k) block_free(&d->K[k]);
+    for (int k = 0; k < NB; ++k) { free(d->BG[k]); d->BG[k] = NULL; }
+}
+
+static int dom_init(dom *d, const orc_cfg *cfg, double *const f[NF], double *const bg[NB]) {
+    memset(d, 0, sizeof(*d));
+    d->cfg = *cfg;
+    make_rhs_par(cfg, &d->par);
+    d->nx = cfg->nx; d->ny = cfg->ny;
+    d->nxe = cfg->nx + 2 * G; d->nye = cfg->ny + 2 * G;
+    int rc = block_alloc(&d->U, d->nxe, d->nye);
+    if (!rc) rc = block_alloc(&d->S, d->nxe, d->nye);
+    for (int k = 0; k < 4 && !rc; ++k) rc = block_alloc(&d->K[k], d->nxe, d->nye);
+    if (!rc && cfg->background_on) {
+        for (int k = 0; k < NB; ++k) {
+            d->BG[k] = alloc0((size_t)d->nxe * d->nye);
+            if (!d->BG[k]) { rc = ORC_ENOMEM; break; }
+        }
+    }
+    if (rc) { dom_free(d); return rc; }
+    for (int k = 0; k < NF; ++k)
+        for (int j = 0; j < d->ny; ++j)
+            memcpy(d->U.f[k] + (size_t)G + (size_t)(j + G) * d->nxe, f[k] + (size_t)j * d->nx,
+                   sizeof(double) * d->nx);
+    if (cfg->background_on) {
+        for (int k = 0; k < NB; ++k) {
+            for (int j = 0; j < d->ny; ++j)
+                memcpy(d->BG[k] + (size_t)G + (size_t)(j + G) * d->nxe, bg[k] + (size_t)j * d->nx,
+                       sizeof(double) * d->nx);
+            fill_ghosts_one(d->BG[k], d->nx, d->ny, cfg->bc);
+        }
+    }
+    return ORC_OK;
+}
+
+static void dom_out(const dom *d, double *const f[NF]) {
+    for (int k = 0; k < NF; ++k)
+        for (int j = 0; j < d->ny; ++j)
+            memcpy(f[k] + (size_t)j * d->nx, d->U.f[k] + (size_t)G + (size_t)(j + G) * d->nxe,
+                   sizeof(double) * d->nx);
+}
+
+static void fill_block(dom *d, block *b) {
+    for (int k = 0; k < NF; ++k) fill_ghosts_one(b->f[k], d->nx, d->ny, d->cfg.bc);
+}
+
+/* S = U + a * K on the interior */
+static void axpy_interior(dom *d, block *S, const block *U, double a, const block *K) {
+    for (int k = 0; k < NF; ++k) {
+#pragma omp parallel for schedule(static)
+        for (int j = G; j < d->nye - G; ++j)
+            for (int i = G; i < d->nxe - G; ++i) {
+                size_t c = (size_t)i + (size_t)j * d->nxe;
+                S->f[k][c] = U->f[k][c] + a * K->f[k][c];
+            }
+    }
+}
+
+/* one classic RK4 step (section 2):
+ *   S1 = U + dt/2 L(U), S2 = U + dt/2 L(S1), S3 = U + dt L(S2),
+ *   U+ = U + dt/6 (K1 + 2 K2 + 2 K3 + K4); the halo is refilled before every L. */
+static int dom_step(dom *d, double dt, double cmax) {
+    int rc;
+    fill_block(d, &d->U);
+    rc = rhs_block(d->nxe, d->nye, d->U.f, d->BG, &d->par, cmax, d->K[0].f);
+    if (rc) return rc;
+    axpy_interior(d, &d->S, &d->U, 0.5 * dt, &d->K[0]);
+    fill_block(d, &d->S);
+    rc = rhs_block(d->nxe, d->nye, d->S.f, d->BG, &d->par, cmax, d->K[1].f);
+    if (rc) return rc;
+    axpy_interior(d, &d->S, &d->U, 0.5 * dt, &d->K[1]);
+    fill_block(d, &d->S);
+    rc = rhs_block(d->nxe, d->nye, d->S.f, d->BG, &d->par, cmax, d->K[2].f);
+    if (rc) return rc;
+    axpy_interior(d, &d->S, &d->U, dt, &d->K[2]);
+    fill_block(d, &d->S);
+    rc = rhs_block(d->nxe, d->nye, d->S.f, d->BG, &d->par, cmax, d->K[3].f);
+    if (rc) return rc;
+    for (int k = 0; k < NF; ++k) {
+        double *u = d->U.f[k];
+        const double *k1 = d->K[0].f[k], *k2 = d->K[1].f[k], *k3 = d->K[2].f[k], *k4 = d->K[3].f[k];
+#pragma omp parallel for schedule(static)
+        for (int j = G; j < d->nye - G; ++j)
+            for (int i = G; i < d->nxe - G; ++i) {
+                size_t c = (size_t)i + (size_t)j * d->nxe;
+                u[c] = u[c] + (dt / 6.0) * (((k1[c] + 2.0 * k2[c]) + 2.0 * k3[c]) + k4[c]);
+            }
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* exported entry points                                                */
+/* ------------------------------------------------------------------ */
+
+/* Advance up to nsteps RK4 steps.  t_end <= 0: no clamp.  Otherwise
+ * dt = min(dt, t_end - t) and the run stops once t_end - t <= 1e-12 t_end.
+ * The time step and c_max are taken from the state at the start of each
+ * step.  A non-physical start state stops the run with ORC_ENONPHYS and
+ * leaves that state in f.  info[0] = last dt, info[1] = last c_max,
+ * info[2] = c_x, info[3] = c_y of the last step. */
+int orc_advance(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], int nsteps,
+                double t_end, double *t, int *steps_done, double info[4]) {
+    if (!cfg_ok(cfg) || !f || !t || nsteps < 0) return ORC_EINVAL;
+    if (cfg->background_on && !bg) return ORC_EINVAL;
+    dom d;
+    int rc = dom_init(&d, cfg, f, bg);
+    if (rc) return rc;
+    int done = 0;
+    for (int step = 0; step < nsteps; ++step) {
+        if (t_end > 0.0 && t_end - *t <= 1e-12 * t_end) break;
+        double c[3];
+        rc = wavespeed_ext(cfg, d.U.f, d.BG, d.nxe, G, G + d.nx, G, G + d.ny, c);
+        if (rc) break;
+        double dt = cfl_dt(cfg, c);
+        if (t_end > 0.0) dt = dmin(dt, t_end - *t);
+        if (info) { info[0] = dt; info[1] = c[2]; info[2] = c[0]; info[3] = c[1]; }
+        rc = dom_step(&d, dt, c[2]);
+        if (rc) break;
+        *t = *t + dt;
+        ++done;
+    }
+    dom_out(&d, f);
+    dom_free(&d);
+    if (steps_done) *steps_done = done;
+    return rc;
+}
+
+/* Wave speeds of a state: out = {c_x, c_y, c_max, dt}.  Returns
+ * ORC_ENONPHYS if any cell has rho <= 0, p_k <= 0 or a non-finite value. */
+int orc_wavespeed(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], double out[4]) {
+    if (!cfg_ok(cfg) || !f || !out) return ORC_EINVAL;
+    if (cfg->background_on && !bg) return ORC_EINVAL;
+    double c[3];
+    int rc = wavespeed_ext(cfg, f, bg, cfg->nx, 0, cfg->nx, 0, cfg->ny, c);
+    out[0] = c[0]; out[1] = c[1]; out[2] = c[2];
+    out[3] = cfl_dt(cfg, c);
+    return rc;
+}
+
+/* Right-hand side L(U) on the interior (halo filled per cfg->bc) with a
+ * given c_max for the hyper-diffusion coefficients. */
+int orc_rhs(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], double cmax,
+            double *const K[NF]) {
+    if (!cfg_ok(cfg) || !f || !K) return ORC_EINVAL;
+    if (cfg->background_on && !bg) return ORC_EINVAL;
+    dom d;
+    int rc = dom_init(&d, cfg, f, bg);
+    if (rc) return rc;
+    fill_block(&d, &d.U);
+    rc = rhs_block(d.nxe, d.nye, d.U.f, d.BG, &d.par, cmax, d.K[0].f);
+    if (!rc)
+        for (int k = 0; k < NF; ++k)
+            for (int j = 0; j < d.ny; ++j)
+                memcpy(K[k] + (size_t)j * d.nx, d.K[0].f[k] + (size_t)G + (size_t)(j + G) * d.nxe,
+                       sizeof(double) * d.nx);
+    dom_free(&d);
+    return rc;
+}
+
+/* One RK4 step on a patch of a larger 2-D domain whose outer 12 cells are
+ * supplied by the caller (no boundary condition is applied): each stage
+ * consumes 3 cells of margin.  dt and c_max are those of the whole domain.
+ * f: px*py fields (row-major), bg: px*py background (or NULL),
+ * out: (px-24)*(py-24) fields. */
+int orc_step_patch(const orc_cfg *cfg, int px, int py, double *const f[NF], double *const bg[NB],
+                   double dt, double cmax, double *const out[NF]) {
+    if (!cfg || px < 25 || py < 25 || !f || !out) return ORC_EINVAL;
+    if (cfg->background_on && !bg) return ORC_EINVAL;
+    rhs_par P;
+    make_rhs_par(cfg, &P);
+    const int M = 4 * G;
+    int rc = ORC_OK;
+    /* nested blocks: level L has size (px - 2 G L) x (py - 2 G L), offset G L */
+    block U0, Sb[4], Kb[4];
+    double *BGl[4][NB];
+    memset(BGl, 0, sizeof(BGl));
+    memset(Sb, 0, sizeof(Sb)); memset(Kb, 0, sizeof(Kb));
+    rc = block_alloc(&U0, px, py);
+    for (int l = 0; l < 4 && !rc; ++l) {
+        rc = block_alloc(&Sb[l], px - 2 * G * l, py - 2 * G * l);
+        if (!rc) rc = block_alloc(&Kb[l], px - 2 * G * l, py - 2 * G * l);
+        if (!rc && cfg->background_on) {
+            for (int k = 0; k < NB; ++k) {
+                BGl[l][k] = alloc0((size_t)(px - 2 * G * l) * (py - 2 * G * l));
+                if (!BGl[l][k]) { rc = ORC_ENOMEM; break; }
+            }
+        }
+    }
+    if (rc) goto out;
+    for (int k = 0; k < NF; ++k) memcpy(U0.f[k], f[k], sizeof(double) * (size_t)px * py);
+    for (int l = 0; l < 4 && cfg->background_on; ++l) {
+        int w = px - 2 * G * l, h = py - 2 * G * l, o = G * l;
+        for (int k = 0; k < NB; ++k)
+            for (int j = 0; j < h; ++j)
+                for (int i = 0; i < w; ++i)
+                    BGl[l][k][(size_t)i + (size_t)j * w] = bg[k][(size_t)(i + o) + (size_t)(j + o) * px];
+    }
+    /* stage inputs: level 0 is U itself */
+    for (int k = 0; k < NF; ++k) memcpy(Sb[0].f[k], f[k], sizeof(double) * (size_t)px * py);
+    {
+        const double coef[3] = {0.5 * dt, 0.5 * dt, dt};
+        for (int l = 0; l < 4; ++l) {
+            int w = px - 2 * G * l, h = py - 2 * G * l;
+            rc = rhs_block(w, h, Sb[l].f, cfg->background_on ? BGl[l] : NULL, &P, cmax, Kb[l].f);
+            if (rc) goto out;
+            if (l == 3) break;
+            /* next stage input on the inner block (offset G inside level l) */
+            int wn = w - 2 * G, hn = h - 2 * G, on = G * (l + 1);
+            for (int k = 0; k < NF; ++k)
+                for (int j = 0; j < hn; ++j)
+                    for (int i = 0; i < wn; ++i) {
+                        size_t cu = (size_t)(i + on) + (size_t)(j + on) * px;
+                        size_t ck = (size_t)(i + G) + (size_t)(j + G) * w;
+                        Sb[l + 1].f[k][(size_t)i + (size_t)j * wn] = U0.f[k][cu] + coef[l] * Kb[l].f[k][ck];
+                    }
+        }
+    }
+    {
+        int wo = px - 2 * M, ho = py - 2 * M;
+        for (int k = 0; k < NF; ++k)
+            for (int j = 0; j < ho; ++j)
+                for (int i = 0; i < wo; ++i) {
+                    size_t cu = (size_t)(i + M) + (size_t)(j + M) * px;
+                    double k1 = Kb[0].f[k][(size_t)(i + M) + (size_t)(j + M) * (px)];
+                    double k2 = Kb[1].f[k][(size_t)(i + M - G) + (size_t)(j + M - G) * (px - 2 * G)];
+                    double k3 = Kb[2].f[k][(size_t)(i + M - 2 * G) + (size_t)(j + M - 2 * G) * (px - 4 * G)];
+                    double k4 = Kb[3].f[k][(size_t)(i + M - 3 * G) + (size_t)(j + M - 3 * G) * (px - 6 * G)];
+                    out[k][(size_t)i + (size_t)j * wo] =
+                        U0.f[k][cu] + (dt / 6.0) * (((k1 + 2.0 * k2) + 2.0 * k3) + k4);
+                }
+    }
+out:
+    block_free(&U0);
+    for (int l = 0; l < 4; ++l) {
+        block_free(&Sb[l]); block_free(&Kb[l]);
+        for (int k = 0; k < NB; ++k) free(BGl[l][k]);
+    }
+    return rc;
+}
+
+/* pairwise sum of a contiguous run */
+static double psum(const double *a, size_t n) {
+    if (n <= 8) {
+        double s = 0.0;
+        for (size_t i = 0; i < n; ++i) s += a[i];
+        return s;
+    }
+    size_t h = n / 2;
+    return psum(a, h) + psum(a + h, n - h);
+}
+
+/* Conservation sums: sum over the interior of each evolved field times
+ * dx dy, by pairwise summation in row-major order. */
+int orc_sums(const orc_cfg *cfg, double *const f[NF], double sums[NF]) {
+    if (!cfg_ok(cfg) || !f || !sums) return ORC_EINVAL;
+    double dx = (cfg->x1 - cfg->x0) / cfg->nx, dy = (cfg->y1 - cfg->y0) / cfg->ny;
+    for (int k = 0; k < NF; ++k) sums[k] = psum(f[k], (size_t)cfg->nx * cfg->ny) * (dx * dy);
+    return ORC_OK;
+}
+
+/* The fourth-order central difference of a periodic line, with spacing h
+ * (the same routine the right-hand side uses). */
+int orc_deriv_line(int n, const double *q, double h, double *out) {
+    if (n < 1 || !q || !out) return ORC_EINVAL;
+    double *e = alloc0((size_t)n + 2 * G);
+    if (!e) return ORC_ENOMEM;
+    for (int i = -G; i < n + G; ++i) e[i + G] = q[imod(i, n)];
+    for (int i = 0; i < n; ++i) out[i] = d4(e, i + G, 1, h);
+    free(e);
+    return ORC_OK;
+}
+
+/* Hyper-diffusion ratio R on the n faces i+1/2 (i = 0..n-1) of a periodic
+ * line (the same routine the right-hand side uses). */
+int orc_hd_ratio_line(int n, const double *q, double *R) {
+    if (n < 1 || !q || !R) return ORC_EINVAL;
+    double *e = alloc0((size_t)n + 2 * G + 2);
+    if (!e) return ORC_ENOMEM;
+    for (int i = -G; i < n + G + 1; ++i) e[i + G] = q[imod(i, n)];
+    for (int i = 0; i < n; ++i) R[i] = hd_ratio(e, i + G, 1);
+    free(e);
+    return ORC_OK;
+}
