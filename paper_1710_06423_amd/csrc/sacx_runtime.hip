@@ -1,0 +1,939 @@
+// sacx_runtime.hip -- host runtime and C ABI of libsacx, plus the small
+// auxiliary kernels (halo exchange, boundary fills, reductions, step scalars,
+// field import/export).
+//
+// Time stepping (paper section 2, classic RK4) uses four state buffers U, B1,
+// B2, A and the stage kernel's fused combine:
+//   stage 1: B1 = U  + dt/2 L(U)
+//   stage 2: B2 = U  + dt/2 L(B1),   A = 2U + ((B1 - U) + dt L(B1))
+//   stage 3: B1 = U  + dt   L(B2)
+//   stage 4: U  = B1 + (A - 2 B1)/3 + dt/6 L(B1)
+// which is algebraically U + dt/6 (K1 + 2 K2 + 2 K3 + K4), leaves a state
+// with L = 0 bit-for-bit unchanged, and moves 12 field values per cell and
+// step (stencil reads 4, pointwise reads 3, writes 5).
+//
+// Before every stage the halo of the stage input is refilled (paper section 3,
+// exchange_halo): periodic directions pack both boundary strips into device
+// exchange buffers and unpack them into the opposite ghost layers (the
+// self-exchange of a subdomain that is its own neighbour); open directions copy
+// the edge cell outward.  x goes first, then y over the padded width, so the
+// corners are filled.
+//
+// The time step is computed on the device: stage 4 reduces max(|v_d| + c_f)
+// of the new state into the next slot of a double-buffered accumulator, a
+// one-thread kernel turns it into dt (with the end-time clamp) before the
+// next step, and another advances t after it.  Nothing synchronises with the
+// host inside sacx_advance.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sacx_internal.h"
+
+using namespace sacx;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(SACX_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+// ------------------------------------------------------------------ context
+
+struct sacx_ctx {
+    sacx_grid grid;
+    sacx_params params;
+    int device;
+    hipStream_t stream;
+    Layout L;
+    size_t elem;
+    int bc[4];
+    char *ws;
+    size_t ws_bytes;
+    DevScalars *sc;
+    double *sums;      // 6 doubles
+    double *partials;  // npart x 6
+    int npart;
+    void *U[NF], *B1[NF], *B2[NF], *A[NF], *BG[NBG];
+    void *hx[2], *hy[2];
+    bool initialized;
+    int ty;
+    double dx, dy;
+    // profiling: event pairs recorded around launch groups, resolved at read
+    bool prof_on;
+    std::vector<hipEvent_t> *ev_pool;
+    std::vector<std::pair<int, std::pair<int, int>>> *ev_marks;  // (class, (start, stop) pool index)
+    int ev_used;
+    sacx_profile prof;
+};
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kPartials = 512;
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Plan {
+    Layout L;
+    size_t elem;
+    size_t field_bytes;
+    size_t off_sc, off_sums, off_part, off_state, off_bg, off_hx, off_hy, total;
+    size_t hx_bytes, hy_bytes;
+};
+
+int check_grid(const sacx_grid *g, const sacx_params *p) {
+    if (!g || !p) return fail(SACX_EINVAL, "grid/params must not be NULL");
+    if (g->nx < 1 || g->ny < 1) return fail(SACX_EINVAL, "nx, ny must be >= 1 (got %d, %d)", g->nx, g->ny);
+    if (g->nx < 2 && g->ny < 2) return fail(SACX_EINVAL, "at least one direction needs 2 or more cells");
+    if ((int64_t)g->nx * g->ny > ((int64_t)1 << 34)) return fail(SACX_EINVAL, "grid too large");
+    if (g->nx > (1 << 24) || g->ny > (1 << 24)) return fail(SACX_EINVAL, "grid dimension too large");
+    if (!(g->x1 > g->x0) || !(g->y1 > g->y0)) return fail(SACX_EINVAL, "empty physical extent");
+    if (g->precision != SACX_FP64 && g->precision != SACX_FP32)
+        return fail(SACX_EINVAL, "precision must be SACX_FP64 or SACX_FP32");
+    if (g->background_on != 0 && g->background_on != 1) return fail(SACX_EINVAL, "background_on must be 0 or 1");
+    if (!(p->gamma > 1.0) || !std::isfinite(p->gamma)) return fail(SACX_EINVAL, "gamma must be > 1");
+    if (!(p->cfl > 0.0) || !std::isfinite(p->cfl)) return fail(SACX_EINVAL, "cfl must be > 0");
+    for (int k = 0; k < 4; ++k)
+        if (!(p->c2[k] >= 0.0) || !(p->cshk[k] >= 0.0) || !std::isfinite(p->c2[k]) || !std::isfinite(p->cshk[k]))
+            return fail(SACX_EINVAL, "hyper-diffusion constants must be finite and >= 0");
+    return SACX_OK;
+}
+
+Plan make_plan(const sacx_grid *g) {
+    Plan P;
+    P.elem = g->precision == SACX_FP64 ? 8 : 4;
+    const int per = (int)(kAlign / P.elem);
+    P.L.nx = g->nx;
+    P.L.ny = g->ny;
+    P.L.xoff = per;
+    P.L.pitch = (int)round_up((size_t)per + g->nx + G, (size_t)per);
+    P.L.rows = g->ny + 2 * G;
+    P.L.field_elems = (int64_t)P.L.rows * P.L.pitch;
+    P.field_bytes = round_up((size_t)P.L.field_elems * P.elem, kAlign);
+    size_t off = 0;
+    P.off_sc = off; off += round_up(sizeof(DevScalars), kAlign);
+    P.off_sums = off; off += kAlign;
+    P.off_part = off; off += round_up((size_t)kPartials * NF * sizeof(double), kAlign);
+    P.off_state = off; off += 4 * NF * P.field_bytes;
+    P.off_bg = off; off += g->background_on ? NBG * P.field_bytes : 0;
+    P.hx_bytes = round_up((size_t)NF * G * g->ny * P.elem, kAlign);
+    P.hy_bytes = round_up((size_t)NF * G * (g->nx + 2 * G) * P.elem, kAlign);
+    P.off_hx = off; off += 2 * P.hx_bytes;
+    P.off_hy = off; off += 2 * P.hy_bytes;
+    P.total = off;
+    return P;
+}
+
+int default_ty(const Layout &L) {
+    // enough blocks to fill 256 CUs while keeping the 6-row warm-up small
+    const int64_t xt = (L.nx + 249) / 250;
+    int ty = 128;
+    while (ty > 8 && xt * ((L.ny + ty - 1) / ty) < 2048) ty /= 2;
+    return ty;
+}
+
+// ------------------------------------------------------------------ kernels
+
+template <typename real>
+struct FPtr {
+    real *p[NF];
+};
+
+__device__ __forceinline__ int64_t eidx(const Layout &L, int i, int j) {
+    return (int64_t)L.xoff + i + (int64_t)(j + G) * L.pitch;
+}
+
+__device__ __forceinline__ bool step_active(const DevScalars *sc) { return sc->active != 0; }
+
+// x strips: buffer [f][g][j], j in [0, ny)
+template <typename real>
+__global__ void k_pack_x(FPtr<real> S, int nf, Layout L, real *b0, real *b1, int sides, const DevScalars *sc) {
+    if (sc && !step_active(sc)) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int f = blockIdx.y;
+    const int side = (sides == 2) ? (int)blockIdx.z : sides - 10;
+    if (j >= L.ny || f >= nf) return;
+    real *b = side == 0 ? b0 : b1;
+    const int c0 = side == 0 ? 0 : L.nx - G;
+#pragma unroll
+    for (int g = 0; g < G; ++g) b[((int64_t)f * G + g) * L.ny + j] = S.p[f][eidx(L, c0 + g, j)];
+}
+
+template <typename real>
+__global__ void k_unpack_x(FPtr<real> S, int nf, Layout L, const real *b0, const real *b1, int sides,
+                           const DevScalars *sc) {
+    if (sc && !step_active(sc)) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int f = blockIdx.y;
+    const int side = (sides == 2) ? (int)blockIdx.z : sides - 10;
+    if (j >= L.ny || f >= nf) return;
+    const real *b = side == 0 ? b0 : b1;
+    const int cg = side == 0 ? -G : L.nx;
+#pragma unroll
+    for (int g = 0; g < G; ++g) S.p[f][eidx(L, cg + g, j)] = b[((int64_t)f * G + g) * L.ny + j];
+}
+
+// y strips over the padded width: buffer [f][g][i + G], i in [-G, nx + G)
+template <typename real>
+__global__ void k_pack_y(FPtr<real> S, int nf, Layout L, real *b0, real *b1, int sides, const DevScalars *sc) {
+    if (sc && !step_active(sc)) return;
+    const int w = L.nx + 2 * G;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int f = blockIdx.y;
+    const int side = (sides == 2) ? (int)blockIdx.z : sides - 10;
+    if (i >= w || f >= nf) return;
+    real *b = side == 0 ? b0 : b1;
+    const int r0 = side == 0 ? 0 : L.ny - G;
+#pragma unroll
+    for (int g = 0; g < G; ++g) b[((int64_t)f * G + g) * w + i] = S.p[f][eidx(L, i - G, r0 + g)];
+}
+
+template <typename real>
+__global__ void k_unpack_y(FPtr<real> S, int nf, Layout L, const real *b0, const real *b1, int sides,
+                           const DevScalars *sc) {
+    if (sc && !step_active(sc)) return;
+    const int w = L.nx + 2 * G;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int f = blockIdx.y;
+    const int side = (sides == 2) ? (int)blockIdx.z : sides - 10;
+    if (i >= w || f >= nf) return;
+    const real *b = side == 0 ? b0 : b1;
+    const int rg = side == 0 ? -G : L.ny;
+#pragma unroll
+    for (int g = 0; g < G; ++g) S.p[f][eidx(L, i - G, rg + g)] = b[((int64_t)f * G + g) * w + i];
+}
+
+// open (zero-gradient) or small-periodic (index modulo n) fills
+template <typename real>
+__global__ void k_fill_x(FPtr<real> S, int nf, Layout L, int periodic, const DevScalars *sc) {
+    if (sc && !step_active(sc)) return;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int f = blockIdx.y;
+    if (j >= L.ny || f >= nf) return;
+    for (int g = 1; g <= G; ++g) {
+        int il = -g, ir = L.nx - 1 + g;
+        int sl, sr;
+        if (periodic) {
+            sl = ((il % L.nx) + L.nx) % L.nx;
+            sr = ir % L.nx;
+        } else {
+            sl = 0;
+            sr = L.nx - 1;
+        }
+        S.p[f][eidx(L, il, j)] = S.p[f][eidx(L, sl, j)];
+        S.p[f][eidx(L, ir, j)] = S.p[f][eidx(L, sr, j)];
+    }
+}
+
+template <typename real>
+__global__ void k_fill_y(FPtr<real> S, int nf, Layout L, int periodic, const DevScalars *sc) {
+    if (sc && !step_active(sc)) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x - G;
+    const int f = blockIdx.y;
+    if (i >= L.nx + G || f >= nf) return;
+    for (int g = 1; g <= G; ++g) {
+        int jl = -g, jr = L.ny - 1 + g;
+        int sl, sr;
+        if (periodic) {
+            sl = ((jl % L.ny) + L.ny) % L.ny;
+            sr = jr % L.ny;
+        } else {
+            sl = 0;
+            sr = L.ny - 1;
+        }
+        S.p[f][eidx(L, i, jl)] = S.p[f][eidx(L, i, sl)];
+        S.p[f][eidx(L, i, jr)] = S.p[f][eidx(L, i, sr)];
+    }
+}
+
+// caller arrays <-> internal storage
+template <typename T>
+struct CPtr {
+    const T *p[NF];
+};
+template <typename T>
+struct MPtr {
+    T *p[NF];
+};
+
+template <typename real, typename T>
+__global__ void k_import(FPtr<real> D, CPtr<T> src, int nf, Layout L, int64_t pitch) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= L.nx) return;
+    for (int f = 0; f < nf; ++f) D.p[f][eidx(L, i, j)] = (real)src.p[f][(int64_t)j * pitch + i];
+}
+
+template <typename real, typename T>
+__global__ void k_export(FPtr<real> Sx, MPtr<T> dst, uint32_t mask, Layout L, int64_t pitch) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= L.nx) return;
+    for (int f = 0; f < NF; ++f)
+        if (mask & (1u << f)) dst.p[f][(int64_t)j * pitch + i] = (T)Sx.p[f][eidx(L, i, j)];
+}
+
+// wave speeds of a state into accumulator slot `slot`
+template <typename real>
+__global__ void k_wavespeed(FPtr<real> U, FPtr<real> B, int bg, Layout L, double gamma, DevScalars *sc, int slot) {
+    double cx = 0.0, cy = 0.0;
+    int bad = 0;
+    const real gm1 = (real)(gamma - 1.0), half = (real)0.5, gam = (real)gamma;
+    const int64_t n = (int64_t)L.nx * L.ny;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k % L.nx), j = (int)(k / L.nx);
+        const int64_t e = eidx(L, i, j);
+        real rb = 0, eb = 0, bxb = 0, byb = 0;
+        if (bg) { rb = B.p[0][e]; eb = B.p[1][e]; bxb = B.p[2][e]; byb = B.p[3][e]; }
+        const real rt = U.p[0][e], mx = U.p[1][e], my = U.p[2][e], et = U.p[3][e], bxt = U.p[4][e], byt = U.p[5][e];
+        const real r = rb + rt;
+        const real ir = (real)1 / r;
+        const real ux = mx * ir, uy = my * ir;
+        const real kin = half * (mx * ux + my * uy);
+        const real bbd = bxb * bxt + byb * byt;
+        const real bt2 = bxt * bxt + byt * byt;
+        const real pkt = gm1 * (((et - kin) - bbd) - half * bt2);
+        const real b2b = bxb * bxb + byb * byb;
+        const real pkb = gm1 * (eb - half * b2b);
+        const real pk = pkb + pkt;
+        const real bx = bxb + bxt, by = byb + byt;
+        const real cf = sqrt((gam * pk + (bx * bx + by * by)) * ir);
+        const bool fin = isfinite(rt) && isfinite(mx) && isfinite(my) && isfinite(et) && isfinite(bxt) &&
+                         isfinite(byt) && isfinite(cf);
+        if (!(r > (real)0) || !(pk > (real)0) || !fin) {
+            bad = 1;
+            continue;
+        }
+        cx = fmax(cx, (double)(fabs(ux) + cf));
+        cy = fmax(cy, (double)(fabs(uy) + cf));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        cx = fmax(cx, __shfl_xor(cx, off));
+        cy = fmax(cy, __shfl_xor(cy, off));
+        bad |= __shfl_xor(bad, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&sc->cacc[slot][0], (unsigned long long)__double_as_longlong(cx));
+        atomicMax(&sc->cacc[slot][1], (unsigned long long)__double_as_longlong(cy));
+        if (bad) atomicOr(&sc->nonphys, 1);
+    }
+}
+
+__global__ void k_reset_scalars(DevScalars *sc, double t0) {
+    sc->t = t0;
+    sc->dt = 0.0;
+    sc->cmax = 0.0;
+    sc->t_end = 0.0;
+    sc->cacc[0][0] = sc->cacc[0][1] = sc->cacc[1][0] = sc->cacc[1][1] = 0ull;
+    sc->last_cx = sc->last_cy = sc->last_cmax = 0.0;
+    sc->steps = 0;
+    sc->cur = 0;
+    sc->active = 1;
+    sc->nonphys = 0;
+    sc->pad = 0;
+}
+
+// dt for the step about to start (CFL time step with the end-time clamp)
+__global__ void k_step_begin(DevScalars *sc, double t_end, double cfl, double dx, double dy, int ax, int ay) {
+    sc->t_end = t_end;
+    if (sc->nonphys) { sc->active = 0; return; }
+    const double t = sc->t;
+    if (t_end > 0.0 && t_end - t <= 1e-12 * t_end) { sc->active = 0; return; }
+    const double cx = __longlong_as_double((long long)sc->cacc[sc->cur][0]);
+    const double cy = __longlong_as_double((long long)sc->cacc[sc->cur][1]);
+    double h;
+    if (ax && ay) h = (dx / cx < dy / cy) ? dx / cx : dy / cy;
+    else if (ax) h = dx / cx;
+    else h = dy / cy;
+    double dt = cfl * h;
+    if (t_end > 0.0) dt = (dt < t_end - t) ? dt : t_end - t;
+    sc->dt = dt;
+    sc->cmax = (ax && ay) ? (cx > cy ? cx : cy) : (ax ? cx : cy);
+    sc->last_cx = cx;
+    sc->last_cy = cy;
+    sc->last_cmax = sc->cmax;
+    sc->cacc[sc->cur ^ 1][0] = 0ull;
+    sc->cacc[sc->cur ^ 1][1] = 0ull;
+    sc->active = 1;
+}
+
+__global__ void k_step_end(DevScalars *sc) {
+    if (!sc->active) return;
+    sc->t = sc->t + sc->dt;
+    sc->steps = sc->steps + 1;
+    sc->cur ^= 1;
+}
+
+// conservation sums: per-block partial sums of rows, then a fixed-order final sum
+template <typename real>
+__global__ void k_sums_partial(FPtr<real> U, Layout L, double *partials, int npart) {
+    __shared__ double red[NF][256];
+    double acc[NF] = {0, 0, 0, 0, 0, 0};
+    for (int j = blockIdx.x; j < L.ny; j += npart)
+        for (int i = threadIdx.x; i < L.nx; i += blockDim.x)
+            for (int f = 0; f < NF; ++f) acc[f] += (double)U.p[f][eidx(L, i, j)];
+    for (int f = 0; f < NF; ++f) red[f][threadIdx.x] = acc[f];
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int f = 0; f < NF; ++f) red[f][threadIdx.x] += red[f][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int f = 0; f < NF; ++f) partials[(int64_t)blockIdx.x * NF + f] = red[f][0];
+}
+
+__global__ void k_sums_final(const double *partials, int npart, double *out, double cell) {
+    if (threadIdx.x >= NF) return;
+    double s = 0.0;
+    for (int b = 0; b < npart; ++b) s += partials[(int64_t)b * NF + threadIdx.x];
+    out[threadIdx.x] = s * cell;
+}
+
+// ------------------------------------------------------------------ host helpers
+
+// event marks: class 0..3 = stage kernels, 4 = halo, 5 = scalar kernels
+int prof_event(sacx_ctx *c) {
+    if (c->ev_used == (int)c->ev_pool->size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        c->ev_pool->push_back(e);
+    }
+    int k = c->ev_used++;
+    if (hipEventRecord((*c->ev_pool)[k], c->stream) != hipSuccess) return -1;
+    return k;
+}
+
+struct ProfScope {
+    sacx_ctx *c;
+    int cls, start;
+    ProfScope(sacx_ctx *c_, int cls_) : c(c_), cls(cls_), start(-1) {
+        if (c->prof_on) start = prof_event(c);
+    }
+    ~ProfScope() {
+        if (c->prof_on && start >= 0) {
+            int stop = prof_event(c);
+            if (stop >= 0) c->ev_marks->push_back({cls, {start, stop}});
+        }
+    }
+};
+
+
+template <typename real>
+FPtr<real> fptr(void *const *p, int nf) {
+    FPtr<real> f;
+    for (int k = 0; k < NF; ++k) f.p[k] = (real *)(k < nf ? p[k] : p[0]);
+    return f;
+}
+
+template <typename real>
+int fill_halo_t(sacx_ctx *c, void *const *fields, int nf, bool gated) {
+    const Layout &L = c->L;
+    const DevScalars *sc = gated ? c->sc : nullptr;
+    FPtr<real> S = fptr<real>(fields, nf);
+    const int T = 256;
+    // x direction (interior rows)
+    if (c->bc[0] == SACX_PERIODIC && L.nx >= G) {
+        dim3 g((L.ny + T - 1) / T, nf, 2);
+        hipLaunchKernelGGL(k_pack_x<real>, g, dim3(T), 0, c->stream, S, nf, L, (real *)c->hx[0], (real *)c->hx[1], 2, sc);
+        // self-exchange: what x- packed becomes the x+ halo and vice versa
+        hipLaunchKernelGGL(k_unpack_x<real>, g, dim3(T), 0, c->stream, S, nf, L, (const real *)c->hx[1],
+                           (const real *)c->hx[0], 2, sc);
+    } else {
+        dim3 g((L.ny + T - 1) / T, nf);
+        hipLaunchKernelGGL(k_fill_x<real>, g, dim3(T), 0, c->stream, S, nf, L, c->bc[0] == SACX_PERIODIC ? 1 : 0, sc);
+    }
+    // y direction over the padded width (corners included)
+    const int w = L.nx + 2 * G;
+    if (c->bc[2] == SACX_PERIODIC && L.ny >= G) {
+        dim3 g((w + T - 1) / T, nf, 2);
+        hipLaunchKernelGGL(k_pack_y<real>, g, dim3(T), 0, c->stream, S, nf, L, (real *)c->hy[0], (real *)c->hy[1], 2, sc);
+        hipLaunchKernelGGL(k_unpack_y<real>, g, dim3(T), 0, c->stream, S, nf, L, (const real *)c->hy[1],
+                           (const real *)c->hy[0], 2, sc);
+    } else {
+        dim3 g((w + T - 1) / T, nf);
+        hipLaunchKernelGGL(k_fill_y<real>, g, dim3(T), 0, c->stream, S, nf, L, c->bc[2] == SACX_PERIODIC ? 1 : 0, sc);
+    }
+    HIPCHK(hipGetLastError());
+    return SACX_OK;
+}
+
+int fill_halo(sacx_ctx *c, void *const *fields, int nf, bool gated) {
+    return c->grid.precision == SACX_FP64 ? fill_halo_t<double>(c, fields, nf, gated)
+                                          : fill_halo_t<float>(c, fields, nf, gated);
+}
+
+template <typename real>
+StageArgs<real> stage_args(sacx_ctx *c) {
+    StageArgs<real> a;
+    std::memset(&a, 0, sizeof(a));
+    a.L = c->L;
+    a.ty = c->ty;
+    a.dx = c->dx;
+    a.dy = c->dy;
+    a.gamma = c->params.gamma;
+    for (int k = 0; k < 4; ++k) { a.c2[k] = c->params.c2[k]; a.cshk[k] = c->params.cshk[k]; }
+    a.hd_cross_on = c->params.hd_cross_on;
+    a.active_x = c->grid.nx > 1;
+    a.active_y = c->grid.ny > 1;
+    a.sc = c->sc;
+    for (int k = 0; k < NBG; ++k) a.BG[k] = (const real *)(c->grid.background_on ? c->BG[k] : nullptr);
+    return a;
+}
+
+template <typename real>
+int run_stage(sacx_ctx *c, int stage, void *const *S, void *const *U, void *const *A, void *const *o1,
+              void *const *o2) {
+    StageArgs<real> a = stage_args<real>(c);
+    for (int f = 0; f < NF; ++f) {
+        a.S[f] = (const real *)S[f];
+        a.U[f] = (const real *)(U ? U[f] : S[f]);
+        a.A[f] = (const real *)(A ? A[f] : S[f]);
+        a.out1[f] = (real *)o1[f];
+        a.out2[f] = (real *)(o2 ? o2[f] : o1[f]);
+    }
+    HIPCHK(launch_stage<real>(stage, c->params.hd_on != 0, c->grid.background_on != 0, a, c->stream));
+    return SACX_OK;
+}
+
+int stage(sacx_ctx *c, int s, void *const *S, void *const *U, void *const *A, void *const *o1, void *const *o2) {
+    {
+        ProfScope ps(c, 4);
+        int rc = fill_halo(c, S, NF, true);
+        if (rc) return rc;
+    }
+    ProfScope ps(c, s - 1);
+    return c->grid.precision == SACX_FP64 ? run_stage<double>(c, s, S, U, A, o1, o2)
+                                          : run_stage<float>(c, s, S, U, A, o1, o2);
+}
+
+int wavespeed_into(sacx_ctx *c, int slot) {
+    const int64_t n = (int64_t)c->L.nx * c->L.ny;
+    const int T = 256;
+    int blocks = (int)std::min<int64_t>((n + T - 1) / T, 4096);
+    if (c->grid.precision == SACX_FP64)
+        hipLaunchKernelGGL(k_wavespeed<double>, dim3(blocks), dim3(T), 0, c->stream, fptr<double>(c->U, NF),
+                           fptr<double>(c->grid.background_on ? c->BG : c->U, NBG), c->grid.background_on, c->L,
+                           c->params.gamma, c->sc, slot);
+    else
+        hipLaunchKernelGGL(k_wavespeed<float>, dim3(blocks), dim3(T), 0, c->stream, fptr<float>(c->U, NF),
+                           fptr<float>(c->grid.background_on ? c->BG : c->U, NBG), c->grid.background_on, c->L,
+                           c->params.gamma, c->sc, slot);
+    HIPCHK(hipGetLastError());
+    return SACX_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int sacx_abi_version(void) { return SACX_ABI_VERSION; }
+
+const char *sacx_strerror(int code) {
+    switch (code) {
+        case SACX_OK: return "success";
+        case SACX_EINVAL: return "invalid argument";
+        case SACX_ENOSPC: return "workspace or buffer too small";
+        case SACX_EDEVICE: return "HIP runtime error";
+        case SACX_ENONPHYS: return "non-physical state (rho <= 0, p <= 0 or non-finite)";
+        case SACX_EUNSUP: return "unsupported request";
+        case SACX_ESTATE: return "call out of order";
+        default: return "unknown status code";
+    }
+}
+
+const char *sacx_last_error(void) { return g_last_error.c_str(); }
+
+int sacx_workspace_size(const sacx_grid *grid, const sacx_params *params, size_t *bytes) {
+    int rc = check_grid(grid, params);
+    if (rc) return rc;
+    if (!bytes) return fail(SACX_EINVAL, "bytes must not be NULL");
+    *bytes = make_plan(grid).total;
+    return SACX_OK;
+}
+
+int sacx_create(const sacx_grid *grid, const sacx_params *params, void *d_ws, size_t ws_bytes, void *hip_stream,
+                sacx_ctx **out) {
+    int rc = check_grid(grid, params);
+    if (rc) return rc;
+    if (!out) return fail(SACX_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!d_ws) return fail(SACX_EINVAL, "workspace pointer is NULL");
+    if (((uintptr_t)d_ws) % kAlign) return fail(SACX_EINVAL, "workspace must be 256-byte aligned");
+    Plan P = make_plan(grid);
+    if (ws_bytes < P.total)
+        return fail(SACX_ENOSPC, "workspace has %zu bytes, %zu needed", ws_bytes, P.total);
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    sacx_ctx *c = new (std::nothrow) sacx_ctx;
+    if (!c) return fail(SACX_EINVAL, "out of host memory");
+    std::memset((void *)c, 0, sizeof(*c));
+    c->grid = *grid;
+    c->params = *params;
+    c->device = dev;
+    c->stream = (hipStream_t)hip_stream;
+    c->L = P.L;
+    c->elem = P.elem;
+    for (int s = 0; s < 4; ++s) c->bc[s] = SACX_PERIODIC;
+    c->ws = (char *)d_ws;
+    c->ws_bytes = ws_bytes;
+    c->sc = (DevScalars *)(c->ws + P.off_sc);
+    c->sums = (double *)(c->ws + P.off_sums);
+    c->partials = (double *)(c->ws + P.off_part);
+    c->npart = (int)std::min<int64_t>(kPartials, grid->ny);
+    char *st = c->ws + P.off_state;
+    for (int f = 0; f < NF; ++f) {
+        c->U[f] = st + (0 * NF + f) * P.field_bytes;
+        c->B1[f] = st + (1 * NF + f) * P.field_bytes;
+        c->B2[f] = st + (2 * NF + f) * P.field_bytes;
+        c->A[f] = st + (3 * NF + f) * P.field_bytes;
+    }
+    for (int k = 0; k < NBG; ++k) c->BG[k] = grid->background_on ? c->ws + P.off_bg + k * P.field_bytes : nullptr;
+    c->hx[0] = c->ws + P.off_hx;
+    c->hx[1] = c->ws + P.off_hx + P.hx_bytes;
+    c->hy[0] = c->ws + P.off_hy;
+    c->hy[1] = c->ws + P.off_hy + P.hy_bytes;
+    c->ty = default_ty(c->L);
+    c->dx = (grid->x1 - grid->x0) / grid->nx;
+    c->dy = (grid->y1 - grid->y0) / grid->ny;
+    c->initialized = false;
+    c->prof_on = false;
+    c->ev_pool = new (std::nothrow) std::vector<hipEvent_t>();
+    c->ev_marks = new (std::nothrow) std::vector<std::pair<int, std::pair<int, int>>>();
+    if (!c->ev_pool || !c->ev_marks) {
+        delete c->ev_pool;
+        delete c->ev_marks;
+        delete c;
+        return fail(SACX_EINVAL, "out of host memory");
+    }
+    c->ev_used = 0;
+    *out = c;
+    return SACX_OK;
+}
+
+int sacx_destroy(sacx_ctx *ctx) {
+    if (!ctx) return SACX_OK;
+    if (ctx->ev_pool) {
+        for (hipEvent_t e : *ctx->ev_pool) (void)hipEventDestroy(e);
+        delete ctx->ev_pool;
+    }
+    delete ctx->ev_marks;
+    delete ctx;
+    return SACX_OK;
+}
+
+int sacx_profile_enable(sacx_ctx *ctx, int32_t on) {
+    if (!ctx) return fail(SACX_EINVAL, "ctx must not be NULL");
+    std::memset(&ctx->prof, 0, sizeof(ctx->prof));
+    ctx->ev_marks->clear();
+    ctx->ev_used = 0;
+    ctx->prof_on = on != 0;
+    return SACX_OK;
+}
+
+int sacx_profile_read(sacx_ctx *ctx, sacx_profile *out) {
+    if (!ctx || !out) return fail(SACX_EINVAL, "ctx/out must not be NULL");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    for (const auto &m : *ctx->ev_marks) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, (*ctx->ev_pool)[m.second.first], (*ctx->ev_pool)[m.second.second]));
+        if (m.first < 4) {
+            ctx->prof.ms_stage[m.first] += ms;
+            ctx->prof.n_stage[m.first] += 1;
+        } else if (m.first == 4) {
+            ctx->prof.ms_halo += ms;
+            ctx->prof.n_halo += 1;
+        } else {
+            ctx->prof.ms_scalar += ms;
+            ctx->prof.n_scalar += 1;
+        }
+    }
+    ctx->ev_marks->clear();
+    ctx->ev_used = 0;
+    *out = ctx->prof;
+    return SACX_OK;
+}
+
+int sacx_set_boundaries(sacx_ctx *ctx, const int32_t bc[4]) {
+    if (!ctx || !bc) return fail(SACX_EINVAL, "ctx/bc must not be NULL");
+    for (int s = 0; s < 4; ++s)
+        if (bc[s] != SACX_PERIODIC && bc[s] != SACX_OPEN) return fail(SACX_EINVAL, "bc[%d] = %d is not a boundary kind", s, bc[s]);
+    if ((bc[0] == SACX_PERIODIC) != (bc[1] == SACX_PERIODIC))
+        return fail(SACX_EINVAL, "periodic x boundaries must be paired");
+    if ((bc[2] == SACX_PERIODIC) != (bc[3] == SACX_PERIODIC))
+        return fail(SACX_EINVAL, "periodic y boundaries must be paired");
+    if (ctx->grid.nx == 1 && bc[0] != SACX_PERIODIC) return fail(SACX_EINVAL, "a one-cell direction must be periodic");
+    if (ctx->grid.ny == 1 && bc[2] != SACX_PERIODIC) return fail(SACX_EINVAL, "a one-cell direction must be periodic");
+    for (int s = 0; s < 4; ++s) ctx->bc[s] = bc[s];
+    return SACX_OK;
+}
+
+int sacx_init_state(sacx_ctx *ctx, const void *const *d_fields, const void *const *d_bg, int64_t pitch,
+                    int32_t in_precision, double t0) {
+    if (!ctx || !d_fields) return fail(SACX_EINVAL, "ctx/fields must not be NULL");
+    for (int f = 0; f < NF; ++f)
+        if (!d_fields[f]) return fail(SACX_EINVAL, "field pointer %d is NULL", f);
+    if (pitch < ctx->grid.nx) return fail(SACX_EINVAL, "pitch %lld < nx %d", (long long)pitch, ctx->grid.nx);
+    if (in_precision != SACX_FP64 && in_precision != SACX_FP32) return fail(SACX_EINVAL, "bad input precision");
+    if (ctx->grid.background_on && !d_bg) return fail(SACX_EINVAL, "background arrays required (background_on)");
+    if (ctx->grid.background_on)
+        for (int k = 0; k < NBG; ++k)
+            if (!d_bg[k]) return fail(SACX_EINVAL, "background pointer %d is NULL", k);
+    if (!std::isfinite(t0)) return fail(SACX_EINVAL, "t0 must be finite");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    const Layout &L = ctx->L;
+    dim3 g((L.nx + 255) / 256, L.ny);
+    const bool f64 = ctx->grid.precision == SACX_FP64;
+    auto import = [&](void *const *dst, const void *const *src, int nf) {
+        if (f64) {
+            if (in_precision == SACX_FP64) {
+                CPtr<double> t;
+                for (int k = 0; k < NF; ++k) t.p[k] = (const double *)src[k < nf ? k : 0];
+                hipLaunchKernelGGL((k_import<double, double>), g, dim3(256), 0, ctx->stream, fptr<double>(dst, nf), t, nf, L, pitch);
+            } else {
+                CPtr<float> t;
+                for (int k = 0; k < NF; ++k) t.p[k] = (const float *)src[k < nf ? k : 0];
+                hipLaunchKernelGGL((k_import<double, float>), g, dim3(256), 0, ctx->stream, fptr<double>(dst, nf), t, nf, L, pitch);
+            }
+        } else {
+            if (in_precision == SACX_FP64) {
+                CPtr<double> t;
+                for (int k = 0; k < NF; ++k) t.p[k] = (const double *)src[k < nf ? k : 0];
+                hipLaunchKernelGGL((k_import<float, double>), g, dim3(256), 0, ctx->stream, fptr<float>(dst, nf), t, nf, L, pitch);
+            } else {
+                CPtr<float> t;
+                for (int k = 0; k < NF; ++k) t.p[k] = (const float *)src[k < nf ? k : 0];
+                hipLaunchKernelGGL((k_import<float, float>), g, dim3(256), 0, ctx->stream, fptr<float>(dst, nf), t, nf, L, pitch);
+            }
+        }
+    };
+    import(ctx->U, d_fields, NF);
+    if (ctx->grid.background_on) {
+        import(ctx->BG, d_bg, NBG);
+        int rc = fill_halo(ctx, ctx->BG, NBG, false);
+        if (rc) return rc;
+    }
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, ctx->stream, ctx->sc, t0);
+    int rc = fill_halo(ctx, ctx->U, NF, false);
+    if (rc) return rc;
+    rc = wavespeed_into(ctx, 0);
+    if (rc) return rc;
+    HIPCHK(hipGetLastError());
+    ctx->initialized = true;
+    return SACX_OK;
+}
+
+int sacx_advance(sacx_ctx *ctx, int32_t nsteps, double t_end, int32_t *steps_done, double *t_now) {
+    if (!ctx) return fail(SACX_EINVAL, "ctx must not be NULL");
+    if (nsteps < 0) return fail(SACX_EINVAL, "nsteps must be >= 0");
+    if (!std::isfinite(t_end)) return fail(SACX_EINVAL, "t_end must be finite");
+    if (!ctx->initialized) return fail(SACX_ESTATE, "sacx_init_state has not been called");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    long long steps0 = 0;
+    const bool sync = steps_done || t_now;
+    if (sync) {
+        HIPCHK(hipMemcpyAsync(&steps0, &ctx->sc->steps, sizeof(steps0), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+    }
+    const int ax = ctx->grid.nx > 1, ay = ctx->grid.ny > 1;
+    // A synchronising call enqueues in chunks and stops early once the device
+    // reports that stepping ended (end time reached or non-physical state).
+    const int chunk = sync ? 128 : (nsteps > 0 ? nsteps : 1);
+    for (int n0 = 0; n0 < nsteps; n0 += chunk) {
+        const int n1 = std::min(nsteps, n0 + chunk);
+        for (int n = n0; n < n1; ++n) {
+            {
+                ProfScope ps(ctx, 5);
+                hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, ctx->stream, ctx->sc, t_end, ctx->params.cfl,
+                                   ctx->dx, ctx->dy, ax, ay);
+            }
+            int rc;
+            if ((rc = stage(ctx, 1, ctx->U, nullptr, nullptr, ctx->B1, nullptr))) return rc;
+            if ((rc = stage(ctx, 2, ctx->B1, ctx->U, nullptr, ctx->B2, ctx->A))) return rc;
+            if ((rc = stage(ctx, 3, ctx->B2, ctx->U, nullptr, ctx->B1, nullptr))) return rc;
+            if ((rc = stage(ctx, 4, ctx->B1, nullptr, ctx->A, ctx->U, nullptr))) return rc;
+            {
+                ProfScope ps(ctx, 5);
+                hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, ctx->stream, ctx->sc);
+            }
+            HIPCHK(hipGetLastError());
+        }
+        if (sync && n1 < nsteps) {
+            int act = 1;
+            HIPCHK(hipMemcpyAsync(&act, &ctx->sc->active, sizeof(act), hipMemcpyDeviceToHost, ctx->stream));
+            HIPCHK(hipStreamSynchronize(ctx->stream));
+            if (!act) break;
+        }
+    }
+    if (sync) {
+        DevScalars h;
+        HIPCHK(hipMemcpyAsync(&h, ctx->sc, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHK(hipStreamSynchronize(ctx->stream));
+        if (steps_done) *steps_done = (int32_t)(h.steps - steps0);
+        if (t_now) *t_now = h.t;
+        if (h.nonphys) return fail(SACX_ENONPHYS, "non-physical state after %lld steps", h.steps);
+    }
+    return SACX_OK;
+}
+
+int sacx_read_fields(sacx_ctx *ctx, void *const *d_out, int64_t pitch, uint32_t field_mask, int32_t out_precision) {
+    if (!ctx || !d_out) return fail(SACX_EINVAL, "ctx/out must not be NULL");
+    if (!ctx->initialized) return fail(SACX_ESTATE, "sacx_init_state has not been called");
+    if (pitch < ctx->grid.nx) return fail(SACX_EINVAL, "pitch < nx");
+    if (out_precision != SACX_FP64 && out_precision != SACX_FP32) return fail(SACX_EINVAL, "bad output precision");
+    if (field_mask & ~0x3Fu) return fail(SACX_EINVAL, "field_mask has bits beyond the 6 fields");
+    for (int f = 0; f < NF; ++f)
+        if ((field_mask & (1u << f)) && !d_out[f]) return fail(SACX_EINVAL, "output pointer %d is NULL", f);
+    if (!field_mask) return SACX_OK;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    const Layout &L = ctx->L;
+    dim3 g((L.nx + 255) / 256, L.ny);
+    MPtr<double> td;
+    MPtr<float> tf;
+    for (int f = 0; f < NF; ++f) {
+        void *p = (field_mask & (1u << f)) ? d_out[f] : nullptr;
+        td.p[f] = (double *)p;
+        tf.p[f] = (float *)p;
+    }
+    if (ctx->grid.precision == SACX_FP64) {
+        if (out_precision == SACX_FP64)
+            hipLaunchKernelGGL((k_export<double, double>), g, dim3(256), 0, ctx->stream, fptr<double>(ctx->U, NF), td, field_mask, L, pitch);
+        else
+            hipLaunchKernelGGL((k_export<double, float>), g, dim3(256), 0, ctx->stream, fptr<double>(ctx->U, NF), tf, field_mask, L, pitch);
+    } else {
+        if (out_precision == SACX_FP64)
+            hipLaunchKernelGGL((k_export<float, double>), g, dim3(256), 0, ctx->stream, fptr<float>(ctx->U, NF), td, field_mask, L, pitch);
+        else
+            hipLaunchKernelGGL((k_export<float, float>), g, dim3(256), 0, ctx->stream, fptr<float>(ctx->U, NF), tf, field_mask, L, pitch);
+    }
+    HIPCHK(hipGetLastError());
+    return SACX_OK;
+}
+
+int sacx_diagnostics(sacx_ctx *ctx, sacx_diag *out) {
+    if (!ctx || !out) return fail(SACX_EINVAL, "ctx/out must not be NULL");
+    if (!ctx->initialized) return fail(SACX_ESTATE, "sacx_init_state has not been called");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    if (ctx->grid.precision == SACX_FP64)
+        hipLaunchKernelGGL(k_sums_partial<double>, dim3(ctx->npart), dim3(256), 0, ctx->stream,
+                           fptr<double>(ctx->U, NF), ctx->L, ctx->partials, ctx->npart);
+    else
+        hipLaunchKernelGGL(k_sums_partial<float>, dim3(ctx->npart), dim3(256), 0, ctx->stream,
+                           fptr<float>(ctx->U, NF), ctx->L, ctx->partials, ctx->npart);
+    hipLaunchKernelGGL(k_sums_final, dim3(1), dim3(64), 0, ctx->stream, (const double *)ctx->partials, ctx->npart,
+                       ctx->sums, ctx->dx * ctx->dy);
+    HIPCHK(hipGetLastError());
+    DevScalars h;
+    double sums[NF];
+    HIPCHK(hipMemcpyAsync(&h, ctx->sc, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(sums, ctx->sums, sizeof(sums), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    const double cx = __builtin_bit_cast(double, h.cacc[h.cur][0]);
+    const double cy = __builtin_bit_cast(double, h.cacc[h.cur][1]);
+    out->t = h.t;
+    out->dt = h.dt;
+    out->c_x = cx;
+    out->c_y = cy;
+    const int ax = ctx->grid.nx > 1, ay = ctx->grid.ny > 1;
+    out->c_max = (ax && ay) ? std::max(cx, cy) : (ax ? cx : cy);
+    for (int f = 0; f < NF; ++f) out->sums[f] = sums[f];
+    out->steps = h.steps;
+    out->nonphys = h.nonphys;
+    return SACX_OK;
+}
+
+int sacx_halo_buffer_size(const sacx_ctx *ctx, int32_t side, size_t *bytes) {
+    if (!ctx || !bytes) return fail(SACX_EINVAL, "ctx/bytes must not be NULL");
+    if (side < 0 || side > 3) return fail(SACX_EINVAL, "side must be 0..3");
+    const size_t along = side < 2 ? (size_t)ctx->grid.ny : (size_t)ctx->grid.nx + 2 * G;
+    *bytes = (size_t)NF * G * along * ctx->elem;
+    return SACX_OK;
+}
+
+static int halo_io(sacx_ctx *ctx, int32_t side, void *buf, bool pack) {
+    if (!ctx || !buf) return fail(SACX_EINVAL, "ctx/buffer must not be NULL");
+    if (side < 0 || side > 3) return fail(SACX_EINVAL, "side must be 0..3");
+    if (!ctx->initialized) return fail(SACX_ESTATE, "sacx_init_state has not been called");
+    const Layout &L = ctx->L;
+    if ((side < 2 && L.nx < G) || (side >= 2 && L.ny < G))
+        return fail(SACX_EUNSUP, "halo exchange needs at least %d cells across", G);
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    const int T = 256;
+    const int s = side & 1;
+    const bool f64 = ctx->grid.precision == SACX_FP64;
+    if (side < 2) {
+        dim3 g((L.ny + T - 1) / T, NF, 1);
+        if (f64) {
+            if (pack) hipLaunchKernelGGL(k_pack_x<double>, g, dim3(T), 0, ctx->stream, fptr<double>(ctx->U, NF), NF, L, (double *)buf, (double *)buf, 10 + s, (const DevScalars *)nullptr);
+            else hipLaunchKernelGGL(k_unpack_x<double>, g, dim3(T), 0, ctx->stream, fptr<double>(ctx->U, NF), NF, L, (const double *)buf, (const double *)buf, 10 + s, (const DevScalars *)nullptr);
+        } else {
+            if (pack) hipLaunchKernelGGL(k_pack_x<float>, g, dim3(T), 0, ctx->stream, fptr<float>(ctx->U, NF), NF, L, (float *)buf, (float *)buf, 10 + s, (const DevScalars *)nullptr);
+            else hipLaunchKernelGGL(k_unpack_x<float>, g, dim3(T), 0, ctx->stream, fptr<float>(ctx->U, NF), NF, L, (const float *)buf, (const float *)buf, 10 + s, (const DevScalars *)nullptr);
+        }
+    } else {
+        dim3 g((L.nx + 2 * G + T - 1) / T, NF, 1);
+        if (f64) {
+            if (pack) hipLaunchKernelGGL(k_pack_y<double>, g, dim3(T), 0, ctx->stream, fptr<double>(ctx->U, NF), NF, L, (double *)buf, (double *)buf, 10 + s, (const DevScalars *)nullptr);
+            else hipLaunchKernelGGL(k_unpack_y<double>, g, dim3(T), 0, ctx->stream, fptr<double>(ctx->U, NF), NF, L, (const double *)buf, (const double *)buf, 10 + s, (const DevScalars *)nullptr);
+        } else {
+            if (pack) hipLaunchKernelGGL(k_pack_y<float>, g, dim3(T), 0, ctx->stream, fptr<float>(ctx->U, NF), NF, L, (float *)buf, (float *)buf, 10 + s, (const DevScalars *)nullptr);
+            else hipLaunchKernelGGL(k_unpack_y<float>, g, dim3(T), 0, ctx->stream, fptr<float>(ctx->U, NF), NF, L, (const float *)buf, (const float *)buf, 10 + s, (const DevScalars *)nullptr);
+        }
+    }
+    HIPCHK(hipGetLastError());
+    return SACX_OK;
+}
+
+int sacx_halo_pack(sacx_ctx *ctx, int32_t side, void *d_buf) { return halo_io(ctx, side, d_buf, true); }
+
+int sacx_halo_unpack(sacx_ctx *ctx, int32_t side, const void *d_buf) {
+    return halo_io(ctx, side, const_cast<void *>(d_buf), false);
+}
+
+}  // extern "C"

@@ -1,0 +1,269 @@
+"""ctypes binding of libsacx (the C ABI declared in include/sacx.h).
+
+Argument marshalling only: every step of the method runs in the HIP
+library; PyTorch provides device memory (the caller-owned workspace and
+field buffers) and the stream.  If the library is not built the import of
+this module succeeds but every call raises -- there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsacx.so")
+
+OK, EINVAL, ENOSPC, EDEVICE, ENONPHYS, EUNSUP, ESTATE = 0, -1, -2, -3, -4, -5, -6
+PERIODIC, OPEN = 0, 1
+FP64, FP32 = 0, 1
+GHOST = 3
+FIELDS = ("rho", "mx", "my", "e", "bx", "by")
+BACKGROUND_FIELDS = ("rho_b", "e_b", "bx_b", "by_b")
+
+# Hyper-diffusion constants (density, thermal energy, velocity, field): the
+# scheme's frozen defaults; the paper gives no values.
+DEFAULT_C2 = (0.02, 0.02, 0.2, 0.02)
+DEFAULT_CSHK = (0.5, 0.5, 0.5, 0.5)
+
+EXPORTED = (
+    "sacx_abi_version", "sacx_strerror", "sacx_last_error", "sacx_workspace_size", "sacx_create",
+    "sacx_destroy", "sacx_set_boundaries", "sacx_init_state", "sacx_advance", "sacx_read_fields",
+    "sacx_diagnostics", "sacx_halo_buffer_size", "sacx_halo_pack", "sacx_halo_unpack",
+    "sacx_profile_enable", "sacx_profile_read",
+)
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("x1", ctypes.c_double),
+                ("y0", ctypes.c_double), ("y1", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("background_on", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
+                ("hd_on", ctypes.c_int32), ("hd_cross_on", ctypes.c_int32),
+                ("c2", ctypes.c_double * 4), ("cshk", ctypes.c_double * 4)]
+
+
+class Diag(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double),
+                ("c_x", ctypes.c_double), ("c_y", ctypes.c_double), ("c_max", ctypes.c_double),
+                ("sums", ctypes.c_double * 6), ("steps", ctypes.c_int64), ("nonphys", ctypes.c_int32)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("ms_stage", ctypes.c_double * 4), ("ms_halo", ctypes.c_double), ("ms_scalar", ctypes.c_double),
+                ("n_stage", ctypes.c_int64 * 4), ("n_halo", ctypes.c_int64), ("n_scalar", ctypes.c_int64)]
+
+
+class SacxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(msg)
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """Load libsacx.so; raise if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1710_06423_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    lib.sacx_abi_version.restype = ctypes.c_int
+    lib.sacx_strerror.restype = ctypes.c_char_p
+    lib.sacx_strerror.argtypes = [ctypes.c_int]
+    lib.sacx_last_error.restype = ctypes.c_char_p
+    lib.sacx_workspace_size.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), ctypes.POINTER(ctypes.c_size_t)]
+    lib.sacx_create.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Params), P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+    lib.sacx_destroy.argtypes = [P]
+    lib.sacx_set_boundaries.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
+    lib.sacx_init_state.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.c_double]
+    lib.sacx_advance.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
+                                 ctypes.POINTER(ctypes.c_double)]
+    lib.sacx_read_fields.argtypes = [P, ctypes.POINTER(P), ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32]
+    lib.sacx_diagnostics.argtypes = [P, ctypes.POINTER(Diag)]
+    lib.sacx_halo_buffer_size.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
+    lib.sacx_halo_pack.argtypes = [P, ctypes.c_int32, P]
+    lib.sacx_halo_unpack.argtypes = [P, ctypes.c_int32, P]
+    lib.sacx_profile_enable.argtypes = [P, ctypes.c_int32]
+    lib.sacx_profile_read.argtypes = [P, ctypes.POINTER(Profile)]
+    for n in EXPORTED:
+        if n not in ("sacx_strerror", "sacx_last_error"):
+            getattr(lib, n).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, what: str):
+    if rc != OK:
+        lib = load_library()
+        msg = lib.sacx_last_error().decode() or lib.sacx_strerror(rc).decode()
+        raise SacxError(rc, f"{what}: {msg} (code {rc})")
+
+
+def make_grid(nx, ny, x0, x1, y0, y1, precision=FP64, background_on=False) -> Grid:
+    return Grid(int(nx), int(ny), float(x0), float(x1), float(y0), float(y1), int(precision), int(bool(background_on)))
+
+
+def make_params(gamma, cfl=0.3, hd_on=True, hd_cross_on=True, c2=DEFAULT_C2, cshk=DEFAULT_CSHK) -> Params:
+    return Params(float(gamma), float(cfl), int(bool(hd_on)), int(bool(hd_cross_on)),
+                  (ctypes.c_double * 4)(*c2), (ctypes.c_double * 4)(*cshk))
+
+
+def workspace_size(grid: Grid, params: Params) -> int:
+    lib = load_library()
+    n = ctypes.c_size_t(0)
+    _check(lib.sacx_workspace_size(ctypes.byref(grid), ctypes.byref(params), ctypes.byref(n)), "sacx_workspace_size")
+    return n.value
+
+
+def _ptrs(tensors: Sequence[Optional[torch.Tensor]]):
+    arr = (ctypes.c_void_p * len(tensors))()
+    for k, t in enumerate(tensors):
+        arr[k] = None if t is None else t.data_ptr()
+    return arr
+
+
+class Solver:
+    """One subdomain context (sacx_ctx) with its torch-owned workspace."""
+
+    def __init__(self, grid: Grid, params: Params, bc=(PERIODIC,) * 4, device="cuda",
+                 stream: Optional[torch.cuda.Stream] = None):
+        self.lib = load_library()
+        self.grid, self.params = grid, params
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = workspace_size(grid, params)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.ctx = ctypes.c_void_p(None)
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_create(ctypes.byref(grid), ctypes.byref(params),
+                                        ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.ctx)),
+                   "sacx_create")
+        self.set_boundaries(bc)
+        self.dtype = torch.float64 if grid.precision == FP64 else torch.float32
+
+    @classmethod
+    def from_problem(cls, prob, precision=FP64, cfl=0.3, hd_on=True, hd_cross_on=True, c2=DEFAULT_C2,
+                     cshk=DEFAULT_CSHK, device="cuda", init=True, **kw) -> "Solver":
+        grid = make_grid(prob.nx, prob.ny, prob.x0, prob.x1, prob.y0, prob.y1, precision,
+                         prob.background is not None)
+        params = make_params(prob.gamma, cfl, hd_on, hd_cross_on, c2, cshk)
+        s = cls(grid, params, tuple(prob.bc), device=device, **kw)
+        if init:
+            f = torch.stack([torch.from_numpy(prob.fields[k]) for k in FIELDS]).to(s.device)
+            bg = None
+            if prob.background is not None:
+                bg = torch.stack([torch.from_numpy(prob.background[k]) for k in BACKGROUND_FIELDS]).to(s.device)
+            s.init_state(f, bg, t0=prob.t0)
+        return s
+
+    def close(self):
+        if self.ctx:
+            self.lib.sacx_destroy(self.ctx)
+            self.ctx = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_boundaries(self, bc):
+        arr = (ctypes.c_int32 * 4)(*[int(b) for b in bc])
+        _check(self.lib.sacx_set_boundaries(self.ctx, arr), "sacx_set_boundaries")
+
+    def init_state(self, fields: torch.Tensor, bg: Optional[torch.Tensor] = None, t0: float = 0.0):
+        """fields: (6, ny, nx) float64/float32 device tensor (rows contiguous)."""
+        if fields.dim() != 3 or fields.shape[0] != 6 or fields.device != self.device:
+            raise ValueError(f"fields must be a (6, ny, nx) tensor on {self.device}, got {tuple(fields.shape)} on {fields.device}")
+        if fields.shape[1] != self.grid.ny or fields.shape[2] != self.grid.nx:
+            raise ValueError("fields shape does not match the grid")
+        fields = fields.contiguous()
+        prec = FP64 if fields.dtype == torch.float64 else FP32
+        self._init_keep = (fields, bg)
+        bgp = None
+        if bg is not None:
+            bg = bg.to(fields.dtype).contiguous()
+            bgp = _ptrs([bg[k] for k in range(4)])
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_init_state(self.ctx, _ptrs([fields[k] for k in range(6)]), bgp,
+                                            fields.shape[2], prec, float(t0)), "sacx_init_state")
+
+    def advance(self, nsteps: int, t_end: float = 0.0, sync: bool = True):
+        """Enqueue nsteps; with sync, return (steps_done, t) and raise on a non-physical stop."""
+        with torch.cuda.device(self.device):
+            if not sync:
+                _check(self.lib.sacx_advance(self.ctx, int(nsteps), float(t_end), None, None), "sacx_advance")
+                return None
+            done = ctypes.c_int32(0)
+            t = ctypes.c_double(0.0)
+            rc = self.lib.sacx_advance(self.ctx, int(nsteps), float(t_end), ctypes.byref(done), ctypes.byref(t))
+            self.last_rc = rc
+            _check(rc, "sacx_advance")
+            return done.value, t.value
+
+    def advance_rc(self, nsteps: int, t_end: float = 0.0):
+        """Like advance(sync=True) but return (rc, steps_done, t) instead of raising on ENONPHYS."""
+        with torch.cuda.device(self.device):
+            done = ctypes.c_int32(0)
+            t = ctypes.c_double(0.0)
+            rc = self.lib.sacx_advance(self.ctx, int(nsteps), float(t_end), ctypes.byref(done), ctypes.byref(t))
+            if rc not in (OK, ENONPHYS):
+                _check(rc, "sacx_advance")
+            return rc, done.value, t.value
+
+    def read_fields(self, dtype: torch.dtype = torch.float64, mask: int = 0x3F) -> torch.Tensor:
+        out = torch.zeros((6, self.grid.ny, self.grid.nx), dtype=dtype, device=self.device)
+        prec = FP64 if dtype == torch.float64 else FP32
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_read_fields(self.ctx, _ptrs([out[k] for k in range(6)]), self.grid.nx, mask, prec),
+                   "sacx_read_fields")
+        return out
+
+    def diagnostics(self) -> Dict:
+        d = Diag()
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_diagnostics(self.ctx, ctypes.byref(d)), "sacx_diagnostics")
+        return {"t": d.t, "dt": d.dt, "c_x": d.c_x, "c_y": d.c_y, "c_max": d.c_max,
+                "sums": list(d.sums), "steps": d.steps, "nonphys": d.nonphys}
+
+    def halo_buffer(self, side: int) -> torch.Tensor:
+        n = ctypes.c_size_t(0)
+        _check(self.lib.sacx_halo_buffer_size(self.ctx, int(side), ctypes.byref(n)), "sacx_halo_buffer_size")
+        return torch.zeros(n.value // (8 if self.grid.precision == FP64 else 4), dtype=self.dtype,
+                           device=self.device)
+
+    def halo_pack(self, side: int, buf: torch.Tensor):
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_halo_pack(self.ctx, int(side), ctypes.c_void_p(buf.data_ptr())), "sacx_halo_pack")
+
+    def halo_unpack(self, side: int, buf: torch.Tensor):
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_halo_unpack(self.ctx, int(side), ctypes.c_void_p(buf.data_ptr())), "sacx_halo_unpack")
+
+    def profile_enable(self, on: bool = True):
+        _check(self.lib.sacx_profile_enable(self.ctx, int(bool(on))), "sacx_profile_enable")
+
+    def profile_read(self) -> Dict:
+        p = Profile()
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_profile_read(self.ctx, ctypes.byref(p)), "sacx_profile_read")
+        return {"ms_stage": list(p.ms_stage), "n_stage": list(p.n_stage), "ms_halo": p.ms_halo,
+                "n_halo": p.n_halo, "ms_scalar": p.ms_scalar, "n_scalar": p.n_scalar}

@@ -1,0 +1,129 @@
+"""C ABI checks that need no GPU: exported symbols, struct layout, host-only
+argument validation and workspace arithmetic."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sacx.h")
+
+
+@pytest.fixture(scope="module")
+def sx():
+    from paper_1710_06423_amd import sacx
+    if not os.path.exists(sacx.LIB_PATH):
+        from paper_1710_06423_amd import build
+        build.build()
+    sacx.load_library()
+    return sacx
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(sacx_\w+)\s*\(", text, re.M)))
+
+
+def test_every_declared_symbol_is_exported(sx):
+    lib = sx.load_library()
+    names = declared_functions()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(sx.EXPORTED)
+
+
+def test_abi_version_matches_header(sx):
+    m = re.search(r"#define SACX_ABI_VERSION (\d+)", open(HEADER).read())
+    assert sx.load_library().sacx_abi_version() == int(m.group(1))
+
+
+def test_struct_layout_matches_header(sx, tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "sacx.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\\n", sizeof(sacx_grid), sizeof(sacx_params), sizeof(sacx_diag), sizeof(sacx_profile));
+  printf("%zu %zu %zu\\n", offsetof(sacx_grid, precision), offsetof(sacx_params, c2), offsetof(sacx_diag, steps));
+  printf("%zu %zu\\n", offsetof(sacx_profile, n_stage), offsetof(sacx_diag, nonphys));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), "-o", str(exe), str(src)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals[:4] == [ctypes.sizeof(sx.Grid), ctypes.sizeof(sx.Params), ctypes.sizeof(sx.Diag),
+                        ctypes.sizeof(sx.Profile)]
+    assert vals[4] == sx.Grid.precision.offset
+    assert vals[5] == sx.Params.c2.offset
+    assert vals[6] == sx.Diag.steps.offset
+    assert vals[7] == sx.Profile.n_stage.offset
+    assert vals[8] == sx.Diag.nonphys.offset
+
+
+def test_strerror_and_codes(sx):
+    lib = sx.load_library()
+    for code in (0, -1, -2, -3, -4, -5, -6):
+        assert lib.sacx_strerror(code)
+    assert b"unknown" in lib.sacx_strerror(-99)
+
+
+def test_workspace_size_arithmetic(sx):
+    p = sx.make_params(5 / 3)
+    a = sx.workspace_size(sx.make_grid(1000, 1000, 0, 1, 0, 1), p)
+    b = sx.workspace_size(sx.make_grid(2000, 2000, 0, 1, 0, 1), p)
+    c = sx.workspace_size(sx.make_grid(1000, 1000, 0, 1, 0, 1, precision=sx.FP32), p)
+    d = sx.workspace_size(sx.make_grid(1000, 1000, 0, 1, 0, 1, background_on=True), p)
+    assert a % 256 == 0 and b > 3.9 * a * 0.9 and c < a and d > a
+    # 4 state copies x 6 fields x (ny + 6) rows x pitch x 8 bytes dominate
+    assert a >= 4 * 6 * 1006 * 1035 * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(ny=-3), dict(nx=1, ny=1), dict(x1=0.0), dict(precision=7), dict(background_on=2),
+])
+def test_invalid_grids_rejected(sx, bad):
+    kw = dict(nx=16, ny=16, x0=0.0, x1=1.0, y0=0.0, y1=1.0, precision=0, background_on=0)
+    kw.update(bad)
+    g = sx.Grid(kw["nx"], kw["ny"], kw["x0"], kw["x1"], kw["y0"], kw["y1"], kw["precision"], kw["background_on"])
+    with pytest.raises(sx.SacxError) as e:
+        sx.workspace_size(g, sx.make_params(5 / 3))
+    assert e.value.code == sx.EINVAL
+
+
+@pytest.mark.parametrize("bad", [dict(gamma=1.0), dict(cfl=0.0), dict(c2=(-1, 0, 0, 0)), dict(cshk=(0, float("nan"), 0, 0))])
+def test_invalid_params_rejected(sx, bad):
+    kw = dict(gamma=5 / 3, cfl=0.3, c2=sx.DEFAULT_C2, cshk=sx.DEFAULT_CSHK)
+    kw.update(bad)
+    p = sx.make_params(kw["gamma"], kw["cfl"], True, True, kw["c2"], kw["cshk"])
+    with pytest.raises(sx.SacxError) as e:
+        sx.workspace_size(sx.make_grid(8, 8, 0, 1, 0, 1), p)
+    assert e.value.code == sx.EINVAL
+
+
+def test_create_rejects_bad_workspace_without_touching_the_device(sx):
+    lib = sx.load_library()
+    g, p = sx.make_grid(8, 8, 0, 1, 0, 1), sx.make_params(5 / 3)
+    out = ctypes.c_void_p()
+    assert lib.sacx_create(ctypes.byref(g), ctypes.byref(p), None, 1 << 20, None, ctypes.byref(out)) == sx.EINVAL
+    assert b"NULL" in lib.sacx_last_error()
+    assert lib.sacx_create(ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(256 * 7 + 8), 1 << 20, None,
+                           ctypes.byref(out)) == sx.EINVAL
+    assert lib.sacx_create(ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(1 << 20), 1024, None,
+                           ctypes.byref(out)) == sx.ENOSPC
+    assert lib.sacx_destroy(None) == 0
+
+
+def test_product_path_does_not_reference_the_oracle():
+    """The HIP library and its binding share no code with the oracle."""
+    pkg = os.path.join(ROOT, "paper_1710_06423_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "sacx_oracle" not in text, fn
