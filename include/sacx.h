@@ -174,6 +174,15 @@ int sacx_halo_buffer_size(const sacx_ctx *ctx, int32_t side, size_t *bytes);
 int sacx_halo_pack(sacx_ctx *ctx, int32_t side, void *d_buf);
 int sacx_halo_unpack(sacx_ctx *ctx, int32_t side, const void *d_buf);
 
+/* Launch shape of the fused stage kernel: `threads` per block (64, 128 or
+ * 256; a block owns threads - 6 columns) and `rows` output rows per block
+ * strip (1..4096; each strip recomputes 6 rows of halo).  0 keeps the
+ * current value.  Results do not depend on the shape (bit-identical); only
+ * speed does.  Used by the tile autotuner.  Contexts with background_on
+ * accept threads = 64 only (EUNSUP otherwise). */
+int sacx_set_launch(sacx_ctx *ctx, int32_t threads, int32_t rows);
+int sacx_get_launch(const sacx_ctx *ctx, int32_t *threads, int32_t *rows);
+
 /* Per-phase timing on the context stream (HIP events around every launch
  * group), used to split a run into useful computation and halo exchange as in
  * the paper's cost model T = T_comp + T_comm + T_idle (section 6).

@@ -33,6 +33,10 @@ struct DevScalars {
     double dt;           // time step of the step in progress / last taken
     double cmax;         // c_max used by the step in progress
     double t_end;        // end time of the current advance call (<= 0: none)
+    // per-step constants derived from dt and c_max (computed once, read by
+    // every stage kernel as uniform values)
+    double hdt, dt6;     // dt/2, dt/6
+    double kx2[4], ky2[4];  // c2 * h_d * c_max per constant class
     unsigned long long cacc[2][2];  // [slot][x, y] wave-speed maxima
     double last_cx, last_cy, last_cmax;
     long long steps;     // steps since init
@@ -40,6 +44,15 @@ struct DevScalars {
     int active;          // 1 while the step in progress proceeds
     int nonphys;         // sticky: a non-physical state was reduced
     int pad;
+};
+
+// grid constants of the scheme, computed once on the host in FP64
+// (reciprocals of grid spacings, closure constants, compression-term scales)
+struct SchemeConsts {
+    double gamma, gm1, igm1;
+    double i12dx, i12dy, idx, idy, i2dx, i2dy;
+    double kxs[4], kys[4];   // cshk * h_d * h_d
+    double third;
 };
 
 template <typename real>
@@ -52,11 +65,9 @@ struct StageArgs {
     const real *BG[NBG];  // static background (optional)
     Layout L;
     int ty;               // output rows per block
-    double dx, dy;
-    double gamma;
-    double c2[4], cshk[4];
+    int nt;               // threads per block (one column each)
+    SchemeConsts k;
     int hd_cross_on;
-    int active_x, active_y;  // direction has more than one cell
     DevScalars *sc;
 };
 

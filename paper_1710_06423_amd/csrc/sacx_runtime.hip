@@ -80,8 +80,9 @@ struct sacx_ctx {
     void *U[NF], *B1[NF], *B2[NF], *A[NF], *BG[NBG];
     void *hx[2], *hy[2];
     bool initialized;
-    int ty;
+    int ty, nt;
     double dx, dy;
+    SchemeConsts kc;
     // profiling: event pairs recorded around launch groups, resolved at read
     bool prof_on;
     std::vector<hipEvent_t> *ev_pool;
@@ -148,11 +149,12 @@ Plan make_plan(const sacx_grid *g) {
     return P;
 }
 
-int default_ty(const Layout &L) {
-    // enough blocks to fill 256 CUs while keeping the 6-row warm-up small
-    const int64_t xt = (L.nx + 249) / 250;
-    int ty = 128;
-    while (ty > 8 && xt * ((L.ny + ty - 1) / ty) < 2048) ty /= 2;
+int default_ty(const Layout &L, int nt) {
+    // enough blocks to fill 256 CUs several times while keeping the 6-row
+    // warm-up of every strip small
+    const int64_t xt = (L.nx + nt - 2 * G - 1) / (nt - 2 * G);
+    int ty = 256;
+    while (ty > 8 && xt * ((L.ny + ty - 1) / ty) < 1024) ty /= 2;
     return ty;
 }
 
@@ -358,7 +360,15 @@ __global__ void k_reset_scalars(DevScalars *sc, double t0) {
 }
 
 // dt for the step about to start (CFL time step with the end-time clamp)
-__global__ void k_step_begin(DevScalars *sc, double t_end, double cfl, double dx, double dy, int ax, int ay) {
+struct StepConsts {
+    double cfl, dx, dy;
+    double c2[4];
+    int ax, ay;
+};
+
+__global__ void k_step_begin(DevScalars *sc, double t_end, StepConsts k) {
+    const double cfl = k.cfl, dx = k.dx, dy = k.dy;
+    const int ax = k.ax, ay = k.ay;
     sc->t_end = t_end;
     if (sc->nonphys) { sc->active = 0; return; }
     const double t = sc->t;
@@ -376,6 +386,12 @@ __global__ void k_step_begin(DevScalars *sc, double t_end, double cfl, double dx
     sc->last_cx = cx;
     sc->last_cy = cy;
     sc->last_cmax = sc->cmax;
+    sc->hdt = 0.5 * dt;
+    sc->dt6 = dt / 6.0;
+    for (int m = 0; m < 4; ++m) {
+        sc->kx2[m] = k.c2[m] * dx * sc->cmax;
+        sc->ky2[m] = k.c2[m] * dy * sc->cmax;
+    }
     sc->cacc[sc->cur ^ 1][0] = 0ull;
     sc->cacc[sc->cur ^ 1][1] = 0ull;
     sc->active = 1;
@@ -493,13 +509,9 @@ StageArgs<real> stage_args(sacx_ctx *c) {
     std::memset(&a, 0, sizeof(a));
     a.L = c->L;
     a.ty = c->ty;
-    a.dx = c->dx;
-    a.dy = c->dy;
-    a.gamma = c->params.gamma;
-    for (int k = 0; k < 4; ++k) { a.c2[k] = c->params.c2[k]; a.cshk[k] = c->params.cshk[k]; }
+    a.nt = c->nt;
+    a.k = c->kc;
     a.hd_cross_on = c->params.hd_cross_on;
-    a.active_x = c->grid.nx > 1;
-    a.active_y = c->grid.ny > 1;
     a.sc = c->sc;
     for (int k = 0; k < NBG; ++k) a.BG[k] = (const real *)(c->grid.background_on ? c->BG[k] : nullptr);
     return a;
@@ -631,9 +643,30 @@ int sacx_create(const sacx_grid *grid, const sacx_params *params, void *d_ws, si
     c->hx[1] = c->ws + P.off_hx + P.hx_bytes;
     c->hy[0] = c->ws + P.off_hy;
     c->hy[1] = c->ws + P.off_hy + P.hy_bytes;
-    c->ty = default_ty(c->L);
+    // measured on MI355X at OT 8000^2: FP64 is best with 2-wave blocks,
+    // FP32 with 4-wave blocks; strips of 256 rows keep the 6-row warm-up small
+    c->nt = grid->background_on ? 64 : (grid->precision == SACX_FP64 ? 128 : 256);
+    c->ty = default_ty(c->L, c->nt);
     c->dx = (grid->x1 - grid->x0) / grid->nx;
     c->dy = (grid->y1 - grid->y0) / grid->ny;
+    {
+        // grid constants in the same FP64 operations as the defining sequence
+        SchemeConsts &k = c->kc;
+        k.gamma = params->gamma;
+        k.gm1 = params->gamma - 1.0;
+        k.igm1 = 1.0 / k.gm1;
+        k.i12dx = 1.0 / (12.0 * c->dx);
+        k.i12dy = 1.0 / (12.0 * c->dy);
+        k.idx = 1.0 / c->dx;
+        k.idy = 1.0 / c->dy;
+        k.i2dx = 1.0 / (2.0 * c->dx);
+        k.i2dy = 1.0 / (2.0 * c->dy);
+        for (int m = 0; m < 4; ++m) {
+            k.kxs[m] = params->cshk[m] * c->dx * c->dx;
+            k.kys[m] = params->cshk[m] * c->dy * c->dy;
+        }
+        k.third = 1.0 / 3.0;
+    }
     c->initialized = false;
     c->prof_on = false;
     c->ev_pool = new (std::nothrow) std::vector<hipEvent_t>();
@@ -657,6 +690,29 @@ int sacx_destroy(sacx_ctx *ctx) {
     }
     delete ctx->ev_marks;
     delete ctx;
+    return SACX_OK;
+}
+
+int sacx_set_launch(sacx_ctx *ctx, int32_t threads, int32_t rows) {
+    if (!ctx) return fail(SACX_EINVAL, "ctx must not be NULL");
+    if (threads != 0 && threads != 64 && threads != 128 && threads != 256)
+        return fail(SACX_EINVAL, "threads must be 64, 128 or 256 (got %d)", threads);
+    if (rows < 0 || rows > 4096) return fail(SACX_EINVAL, "rows must be in 1..4096 (got %d)", rows);
+    // Background-on contexts keep single-wave blocks: their multi-wave
+    // builds with hyper-diffusion gave wrong values in the first rows of each
+    // strip of the stage-4 launch (cause not identified; the single-wave
+    // build is verified bit-exact), so they only accept 64 threads.
+    if (threads && threads != 64 && ctx->grid.background_on)
+        return fail(SACX_EUNSUP, "background-on contexts run 64-thread blocks only");
+    if (threads) ctx->nt = threads;
+    if (rows) ctx->ty = rows;
+    return SACX_OK;
+}
+
+int sacx_get_launch(const sacx_ctx *ctx, int32_t *threads, int32_t *rows) {
+    if (!ctx || !threads || !rows) return fail(SACX_EINVAL, "ctx/threads/rows must not be NULL");
+    *threads = ctx->nt;
+    *rows = ctx->ty;
     return SACX_OK;
 }
 
@@ -779,6 +835,13 @@ int sacx_advance(sacx_ctx *ctx, int32_t nsteps, double t_end, int32_t *steps_don
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }
     const int ax = ctx->grid.nx > 1, ay = ctx->grid.ny > 1;
+    StepConsts sk;
+    sk.cfl = ctx->params.cfl;
+    sk.dx = ctx->dx;
+    sk.dy = ctx->dy;
+    for (int m = 0; m < 4; ++m) sk.c2[m] = ctx->params.c2[m];
+    sk.ax = ax;
+    sk.ay = ay;
     // A synchronising call enqueues in chunks and stops early once the device
     // reports that stepping ended (end time reached or non-physical state).
     const int chunk = sync ? 128 : (nsteps > 0 ? nsteps : 1);
@@ -787,8 +850,7 @@ int sacx_advance(sacx_ctx *ctx, int32_t nsteps, double t_end, int32_t *steps_don
         for (int n = n0; n < n1; ++n) {
             {
                 ProfScope ps(ctx, 5);
-                hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, ctx->stream, ctx->sc, t_end, ctx->params.cfl,
-                                   ctx->dx, ctx->dy, ax, ay);
+                hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, ctx->stream, ctx->sc, t_end, sk);
             }
             int rc;
             if ((rc = stage(ctx, 1, ctx->U, nullptr, nullptr, ctx->B1, nullptr))) return rc;

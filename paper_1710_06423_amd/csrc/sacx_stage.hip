@@ -7,55 +7,51 @@
 // for the next CFL time step.
 //
 // Work decomposition (MI355X: wave64, 160 KB LDS per CU, HBM-bound stencil):
-//  * a block of NT = 256 threads owns TX = 250 output columns; thread t holds
-//    column c = x0 - 3 + t, so the 3-cell apron on each side is computed by
-//    the 6 edge threads (2.4 % redundant work in x);
+//  * a block of NT threads (one wave for NT = 64) owns TX = NT - 6 output
+//    columns; thread t holds column c = x0 - 3 + t, so the 3-cell apron on
+//    each side is computed by the 6 edge threads;
 //  * the block marches up a strip of `ty` output rows, loading each state row
-//    once (coalesced 2 KB row segments); quantities that only couple cells of
-//    one column (y differences, y-face hyper-diffusion windows) live in
-//    per-thread register windows, so the 3-cell y apron costs 6 warm-up rows
-//    per strip instead of an LDS tile halo;
+//    once (coalesced row segments, the next row prefetched while the current
+//    one is computed); quantities that only couple cells of one column (y
+//    differences, y-face hyper-diffusion windows) live in per-thread register
+//    windows, so the 3-cell y apron costs 6 warm-up rows per strip instead of
+//    an LDS tile halo;
 //  * cross-column coupling (x differences, x-face windows, the four-face
-//    averages of the cross terms) goes through small LDS row buffers, four
-//    barriers per row;
+//    averages of the cross terms) goes through small LDS row buffers;
 //  * the stage combine, and in stage 4 the wave-speed reduction, are fused in
 //    the epilogue: each evolved field is read once as a stencil input and
 //    once pointwise, then written once, so the whole RK4 step moves 12 field
-//    values per cell (the 12-access form described in sacx_runtime.hip).
+//    values per cell (the arrangement described in sacx_runtime.hip).
 //
 // Pipeline of iteration r (row r is the newest row loaded):
-//   A  : load S(r); primitives, ideal fluxes; publish x-neighbour data
-//   A' : D_x F_x(r); x-face ratio R and first difference at row r; x-face
-//        means; compression s at row r-1 (needs v_y of rows r-2 and r)
-//   C  : x-face G = nu d1 / h at row r-1; y-face G at face (r-3)+1/2
+//   A  : primitives and ideal fluxes of row r; publish the row to LDS;
+//        D_y F_y of row r-2 from the flux window
+//   A' : D_x F_x of row r; ideal L of row r-2; compression s of row r-1
+//   C  : x-face G = nu d1 / h of row r-1 (from the previous row buffer);
+//        y-face G of face (r-3)+1/2
 //   D  : face fluxes H_x at (c+1/2, r-3) and H_y at (c, (r-3)+1/2)
-//   E  : L(S) at row j = r-3 and the stage combine
+//   E  : L(S) of row j = r-3 and the stage combine
 //
-// Arithmetic: every operation is the same IEEE double (or float) operation,
-// in the same order, as in the scheme's defining sequence (the test oracle):
-// divisions by grid constants are multiplications by reciprocals computed in
-// FP64, no multiply-add is fused (the library is built with
-// -ffp-contract=off), and the stage combine is the storage-saving RK4
-// arrangement.  The hyper-diffusion coefficient, a ratio of maxima of
-// differences, amplifies any rounding difference by many orders of magnitude
-// over a run, so FP64 results are reproduced bit for bit instead.
+// Arithmetic: every operation is the same IEEE operation, in the same order,
+// as in the scheme's defining sequence (the test oracle): divisions by grid
+// constants are multiplications by reciprocals computed once in FP64, no
+// multiply-add is fused (the library is built with -ffp-contract=off), and
+// the stage combine is the storage-saving RK4 arrangement.  Maxima of
+// non-negative values use the hardware max (equal values).  The
+// hyper-diffusion coefficient, a ratio of maxima of differences, amplifies
+// any rounding difference by many orders of magnitude over a run, so the
+// FP64 results are reproduced bit for bit instead of to a tolerance.
 #include "sacx_internal.h"
 
 namespace sacx {
 
-constexpr int NT = 256;
-constexpr int TX = NT - 2 * G;
-
-// slots of the hyper-diffusion quantity sets: x faces {rho~, eps~, v_x, v_y, B~_y},
-// y faces {rho~, eps~, v_x, v_y, B~_x}
-enum { QR = 0, QE = 1, QVX = 2, QVY = 3, QB = 4 };
+// slots of the row buffers: the x-face quantity set {rho~, eps~, v_x, v_y,
+// B~_y} (the y-face set has B~_x in slot QB) and the totals rho, B_y
+enum { QR = 0, QE = 1, QVX = 2, QVY = 3, QB = 4, QRHO = 5, QBYT = 6, NQ = 7 };
 // flux component slots: x {rho, m_x, m_y, e, B_y}, y {rho, m_x, m_y, e, B_x}
 enum { CR = 0, CMX = 1, CMY = 2, CE = 3, CB = 4 };
 // constant class of each quantity slot: density, thermal energy, velocity, field
-__device__ __forceinline__ int qclass(int k) { return k == QR ? 0 : (k == QE ? 1 : (k == QB ? 3 : 2)); }
-
-template <typename real>
-__device__ __forceinline__ real rmax(real a, real b) { return a > b ? a : b; }
+__device__ __forceinline__ constexpr int qclass(int k) { return k == QR ? 0 : (k == QE ? 1 : (k == QB ? 3 : 2)); }
 
 // Hyper-diffusion coefficient ratio at the face between q2 and q3, from the
 // six values q[i-2..i+3]: max |third difference| over the 3 faces around the
@@ -64,30 +60,34 @@ __device__ __forceinline__ real rmax(real a, real b) { return a > b ? a : b; }
 template <typename real>
 __device__ __forceinline__ real hd_ratio(real q0, real q1, real q2, real q3, real q4, real q5) {
     const real three = (real)3;
-    real d3a = (q3 - q0) - three * (q2 - q1);
-    real d3b = (q4 - q1) - three * (q3 - q2);
-    real d3c = (q5 - q2) - three * (q4 - q3);
-    real n = 0;
-    n = rmax(n, fabs(d3a));
-    n = rmax(n, fabs(d3b));
-    n = rmax(n, fabs(d3c));
-    real m = 0;
-    m = rmax(m, fabs(q1 - q0));
-    m = rmax(m, fabs(q2 - q1));
-    m = rmax(m, fabs(q3 - q2));
-    m = rmax(m, fabs(q4 - q3));
-    m = rmax(m, fabs(q5 - q4));
+    const real d3a = (q3 - q0) - three * (q2 - q1);
+    const real d3b = (q4 - q1) - three * (q3 - q2);
+    const real d3c = (q5 - q2) - three * (q4 - q3);
+    const real n = fmax(fmax(fabs(d3a), fabs(d3b)), fabs(d3c));
+    const real m = fmax(fmax(fmax(fabs(q1 - q0), fabs(q2 - q1)), fmax(fabs(q3 - q2), fabs(q4 - q3))), fabs(q5 - q4));
     return m > (real)0 ? n / m : (real)0;
 }
 
-template <typename real, int STAGE, bool HD, bool BG>
+template <typename real>
+struct Row6 {
+    real v[NF];
+};
+
+template <typename real, int NT, int STAGE, bool HD, bool BG>
 __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
-    DevScalars *sc = a.sc;
+    constexpr int TX = NT - 2 * G;
+    const DevScalars *sc = a.sc;
     if (!sc->active) return;
-    const double dtd = sc->dt;
-    const real cmax = (real)sc->cmax;
-    const real dt = (real)dtd, hdt = (real)(0.5 * dtd), dt6 = (real)(dtd / 6.0);
-    const real third = (real)(1.0 / 3.0);
+    const real dt = (real)sc->dt, hdt = (real)sc->hdt, dt6 = (real)sc->dt6;
+    real kx2[4], ky2[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) { kx2[k] = (real)sc->kx2[k]; ky2[k] = (real)sc->ky2[k]; }
+
+    const SchemeConsts &kc = a.k;
+    const real gamma = (real)kc.gamma, gm1 = (real)kc.gm1, igm1 = (real)kc.igm1;
+    const real i12dx = (real)kc.i12dx, i12dy = (real)kc.i12dy, idx = (real)kc.idx, idy = (real)kc.idy;
+    const real i2dx = (real)kc.i2dx, i2dy = (real)kc.i2dy, third = (real)kc.third;
+    const real half = (real)0.5, two = (real)2, eight = (real)8, zero = (real)0;
 
     const Layout L = a.L;
     const int tid = threadIdx.x;
@@ -97,23 +97,6 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
     const int y0 = blockIdx.y * a.ty;
     const int y1 = min(y0 + a.ty, L.ny);
     const bool outcol = tid >= G && tid < NT - G && c < L.nx;
-
-    const real gamma = (real)a.gamma;
-    const real gm1 = (real)(a.gamma - 1.0);
-    const real igm1 = (real)(1.0 / (a.gamma - 1.0));
-    const real half = (real)0.5, two = (real)2, eight = (real)8;
-    const real i12dx = (real)(1.0 / (12.0 * a.dx)), i12dy = (real)(1.0 / (12.0 * a.dy));
-    const real idx = (real)(1.0 / a.dx), idy = (real)(1.0 / a.dy);
-    const real i2dx = (real)(1.0 / (2.0 * a.dx)), i2dy = (real)(1.0 / (2.0 * a.dy));
-    real kx2[4], kxs[4], ky2[4], kys[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        kx2[k] = (real)(a.c2[k] * a.dx * (double)sc->cmax);
-        ky2[k] = (real)(a.c2[k] * a.dy * (double)sc->cmax);
-        kxs[k] = (real)(a.cshk[k] * a.dx * a.dx);
-        kys[k] = (real)(a.cshk[k] * a.dy * a.dy);
-    }
-    (void)cmax;
     const bool cross = a.hd_cross_on != 0;
 
     // clamped LDS neighbour indices (edge threads compute unused values)
@@ -123,62 +106,87 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
     const int tp2 = tid + 2 < NT ? tid + 2 : NT - 1;
     const int tp3 = tid + 3 < NT ? tid + 3 : NT - 1;
 
-    __shared__ real sh_fx[5][NT];   // x fluxes of the newest row
-    __shared__ real sh_qx[5][NT];   // x-face quantity set of the newest row
-    __shared__ real sh_rho[NT];     // total density, newest row
-    __shared__ real sh_byT[NT];     // total B_y, newest row
-    __shared__ real sh_s[NT];       // compression s, row r-1
-    __shared__ real sh_gx[2][3][NT];  // x-face G(v_y), G(B~_y), ring over rows (mod 3)
-    __shared__ real sh_gy[2][2][NT];  // y-face G(v_x), G(B~_x), ring over faces (mod 2)
-    __shared__ real sh_hx[5][NT];     // x-face fluxes H_x at row r-3
+    __shared__ real sh_fx[5][NT];        // x fluxes of row r
+    __shared__ real sh_q[2][NQ][NT];     // row buffers of rows r (slot r&1) and r-1
+    __shared__ real sh_s[NT];            // compression s of row r-1
+    __shared__ real sh_gx[2][3][NT];     // x-face G(v_y), G(B~_y), ring over rows (mod 3)
+    __shared__ real sh_gy[2][2][NT];     // y-face G(v_x), G(B~_x), ring over faces (mod 2)
+    __shared__ real sh_hx[5][NT];        // x-face fluxes H_x of row r-3
 
     const int64_t colofs = (int64_t)L.xoff + (colv ? c : L.nx + G - 1);
+    const int rbeg = y0 - G, rend = y1 - 1 + G;
 
     // ---------------- per-thread windows (column-local data) ----------------
-    real qw[5][6];      // y-face set, rows r-5..r
-    real rhow[4], bxTw[4];  // totals rows r-3..r (background on)
-    real fyw[5][5];     // y fluxes rows r-4..r
-    real dyd[5];        // D_y F_y of row r-3
-    real dxd[3][5];     // D_x F_x of rows r-3..r-1
-    real bgv[4][4];     // D_x v_x, D_x v_y of rows r-3..r-1 (background on): [row][0..1]
-    real rxd[5], d1xd[5];   // x-face R and d1 of row r-1
-    real fmx[3][4];     // x-face means (rho, v_x, v_y, B_y) of rows r-3..r-1
-    real dvxp;          // d_x v_x of row r-1
-    real sw[2];         // s of rows r-3, r-2
-    real gxw[2][5];     // own x-face G of rows r-3, r-2
-    real gyp[2];        // own y-face G(v_x), G(B~_x) at face (r-4)+1/2
-    real hyp[5];        // own y-face H at face (r-4)+1/2
+    real qw[5][6];       // y-face set {rho~, eps~, v_x, v_y, B~_x}, rows r-5..r
+    real rbq[4], bxq[4];   // background rho_b, B_bx of rows r-3..r (background on)
+    real fyw[5][4];      // y fluxes of rows r-4..r-1
+    real dxd[2][5];      // D_x F_x of rows r-2, r-1
+    real bgx[2][2];      // D_x v_x, D_x v_y of rows r-2, r-1 (background on)
+    real kip[6];         // ideal L (+ background terms) of row r-3
+    real fmx[2][4];      // x-face means (rho, v_x, v_y, B_y) of rows r-3, r-2
+    real sw[2];          // s of rows r-3, r-2
+    real gxw[2][5];      // own x-face G of rows r-3, r-2
+    real gyp[2];         // own y-face G(v_x), G(B~_x) at face (r-4)+1/2
+    real hyp[5];         // own y-face H at face (r-4)+1/2
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
 #pragma unroll
         for (int m = 0; m < 6; ++m) qw[k][m] = 0;
 #pragma unroll
-        for (int m = 0; m < 5; ++m) fyw[k][m] = 0;
-        dyd[k] = 0; rxd[k] = 0; d1xd[k] = 0; hyp[k] = 0;
-        gxw[0][k] = 0; gxw[1][k] = 0;
-#pragma unroll
-        for (int m = 0; m < 3; ++m) dxd[m][k] = 0;
+        for (int m = 0; m < 4; ++m) fyw[k][m] = 0;
+        dxd[0][k] = dxd[1][k] = 0;
+        gxw[0][k] = gxw[1][k] = 0;
+        hyp[k] = 0;
     }
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        rhow[m] = 0; bxTw[m] = 0;
+    for (int k = 0; k < 6; ++k) kip[k] = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) bgv[m][k] = 0;
-    }
+    for (int m = 0; m < 4; ++m) rbq[m] = bxq[m] = 0;
 #pragma unroll
-    for (int m = 0; m < 3; ++m)
+    for (int m = 0; m < 2; ++m) {
+        bgx[m][0] = bgx[m][1] = 0;
+        sw[m] = 0;
+        gyp[m] = 0;
 #pragma unroll
         for (int k = 0; k < 4; ++k) fmx[m][k] = 0;
-    dvxp = 0; sw[0] = sw[1] = 0; gyp[0] = gyp[1] = 0;
+    }
 
     double cx_t = 0.0, cy_t = 0.0;
     int bad_t = 0;
 
-    for (int r = y0 - G; r <= y1 - 1 + G; ++r) {
+    // prefetch of the next state row
+    Row6<real> nxt;
+    {
+        const int64_t ro = colofs + (int64_t)(rbeg + G) * L.pitch;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) nxt.v[f] = a.S[f][ro];
+    }
+
+    for (int r = rbeg; r <= rend; ++r) {
         const int64_t ro = colofs + (int64_t)(r + G) * L.pitch;
-        // ================= A: load row r, primitives, fluxes =================
-        const real rt = a.S[0][ro], mx = a.S[1][ro], my = a.S[2][ro];
-        const real et = a.S[3][ro], bxt = a.S[4][ro], byt = a.S[5][ro];
+        const Row6<real> cur = nxt;
+        if (r < rend) {
+            const int64_t rn = ro + L.pitch;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) nxt.v[f] = a.S[f][rn];
+        }
+        // pointwise operands of this iteration's output row j = r-3, issued
+        // now so that their latency overlaps the row's arithmetic
+        const int j = r - G;
+        const bool outrow = j >= y0 && outcol;
+        const int64_t oo = (int64_t)L.xoff + c + (int64_t)(j + G) * L.pitch;
+        Row6<real> pS, pU;
+        if (outrow) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                if (STAGE != 3) pS.v[f] = a.S[f][oo];
+                if (STAGE == 2 || STAGE == 3) pU.v[f] = a.U[f][oo];
+                if (STAGE == 4) pU.v[f] = a.A[f][oo];
+            }
+        }
+        const int slot = r & 1, pslot = slot ^ 1;
+        // ================= A: row r =================
+        const real rt = cur.v[0], mx = cur.v[1], my = cur.v[2], et = cur.v[3], bxt = cur.v[4], byt = cur.v[5];
         real rb = 0, eb = 0, bxb = 0, byb = 0;
         if (BG) { rb = a.BG[0][ro]; eb = a.BG[1][ro]; bxb = a.BG[2][ro]; byb = a.BG[3][ro]; }
         const real rho = rb + rt;
@@ -194,89 +202,105 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
         const real bvt = bxt * vx + byt * vy;
         const real bvb = bxb * vx + byb * vy;
         const real ef = et + eb + pt;
-        real fx[5], fy[5];
-        fx[CR] = mx;
-        fx[CMX] = (vx * mx - (bxt * bxt + two * bxt * bxb)) + pt;
-        fx[CMY] = vx * my - (bxt * byt + bxt * byb + bxb * byt);
-        fx[CE] = ((vx * ef - bxt * bvt) - bxt * bvb) - bxb * bvt;
-        fx[CB] = vx * byT - bxT * vy;
+        real fy[5];
+        sh_fx[CR][tid] = mx;
+        sh_fx[CMX][tid] = (vx * mx - (bxt * bxt + two * bxt * bxb)) + pt;
+        sh_fx[CMY][tid] = vx * my - (bxt * byt + bxt * byb + bxb * byt);
+        sh_fx[CE][tid] = ((vx * ef - bxt * bvt) - bxt * bvb) - bxb * bvt;
+        sh_fx[CB][tid] = vx * byT - bxT * vy;
         fy[CR] = my;
         fy[CMX] = vy * mx - (byt * bxt + byt * bxb + byb * bxt);
         fy[CMY] = (vy * my - (byt * byt + two * byt * byb)) + pt;
         fy[CE] = ((vy * ef - byt * bvt) - byt * bvb) - byb * bvt;
         fy[CB] = vy * bxT - byT * vx;
-
-#pragma unroll
-        for (int k = 0; k < 5; ++k) sh_fx[k][tid] = fx[k];
         if (HD || BG) {
-            sh_qx[QR][tid] = rt;
-            sh_qx[QE][tid] = eps;
-            sh_qx[QVX][tid] = vx;
-            sh_qx[QVY][tid] = vy;
-            sh_qx[QB][tid] = byt;
-            sh_rho[tid] = rho;
-            sh_byT[tid] = byT;
+            sh_q[slot][QR][tid] = rt;
+            sh_q[slot][QE][tid] = eps;
+            sh_q[slot][QVX][tid] = vx;
+            sh_q[slot][QVY][tid] = vy;
+            sh_q[slot][QB][tid] = byt;
+            sh_q[slot][QRHO][tid] = rho;
+            sh_q[slot][QBYT][tid] = byT;
         }
-        // shift column windows and insert row r
+        // D_y F_y of row r-2 (rows r-4..r)
+        real dyn[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k) {
+            dyn[k] = (eight * (fyw[k][3] - fyw[k][1]) - (fy[k] - fyw[k][0])) * i12dy;
+            fyw[k][0] = fyw[k][1]; fyw[k][1] = fyw[k][2]; fyw[k][2] = fyw[k][3]; fyw[k][3] = fy[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
 #pragma unroll
             for (int m = 0; m < 5; ++m) qw[k][m] = qw[k][m + 1];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) fyw[k][m] = fyw[k][m + 1];
-            fyw[k][4] = fy[k];
-        }
         qw[QR][5] = rt; qw[QE][5] = eps; qw[QVX][5] = vx; qw[QVY][5] = vy; qw[QB][5] = bxt;
+        if (BG) {
 #pragma unroll
-        for (int m = 0; m < 3; ++m) { rhow[m] = rhow[m + 1]; bxTw[m] = bxTw[m + 1]; }
-        rhow[3] = rho; bxTw[3] = bxT;
+            for (int m = 0; m < 3; ++m) { rbq[m] = rbq[m + 1]; bxq[m] = bxq[m + 1]; }
+            rbq[3] = rb; bxq[3] = bxb;
+        }
         __syncthreads();  // B1
 
-        // ================= A': x work on row r =================
+        // ================= A': x work on row r, ideal L of row r-2 =================
         real dxn[5];
 #pragma unroll
         for (int k = 0; k < 5; ++k)
             dxn[k] = (eight * (sh_fx[k][tp1] - sh_fx[k][tm1]) - (sh_fx[k][tp2] - sh_fx[k][tm2])) * i12dx;
+        real kin6[6];
+        kin6[0] = -(dxd[0][CR] + dyn[CR]);
+        kin6[1] = -(dxd[0][CMX] + dyn[CMX]);
+        kin6[2] = -(dxd[0][CMY] + dyn[CMY]);
+        kin6[3] = -(dxd[0][CE] + dyn[CE]);
+        kin6[4] = -(zero + dyn[CB]);   // B~_x has no x flux
+        kin6[5] = -(dxd[0][CB] + zero);  // B~_y has no y flux
         real bgn0 = 0, bgn1 = 0;
         if (BG) {
-            bgn0 = (eight * (sh_qx[QVX][tp1] - sh_qx[QVX][tm1]) - (sh_qx[QVX][tp2] - sh_qx[QVX][tm2])) * i12dx;
-            bgn1 = (eight * (sh_qx[QVY][tp1] - sh_qx[QVY][tm1]) - (sh_qx[QVY][tp2] - sh_qx[QVY][tm2])) * i12dx;
+            bgn0 = (eight * (sh_q[slot][QVX][tp1] - sh_q[slot][QVX][tm1]) - (sh_q[slot][QVX][tp2] - sh_q[slot][QVX][tm2])) * i12dx;
+            bgn1 = (eight * (sh_q[slot][QVY][tp1] - sh_q[slot][QVY][tm1]) - (sh_q[slot][QVY][tp2] - sh_q[slot][QVY][tm2])) * i12dx;
+            // e~ of row r-2 gets -p_tb div v + sum_kl B_bk B_bl d_k v_l
+            const int64_t r2 = colofs + (int64_t)((r - 2 < -G ? -G : r - 2) + G) * L.pitch;
+            const real eb2 = a.BG[1][r2], bxb2 = a.BG[2][r2], byb2 = a.BG[3][r2];
+            const real dxvx = bgx[0][0], dxvy = bgx[0][1];
+            const real dyvx = (eight * (qw[QVX][4] - qw[QVX][2]) - (qw[QVX][5] - qw[QVX][1])) * i12dy;
+            const real dyvy = (eight * (qw[QVY][4] - qw[QVY][2]) - (qw[QVY][5] - qw[QVY][1])) * i12dy;
+            const real b2b = bxb2 * bxb2 + byb2 * byb2;
+            const real pkb = gm1 * (eb2 - half * b2b);
+            const real ptb = pkb + half * b2b;
+            const real bb = (bxb2 * bxb2 * dxvx + byb2 * byb2 * dyvy) + (bxb2 * byb2 * dxvy + byb2 * bxb2 * dyvx);
+            kin6[3] = kin6[3] + (bb - ptb * (dxvx + dyvy));
         }
-        real rxn[5], d1xn[5], fmn[4], gxn[5], gyn[5], hyn[5];
-        real s_new = 0, dvxn = 0;
+
+        real gyn[5], hyn[5], gxn[5], fmn[4];
+        real s_new = 0;
         if (HD) {
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                const real q0 = sh_qx[k][tm2], q1 = sh_qx[k][tm1], q2 = sh_qx[k][tid];
-                const real q3 = sh_qx[k][tp1], q4 = sh_qx[k][tp2], q5 = sh_qx[k][tp3];
-                rxn[k] = hd_ratio(q0, q1, q2, q3, q4, q5);
-                d1xn[k] = q3 - q2;
-            }
-            fmn[0] = half * (rho + sh_rho[tp1]);
-            fmn[1] = half * (vx + sh_qx[QVX][tp1]);
-            fmn[2] = half * (vy + sh_qx[QVY][tp1]);
-            fmn[3] = half * (byT + sh_byT[tp1]);
-            dvxn = (sh_qx[QVX][tp1] - sh_qx[QVX][tm1]) * i2dx;
-            // s at row r-1: v_y of rows r (qw idx 5) and r-2 (idx 3)
-            const real dv = dvxp + (qw[QVY][5] - qw[QVY][3]) * i2dy;
-            s_new = rmax((real)0, -dv);
+            // compression s of row r-1: d_x v_x from the previous row buffer,
+            // d_y v_y from v_y of rows r and r-2
+            const real dv = (sh_q[pslot][QVX][tp1] - sh_q[pslot][QVX][tm1]) * i2dx + (qw[QVY][5] - qw[QVY][3]) * i2dy;
+            s_new = fmax(zero, -dv);
             sh_s[tid] = s_new;
             __syncthreads();  // B2
 
-            // ================= C: x-face G at row r-1, y-face G at face (r-3)+1/2 ===
-            const real sfx = rmax(s_new, sh_s[tp1]);
+            // ================= C: x-face G of row r-1, y-face G of face (r-3)+1/2 =================
+            const real sfx = fmax(s_new, sh_s[tp1]);
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
                 const int cl = qclass(k);
-                const real nu = kx2[cl] * rxd[k] + kxs[cl] * sfx;
-                gxn[k] = nu * d1xd[k] * idx;
+                const real q0 = sh_q[pslot][k][tm2], q1 = sh_q[pslot][k][tm1], q2 = sh_q[pslot][k][tid];
+                const real q3 = sh_q[pslot][k][tp1], q4 = sh_q[pslot][k][tp2], q5 = sh_q[pslot][k][tp3];
+                const real R = hd_ratio(q0, q1, q2, q3, q4, q5);
+                const real nu = kx2[cl] * R + (real)kc.kxs[cl] * sfx;
+                gxn[k] = nu * (q3 - q2) * idx;
             }
-            const real sfy = rmax(sw[0], sw[1]);
+            fmn[0] = half * (sh_q[pslot][QRHO][tid] + sh_q[pslot][QRHO][tp1]);
+            fmn[1] = half * (sh_q[pslot][QVX][tid] + sh_q[pslot][QVX][tp1]);
+            fmn[2] = half * (sh_q[pslot][QVY][tid] + sh_q[pslot][QVY][tp1]);
+            fmn[3] = half * (sh_q[pslot][QBYT][tid] + sh_q[pslot][QBYT][tp1]);
+            const real sfy = fmax(sw[0], sw[1]);
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
                 const int cl = qclass(k);
                 const real R = hd_ratio(qw[k][0], qw[k][1], qw[k][2], qw[k][3], qw[k][4], qw[k][5]);
-                const real nu = ky2[cl] * R + kys[cl] * sfy;
+                const real nu = ky2[cl] * R + (real)kc.kys[cl] * sfy;
                 gyn[k] = nu * (qw[k][3] - qw[k][2]) * idy;
             }
             const int sx = (r - 1 + 3 * 4096) % 3;   // ring slot of row r-1 (rows >= -3)
@@ -290,15 +314,16 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
             // ================= D: face fluxes of row j = r-3 =================
             const int sxj = (r - 3 + 3 * 4096) % 3, sxj1 = (r - 2 + 3 * 4096) % 3;
             const int syp = sy ^ 1;
-            // H_x at (c+1/2, j)
             real a4vx = 0, a4bx = 0, a4vy = 0, a4by = 0;
             if (cross) {
-                a4vx = ((gyp[0] + gyn[QVX]) + (sh_gy[0][syp][tp1] + sh_gy[0][sy][tp1])) * (real)0.25;
-                a4bx = ((gyp[1] + gyn[QB]) + (sh_gy[1][syp][tp1] + sh_gy[1][sy][tp1])) * (real)0.25;
-                a4vy = ((sh_gx[0][sxj][tm1] + gxw[0][QVY]) + (sh_gx[0][sxj1][tm1] + gxw[1][QVY])) * (real)0.25;
-                a4by = ((sh_gx[1][sxj][tm1] + gxw[0][QB]) + (sh_gx[1][sxj1][tm1] + gxw[1][QB])) * (real)0.25;
+                const real q = (real)0.25;
+                a4vx = ((gyp[0] + gyn[QVX]) + (sh_gy[0][syp][tp1] + sh_gy[0][sy][tp1])) * q;
+                a4bx = ((gyp[1] + gyn[QB]) + (sh_gy[1][syp][tp1] + sh_gy[1][sy][tp1])) * q;
+                a4vy = ((sh_gx[0][sxj][tm1] + gxw[0][QVY]) + (sh_gx[0][sxj1][tm1] + gxw[1][QVY])) * q;
+                a4by = ((sh_gx[1][sxj][tm1] + gxw[0][QB]) + (sh_gx[1][sxj1][tm1] + gxw[1][QB])) * q;
             }
             {
+                // H_x at (c+1/2, j)
                 const real rf = fmx[0][0], vxf = fmx[0][1], vyf = fmx[0][2], byf = fmx[0][3];
                 const real txx = rf * gxw[0][QVX];
                 const real txy = half * rf * (gxw[0][QVY] + a4vx);
@@ -310,11 +335,15 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
                 sh_hx[CB][tid] = ez;
             }
             {
-                // H_y at (c, j+1/2): rows j (idx 2 of qw / 0 of rhow) and j+1
-                const real rf = half * (rhow[0] + rhow[1]);
+                // H_y at (c, j+1/2): rows j (qw idx 2) and j+1 (idx 3)
+                const real rj = BG ? rbq[0] + qw[QR][2] : qw[QR][2];
+                const real rj1 = BG ? rbq[1] + qw[QR][3] : qw[QR][3];
+                const real bj = BG ? bxq[0] + qw[QB][2] : qw[QB][2];
+                const real bj1 = BG ? bxq[1] + qw[QB][3] : qw[QB][3];
+                const real rf = half * (rj + rj1);
                 const real vxf = half * (qw[QVX][2] + qw[QVX][3]);
                 const real vyf = half * (qw[QVY][2] + qw[QVY][3]);
-                const real bxf = half * (bxTw[0] + bxTw[1]);
+                const real bxf = half * (bj + bj1);
                 const real tyy = rf * gyn[QVY];
                 const real tyx = half * rf * (gyn[QVX] + a4vy);
                 const real ez = a4by - gyn[QB];
@@ -328,61 +357,40 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
         __syncthreads();  // B4 (also orders the next row's LDS writes after all reads)
 
         // ================= E: output row j = r-3 =================
-        const int j = r - G;
-        if (j >= y0 && outcol) {
-            const int64_t oo = (int64_t)L.xoff + c + (int64_t)(j + G) * L.pitch;
-            // ideal part: -(D_x F_x + D_y F_y) per evolved field
+        if (outrow) {
             real K[6];
-            K[0] = -(dxd[0][CR] + dyd[CR]);
-            K[1] = -(dxd[0][CMX] + dyd[CMX]);
-            K[2] = -(dxd[0][CMY] + dyd[CMY]);
-            K[3] = -(dxd[0][CE] + dyd[CE]);
-            // B~_x has no x flux and B~_y no y flux: their (zero) differences
-            // still enter the sums, as in the defining sequence
-            K[4] = -((real)0 + dyd[CB]);
-            K[5] = -(dxd[0][CB] + (real)0);
-            if (BG) {
-                // e~ gets -p_tb div v + sum_kl B_bk B_bl d_k v_l
-                const real bxb0 = a.BG[2][oo], byb0 = a.BG[3][oo], eb0 = a.BG[1][oo];
-                const real dxvx = bgv[0][0], dxvy = bgv[0][1];
-                const real dyvx = (eight * (qw[QVX][3] - qw[QVX][1]) - (qw[QVX][4] - qw[QVX][0])) * i12dy;
-                const real dyvy = (eight * (qw[QVY][3] - qw[QVY][1]) - (qw[QVY][4] - qw[QVY][0])) * i12dy;
-                const real b2b = bxb0 * bxb0 + byb0 * byb0;
-                const real pkb = gm1 * (eb0 - half * b2b);
-                const real ptb = pkb + half * b2b;
-                const real bb = (bxb0 * bxb0 * dxvx + byb0 * byb0 * dyvy) + (bxb0 * byb0 * dxvy + byb0 * bxb0 * dyvx);
-                K[3] = K[3] + (bb - ptb * (dxvx + dyvy));
-            }
+#pragma unroll
+            for (int f = 0; f < 6; ++f) K[f] = kip[f];
             if (HD) {
                 K[0] = K[0] + ((sh_hx[CR][tid] - sh_hx[CR][tm1]) * idx + (hyn[CR] - hyp[CR]) * idy);
                 K[1] = K[1] + ((sh_hx[CMX][tid] - sh_hx[CMX][tm1]) * idx + (hyn[CMX] - hyp[CMX]) * idy);
                 K[2] = K[2] + ((sh_hx[CMY][tid] - sh_hx[CMY][tm1]) * idx + (hyn[CMY] - hyp[CMY]) * idy);
                 K[3] = K[3] + ((sh_hx[CE][tid] - sh_hx[CE][tm1]) * idx + (hyn[CE] - hyp[CE]) * idy);
-                K[4] = K[4] + ((real)0 + (hyn[CB] - hyp[CB]) * idy);
-                K[5] = K[5] + ((sh_hx[CB][tid] - sh_hx[CB][tm1]) * idx + (real)0);
+                K[4] = K[4] + (zero + (hyn[CB] - hyp[CB]) * idy);
+                K[5] = K[5] + ((sh_hx[CB][tid] - sh_hx[CB][tm1]) * idx + zero);
             }
             if (STAGE == 1) {
 #pragma unroll
-                for (int f = 0; f < NF; ++f) a.out1[f][oo] = a.S[f][oo] + hdt * K[f];
+                for (int f = 0; f < NF; ++f) a.out1[f][oo] = pS.v[f] + hdt * K[f];
             } else if (STAGE == 2) {
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
-                    const real u = a.U[f][oo], s = a.S[f][oo];
+                    const real u = pU.v[f], s = pS.v[f];
                     a.out1[f][oo] = u + hdt * K[f];
                     a.out2[f][oo] = (u + u) + ((s - u) + dt * K[f]);
                 }
             } else if (STAGE == 3) {
 #pragma unroll
-                for (int f = 0; f < NF; ++f) a.out1[f][oo] = a.U[f][oo] + dt * K[f];
+                for (int f = 0; f < NF; ++f) a.out1[f][oo] = pU.v[f] + dt * K[f];
             } else {
                 real un[6];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
-                    const real av = a.A[f][oo], s = a.S[f][oo];
+                    const real av = pU.v[f], s = pS.v[f];
                     un[f] = (s + (av - (s + s)) * third) + dt6 * K[f];
                     a.out1[f][oo] = un[f];
                 }
-                // wave speeds of the new state (for the next step's dt and c_max)
+                // wave speeds of the new state (next step's dt and c_max)
                 real rb0 = 0, eb0 = 0, bxb0 = 0, byb0 = 0;
                 if (BG) { rb0 = a.BG[0][oo]; eb0 = a.BG[1][oo]; bxb0 = a.BG[2][oo]; byb0 = a.BG[3][oo]; }
                 const real r0 = rb0 + un[0];
@@ -410,24 +418,21 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
 
         // ================= end of row: advance the windows =================
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            dxd[0][k] = dxd[1][k]; dxd[1][k] = dxd[2][k]; dxd[2][k] = dxn[k];
-            dyd[k] = (eight * (fyw[k][3] - fyw[k][1]) - (fyw[k][4] - fyw[k][0])) * i12dy;
-        }
+        for (int k = 0; k < 5; ++k) { dxd[0][k] = dxd[1][k]; dxd[1][k] = dxn[k]; }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) kip[k] = kin6[k];
         if (BG) {
-            bgv[0][0] = bgv[1][0]; bgv[1][0] = bgv[2][0]; bgv[2][0] = bgn0;
-            bgv[0][1] = bgv[1][1]; bgv[1][1] = bgv[2][1]; bgv[2][1] = bgn1;
+            bgx[0][0] = bgx[1][0]; bgx[1][0] = bgn0;
+            bgx[0][1] = bgx[1][1]; bgx[1][1] = bgn1;
         }
         if (HD) {
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
-                rxd[k] = rxn[k]; d1xd[k] = d1xn[k];
                 gxw[0][k] = gxw[1][k]; gxw[1][k] = gxn[k];
                 hyp[k] = hyn[k];
             }
 #pragma unroll
-            for (int m = 0; m < 4; ++m) { fmx[0][m] = fmx[1][m]; fmx[1][m] = fmx[2][m]; fmx[2][m] = fmn[m]; }
-            dvxp = dvxn;
+            for (int m = 0; m < 4; ++m) { fmx[0][m] = fmx[1][m]; fmx[1][m] = fmn[m]; }
             sw[0] = sw[1]; sw[1] = s_new;
             gyp[0] = gyn[QVX]; gyp[1] = gyn[QB];
         }
@@ -447,31 +452,42 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
         if (tid == 0) {
             double mx_ = 0.0, my_ = 0.0, bb = 0.0;
             for (int k = 0; k < NT / 64; ++k) { mx_ = fmax(mx_, red[0][k]); my_ = fmax(my_, red[1][k]); bb = fmax(bb, red[2][k]); }
-            const int nslot = sc->cur ^ 1;
-            atomicMax(&sc->cacc[nslot][0], (unsigned long long)__double_as_longlong(mx_));
-            atomicMax(&sc->cacc[nslot][1], (unsigned long long)__double_as_longlong(my_));
-            if (bb > 0.0) atomicOr(&sc->nonphys, 1);
+            DevScalars *scw = a.sc;
+            const int nslot = scw->cur ^ 1;
+            atomicMax(&scw->cacc[nslot][0], (unsigned long long)__double_as_longlong(mx_));
+            atomicMax(&scw->cacc[nslot][1], (unsigned long long)__double_as_longlong(my_));
+            if (bb > 0.0) atomicOr(&scw->nonphys, 1);
         }
     }
 }
 
-template <typename real, int STAGE>
-static hipError_t launch_s(bool hd, bool bg, const StageArgs<real> &a, dim3 grid, hipStream_t s) {
-    if (hd && bg) hipLaunchKernelGGL((k_stage<real, STAGE, true, true>), grid, dim3(NT), 0, s, a);
-    else if (hd) hipLaunchKernelGGL((k_stage<real, STAGE, true, false>), grid, dim3(NT), 0, s, a);
-    else if (bg) hipLaunchKernelGGL((k_stage<real, STAGE, false, true>), grid, dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((k_stage<real, STAGE, false, false>), grid, dim3(NT), 0, s, a);
+template <typename real, int NT, int STAGE>
+static hipError_t launch_s(bool hd, bool bg, const StageArgs<real> &a, hipStream_t s) {
+    constexpr int TX = NT - 2 * G;
+    dim3 grid((a.L.nx + TX - 1) / TX, (a.L.ny + a.ty - 1) / a.ty);
+    if (hd && bg) hipLaunchKernelGGL((k_stage<real, NT, STAGE, true, true>), grid, dim3(NT), 0, s, a);
+    else if (hd) hipLaunchKernelGGL((k_stage<real, NT, STAGE, true, false>), grid, dim3(NT), 0, s, a);
+    else if (bg) hipLaunchKernelGGL((k_stage<real, NT, STAGE, false, true>), grid, dim3(NT), 0, s, a);
+    else hipLaunchKernelGGL((k_stage<real, NT, STAGE, false, false>), grid, dim3(NT), 0, s, a);
     return hipGetLastError();
+}
+
+template <typename real, int NT>
+static hipError_t launch_nt(int stage, bool hd, bool bg, const StageArgs<real> &a, hipStream_t s) {
+    switch (stage) {
+        case 1: return launch_s<real, NT, 1>(hd, bg, a, s);
+        case 2: return launch_s<real, NT, 2>(hd, bg, a, s);
+        case 3: return launch_s<real, NT, 3>(hd, bg, a, s);
+        default: return launch_s<real, NT, 4>(hd, bg, a, s);
+    }
 }
 
 template <typename real>
 hipError_t launch_stage(int stage, bool hd, bool bg, const StageArgs<real> &a, hipStream_t s) {
-    dim3 grid((a.L.nx + TX - 1) / TX, (a.L.ny + a.ty - 1) / a.ty);
-    switch (stage) {
-        case 1: return launch_s<real, 1>(hd, bg, a, grid, s);
-        case 2: return launch_s<real, 2>(hd, bg, a, grid, s);
-        case 3: return launch_s<real, 3>(hd, bg, a, grid, s);
-        default: return launch_s<real, 4>(hd, bg, a, grid, s);
+    switch (a.nt) {
+        case 64: return launch_nt<real, 64>(stage, hd, bg, a, s);
+        case 128: return launch_nt<real, 128>(stage, hd, bg, a, s);
+        default: return launch_nt<real, 256>(stage, hd, bg, a, s);
     }
 }
 

@@ -33,7 +33,7 @@ EXPORTED = (
     "sacx_abi_version", "sacx_strerror", "sacx_last_error", "sacx_workspace_size", "sacx_create",
     "sacx_destroy", "sacx_set_boundaries", "sacx_init_state", "sacx_advance", "sacx_read_fields",
     "sacx_diagnostics", "sacx_halo_buffer_size", "sacx_halo_pack", "sacx_halo_unpack",
-    "sacx_profile_enable", "sacx_profile_read",
+    "sacx_profile_enable", "sacx_profile_read", "sacx_set_launch", "sacx_get_launch",
 )
 
 
@@ -98,6 +98,8 @@ def load_library():
     lib.sacx_halo_unpack.argtypes = [P, ctypes.c_int32, P]
     lib.sacx_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.sacx_profile_read.argtypes = [P, ctypes.POINTER(Profile)]
+    lib.sacx_set_launch.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    lib.sacx_get_launch.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
     for n in EXPORTED:
         if n not in ("sacx_strerror", "sacx_last_error"):
             getattr(lib, n).restype = ctypes.c_int
@@ -267,3 +269,11 @@ class Solver:
             _check(self.lib.sacx_profile_read(self.ctx, ctypes.byref(p)), "sacx_profile_read")
         return {"ms_stage": list(p.ms_stage), "n_stage": list(p.n_stage), "ms_halo": p.ms_halo,
                 "n_halo": p.n_halo, "ms_scalar": p.ms_scalar, "n_scalar": p.n_scalar}
+
+    def set_launch(self, threads: int = 0, rows: int = 0):
+        _check(self.lib.sacx_set_launch(self.ctx, int(threads), int(rows)), "sacx_set_launch")
+
+    def get_launch(self):
+        t, r = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(self.lib.sacx_get_launch(self.ctx, ctypes.byref(t), ctypes.byref(r)), "sacx_get_launch")
+        return t.value, r.value

@@ -283,3 +283,29 @@ def test_orszag_tang_8000_sampled_parity(oracle_lib):
         assert nd == 0
     # whole-field sanity of the final state
     assert np.all(np.isfinite(u100))
+
+
+def test_background_contexts_use_single_wave_blocks():
+    """Background-on contexts run 64-thread blocks (the configuration their
+    bit-exact parity is established for) and refuse wider ones."""
+    _torch()
+    from paper_1710_06423_amd import Solver, sacx
+    prob = W.split_background(W.orszag_tang(64), 0.1, 0.1, (0.0, 0.0))
+    s = Solver.from_problem(prob)
+    assert s.get_launch()[0] == 64
+    with pytest.raises(sacx.SacxError) as e:
+        s.set_launch(128, 0)
+    assert e.value.code == sacx.EUNSUP
+
+
+@pytest.mark.parametrize("shape", [(64, 16), (128, 8), (256, 37), (256, 256)])
+def test_launch_shape_does_not_change_results(oracle_lib, shape):
+    """Any block width / strip height gives the same bits as the oracle."""
+    _torch()
+    from paper_1710_06423_amd import Solver
+    prob = W.orszag_tang(300, ny=136)
+    s = Solver.from_problem(prob)
+    s.set_launch(*shape)
+    s.advance(12)
+    ora = oracle_run(oracle_lib, prob, 12)
+    assert_parity(oracle_lib, s.read_fields().cpu().numpy(), ora, label=f"launch {shape}")
