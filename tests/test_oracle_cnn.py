@@ -1,0 +1,124 @@
+"""Pins of the FP64 reference of the surrogate network."""
+
+import numpy as np
+
+from oracle import cnn
+
+
+def test_identity_kernel_is_identity():
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=(3, 7, 5))
+    w = np.zeros((3, 3, 3, 3))
+    for c in range(3):
+        w[c, c, 1, 1] = 1.0
+    assert np.array_equal(cnn.conv3x3(x, w, np.zeros(3)), x)
+
+
+def test_shift_kernel_is_periodic_shift():
+    """A single 1 at offset (dy, dx) reads the periodic neighbour x[i+dy, j+dx]."""
+    rng = np.random.default_rng(1)
+    x = rng.normal(size=(1, 6, 9))
+    for dy, dx in cnn.OFFSETS:
+        w = np.zeros((1, 1, 3, 3))
+        w[0, 0, dy + 1, dx + 1] = 1.0
+        y = cnn.conv3x3(x, w, np.zeros(1))
+        i, j = 2, 8
+        assert y[0, i, j] == x[0, (i + dy) % 6, (j + dx) % 9]
+
+
+def test_conv_brute_force():
+    rng = np.random.default_rng(2)
+    x = rng.normal(size=(2, 4, 5))
+    w = rng.normal(size=(3, 2, 3, 3))
+    b = rng.normal(size=3)
+    y = cnn.conv3x3(x, w, b)
+    for o in range(3):
+        for i in range(4):
+            for j in range(5):
+                s = b[o]
+                for c in range(2):
+                    for dy in (-1, 0, 1):
+                        for dx in (-1, 0, 1):
+                            s += w[o, c, dy + 1, dx + 1] * x[c, (i + dy) % 4, (j + dx) % 5]
+                assert abs(y[o, i, j] - s) < 1e-12
+
+
+def test_translation_equivariance():
+    rng = np.random.default_rng(3)
+    p = cnn.init_params(3)
+    x = rng.normal(size=(6, 8, 8))
+    y, _ = cnn.forward(p, x)
+    ys, _ = cnn.forward(p, np.roll(x, (2, -3), axis=(1, 2)))
+    assert np.allclose(ys, np.roll(y, (2, -3), axis=(1, 2)), atol=1e-12)
+
+
+def test_output_bounds():
+    rng = np.random.default_rng(4)
+    p = cnn.init_params(4)
+    y, _ = cnn.forward(p, 10 * rng.normal(size=(6, 5, 5)))
+    assert np.all(y >= 0) and np.all(y <= 4)
+
+
+def test_gradients_match_finite_differences():
+    rng = np.random.default_rng(5)
+    p = cnn.init_params(5)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = 0.1 * rng.normal(size=p[k].shape)
+    x = rng.normal(size=(6, 5, 6))
+    t = 4 * rng.uniform(size=(10, 5, 6))
+    pred, acts = cnn.forward(p, x)
+    g = cnn.backward(p, acts, t)
+    eps = 1e-6
+    for k in p:
+        flat = p[k].reshape(-1)
+        idxs = rng.choice(flat.size, size=min(6, flat.size), replace=False)
+        for i in idxs:
+            old = flat[i]
+            flat[i] = old + eps
+            lp = cnn.loss(cnn.forward(p, x)[0], t)
+            flat[i] = old - eps
+            lm = cnn.loss(cnn.forward(p, x)[0], t)
+            flat[i] = old
+            fd = (lp - lm) / (2 * eps)
+            an = g[k].reshape(-1)[i]
+            assert abs(fd - an) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (k, i, fd, an)
+
+
+def test_input_gradient_matches_finite_differences():
+    """The conv backward-data path (transposed offsets) on its own."""
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=(3, 4, 5))
+    w = rng.normal(size=(2, 3, 3, 3))
+    dy_ = rng.normal(size=(2, 4, 5))
+    dx_, _, _ = cnn.conv3x3_grads(x, w, dy_)
+    f = lambda xx: float(np.sum(dy_ * cnn.conv3x3(xx, w, np.zeros(2))))  # noqa: E731
+    for idx in [(0, 0, 0), (1, 3, 4), (2, 1, 2)]:
+        e = np.zeros_like(x)
+        e[idx] = 1e-6
+        fd = (f(x + e) - f(x - e)) / 2e-6
+        assert abs(fd - dx_[idx]) < 1e-7
+
+
+def test_adam_first_step_moves_by_lr():
+    """With bias correction the first Adam step moves each weight by lr * sign(g)."""
+    p = {"w": np.array([1.0, -2.0, 3.0])}
+    g = {"w": np.array([0.5, -4.0, 1e-3])}
+    m = {"w": np.zeros(3)}
+    v = {"w": np.zeros(3)}
+    cnn.adam_step(p, g, m, v, 1, lr=0.01, eps=0.0)
+    assert np.allclose(p["w"], [0.99, -1.99, 2.99], atol=1e-15)
+
+
+def test_training_reduces_loss():
+    rng = np.random.default_rng(7)
+    p = cnn.init_params(7)
+    x = rng.normal(size=(6, 6, 6))
+    t = 4 / (1 + np.exp(-x[:1].repeat(10, axis=0)))
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(val) for k, val in p.items()}
+    l0 = cnn.loss(cnn.forward(p, x)[0], t)
+    for it in range(1, 31):
+        pred, acts = cnn.forward(p, x)
+        cnn.adam_step(p, cnn.backward(p, acts, t), m, v, it, lr=3e-3)
+    assert cnn.loss(cnn.forward(p, x)[0], t) < 0.5 * l0
