@@ -89,8 +89,17 @@ def _load():
             lib.orc_sums.argtypes = [ctypes.POINTER(_Cfg), _PP, _P]
             lib.orc_deriv_line.argtypes = [ctypes.c_int, _P, ctypes.c_double, _P]
             lib.orc_hd_ratio_line.argtypes = [ctypes.c_int, _P, _P]
+            _F = ctypes.POINTER(ctypes.c_float)
+            _I = ctypes.POINTER(ctypes.c_int)
+            lib.orc_advance_ext.argtypes = [ctypes.POINTER(_Cfg), _PP, ctypes.c_int, ctypes.c_double,
+                                            _P, _I, _P, _F]
+            lib.orc_rhs_ext.argtypes = [ctypes.POINTER(_Cfg), _PP, ctypes.c_double, _PP, _F]
+            lib.orc_hd_ratio_fields.argtypes = [ctypes.POINTER(_Cfg), _PP, _PP, _P]
+            lib.orc_hd_check.argtypes = [ctypes.POINTER(_Cfg), _PP, _F, ctypes.c_double, ctypes.c_int,
+                                         _I, _I, _P, _P]
             for name in ("orc_advance", "orc_wavespeed", "orc_rhs", "orc_step_patch", "orc_sums",
-                         "orc_deriv_line", "orc_hd_ratio_line", "orc_abi_version"):
+                         "orc_deriv_line", "orc_hd_ratio_line", "orc_abi_version", "orc_advance_ext",
+                         "orc_rhs_ext", "orc_hd_ratio_fields", "orc_hd_check"):
                 getattr(lib, name).restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -160,6 +169,27 @@ class State:
             raise OracleError(rc, "orc_advance")
         return rc, done.value
 
+    def advance_ext(self, nsteps: int, rext: np.ndarray, t_end: float = 0.0) -> int:
+        """Advance with the coefficient ratios taken from rext (10, ny, nx) float32
+        wherever a value is not negative (held fixed for the whole call)."""
+        lib = _load()
+        r = _f32_planes(rext, self.prob.nx, self.prob.ny)
+        t = ctypes.c_double(self.t)
+        done = ctypes.c_int(0)
+        info = np.zeros(4)
+        rc = lib.orc_advance_ext(ctypes.byref(self.cfg), _ptrs(self.f), int(nsteps), float(t_end),
+                                 ctypes.byref(t), ctypes.byref(done), info.ctypes.data_as(_P),
+                                 r.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+        self.t = t.value
+        self.steps += done.value
+        self.last = info
+        if rc != OK:
+            raise OracleError(rc, "orc_advance_ext")
+        return done.value
+
+    def ratio_fields(self) -> np.ndarray:
+        return ratio_fields(self.cfg, self.f, self.bg)
+
     def run(self, nsteps: int, t_end: float = 0.0) -> int:
         rc, done = self.advance(nsteps, t_end)
         if rc != OK:
@@ -218,6 +248,56 @@ def step_patch(cfg: _Cfg, patch: Sequence[np.ndarray], bg_patch, dt: float, cmax
     if rc != OK:
         raise OracleError(rc, "orc_step_patch")
     return np.stack(out)
+
+
+def _f32_planes(r, nx: int, ny: int) -> np.ndarray:
+    r = np.ascontiguousarray(r, dtype=np.float32)
+    if r.shape != (10, ny, nx):
+        raise ValueError(f"ratio fields must have shape (10, {ny}, {nx}), got {r.shape}")
+    return r
+
+
+def rhs_ext(cfg: _Cfg, f: Sequence[np.ndarray], cmax: float, rext: np.ndarray) -> np.ndarray:
+    """L(U) with externally supplied coefficient ratios (negative = plain)."""
+    lib = _load()
+    f = [_c64(a) for a in f]
+    r = _f32_planes(rext, cfg.nx, cfg.ny)
+    K = [np.zeros_like(f[0]) for _ in range(6)]
+    rc = lib.orc_rhs_ext(ctypes.byref(cfg), _ptrs(f), float(cmax), _ptrs(K),
+                         r.ctypes.data_as(ctypes.POINTER(ctypes.c_float)))
+    if rc != OK:
+        raise OracleError(rc, "orc_rhs_ext")
+    return np.stack(K)
+
+
+def ratio_fields(cfg: _Cfg, f: Sequence[np.ndarray], bg=None) -> np.ndarray:
+    """Plain coefficient ratios of every face: (10, ny, nx); planes 0-4 x faces
+    {rho~, eps~, v_x, v_y, B~_y}, 5-9 y faces {rho~, eps~, v_x, v_y, B~_x}."""
+    lib = _load()
+    f = [_c64(a) for a in f]
+    bgp = _ptrs([_c64(a) for a in bg]) if bg is not None else None
+    out = np.zeros((10, cfg.ny, cfg.nx))
+    rc = lib.orc_hd_ratio_fields(ctypes.byref(cfg), _ptrs(f), bgp, out.ctypes.data_as(_P))
+    if rc != OK:
+        raise OracleError(rc, "orc_hd_ratio_fields")
+    return out
+
+
+def hd_check(cfg: _Cfg, f: Sequence[np.ndarray], rnn: np.ndarray, bound: float, tile: int):
+    """Surrogate check: (mask (nty, ntx) of fallback tiles, n_fallback, err_used, err_all)."""
+    lib = _load()
+    f = [_c64(a) for a in f]
+    r = _f32_planes(rnn, cfg.nx, cfg.ny)
+    ntx, nty = -(-cfg.nx // tile), -(-cfg.ny // tile)
+    mask = np.zeros((nty, ntx), dtype=np.int32)
+    nf = ctypes.c_int(0)
+    eu, ea = ctypes.c_double(0), ctypes.c_double(0)
+    rc = lib.orc_hd_check(ctypes.byref(cfg), _ptrs(f), r.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                          float(bound), int(tile), mask.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                          ctypes.byref(nf), ctypes.byref(eu), ctypes.byref(ea))
+    if rc != OK:
+        raise OracleError(rc, "orc_hd_check")
+    return mask, nf.value, eu.value, ea.value
 
 
 def sums(cfg: _Cfg, f: Sequence[np.ndarray]) -> np.ndarray:

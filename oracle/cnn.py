@@ -9,6 +9,14 @@ sum over the nine offsets of a channel contraction of the shifted input.
 
 Used by the tests to check the GPU kernels' forward pass, gradients and
 optimiser step; pinned by finite differences and exact special cases.
+
+Precision: the network is specified with BF16 weights and FP32 accumulation.
+With ``bf16=True`` the reference rounds (round-to-nearest-even) at exactly the
+points where that arithmetic holds BF16 values: the weights, every hidden
+activation (a layer's input) and every back-propagated gradient that enters
+a product (the error signal of each layer).  Sums stay in FP64, so the only
+remaining difference to an FP32-accumulating implementation is the order and
+precision of the sums.
 """
 
 from __future__ import annotations
@@ -19,6 +27,14 @@ import numpy as np
 
 LAYERS = [(6, 32), (32, 32), (32, 32), (32, 10)]
 OFFSETS = [(dy, dx) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]   # row-major over the 3x3 window
+
+
+def bf16_round(x: np.ndarray) -> np.ndarray:
+    """Round to the nearest BF16 value (ties to even), via float32, returned as float64."""
+    f = np.ascontiguousarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
 
 
 def shift(x: np.ndarray, dy: int, dx: int) -> np.ndarray:
@@ -59,14 +75,21 @@ def init_params(seed: int = 0) -> Dict[str, np.ndarray]:
     return p
 
 
-def forward(p: Dict[str, np.ndarray], x: np.ndarray) -> Tuple[np.ndarray, List[np.ndarray]]:
+def _weights(p, l, bf16):
+    w = p[f"w{l}"]
+    return bf16_round(w) if bf16 else w
+
+
+def forward(p: Dict[str, np.ndarray], x: np.ndarray, bf16: bool = False) -> Tuple[np.ndarray, List[np.ndarray]]:
     """Returns the predicted ratios 4 sigmoid(z4) and the cache for backward."""
-    acts = [x]
-    h = x
+    acts = [bf16_round(x) if bf16 else x]
+    h = acts[0]
     for l in range(len(LAYERS)):
-        z = conv3x3(h, p[f"w{l}"], p[f"b{l}"])
+        z = conv3x3(h, _weights(p, l, bf16), p[f"b{l}"])
         if l < len(LAYERS) - 1:
             h = np.maximum(z, 0.0)
+            if bf16:
+                h = bf16_round(h)
         else:
             h = 4.0 / (1.0 + np.exp(-z))
         acts.append(h)
@@ -78,20 +101,60 @@ def loss(pred: np.ndarray, target: np.ndarray) -> float:
     return float(np.mean((pred - target) ** 2))
 
 
-def backward(p: Dict[str, np.ndarray], acts: List[np.ndarray], target: np.ndarray) -> Dict[str, np.ndarray]:
-    """Gradients of the mean squared error w.r.t. every parameter."""
+def backward(p: Dict[str, np.ndarray], acts: List[np.ndarray], target: np.ndarray,
+             bf16: bool = False, count: int = 0) -> Dict[str, np.ndarray]:
+    """Gradients of the mean squared error w.r.t. every parameter.  `count` is
+    the number of outputs the mean runs over (default: this image's)."""
     pred = acts[-1]
-    g = 2.0 * (pred - target) / pred.size
+    n = count if count else pred.size
+    g = 2.0 * (pred - target) / n
     # d(4 sigmoid(z))/dz = pred (1 - pred / 4)
     g = g * pred * (1.0 - pred / 4.0)
     grads = {}
     for l in reversed(range(len(LAYERS))):
+        if bf16:
+            g = bf16_round(g)
         h_in = acts[l]
-        dx_, dw, db = conv3x3_grads(h_in, p[f"w{l}"], g)
+        dx_, dw, db = conv3x3_grads(h_in, _weights(p, l, bf16), g)
         grads[f"w{l}"], grads[f"b{l}"] = dw, db
         if l > 0:
             g = dx_ * (acts[l] > 0.0)
     return grads
+
+
+def batch_loss_and_grads(p, xs, ts, bf16: bool = False):
+    """Mean squared error over a batch of images and its parameter gradients."""
+    count = sum(t.size for t in ts)
+    total = 0.0
+    grads = {k: np.zeros_like(v) for k, v in p.items()}
+    for x, t in zip(xs, ts):
+        pred, acts = forward(p, x, bf16)
+        total += float(np.sum((pred - t) ** 2))
+        g = backward(p, acts, t, bf16, count)
+        for k in grads:
+            grads[k] += g[k]
+    return total / count, grads
+
+
+def flatten(p) -> np.ndarray:
+    """Parameter vector in the order w0, b0, w1, b1, w2, b2, w3, b3, each
+    weight array row-major over (out channel, in channel, ky, kx)."""
+    return np.concatenate([p[f"{a}{l}"].reshape(-1) for l in range(len(LAYERS)) for a in "wb"])
+
+
+def unflatten(theta: np.ndarray) -> Dict[str, np.ndarray]:
+    p, o = {}, 0
+    for l, (ci, co) in enumerate(LAYERS):
+        n = co * ci * 9
+        p[f"w{l}"] = np.asarray(theta[o:o + n], dtype=np.float64).reshape(co, ci, 3, 3)
+        o += n
+        p[f"b{l}"] = np.asarray(theta[o:o + co], dtype=np.float64).copy()
+        o += co
+    assert o == theta.size
+    return p
+
+
+NPARAM = sum(co * ci * 9 + co for ci, co in LAYERS)
 
 
 def adam_step(p, grads, m, v, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -185,7 +185,27 @@ typedef struct {
     double dx, dy, gamma;
     int hd_on, hd_cross_on, bg_on;
     double c2[4], cshk[4];
+    /* optional externally supplied coefficient ratios (the surrogate's
+     * prediction): 10 planes of nx*ny face values, planes 0-4 the x-face
+     * sets, 5-9 the y-face sets, face (i+1/2, j) / (i, j+1/2) stored at
+     * interior cell (i, j).  A negative value selects the plain ratio.  Used
+     * only with blocks that are the whole domain extended by G (periodic). */
+    const float *rext;
+    int rext_nx, rext_ny;
 } rhs_par;
+
+/* coefficient ratio of set `plane` at the face of block cell (i, j): the
+ * supplied value when there is one and it is not negative, else the plain
+ * ratio of the differences */
+static double ratio_or_ext(const rhs_par *P, int plane, int i, int j, const double *q, ptrdiff_t c,
+                           ptrdiff_t st) {
+    if (P->rext) {
+        const int nx = P->rext_nx, ny = P->rext_ny;
+        const float v = P->rext[(size_t)plane * nx * ny + (size_t)imod(j - G, ny) * nx + imod(i - G, nx)];
+        if (v >= 0.0f) return (double)v;
+    }
+    return hd_ratio(q, c, st);
+}
 
 static int rhs_block(int nxe, int nye, double *const S[NF], double *const BG[NB],
                      const rhs_par *P, double cmax, double *const K[NF]) {
@@ -311,7 +331,7 @@ static int rhs_block(int nxe, int nye, double *const S[NF], double *const BG[NB]
                 size_t c = (size_t)i + (size_t)j * nxe;
                 double sf = dmax(s[c], s[c + 1]);
                 for (int k = 0; k < 5; ++k) {
-                    double R = hd_ratio(qx[k], (ptrdiff_t)c, 1);
+                    double R = ratio_or_ext(P, k, i, j, qx[k], (ptrdiff_t)c, 1);
                     double nu = P->c2[cls[k]] * dx * cmax * R + P->cshk[cls[k]] * dx * dx * sf;
                     Gx[k][c] = nu * d1_at(qx[k], (ptrdiff_t)c, 1) * idx;
                 }
@@ -323,7 +343,7 @@ static int rhs_block(int nxe, int nye, double *const S[NF], double *const BG[NB]
                 size_t c = (size_t)i + (size_t)j * nxe;
                 double sf = dmax(s[c], s[c + nxe]);
                 for (int k = 0; k < 5; ++k) {
-                    double R = hd_ratio(qy[k], (ptrdiff_t)c, nxe);
+                    double R = ratio_or_ext(P, 5 + k, i, j, qy[k], (ptrdiff_t)c, nxe);
                     double nu = P->c2[cls[k]] * dy * cmax * R + P->cshk[cls[k]] * dy * dy * sf;
                     Gy[k][c] = nu * d1_at(qy[k], (ptrdiff_t)c, nxe) * idy;
                 }
@@ -414,6 +434,9 @@ static void make_rhs_par(const orc_cfg *c, rhs_par *P) {
     P->hd_cross_on = c->hd_cross_on;
     P->bg_on = c->background_on;
     for (int k = 0; k < 4; ++k) { P->c2[k] = c->c2[k]; P->cshk[k] = c->cshk[k]; }
+    P->rext = NULL;
+    P->rext_nx = c->nx;
+    P->rext_ny = c->ny;
 }
 
 /* ------------------------------------------------------------------ */
@@ -596,13 +619,14 @@ static int dom_step(dom *d, double dt, double cmax) {
  * step.  A non-physical start state stops the run with ORC_ENONPHYS and
  * leaves that state in f.  info[0] = last dt, info[1] = last c_max,
  * info[2] = c_x, info[3] = c_y of the last step. */
-int orc_advance(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], int nsteps,
-                double t_end, double *t, int *steps_done, double info[4]) {
+static int advance_impl(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], int nsteps,
+                        double t_end, double *t, int *steps_done, double info[4], const float *rext) {
     if (!cfg_ok(cfg) || !f || !t || nsteps < 0) return ORC_EINVAL;
     if (cfg->background_on && !bg) return ORC_EINVAL;
     dom d;
     int rc = dom_init(&d, cfg, f, bg);
     if (rc) return rc;
+    d.par.rext = rext;
     int done = 0;
     for (int step = 0; step < nsteps; ++step) {
         if (t_end > 0.0 && t_end - *t <= 1e-12 * t_end) break;
@@ -623,6 +647,22 @@ int orc_advance(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], i
     return rc;
 }
 
+int orc_advance(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], int nsteps,
+                double t_end, double *t, int *steps_done, double info[4]) {
+    return advance_impl(cfg, f, bg, nsteps, t_end, t, steps_done, info, NULL);
+}
+
+/* As orc_advance, with the hyper-diffusion coefficient ratios taken from
+ * rext (10 planes of nx*ny, see rhs_par) wherever a value is not negative,
+ * held fixed for the whole run.  Doubly periodic domains without a
+ * background only. */
+int orc_advance_ext(const orc_cfg *cfg, double *const f[NF], int nsteps, double t_end, double *t,
+                    int *steps_done, double info[4], const float *rext) {
+    if (!cfg_ok(cfg) || !rext || cfg->background_on) return ORC_EINVAL;
+    for (int s = 0; s < 4; ++s) if (cfg->bc[s] != ORC_PERIODIC) return ORC_EINVAL;
+    return advance_impl(cfg, f, NULL, nsteps, t_end, t, steps_done, info, rext);
+}
+
 /* Wave speeds of a state: out = {c_x, c_y, c_max, dt}.  Returns
  * ORC_ENONPHYS if any cell has rho <= 0, p_k <= 0 or a non-finite value. */
 int orc_wavespeed(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], double out[4]) {
@@ -637,13 +677,14 @@ int orc_wavespeed(const orc_cfg *cfg, double *const f[NF], double *const bg[NB],
 
 /* Right-hand side L(U) on the interior (halo filled per cfg->bc) with a
  * given c_max for the hyper-diffusion coefficients. */
-int orc_rhs(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], double cmax,
-            double *const K[NF]) {
+static int rhs_impl(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], double cmax,
+                    double *const K[NF], const float *rext) {
     if (!cfg_ok(cfg) || !f || !K) return ORC_EINVAL;
     if (cfg->background_on && !bg) return ORC_EINVAL;
     dom d;
     int rc = dom_init(&d, cfg, f, bg);
     if (rc) return rc;
+    d.par.rext = rext;
     fill_block(&d, &d.U);
     rc = rhs_block(d.nxe, d.nye, d.U.f, d.BG, &d.par, cmax, d.K[0].f);
     if (!rc)
@@ -653,6 +694,19 @@ int orc_rhs(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], doubl
                        sizeof(double) * d.nx);
     dom_free(&d);
     return rc;
+}
+
+int orc_rhs(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], double cmax,
+            double *const K[NF]) {
+    return rhs_impl(cfg, f, bg, cmax, K, NULL);
+}
+
+/* As orc_rhs with externally supplied coefficient ratios (see orc_advance_ext). */
+int orc_rhs_ext(const orc_cfg *cfg, double *const f[NF], double cmax, double *const K[NF],
+                const float *rext) {
+    if (!cfg_ok(cfg) || !rext || cfg->background_on) return ORC_EINVAL;
+    for (int s = 0; s < 4; ++s) if (cfg->bc[s] != ORC_PERIODIC) return ORC_EINVAL;
+    return rhs_impl(cfg, f, NULL, cmax, K, rext);
 }
 
 /* One RK4 step on a patch of a larger 2-D domain whose outer 12 cells are
@@ -781,5 +835,101 @@ int orc_hd_ratio_line(int n, const double *q, double *R) {
     for (int i = -G; i < n + G + 1; ++i) e[i + G] = q[imod(i, n)];
     for (int i = 0; i < n; ++i) R[i] = hd_ratio(e, i + G, 1);
     free(e);
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* coefficient-ratio fields of a state and the surrogate check          */
+/* ------------------------------------------------------------------ */
+
+/* Plain hyper-diffusion ratios of every face of a 2-D state (halo filled
+ * per cfg->bc): R has 10 planes of nx*ny values, planes 0-4 the x-face sets
+ * {rho~, eps~, v_x, v_y, B~_y} at faces (i+1/2, j), planes 5-9 the y-face
+ * sets {rho~, eps~, v_x, v_y, B~_x} at faces (i, j+1/2).  The primitive
+ * quantities are formed exactly as in the right-hand side. */
+int orc_hd_ratio_fields(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], double *R) {
+    if (!cfg_ok(cfg) || !f || !R || cfg->nx < 2 || cfg->ny < 2) return ORC_EINVAL;
+    if (cfg->background_on && !bg) return ORC_EINVAL;
+    dom d;
+    int rc = dom_init(&d, cfg, f, bg);
+    if (rc) return rc;
+    fill_block(&d, &d.U);
+    const size_t n = (size_t)d.nxe * d.nye;
+    double *vx = alloc0(n), *vy = alloc0(n), *eps = alloc0(n);
+    if (!vx || !vy || !eps) { rc = ORC_ENOMEM; goto out; }
+    {
+        const double gm1 = cfg->gamma - 1.0, igm1 = 1.0 / gm1;
+        for (size_t c = 0; c < n; ++c) {
+            double rb = 0.0, bxb = 0.0, byb = 0.0;
+            if (cfg->background_on) { rb = d.BG[B_RHO][c]; bxb = d.BG[B_BX][c]; byb = d.BG[B_BY][c]; }
+            double rt = d.U.f[F_RHO][c], mx = d.U.f[F_MX][c], my = d.U.f[F_MY][c], et = d.U.f[F_E][c];
+            double bxt = d.U.f[F_BX][c], byt = d.U.f[F_BY][c];
+            double r = rb + rt;
+            double ir = 1.0 / r;
+            double ux = mx * ir, uy = my * ir;
+            double kin = 0.5 * (mx * ux + my * uy);
+            double bbdot = bxb * bxt + byb * byt;
+            double bt2 = bxt * bxt + byt * byt;
+            double pk = gm1 * (((et - kin) - bbdot) - 0.5 * bt2);
+            vx[c] = ux; vy[c] = uy; eps[c] = pk * igm1;
+        }
+        double *qx[5] = {d.U.f[F_RHO], eps, vx, vy, d.U.f[F_BY]};
+        double *qy[5] = {d.U.f[F_RHO], eps, vx, vy, d.U.f[F_BX]};
+        const size_t pl = (size_t)d.nx * d.ny;
+        for (int j = 0; j < d.ny; ++j)
+            for (int i = 0; i < d.nx; ++i) {
+                ptrdiff_t c = (ptrdiff_t)(i + G) + (ptrdiff_t)(j + G) * d.nxe;
+                for (int k = 0; k < 5; ++k) {
+                    R[(size_t)k * pl + (size_t)j * d.nx + i] = hd_ratio(qx[k], c, 1);
+                    R[(size_t)(5 + k) * pl + (size_t)j * d.nx + i] = hd_ratio(qy[k], c, d.nxe);
+                }
+            }
+    }
+out:
+    free(vx); free(vy); free(eps);
+    dom_free(&d);
+    return rc;
+}
+
+/* The surrogate check: the interior is cut into tiles of tile x tile cells
+ * (ragged at the high edges), tile (tx, ty) covering cells
+ * [tx*tile, ...) x [ty*tile, ...), row-major tile index ty*ntx + tx.  A tile
+ * falls back to the plain ratio when any of its 10 face values r satisfies
+ * NOT(|r - R_plain| <= bound) (a non-finite prediction always fails).
+ * mask (ntx*nty ints): 1 = fallback.  err_used = max |r - R_plain| over the
+ * tiles that keep the prediction, err_all = max over every finite error.
+ * Returns the number of fallback tiles in *nfall. */
+int orc_hd_check(const orc_cfg *cfg, double *const f[NF], const float *rnn, double bound, int tile,
+                 int *mask, int *nfall, double *err_used, double *err_all) {
+    if (!cfg_ok(cfg) || !f || !rnn || !mask || tile < 1 || cfg->background_on) return ORC_EINVAL;
+    const int nx = cfg->nx, ny = cfg->ny;
+    double *R = alloc0((size_t)10 * nx * ny);
+    if (!R) return ORC_ENOMEM;
+    int rc = orc_hd_ratio_fields(cfg, f, NULL, R);
+    if (rc) { free(R); return rc; }
+    const int ntx = (nx + tile - 1) / tile, nty = (ny + tile - 1) / tile;
+    double eu = 0.0, ea = 0.0;
+    int nf = 0;
+    for (int ty = 0; ty < nty; ++ty)
+        for (int tx = 0; tx < ntx; ++tx) {
+            int bad = 0;
+            double et = 0.0;
+            for (int k = 0; k < 10; ++k)
+                for (int j = ty * tile; j < ny && j < (ty + 1) * tile; ++j)
+                    for (int i = tx * tile; i < nx && i < (tx + 1) * tile; ++i) {
+                        size_t c = (size_t)k * nx * ny + (size_t)j * nx + i;
+                        double e = fabs((double)rnn[c] - R[c]);
+                        if (!(e <= bound)) bad = 1;
+                        if (isfinite(e)) et = dmax(et, e);
+                    }
+            mask[ty * ntx + tx] = bad;
+            nf += bad;
+            ea = dmax(ea, et);
+            if (!bad) eu = dmax(eu, et);
+        }
+    if (nfall) *nfall = nf;
+    if (err_used) *err_used = eu;
+    if (err_all) *err_all = ea;
+    free(R);
     return ORC_OK;
 }

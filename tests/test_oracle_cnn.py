@@ -122,3 +122,72 @@ def test_training_reduces_loss():
         pred, acts = cnn.forward(p, x)
         cnn.adam_step(p, cnn.backward(p, acts, t), m, v, it, lr=3e-3)
     assert cnn.loss(cnn.forward(p, x)[0], t) < 0.5 * l0
+
+
+def test_bf16_round_known_values():
+    """Round to nearest even on the 8-bit significand."""
+    one = 1.0
+    ulp = 2.0 ** -7                     # BF16 spacing just above 1
+    vals = np.array([one, one + ulp / 2, one + 3 * ulp / 2, one + ulp / 4, one + 3 * ulp / 4,
+                     -2.5, 3.0e38, 1e-40])
+    got = cnn.bf16_round(vals)
+    assert got[0] == 1.0
+    assert got[1] == 1.0                # tie -> even (1.0)
+    assert got[2] == one + 2 * ulp      # tie -> even (1 + 2 ulp)
+    assert got[3] == 1.0
+    assert got[4] == one + ulp
+    assert got[5] == -2.5
+    assert np.isfinite(got[6])
+    # every result is a BF16 value: low 16 bits of the float32 pattern are 0
+    assert np.all((got.astype(np.float32).view(np.uint32) & 0xFFFF) == 0)
+
+
+def test_bf16_mode_close_to_exact_mode():
+    rng = np.random.default_rng(8)
+    p = cnn.init_params(8)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = 0.05 * rng.normal(size=p[k].shape)
+    x = rng.normal(size=(6, 9, 7))
+    t = 4 * rng.uniform(size=(10, 9, 7))
+    y64, a64 = cnn.forward(p, x)
+    y16, a16 = cnn.forward(p, x, bf16=True)
+    assert np.max(np.abs(y16 - y64)) < 0.05 and not np.array_equal(y16, y64)
+    g64 = cnn.backward(p, a64, t)
+    g16 = cnn.backward(p, a16, t, bf16=True)
+    for k in g64:
+        rel = np.linalg.norm(g16[k] - g64[k]) / np.linalg.norm(g64[k])
+        assert rel < 0.15, (k, rel)
+
+
+def test_batch_grads_are_sum_over_images():
+    rng = np.random.default_rng(9)
+    p = cnn.init_params(9)
+    xs = [rng.normal(size=(6, 5, 5)) for _ in range(3)]
+    ts = [4 * rng.uniform(size=(10, 5, 5)) for _ in range(3)]
+    loss, g = cnn.batch_loss_and_grads(p, xs, ts)
+    big_x = np.concatenate(xs, axis=2)      # not periodic-equivalent, so compare per image
+    del big_x
+    manual = 0.0
+    for x, t in zip(xs, ts):
+        manual += cnn.loss(cnn.forward(p, x)[0], t) / 3
+    assert abs(loss - manual) < 1e-12
+    eps = 1e-6
+    flat = p["w1"].reshape(-1)
+    i = 17
+    old = flat[i]
+    flat[i] = old + eps
+    lp = cnn.batch_loss_and_grads(p, xs, ts)[0]
+    flat[i] = old - eps
+    lm = cnn.batch_loss_and_grads(p, xs, ts)[0]
+    flat[i] = old
+    assert abs((lp - lm) / (2 * eps) - g["w1"].reshape(-1)[i]) < 1e-7
+
+
+def test_flatten_roundtrip():
+    p = cnn.init_params(1)
+    th = cnn.flatten(p)
+    assert th.size == cnn.NPARAM == 23146
+    q = cnn.unflatten(th)
+    for k in p:
+        assert np.array_equal(p[k], q[k])
