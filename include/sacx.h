@@ -188,7 +188,8 @@ int sacx_get_launch(const sacx_ctx *ctx, int32_t *threads, int32_t *rows);
  * the paper's cost model T = T_comp + T_comm + T_idle (section 6).
  *  ms_stage[s] / n_stage[s]: the fused stage-s kernel (s = 0..3 for stages 1..4);
  *  ms_halo / n_halo: halo pack + unpack (or boundary fill) before each stage;
- *  ms_scalar / n_scalar: the one-thread time-step kernels.
+ *  ms_scalar / n_scalar: the one-thread time-step kernels;
+ *  ms_surrogate / n_surrogate: surrogate refreshes (prediction and check).
  * sacx_profile_enable(ctx, 1) resets the accumulators and starts recording;
  * (ctx, 0) stops.  sacx_profile_read synchronises and returns the totals. */
 typedef struct sacx_profile {
@@ -198,10 +199,164 @@ typedef struct sacx_profile {
     int64_t n_stage[4];
     int64_t n_halo;
     int64_t n_scalar;
+    double ms_surrogate;
+    int64_t n_surrogate;
 } sacx_profile;
 
 int sacx_profile_enable(sacx_ctx *ctx, int32_t on);
 int sacx_profile_read(sacx_ctx *ctx, sacx_profile *out);
+
+/* ---------------------------------------------------------------------
+ * Batches: many independent subdomains (shock tubes, vortex boxes of
+ * different sizes, gamma, boundaries and time steps) advanced by one
+ * persistent cooperative launch.  Each instance is an ordinary context
+ * (sacx_batch_context) carved from the batch workspace: initialise, read and
+ * inspect it with sacx_init_state / sacx_read_fields / sacx_diagnostics; it
+ * may also be advanced alone with sacx_advance.  A batched step of an
+ * instance gives the same bits as sacx_advance of that instance.
+ * All instances share one precision; hd_on = 1, no background, nx >= 3.
+ * --------------------------------------------------------------------- */
+typedef struct sacx_batch sacx_batch;
+
+/* Workspace bytes for n instances (grids[n], params[n]); host arithmetic. */
+int sacx_batch_workspace_size(int32_t n, const sacx_grid *grids, const sacx_params *params, size_t *bytes);
+
+/* Create a batch in caller-owned device memory (256-byte aligned).  bc: 4n
+ * boundary kinds (x-, x+, y-, y+ per instance) or NULL for all periodic. */
+int sacx_batch_create(int32_t n, const sacx_grid *grids, const sacx_params *params, const int32_t *bc,
+                      void *d_ws, size_t ws_bytes, void *hip_stream, sacx_batch **out);
+int sacx_batch_destroy(sacx_batch *b);
+
+/* The context of instance i (owned by the batch, valid until destroy). */
+int sacx_batch_context(sacx_batch *b, int32_t i, sacx_ctx **out);
+
+/* Tile shapes: threads per block for the whole launch (64/128/256; 0 keeps)
+ * and output rows per tile strip for each instance (rows[n], 1..4096; NULL
+ * keeps).  One-dimensional instances always use one-row tiles.  Results do
+ * not depend on the shapes.  Used by the tile autotuner. */
+int sacx_batch_set_tiles(sacx_batch *b, int32_t threads, const int32_t *rows);
+
+/* Advance every instance by nsteps RK4 steps (each with its own dt) in one
+ * persistent launch per 512 steps.  Every instance must have been
+ * initialised (ESTATE otherwise).  With sync != 0 the call synchronises and
+ * returns SACX_ENONPHYS if any instance stopped on a non-physical state. */
+int sacx_batch_advance(sacx_batch *b, int32_t nsteps, int32_t sync);
+
+
+/* ---------------------------------------------------------------------
+ * Learned hyper-diffusion coefficient.
+ *
+ * Paper section 2 sets each hyper-diffusion coefficient from the ratio R of
+ * third- to first-order differences of the diffused quantity (R in [0, 4] in
+ * this library's reading: the largest |third difference| over the 3 faces
+ * around a face over the largest |first difference| over the 5 faces around
+ * it).  Ten ratio fields are needed per state: on x faces (i+1/2, j) of
+ * {rho~, eps~, v_x, v_y, B~_y} and on y faces (i, j+1/2) of
+ * {rho~, eps~, v_x, v_y, B~_x}; as arrays they are 10 planes ("ratio
+ * planes"), plane k row j element i holding the value of set k at the face
+ * just above cell (i, j) in x (k < 5) or y (k >= 5).
+ *
+ * A small network predicts these ratio planes from the local state:
+ * four 3x3 convolutions with periodic padding, 6 -> 32 -> 32 -> 32 -> 10
+ * channels, ReLU between layers, output 4 sigmoid(z); BF16 weights and
+ * activations with FP32 accumulation on the matrix cores.  Its input is
+ * (rho, v_x, v_y, B_x, B_y, e) per cell, normalised as (f - shift) * scale.
+ * With the surrogate on, a context predicts the ratio planes every K steps,
+ * compares them tile by tile with the plain ratios of the same state and
+ * keeps the prediction only in tiles where every face is within a bound; the
+ * other tiles, and any face given a negative value, use the plain ratio.
+ * The coefficient itself keeps the exact maximum wave speed and compression
+ * term.
+ *
+ * Network buffers (all device memory, caller-owned, 16-byte aligned):
+ *   parameters : SACX_CNN_NPARAM floats, w0 b0 w1 b1 w2 b2 w3 b3, each w_l
+ *                row-major over (out channel, in channel, ky, kx); w[o][c][ky][kx]
+ *                multiplies input channel c at offset (ky-1, kx-1) in (y, x)
+ *   packed     : SACX_CNN_PACKED_BYTES, BF16 weights in matrix-core operand
+ *                order plus FP32 biases (sacx_cnn_pack)
+ *   input      : BF16, n images of h x w pixels, 8 values per pixel (the six
+ *                inputs, then 2 zeros), pixel (img, y, x) at ((img h + y) w + x) 8
+ *   activations: BF16, three hidden layers of 32 values per pixel
+ *   output     : FP32 ratio planes, [img][10][h][w]
+ * Image width must be a multiple of 32.
+ * --------------------------------------------------------------------- */
+#define SACX_CNN_NPARAM 23146
+#define SACX_CNN_PACKED_BYTES 99840
+
+typedef struct sacx_cnn_sizes {
+    size_t input_bytes;  /* input images */
+    size_t act_bytes;    /* hidden activations kept by sacx_cnn_forward */
+    size_t out_bytes;    /* output ratio planes */
+    size_t work_bytes;   /* scratch of sacx_cnn_backward */
+} sacx_cnn_sizes;
+
+/* Buffer sizes for a batch of n images of h x w (host arithmetic). */
+int sacx_cnn_buffer_sizes(int32_t n, int32_t h, int32_t w, sacx_cnn_sizes *out);
+
+/* Convert FP32 parameters to the packed BF16 form (round to nearest even). */
+int sacx_cnn_pack(const float *d_theta, void *d_packed, void *stream);
+
+/* Forward pass: input -> activations (kept for the backward pass) and output. */
+int sacx_cnn_forward(const void *d_packed, const void *d_x, int32_t n, int32_t h, int32_t w, void *d_act,
+                     float *d_out, void *stream);
+
+/* Mean squared error of the output against d_target (same layout) into
+ * *d_loss (one double, device) and its gradient with respect to every
+ * parameter into d_grad (SACX_CNN_NPARAM floats, overwritten).  Sums over
+ * pixels are reduced in a fixed order: results are deterministic. */
+int sacx_cnn_backward(const void *d_packed, const void *d_x, const void *d_act, const float *d_out,
+                      const float *d_target, int32_t n, int32_t h, int32_t w, void *d_work, size_t work_bytes,
+                      float *d_grad, double *d_loss, void *stream);
+
+/* One Adam update (bias-corrected, step counts from 1) of the FP32
+ * parameters with moment buffers d_m, d_v (SACX_CNN_NPARAM floats each). */
+int sacx_cnn_adam(float *d_theta, float *d_m, float *d_v, const float *d_grad, int32_t step, float lr,
+                  float beta1, float beta2, float eps, void *stream);
+
+/* The network input of the context's current state (one nx x ny image,
+ * periodic), norm = shift[6] then scale[6]. */
+int sacx_cnn_inputs(sacx_ctx *ctx, const float norm[12], void *d_x);
+
+/* The plain ratio planes of the context's current state, as FP32, row pitch
+ * `pitch` elements, plane stride pitch * ny (the training target). */
+int sacx_hd_ratio_fields(sacx_ctx *ctx, float *d_r, int64_t pitch);
+
+typedef struct sacx_surrogate {
+    const void *d_packed;   /* packed network (caller-owned, valid while in use);
+                               NULL: the caller writes the ratio planes itself */
+    float norm[12];         /* input shift[6], scale[6] */
+    int32_t refresh_every;  /* K >= 1: predict and check every K steps */
+    int32_t tile;           /* check tile side in cells (>= 1) */
+    double bound;           /* largest |predicted - plain| a kept tile may have */
+} sacx_surrogate;
+
+typedef struct sacx_hd_stats {
+    int64_t refreshes;       /* checks done */
+    int64_t tiles_checked;   /* tiles compared, summed over checks */
+    int64_t tiles_fallback;  /* of which fell back to the plain ratio */
+    double err_used;         /* max |predicted - plain| over kept tiles */
+    double err_all;          /* max over every finite comparison */
+} sacx_hd_stats;
+
+/* Device bytes the surrogate needs for this context (ratio planes, network
+ * input and two activation buffers). */
+int sacx_surrogate_workspace_size(const sacx_ctx *ctx, size_t *bytes);
+
+/* Switch the surrogate on (caller-owned workspace, 256-byte aligned, valid
+ * until sacx_hd_clear_surrogate or sacx_destroy).  Requires hd_on, no
+ * background, all boundaries periodic, ny >= 2 and nx a multiple of 32
+ * (SACX_EUNSUP otherwise).  The first step after this call refreshes.  With
+ * d_packed == NULL the ratio planes (sacx_hd_ratio_buffer) are not
+ * predicted but left as the caller wrote them; they are still checked. */
+int sacx_hd_set_surrogate(sacx_ctx *ctx, const sacx_surrogate *cfg, void *d_ws, size_t ws_bytes);
+int sacx_hd_clear_surrogate(sacx_ctx *ctx);
+
+/* Device address and row pitch (elements) of the surrogate's ratio planes
+ * (plane stride pitch * ny).  Checked tiles that fell back hold -1. */
+int sacx_hd_ratio_buffer(sacx_ctx *ctx, float **d_r, int64_t *pitch);
+
+/* Surrogate counters since sacx_hd_set_surrogate (synchronises). */
+int sacx_hd_read_stats(sacx_ctx *ctx, sacx_hd_stats *out);
 
 #ifdef __cplusplus
 }

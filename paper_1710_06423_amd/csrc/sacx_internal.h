@@ -9,6 +9,17 @@
 
 namespace sacx {
 
+// records the calling thread's last-error message and returns `code`
+int set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return ::sacx::set_error(SACX_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                     __FILE__, __LINE__);                                  \
+    } while (0)
+
 constexpr int G = SACX_GHOST;  // ghost cells per side
 constexpr int NF = 6;          // evolved fields
 constexpr int NBG = 4;         // background fields
@@ -55,6 +66,52 @@ struct SchemeConsts {
     double third;
 };
 
+// constants of the time-step computation
+struct StepConsts {
+    double cfl, dx, dy;
+    double c2[4];
+    int ax, ay;  // direction has more than one cell
+};
+
+// dt for the step about to start: CFL time step from the reduced wave speeds
+// with the end-time clamp, and the per-step constants derived from it
+__device__ inline void step_begin_dev(DevScalars *sc, double t_end, const StepConsts &k) {
+    sc->t_end = t_end;
+    if (sc->nonphys) { sc->active = 0; return; }
+    const double t = sc->t;
+    if (t_end > 0.0 && t_end - t <= 1e-12 * t_end) { sc->active = 0; return; }
+    const double cx = __longlong_as_double((long long)sc->cacc[sc->cur][0]);
+    const double cy = __longlong_as_double((long long)sc->cacc[sc->cur][1]);
+    const double dx = k.dx, dy = k.dy;
+    double h;
+    if (k.ax && k.ay) h = (dx / cx < dy / cy) ? dx / cx : dy / cy;
+    else if (k.ax) h = dx / cx;
+    else h = dy / cy;
+    double dt = k.cfl * h;
+    if (t_end > 0.0) dt = (dt < t_end - t) ? dt : t_end - t;
+    sc->dt = dt;
+    sc->cmax = (k.ax && k.ay) ? (cx > cy ? cx : cy) : (k.ax ? cx : cy);
+    sc->last_cx = cx;
+    sc->last_cy = cy;
+    sc->last_cmax = sc->cmax;
+    sc->hdt = 0.5 * dt;
+    sc->dt6 = dt / 6.0;
+    for (int m = 0; m < 4; ++m) {
+        sc->kx2[m] = k.c2[m] * dx * sc->cmax;
+        sc->ky2[m] = k.c2[m] * dy * sc->cmax;
+    }
+    sc->cacc[sc->cur ^ 1][0] = 0ull;
+    sc->cacc[sc->cur ^ 1][1] = 0ull;
+    sc->active = 1;
+}
+
+__device__ inline void step_end_dev(DevScalars *sc) {
+    if (!sc->active) return;
+    sc->t = sc->t + sc->dt;
+    sc->steps = sc->steps + 1;
+    sc->cur ^= 1;
+}
+
 template <typename real>
 struct StageArgs {
     const real *S[NF];    // stage input (differenced; ghosts filled)
@@ -69,10 +126,86 @@ struct StageArgs {
     SchemeConsts k;
     int hd_cross_on;
     DevScalars *sc;
+    // surrogate ratio planes (10: x-face sets then y-face sets, interior
+    // cells, periodic): a value >= 0 replaces the plain coefficient ratio of
+    // that face, a negative value keeps the plain ratio
+    const float *Rs;
+    int64_t rs_plane;     // elements per plane
+    int rs_pitch;         // elements per row
+};
+
+// arguments of the ratio-field kernels (plain ratios of a state whose halo is
+// filled; no background)
+template <typename real>
+struct RatioArgs {
+    const real *S[NF];
+    Layout L;
+    double gm1, igm1;
+};
+
+// device-side surrogate counters
+struct HdDevStats {
+    unsigned long long tiles_fallback;
+    unsigned long long err_used;   // IEEE bits of a non-negative double (max)
+    unsigned long long err_all;
+    unsigned long long pad;
+};
+
+// round to the nearest BF16 value, ties to even (NaN stays a quiet NaN)
+__device__ __forceinline__ unsigned short bf16_rne(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+// ---------------------------------------------------------------- batches
+// One instance of a batch: its per-stage kernel arguments, time-step
+// constants and ghost-fill description.
+template <typename real>
+struct BatchInst {
+    StageArgs<real> st[4];   // arguments of stages 1..4 (stage inputs, outputs)
+    StepConsts sk;
+    DevScalars *sc;
+    Layout L;
+    int periodic_x, periodic_y;
+    int oned;                // ny == 1: one-dimensional tiles
+    int pad;
+};
+
+struct BatchItem {
+    int inst, tx, ty, pad;   // a tile of one instance
+};
+
+template <typename real>
+struct BatchArgs {
+    const BatchInst<real> *inst;
+    int n;
+    const BatchItem *items;  // tiles of all instances, most expensive first
+    int nitems;
+    const long long *gbeg;   // n + 1 prefix offsets of ghost cells x fields
+    int *ctr;                // work-queue counters, one per (step, stage), zero at launch
+    int nsteps;
 };
 
 // host-side launchers (defined in the .hip units)
 template <typename real>
 hipError_t launch_stage(int stage, bool hd, bool bg, const StageArgs<real> &a, hipStream_t s);
+template <typename real>
+hipError_t launch_ratio_fields(const RatioArgs<real> &a, float *out, int64_t pitch, hipStream_t s);
+template <typename real>
+hipError_t launch_hd_check(const RatioArgs<real> &a, float *rs, int64_t pitch, double bound, int tile,
+                           HdDevStats *st, hipStream_t s);
+struct InputNorm {
+    float v[12];   // shift[6], scale[6]
+};
+template <typename real>
+hipError_t launch_cnn_inputs(const RatioArgs<real> &a, const InputNorm &norm, void *x, hipStream_t s);
+hipError_t cnn_forward_dev(const void *packed, const void *x, int n, int h, int w, void *a1, void *a2, void *a3,
+                           float *out, int64_t oimg, int64_t oplane, int64_t orow, hipStream_t s);
+template <typename real>
+hipError_t launch_batch(const BatchArgs<real> &b, int nt, int blocks, hipStream_t s);
+template <typename real>
+hipError_t batch_blocks_per_cu(int nt, int *blocks);
 
 }  // namespace sacx

@@ -43,8 +43,7 @@ using namespace sacx;
 
 static thread_local std::string g_last_error;
 
-static int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
-static int fail(int code, const char *fmt, ...) {
+int sacx::set_error(int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -53,13 +52,8 @@ static int fail(int code, const char *fmt, ...) {
     g_last_error = buf;
     return code;
 }
+#define fail sacx::set_error
 
-#define HIPCHK(expr)                                                                       \
-    do {                                                                                   \
-        hipError_t e_ = (expr);                                                            \
-        if (e_ != hipSuccess)                                                              \
-            return fail(SACX_EDEVICE, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
-    } while (0)
 
 // ------------------------------------------------------------------ context
 
@@ -89,6 +83,15 @@ struct sacx_ctx {
     std::vector<std::pair<int, std::pair<int, int>>> *ev_marks;  // (class, (start, stop) pool index)
     int ev_used;
     sacx_profile prof;
+    // learned hyper-diffusion coefficient (off unless sacx_hd_set_surrogate)
+    bool sur_on;
+    sacx_surrogate sur;
+    float *sur_r;          // ratio planes
+    int64_t sur_pitch;
+    void *sur_x, *sur_a1, *sur_a2;
+    HdDevStats *sur_st;
+    int64_t sur_since;     // steps enqueued since the last refresh
+    int64_t sur_refreshes, sur_tiles_checked;
 };
 
 namespace {
@@ -360,49 +363,9 @@ __global__ void k_reset_scalars(DevScalars *sc, double t0) {
 }
 
 // dt for the step about to start (CFL time step with the end-time clamp)
-struct StepConsts {
-    double cfl, dx, dy;
-    double c2[4];
-    int ax, ay;
-};
+__global__ void k_step_begin(DevScalars *sc, double t_end, StepConsts k) { step_begin_dev(sc, t_end, k); }
 
-__global__ void k_step_begin(DevScalars *sc, double t_end, StepConsts k) {
-    const double cfl = k.cfl, dx = k.dx, dy = k.dy;
-    const int ax = k.ax, ay = k.ay;
-    sc->t_end = t_end;
-    if (sc->nonphys) { sc->active = 0; return; }
-    const double t = sc->t;
-    if (t_end > 0.0 && t_end - t <= 1e-12 * t_end) { sc->active = 0; return; }
-    const double cx = __longlong_as_double((long long)sc->cacc[sc->cur][0]);
-    const double cy = __longlong_as_double((long long)sc->cacc[sc->cur][1]);
-    double h;
-    if (ax && ay) h = (dx / cx < dy / cy) ? dx / cx : dy / cy;
-    else if (ax) h = dx / cx;
-    else h = dy / cy;
-    double dt = cfl * h;
-    if (t_end > 0.0) dt = (dt < t_end - t) ? dt : t_end - t;
-    sc->dt = dt;
-    sc->cmax = (ax && ay) ? (cx > cy ? cx : cy) : (ax ? cx : cy);
-    sc->last_cx = cx;
-    sc->last_cy = cy;
-    sc->last_cmax = sc->cmax;
-    sc->hdt = 0.5 * dt;
-    sc->dt6 = dt / 6.0;
-    for (int m = 0; m < 4; ++m) {
-        sc->kx2[m] = k.c2[m] * dx * sc->cmax;
-        sc->ky2[m] = k.c2[m] * dy * sc->cmax;
-    }
-    sc->cacc[sc->cur ^ 1][0] = 0ull;
-    sc->cacc[sc->cur ^ 1][1] = 0ull;
-    sc->active = 1;
-}
-
-__global__ void k_step_end(DevScalars *sc) {
-    if (!sc->active) return;
-    sc->t = sc->t + sc->dt;
-    sc->steps = sc->steps + 1;
-    sc->cur ^= 1;
-}
+__global__ void k_step_end(DevScalars *sc) { step_end_dev(sc); }
 
 // conservation sums: per-block partial sums of rows, then a fixed-order final sum
 template <typename real>
@@ -514,7 +477,47 @@ StageArgs<real> stage_args(sacx_ctx *c) {
     a.hd_cross_on = c->params.hd_cross_on;
     a.sc = c->sc;
     for (int k = 0; k < NBG; ++k) a.BG[k] = (const real *)(c->grid.background_on ? c->BG[k] : nullptr);
+    if (c->sur_on) {
+        a.Rs = c->sur_r;
+        a.rs_pitch = (int)c->sur_pitch;
+        a.rs_plane = c->sur_pitch * c->L.ny;
+    }
     return a;
+}
+
+template <typename real>
+RatioArgs<real> ratio_args(sacx_ctx *c) {
+    RatioArgs<real> a;
+    for (int f = 0; f < NF; ++f) a.S[f] = (const real *)c->U[f];
+    a.L = c->L;
+    a.gm1 = c->kc.gm1;
+    a.igm1 = c->kc.igm1;
+    return a;
+}
+
+// surrogate refresh at a step start: predict the ratio planes from U (unless
+// the caller supplies them) and check them against the plain ratios of U
+int sur_refresh(sacx_ctx *c) {
+    int rc = fill_halo(c, c->U, NF, false);
+    if (rc) return rc;
+    const int nx = c->L.nx, ny = c->L.ny;
+    InputNorm nm;
+    for (int k = 0; k < 12; ++k) nm.v[k] = c->sur.norm[k];
+    const bool fp64 = c->grid.precision == SACX_FP64;
+    if (c->sur.d_packed) {
+        HIPCHK(fp64 ? launch_cnn_inputs<double>(ratio_args<double>(c), nm, c->sur_x, c->stream)
+                    : launch_cnn_inputs<float>(ratio_args<float>(c), nm, c->sur_x, c->stream));
+        HIPCHK(cnn_forward_dev(c->sur.d_packed, c->sur_x, 1, ny, nx, c->sur_a1, c->sur_a2, c->sur_a1, c->sur_r, 0,
+                               c->sur_pitch * ny, c->sur_pitch, c->stream));
+    }
+    HIPCHK(fp64 ? launch_hd_check<double>(ratio_args<double>(c), c->sur_r, c->sur_pitch, c->sur.bound, c->sur.tile,
+                                          c->sur_st, c->stream)
+                : launch_hd_check<float>(ratio_args<float>(c), c->sur_r, c->sur_pitch, c->sur.bound, c->sur.tile,
+                                         c->sur_st, c->stream));
+    const int64_t ntx = (nx + c->sur.tile - 1) / c->sur.tile, nty = (ny + c->sur.tile - 1) / c->sur.tile;
+    c->sur_refreshes += 1;
+    c->sur_tiles_checked += ntx * nty;
+    return SACX_OK;
 }
 
 template <typename real>
@@ -615,7 +618,7 @@ int sacx_create(const sacx_grid *grid, const sacx_params *params, void *d_ws, si
         return fail(SACX_ENOSPC, "workspace has %zu bytes, %zu needed", ws_bytes, P.total);
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
-    sacx_ctx *c = new (std::nothrow) sacx_ctx;
+    sacx_ctx *c = new (std::nothrow) sacx_ctx();
     if (!c) return fail(SACX_EINVAL, "out of host memory");
     std::memset((void *)c, 0, sizeof(*c));
     c->grid = *grid;
@@ -669,6 +672,8 @@ int sacx_create(const sacx_grid *grid, const sacx_params *params, void *d_ws, si
     }
     c->initialized = false;
     c->prof_on = false;
+    c->sur_on = false;
+    c->sur_r = nullptr;
     c->ev_pool = new (std::nothrow) std::vector<hipEvent_t>();
     c->ev_marks = new (std::nothrow) std::vector<std::pair<int, std::pair<int, int>>>();
     if (!c->ev_pool || !c->ev_marks) {
@@ -739,6 +744,9 @@ int sacx_profile_read(sacx_ctx *ctx, sacx_profile *out) {
         } else if (m.first == 4) {
             ctx->prof.ms_halo += ms;
             ctx->prof.n_halo += 1;
+        } else if (m.first == 6) {
+            ctx->prof.ms_surrogate += ms;
+            ctx->prof.n_surrogate += 1;
         } else {
             ctx->prof.ms_scalar += ms;
             ctx->prof.n_scalar += 1;
@@ -853,6 +861,13 @@ int sacx_advance(sacx_ctx *ctx, int32_t nsteps, double t_end, int32_t *steps_don
                 hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, ctx->stream, ctx->sc, t_end, sk);
             }
             int rc;
+            if (ctx->sur_on) {
+                if (ctx->sur_since % ctx->sur.refresh_every == 0) {
+                    ProfScope ps(ctx, 6);
+                    if ((rc = sur_refresh(ctx))) return rc;
+                }
+                ctx->sur_since += 1;
+            }
             if ((rc = stage(ctx, 1, ctx->U, nullptr, nullptr, ctx->B1, nullptr))) return rc;
             if ((rc = stage(ctx, 2, ctx->B1, ctx->U, nullptr, ctx->B2, ctx->A))) return rc;
             if ((rc = stage(ctx, 3, ctx->B2, ctx->U, nullptr, ctx->B1, nullptr))) return rc;
@@ -996,6 +1011,425 @@ int sacx_halo_pack(sacx_ctx *ctx, int32_t side, void *d_buf) { return halo_io(ct
 
 int sacx_halo_unpack(sacx_ctx *ctx, int32_t side, const void *d_buf) {
     return halo_io(ctx, side, const_cast<void *>(d_buf), false);
+}
+
+// ------------------------------------------------------------------ surrogate
+
+}  // extern "C"
+
+namespace {
+
+__global__ void k_fill_f32(float *p, int64_t n, float v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_zero_stats(HdDevStats *st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *st = HdDevStats{0ull, 0ull, 0ull, 0ull};
+}
+
+struct SurPlan {
+    int64_t pitch;
+    size_t off_r, off_st, off_x, off_a1, off_a2, total;
+};
+
+SurPlan sur_plan(const sacx_ctx *c) {
+    SurPlan p;
+    const int64_t nx = c->L.nx, ny = c->L.ny;
+    p.pitch = (int64_t)round_up((size_t)nx, 64);
+    size_t o = 0;
+    p.off_r = o;  o = round_up(o + (size_t)10 * p.pitch * ny * sizeof(float), kAlign);
+    p.off_st = o; o = round_up(o + sizeof(HdDevStats), kAlign);
+    p.off_x = o;  o = round_up(o + (size_t)nx * ny * 8 * 2, kAlign);
+    p.off_a1 = o; o = round_up(o + (size_t)nx * ny * 32 * 2, kAlign);
+    p.off_a2 = o; o = round_up(o + (size_t)nx * ny * 32 * 2, kAlign);
+    p.total = o;
+    return p;
+}
+
+int sur_supported(const sacx_ctx *c) {
+    if (!c->params.hd_on) return fail(SACX_EUNSUP, "the surrogate replaces hyper-diffusion ratios: hd_on must be 1");
+    if (c->grid.background_on) return fail(SACX_EUNSUP, "the surrogate needs a context without background");
+    for (int s = 0; s < 4; ++s)
+        if (c->bc[s] != SACX_PERIODIC) return fail(SACX_EUNSUP, "the surrogate needs periodic boundaries on every side");
+    if (c->L.ny < 2) return fail(SACX_EUNSUP, "the surrogate needs ny >= 2");
+    if (c->L.nx % 32 != 0) return fail(SACX_EUNSUP, "the surrogate needs nx to be a multiple of 32 (got %d)", c->L.nx);
+    return SACX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sacx_surrogate_workspace_size(const sacx_ctx *ctx, size_t *bytes) {
+    if (!ctx || !bytes) return fail(SACX_EINVAL, "ctx/bytes must not be NULL");
+    *bytes = sur_plan(ctx).total;
+    return SACX_OK;
+}
+
+int sacx_hd_set_surrogate(sacx_ctx *ctx, const sacx_surrogate *cfg, void *d_ws, size_t ws_bytes) {
+    if (!ctx || !cfg || !d_ws) return fail(SACX_EINVAL, "ctx/cfg/workspace must not be NULL");
+    int rc = sur_supported(ctx);
+    if (rc) return rc;
+    if (cfg->refresh_every < 1) return fail(SACX_EINVAL, "refresh_every must be >= 1");
+    if (cfg->tile < 1) return fail(SACX_EINVAL, "tile must be >= 1");
+    if (!(cfg->bound >= 0.0)) return fail(SACX_EINVAL, "bound must be >= 0");
+    for (int k = 0; k < 12; ++k)
+        if (!std::isfinite(cfg->norm[k])) return fail(SACX_EINVAL, "input normalisation must be finite");
+    if ((uintptr_t)d_ws % kAlign) return fail(SACX_EINVAL, "surrogate workspace must be 256-byte aligned");
+    if (cfg->d_packed && (uintptr_t)cfg->d_packed % 16) return fail(SACX_EINVAL, "packed weights must be 16-byte aligned");
+    const SurPlan p = sur_plan(ctx);
+    if (ws_bytes < p.total)
+        return fail(SACX_ENOSPC, "surrogate workspace too small (%zu < %zu bytes)", ws_bytes, p.total);
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    char *w = (char *)d_ws;
+    ctx->sur = *cfg;
+    ctx->sur_pitch = p.pitch;
+    ctx->sur_r = (float *)(w + p.off_r);
+    ctx->sur_st = (HdDevStats *)(w + p.off_st);
+    ctx->sur_x = w + p.off_x;
+    ctx->sur_a1 = w + p.off_a1;
+    ctx->sur_a2 = w + p.off_a2;
+    ctx->sur_since = 0;
+    ctx->sur_refreshes = 0;
+    ctx->sur_tiles_checked = 0;
+    const int64_t nr = (int64_t)10 * p.pitch * ctx->L.ny;
+    hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, ctx->stream, ctx->sur_r, nr, -1.0f);
+    hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, ctx->stream, ctx->sur_st);
+    HIPCHK(hipGetLastError());
+    ctx->sur_on = true;
+    return SACX_OK;
+}
+
+int sacx_hd_clear_surrogate(sacx_ctx *ctx) {
+    if (!ctx) return fail(SACX_EINVAL, "ctx must not be NULL");
+    ctx->sur_on = false;
+    ctx->sur_r = nullptr;
+    return SACX_OK;
+}
+
+int sacx_hd_ratio_buffer(sacx_ctx *ctx, float **d_r, int64_t *pitch) {
+    if (!ctx || !d_r || !pitch) return fail(SACX_EINVAL, "ctx/d_r/pitch must not be NULL");
+    if (!ctx->sur_on) return fail(SACX_ESTATE, "the surrogate is not set");
+    *d_r = ctx->sur_r;
+    *pitch = ctx->sur_pitch;
+    return SACX_OK;
+}
+
+int sacx_hd_read_stats(sacx_ctx *ctx, sacx_hd_stats *out) {
+    if (!ctx || !out) return fail(SACX_EINVAL, "ctx/out must not be NULL");
+    if (!ctx->sur_on) return fail(SACX_ESTATE, "the surrogate is not set");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    HdDevStats h;
+    HIPCHK(hipMemcpyAsync(&h, ctx->sur_st, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    out->refreshes = ctx->sur_refreshes;
+    out->tiles_checked = ctx->sur_tiles_checked;
+    out->tiles_fallback = (int64_t)h.tiles_fallback;
+    double eu, ea;
+    std::memcpy(&eu, &h.err_used, sizeof(eu));
+    std::memcpy(&ea, &h.err_all, sizeof(ea));
+    out->err_used = eu;
+    out->err_all = ea;
+    return SACX_OK;
+}
+
+int sacx_cnn_inputs(sacx_ctx *ctx, const float norm[12], void *d_x) {
+    if (!ctx || !norm || !d_x) return fail(SACX_EINVAL, "ctx/norm/x must not be NULL");
+    if (!ctx->initialized) return fail(SACX_ESTATE, "sacx_init_state has not been called");
+    if (ctx->grid.background_on) return fail(SACX_EUNSUP, "network inputs need a context without background");
+    if ((uintptr_t)d_x % 16) return fail(SACX_EINVAL, "input buffer must be 16-byte aligned");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    InputNorm nm;
+    for (int k = 0; k < 12; ++k) nm.v[k] = norm[k];
+    HIPCHK(ctx->grid.precision == SACX_FP64 ? launch_cnn_inputs<double>(ratio_args<double>(ctx), nm, d_x, ctx->stream)
+                                            : launch_cnn_inputs<float>(ratio_args<float>(ctx), nm, d_x, ctx->stream));
+    return SACX_OK;
+}
+
+int sacx_hd_ratio_fields(sacx_ctx *ctx, float *d_r, int64_t pitch) {
+    if (!ctx || !d_r) return fail(SACX_EINVAL, "ctx/d_r must not be NULL");
+    if (!ctx->initialized) return fail(SACX_ESTATE, "sacx_init_state has not been called");
+    if (ctx->grid.background_on) return fail(SACX_EUNSUP, "ratio fields need a context without background");
+    if (pitch < ctx->L.nx) return fail(SACX_EINVAL, "pitch must be >= nx");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    int rc = fill_halo(ctx, ctx->U, NF, false);
+    if (rc) return rc;
+    HIPCHK(ctx->grid.precision == SACX_FP64 ? launch_ratio_fields<double>(ratio_args<double>(ctx), d_r, pitch, ctx->stream)
+                                            : launch_ratio_fields<float>(ratio_args<float>(ctx), d_r, pitch, ctx->stream));
+    return SACX_OK;
+}
+
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+
+struct sacx_batch {
+    int n;
+    int precision;
+    int device;
+    hipStream_t stream;
+    std::vector<sacx_ctx *> *ctx;
+    char *tab;          // BatchInst array
+    long long *gbeg;    // n + 1
+    int *ctr;           // work-queue counters
+    int ctr_cap;
+    BatchItem *items;
+    int items_cap;
+    int nitems;
+    int nt;
+    std::vector<int> *rows;
+    bool dirty;
+    int blocks;
+};
+
+namespace {
+
+constexpr int kBatchCtr = 4 * 512;  // counters for up to 512 steps per launch
+constexpr size_t kInstBytes = sizeof(BatchInst<double>) > sizeof(BatchInst<float>) ? sizeof(BatchInst<double>)
+                                                                                    : sizeof(BatchInst<float>);
+
+int64_t batch_items_bound(int n, const sacx_grid *g) {
+    int64_t t = 0;
+    for (int i = 0; i < n; ++i) {
+        const int64_t xt = (g[i].nx + 57) / 58;
+        t += g[i].ny == 1 ? xt : xt * g[i].ny;
+    }
+    return t;
+}
+
+struct BatchPlan {
+    size_t off_tab, off_gbeg, off_ctr, off_items, off_inst, total;
+    std::vector<size_t> inst_off, inst_bytes;
+};
+
+int batch_plan(int n, const sacx_grid *grids, const sacx_params *params, BatchPlan *P) {
+    if (n < 1 || n > 65536) return fail(SACX_EINVAL, "batch size must be 1..65536");
+    if (!grids || !params) return fail(SACX_EINVAL, "grids/params must not be NULL");
+    P->inst_off.resize(n);
+    P->inst_bytes.resize(n);
+    for (int i = 0; i < n; ++i) {
+        int rc = check_grid(&grids[i], &params[i]);
+        if (rc) return rc;
+        if (grids[i].precision != grids[0].precision) return fail(SACX_EINVAL, "all batch instances need one precision");
+        if (grids[i].background_on) return fail(SACX_EUNSUP, "batched instances have no background");
+        if (grids[i].nx < G) return fail(SACX_EUNSUP, "batched instances need nx >= %d", G);
+        if (!params[i].hd_on) return fail(SACX_EUNSUP, "batched instances run with hyper-diffusion on");
+        P->inst_bytes[i] = make_plan(&grids[i]).total;
+    }
+    size_t off = 0;
+    P->off_tab = off; off += round_up((size_t)n * kInstBytes, kAlign);
+    P->off_gbeg = off; off += round_up((size_t)(n + 1) * sizeof(long long), kAlign);
+    P->off_ctr = off; off += round_up((size_t)kBatchCtr * sizeof(int), kAlign);
+    P->off_items = off; off += round_up((size_t)batch_items_bound(n, grids) * sizeof(BatchItem), kAlign);
+    P->off_inst = off;
+    for (int i = 0; i < n; ++i) { P->inst_off[i] = off; off += round_up(P->inst_bytes[i], kAlign); }
+    P->total = off;
+    return SACX_OK;
+}
+
+__global__ void k_zero_ints(int *p, int n) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+template <typename real>
+int batch_build(sacx_batch *b) {
+    const int n = b->n;
+    const int TX = b->nt - 2 * G;
+    std::vector<BatchInst<real>> tab(n);
+    std::vector<long long> gbeg(n + 1, 0);
+    struct Costed { int64_t cost; BatchItem it; };
+    std::vector<Costed> items;
+    for (int i = 0; i < n; ++i) {
+        sacx_ctx *c = (*b->ctx)[i];
+        BatchInst<real> &I = tab[i];
+        std::memset((void *)&I, 0, sizeof(I));
+        void *const *S[4] = {c->U, c->B1, c->B2, c->B1};
+        void *const *U[4] = {c->U, c->U, c->U, c->U};
+        void *const *A[4] = {c->A, c->A, c->A, c->A};
+        void *const *O1[4] = {c->B1, c->B2, c->B1, c->U};
+        void *const *O2[4] = {c->B1, c->A, c->B1, c->U};
+        for (int st = 0; st < 4; ++st) {
+            StageArgs<real> a = stage_args<real>(c);
+            a.nt = b->nt;
+            a.ty = (*b->rows)[i];
+            for (int f = 0; f < NF; ++f) {
+                a.S[f] = (const real *)S[st][f];
+                a.U[f] = (const real *)U[st][f];
+                a.A[f] = (const real *)A[st][f];
+                a.out1[f] = (real *)O1[st][f];
+                a.out2[f] = (real *)O2[st][f];
+            }
+            I.st[st] = a;
+        }
+        I.sk.cfl = c->params.cfl;
+        I.sk.dx = c->dx;
+        I.sk.dy = c->dy;
+        for (int m = 0; m < 4; ++m) I.sk.c2[m] = c->params.c2[m];
+        I.sk.ax = c->grid.nx > 1;
+        I.sk.ay = c->grid.ny > 1;
+        I.sc = c->sc;
+        I.L = c->L;
+        I.periodic_x = c->bc[0] == SACX_PERIODIC;
+        I.periodic_y = c->bc[2] == SACX_PERIODIC;
+        I.oned = (c->grid.ny == 1 && c->grid.nx >= 2) ? 1 : 0;
+        const long long W = c->L.nx + 2 * G;
+        gbeg[i + 1] = gbeg[i] + (long long)NF * (2LL * G * W + 2LL * G * c->L.ny);
+        const int xt = (c->L.nx + TX - 1) / TX;
+        if (I.oned) {
+            for (int x = 0; x < xt; ++x) items.push_back({1, {i, x, 0, 0}});
+        } else {
+            const int ty = (*b->rows)[i];
+            const int yt = (c->L.ny + ty - 1) / ty;
+            for (int y = 0; y < yt; ++y) {
+                const int rows = std::min(ty, c->L.ny - y * ty);
+                for (int x = 0; x < xt; ++x) items.push_back({(int64_t)rows + 2 * G, {i, x, y, 0}});
+            }
+        }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Costed &p, const Costed &q) { return p.cost > q.cost; });
+    if ((int64_t)items.size() > b->items_cap) return fail(SACX_ENOSPC, "batch work list exceeds its bound");
+    std::vector<BatchItem> flat(items.size());
+    for (size_t k = 0; k < items.size(); ++k) flat[k] = items[k].it;
+    b->nitems = (int)flat.size();
+    HIPCHK(hipMemcpyAsync(b->tab, tab.data(), sizeof(BatchInst<real>) * n, hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->gbeg, gbeg.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipMemcpyAsync(b->items, flat.data(), sizeof(BatchItem) * flat.size(), hipMemcpyHostToDevice, b->stream));
+    // host vectors go out of scope: finish the copies first
+    HIPCHK(hipStreamSynchronize(b->stream));
+    int per_cu = 0, cus = 0;
+    HIPCHK(batch_blocks_per_cu<real>(b->nt, &per_cu));
+    HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device));
+    if (per_cu < 1) return fail(SACX_EUNSUP, "batched kernel does not fit on a compute unit with %d threads", b->nt);
+    b->blocks = per_cu * cus;
+    b->dirty = false;
+    return SACX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sacx_batch_workspace_size(int32_t n, const sacx_grid *grids, const sacx_params *params, size_t *bytes) {
+    if (!bytes) return fail(SACX_EINVAL, "bytes must not be NULL");
+    BatchPlan P;
+    int rc = batch_plan(n, grids, params, &P);
+    if (rc) return rc;
+    *bytes = P.total;
+    return SACX_OK;
+}
+
+int sacx_batch_destroy(sacx_batch *b) {
+    if (!b) return SACX_OK;
+    if (b->ctx)
+        for (sacx_ctx *c : *b->ctx) sacx_destroy(c);
+    delete b->ctx;
+    delete b->rows;
+    delete b;
+    return SACX_OK;
+}
+
+int sacx_batch_create(int32_t n, const sacx_grid *grids, const sacx_params *params, const int32_t *bc, void *d_ws,
+                      size_t ws_bytes, void *hip_stream, sacx_batch **out) {
+    if (!out) return fail(SACX_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    BatchPlan P;
+    int rc = batch_plan(n, grids, params, &P);
+    if (rc) return rc;
+    if (!d_ws || ((uintptr_t)d_ws) % kAlign) return fail(SACX_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+    if (ws_bytes < P.total) return fail(SACX_ENOSPC, "workspace has %zu bytes, %zu needed", ws_bytes, P.total);
+    sacx_batch *b = new (std::nothrow) sacx_batch;
+    if (!b) return fail(SACX_EINVAL, "out of host memory");
+    std::memset((void *)b, 0, sizeof(*b));
+    b->ctx = new (std::nothrow) std::vector<sacx_ctx *>();
+    b->rows = new (std::nothrow) std::vector<int>();
+    if (!b->ctx || !b->rows) { sacx_batch_destroy(b); return fail(SACX_EINVAL, "out of host memory"); }
+    b->n = n;
+    b->precision = grids[0].precision;
+    b->stream = (hipStream_t)hip_stream;
+    HIPCHK(hipGetDevice(&b->device));
+    char *ws = (char *)d_ws;
+    b->tab = ws + P.off_tab;
+    b->gbeg = (long long *)(ws + P.off_gbeg);
+    b->ctr = (int *)(ws + P.off_ctr);
+    b->ctr_cap = kBatchCtr;
+    b->items = (BatchItem *)(ws + P.off_items);
+    b->items_cap = (int)batch_items_bound(n, grids);
+    b->nt = b->precision == SACX_FP64 ? 128 : 256;
+    for (int i = 0; i < n; ++i) {
+        sacx_ctx *c = nullptr;
+        rc = sacx_create(&grids[i], &params[i], ws + P.inst_off[i], P.inst_bytes[i], hip_stream, &c);
+        if (rc) { sacx_batch_destroy(b); return rc; }
+        b->ctx->push_back(c);
+        if (bc) {
+            rc = sacx_set_boundaries(c, bc + 4 * i);
+            if (rc) { sacx_batch_destroy(b); return rc; }
+        }
+        b->rows->push_back(grids[i].ny == 1 ? 1 : std::min(64, grids[i].ny));
+    }
+    b->dirty = true;
+    *out = b;
+    return SACX_OK;
+}
+
+int sacx_batch_context(sacx_batch *b, int32_t i, sacx_ctx **out) {
+    if (!b || !out) return fail(SACX_EINVAL, "batch/out must not be NULL");
+    if (i < 0 || i >= b->n) return fail(SACX_EINVAL, "instance %d out of range", i);
+    *out = (*b->ctx)[i];
+    return SACX_OK;
+}
+
+int sacx_batch_set_tiles(sacx_batch *b, int32_t threads, const int32_t *rows) {
+    if (!b) return fail(SACX_EINVAL, "batch must not be NULL");
+    if (threads != 0 && threads != 64 && threads != 128 && threads != 256)
+        return fail(SACX_EINVAL, "threads must be 64, 128 or 256");
+    if (rows)
+        for (int i = 0; i < b->n; ++i)
+            if (rows[i] < 1 || rows[i] > 4096) return fail(SACX_EINVAL, "rows[%d] = %d out of 1..4096", i, rows[i]);
+    if (threads) b->nt = threads;
+    if (rows)
+        for (int i = 0; i < b->n; ++i) (*b->rows)[i] = (*b->ctx)[i]->grid.ny == 1 ? 1 : rows[i];
+    b->dirty = true;
+    return SACX_OK;
+}
+
+int sacx_batch_advance(sacx_batch *b, int32_t nsteps, int32_t sync) {
+    if (!b) return fail(SACX_EINVAL, "batch must not be NULL");
+    if (nsteps < 0) return fail(SACX_EINVAL, "nsteps must be >= 0");
+    for (sacx_ctx *c : *b->ctx)
+        if (!c->initialized) return fail(SACX_ESTATE, "every batch instance needs sacx_init_state first");
+    DeviceGuard dg(b->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the batch device");
+    if (b->dirty) {
+        int rc = b->precision == SACX_FP64 ? batch_build<double>(b) : batch_build<float>(b);
+        if (rc) return rc;
+    }
+    const int per_launch = b->ctr_cap / 4;
+    for (int done = 0; done < nsteps; done += per_launch) {
+        const int k = std::min(per_launch, nsteps - done);
+        hipLaunchKernelGGL(k_zero_ints, dim3(8), dim3(256), 0, b->stream, b->ctr, 4 * k);
+        if (b->precision == SACX_FP64) {
+            BatchArgs<double> a{(const BatchInst<double> *)b->tab, b->n, b->items, b->nitems, b->gbeg, b->ctr, k};
+            HIPCHK(launch_batch<double>(a, b->nt, b->blocks, b->stream));
+        } else {
+            BatchArgs<float> a{(const BatchInst<float> *)b->tab, b->n, b->items, b->nitems, b->gbeg, b->ctr, k};
+            HIPCHK(launch_batch<float>(a, b->nt, b->blocks, b->stream));
+        }
+    }
+    if (sync) {
+        HIPCHK(hipStreamSynchronize(b->stream));
+        for (sacx_ctx *c : *b->ctx) {
+            int np = 0;
+            HIPCHK(hipMemcpy(&np, &c->sc->nonphys, sizeof(int), hipMemcpyDeviceToHost));
+            if (np) return fail(SACX_ENONPHYS, "a batch instance reached a non-physical state");
+        }
+    }
+    return SACX_OK;
 }
 
 }  // extern "C"

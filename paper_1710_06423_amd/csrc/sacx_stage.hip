@@ -41,6 +41,8 @@
 // hyper-diffusion coefficient, a ratio of maxima of differences, amplifies
 // any rounding difference by many orders of magnitude over a run, so the
 // FP64 results are reproduced bit for bit instead of to a tolerance.
+#include <hip/hip_cooperative_groups.h>
+
 #include "sacx_internal.h"
 
 namespace sacx {
@@ -73,8 +75,24 @@ struct Row6 {
     real v[NF];
 };
 
-template <typename real, int NT, int STAGE, bool HD, bool BG>
-__global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
+// LDS of one tile (shared by the 2-D and 1-D tile functions, and by every
+// stage instantiation inside the batched kernel)
+template <typename real, int NT>
+struct TileLds {
+    real fx[5][NT];        // x fluxes of the newest row
+    real q[2][NQ][NT];     // row buffers (rows r and r-1)
+    real s[NT];            // compression s of row r-1
+    real gx[2][3][NT];     // x-face G(v_y), G(B~_y), ring over rows (mod 3)
+    real gy[2][2][NT];     // y-face G(v_x), G(B~_x), ring over faces (mod 2)
+    real hx[5][NT];        // x-face fluxes H_x of row r-3
+    double red[3][NT / 64];  // stage-4 wave-speed reduction
+};
+
+// One tile of the stage: columns [tx*TX, tx*TX + TX), rows of strip ty.
+// Called by the per-subdomain kernel (one tile per block) and by the batched
+// persistent kernel (tiles of many subdomains from a work queue).
+template <typename real, int NT, int STAGE, bool HD, bool BG, bool SUR = false>
+__device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x, int tile_y, TileLds<real, NT> &lds) {
     constexpr int TX = NT - 2 * G;
     const DevScalars *sc = a.sc;
     if (!sc->active) return;
@@ -91,10 +109,10 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
 
     const Layout L = a.L;
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TX;
+    const int x0 = tile_x * TX;
     const int c = x0 - G + tid;
     const bool colv = c < L.nx + G;
-    const int y0 = blockIdx.y * a.ty;
+    const int y0 = tile_y * a.ty;
     const int y1 = min(y0 + a.ty, L.ny);
     const bool outcol = tid >= G && tid < NT - G && c < L.nx;
     const bool cross = a.hd_cross_on != 0;
@@ -106,15 +124,17 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
     const int tp2 = tid + 2 < NT ? tid + 2 : NT - 1;
     const int tp3 = tid + 3 < NT ? tid + 3 : NT - 1;
 
-    __shared__ real sh_fx[5][NT];        // x fluxes of row r
-    __shared__ real sh_q[2][NQ][NT];     // row buffers of rows r (slot r&1) and r-1
-    __shared__ real sh_s[NT];            // compression s of row r-1
-    __shared__ real sh_gx[2][3][NT];     // x-face G(v_y), G(B~_y), ring over rows (mod 3)
-    __shared__ real sh_gy[2][2][NT];     // y-face G(v_x), G(B~_x), ring over faces (mod 2)
-    __shared__ real sh_hx[5][NT];        // x-face fluxes H_x of row r-3
+    auto &sh_fx = lds.fx;
+    auto &sh_q = lds.q;
+    auto &sh_s = lds.s;
+    auto &sh_gx = lds.gx;
+    auto &sh_gy = lds.gy;
+    auto &sh_hx = lds.hx;
 
     const int64_t colofs = (int64_t)L.xoff + (colv ? c : L.nx + G - 1);
     const int rbeg = y0 - G, rend = y1 - 1 + G;
+    // surrogate: this column's periodic image in the ratio planes
+    const int cw = SUR ? ((c % L.nx) + L.nx) % L.nx : 0;
 
     // ---------------- per-thread windows (column-local data) ----------------
     real qw[5][6];       // y-face set {rho~, eps~, v_x, v_y, B~_x}, rows r-5..r
@@ -183,6 +203,18 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
                 if (STAGE == 2 || STAGE == 3) pU.v[f] = a.U[f][oo];
                 if (STAGE == 4) pU.v[f] = a.A[f][oo];
             }
+        }
+        // surrogate ratios of this iteration's faces: x faces of row r-1,
+        // y faces (r-3)+1/2 (periodic images)
+        float rsx[5], rsy[5];
+        if (SUR) {
+            int jx = (r - 1) % L.ny, jy = (r - 3) % L.ny;
+            jx += jx < 0 ? L.ny : 0;
+            jy += jy < 0 ? L.ny : 0;
+            const float *px_ = a.Rs + (int64_t)jx * a.rs_pitch + cw;
+            const float *py_ = a.Rs + 5 * a.rs_plane + (int64_t)jy * a.rs_pitch + cw;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) { rsx[k] = px_[k * a.rs_plane]; rsy[k] = py_[k * a.rs_plane]; }
         }
         const int slot = r & 1, pslot = slot ^ 1;
         // ================= A: row r =================
@@ -285,9 +317,13 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
                 const int cl = qclass(k);
-                const real q0 = sh_q[pslot][k][tm2], q1 = sh_q[pslot][k][tm1], q2 = sh_q[pslot][k][tid];
-                const real q3 = sh_q[pslot][k][tp1], q4 = sh_q[pslot][k][tp2], q5 = sh_q[pslot][k][tp3];
-                const real R = hd_ratio(q0, q1, q2, q3, q4, q5);
+                const real q2 = sh_q[pslot][k][tid], q3 = sh_q[pslot][k][tp1];
+                real R;
+                if (SUR && rsx[k] >= 0.0f)
+                    R = (real)rsx[k];
+                else
+                    R = hd_ratio(sh_q[pslot][k][tm2], sh_q[pslot][k][tm1], q2, q3, sh_q[pslot][k][tp2],
+                                 sh_q[pslot][k][tp3]);
                 const real nu = kx2[cl] * R + (real)kc.kxs[cl] * sfx;
                 gxn[k] = nu * (q3 - q2) * idx;
             }
@@ -299,7 +335,11 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
 #pragma unroll
             for (int k = 0; k < 5; ++k) {
                 const int cl = qclass(k);
-                const real R = hd_ratio(qw[k][0], qw[k][1], qw[k][2], qw[k][3], qw[k][4], qw[k][5]);
+                real R;
+                if (SUR && rsy[k] >= 0.0f)
+                    R = (real)rsy[k];
+                else
+                    R = hd_ratio(qw[k][0], qw[k][1], qw[k][2], qw[k][3], qw[k][4], qw[k][5]);
                 const real nu = ky2[cl] * R + (real)kc.kys[cl] * sfy;
                 gyn[k] = nu * (qw[k][3] - qw[k][2]) * idy;
             }
@@ -440,7 +480,7 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
 
     if (STAGE == 4) {
         // block reduction of the wave speeds, one atomic per block
-        __shared__ double red[3][NT / 64];
+        auto &red = lds.red;
         for (int off = 32; off > 0; off >>= 1) {
             cx_t = fmax(cx_t, __shfl_xor(cx_t, off));
             cy_t = fmax(cy_t, __shfl_xor(cy_t, off));
@@ -461,10 +501,225 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// One-dimensional subdomains (ny = 1, y periodic): every y difference of the
+// defining sequence is an exact zero, so the y half of the pipeline is not
+// computed; those zeros still enter the sums exactly where the defining
+// sequence adds them, so the results are the same bits as the 2-D path.
+// A tile is TX columns of the single row.
+// ---------------------------------------------------------------------------
+template <typename real, int NT, int STAGE, bool HD>
+__device__ __forceinline__ void stage_tile_1d(const StageArgs<real> &a, int tile_x, TileLds<real, NT> &lds) {
+    constexpr int TX = NT - 2 * G;
+    const DevScalars *sc = a.sc;
+    if (!sc->active) return;
+    const real dt = (real)sc->dt, hdt = (real)sc->hdt, dt6 = (real)sc->dt6;
+    real kx2[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) kx2[k] = (real)sc->kx2[k];
+    const SchemeConsts &kc = a.k;
+    const real gamma = (real)kc.gamma, gm1 = (real)kc.gm1, igm1 = (real)kc.igm1;
+    const real i12dx = (real)kc.i12dx, idx = (real)kc.idx, i2dx = (real)kc.i2dx, third = (real)kc.third;
+    const real half = (real)0.5, two = (real)2, eight = (real)8, zero = (real)0;
+    const Layout L = a.L;
+    const int tid = threadIdx.x;
+    const int c = tile_x * TX - G + tid;
+    const bool colv = c < L.nx + G;
+    const bool outcol = tid >= G && tid < NT - G && c < L.nx;
+    const int tm1 = tid >= 1 ? tid - 1 : 0;
+    const int tm2 = tid >= 2 ? tid - 2 : 0;
+    const int tp1 = tid + 1 < NT ? tid + 1 : NT - 1;
+    const int tp2 = tid + 2 < NT ? tid + 2 : NT - 1;
+    const int tp3 = tid + 3 < NT ? tid + 3 : NT - 1;
+    auto &sh_fx = lds.fx;
+    auto &sh_q = lds.q[0];
+    auto &sh_s = lds.s;
+    auto &sh_hx = lds.hx;
+    // row 0 of the subdomain (interior row)
+    const int64_t ro = (int64_t)L.xoff + (colv ? c : L.nx + G - 1) + (int64_t)G * L.pitch;
+    const int64_t oo = (int64_t)L.xoff + c + (int64_t)G * L.pitch;
+    Row6<real> pS, pU;
+    if (outcol) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            if (STAGE != 3) pS.v[f] = a.S[f][oo];
+            if (STAGE == 2 || STAGE == 3) pU.v[f] = a.U[f][oo];
+            if (STAGE == 4) pU.v[f] = a.A[f][oo];
+        }
+    }
+    const real rt = a.S[0][ro], mx = a.S[1][ro], my = a.S[2][ro], et = a.S[3][ro], bxt = a.S[4][ro], byt = a.S[5][ro];
+    const real rho = zero + rt;
+    const real irho = (real)1 / rho;
+    const real vx = mx * irho, vy = my * irho;
+    const real kin = half * (mx * vx + my * vy);
+    const real bbdot = zero * bxt + zero * byt;
+    const real bt2 = bxt * bxt + byt * byt;
+    const real pk = gm1 * (((et - kin) - bbdot) - half * bt2);
+    const real pt = (pk + half * bt2) + bbdot;
+    const real eps = pk * igm1;
+    const real bxT = zero + bxt, byT = zero + byt;
+    const real bvt = bxt * vx + byt * vy;
+    const real bvb = zero * vx + zero * vy;
+    const real ef = et + zero + pt;
+    sh_fx[CR][tid] = mx;
+    sh_fx[CMX][tid] = (vx * mx - (bxt * bxt + two * bxt * zero)) + pt;
+    sh_fx[CMY][tid] = vx * my - (bxt * byt + bxt * zero + zero * byt);
+    sh_fx[CE][tid] = ((vx * ef - bxt * bvt) - bxt * bvb) - zero * bvt;
+    sh_fx[CB][tid] = vx * byT - bxT * vy;
+    sh_q[QR][tid] = rt;
+    sh_q[QE][tid] = eps;
+    sh_q[QVX][tid] = vx;
+    sh_q[QVY][tid] = vy;
+    sh_q[QB][tid] = byt;
+    sh_q[QRHO][tid] = rho;
+    sh_q[QBYT][tid] = byT;
+    __syncthreads();
+    real K[6];
+    {
+        real dxn[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            dxn[k] = (eight * (sh_fx[k][tp1] - sh_fx[k][tm1]) - (sh_fx[k][tp2] - sh_fx[k][tm2])) * i12dx;
+        // D_y of any flux is an exact +0 (identical rows)
+        K[0] = -(dxn[CR] + zero);
+        K[1] = -(dxn[CMX] + zero);
+        K[2] = -(dxn[CMY] + zero);
+        K[3] = -(dxn[CE] + zero);
+        K[4] = -(zero + zero);
+        K[5] = -(dxn[CB] + zero);
+    }
+    if (HD) {
+        const real dv = (sh_q[QVX][tp1] - sh_q[QVX][tm1]) * i2dx + zero;
+        const real s_c = fmax(zero, -dv);
+        sh_s[tid] = s_c;
+        __syncthreads();
+        const real sfx = fmax(s_c, sh_s[tp1]);
+        real gx[5];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const int cl = qclass(k);
+            const real q0 = sh_q[k][tm2], q1 = sh_q[k][tm1], q2 = sh_q[k][tid];
+            const real q3 = sh_q[k][tp1], q4 = sh_q[k][tp2], q5 = sh_q[k][tp3];
+            const real R = hd_ratio(q0, q1, q2, q3, q4, q5);
+            const real nu = kx2[cl] * R + (real)kc.kxs[cl] * sfx;
+            gx[k] = nu * (q3 - q2) * idx;
+        }
+        const real rf = half * (sh_q[QRHO][tid] + sh_q[QRHO][tp1]);
+        const real vxf = half * (sh_q[QVX][tid] + sh_q[QVX][tp1]);
+        const real vyf = half * (sh_q[QVY][tid] + sh_q[QVY][tp1]);
+        const real byf = half * (sh_q[QBYT][tid] + sh_q[QBYT][tp1]);
+        // the four-face averages of y-face G vanish exactly (G_y = +0)
+        const real txx = rf * gx[QVX];
+        const real txy = half * rf * (gx[QVY] + zero);
+        const real ez = gx[QB] - zero;
+        sh_hx[CR][tid] = gx[QR];
+        sh_hx[CMX][tid] = txx;
+        sh_hx[CMY][tid] = txy;
+        sh_hx[CE][tid] = (gx[QE] + (vxf * txx + vyf * txy)) + byf * ez;
+        sh_hx[CB][tid] = ez;
+        __syncthreads();
+        // H_y is the same on both y faces of the row: its difference is +0
+        K[0] = K[0] + ((sh_hx[CR][tid] - sh_hx[CR][tm1]) * idx + zero);
+        K[1] = K[1] + ((sh_hx[CMX][tid] - sh_hx[CMX][tm1]) * idx + zero);
+        K[2] = K[2] + ((sh_hx[CMY][tid] - sh_hx[CMY][tm1]) * idx + zero);
+        K[3] = K[3] + ((sh_hx[CE][tid] - sh_hx[CE][tm1]) * idx + zero);
+        K[4] = K[4] + (zero + zero);
+        K[5] = K[5] + ((sh_hx[CB][tid] - sh_hx[CB][tm1]) * idx + zero);
+    }
+    double cx_t = 0.0, cy_t = 0.0;
+    int bad_t = 0;
+    if (outcol) {
+        if (STAGE == 1) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) a.out1[f][oo] = pS.v[f] + hdt * K[f];
+        } else if (STAGE == 2) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const real u = pU.v[f], s = pS.v[f];
+                a.out1[f][oo] = u + hdt * K[f];
+                a.out2[f][oo] = (u + u) + ((s - u) + dt * K[f]);
+            }
+        } else if (STAGE == 3) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) a.out1[f][oo] = pU.v[f] + dt * K[f];
+        } else {
+            real un[6];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const real av = pU.v[f], s = pS.v[f];
+                un[f] = (s + (av - (s + s)) * third) + dt6 * K[f];
+                a.out1[f][oo] = un[f];
+            }
+            const real r0 = zero + un[0];
+            const real ir0 = (real)1 / r0;
+            const real ux = un[1] * ir0, uy = un[2] * ir0;
+            const real kn = half * (un[1] * ux + un[2] * uy);
+            const real bbd = zero * un[4] + zero * un[5];
+            const real b2t = un[4] * un[4] + un[5] * un[5];
+            const real pkt = gm1 * (((un[3] - kn) - bbd) - half * b2t);
+            const real b2b = zero * zero + zero * zero;
+            const real pkb = gm1 * (zero - half * b2b);
+            const real pkk = pkb + pkt;
+            const real bxx = zero + un[4], byy = zero + un[5];
+            const real cf = sqrt((gamma * pkk + (bxx * bxx + byy * byy)) * ir0);
+            const bool fin = isfinite(un[0]) && isfinite(un[1]) && isfinite(un[2]) && isfinite(un[3]) &&
+                             isfinite(un[4]) && isfinite(un[5]) && isfinite(cf);
+            if (!(r0 > (real)0) || !(pkk > (real)0) || !fin) {
+                bad_t = 1;
+            } else {
+                cx_t = fmax(cx_t, (double)(fabs(ux) + cf));
+                cy_t = fmax(cy_t, (double)(fabs(uy) + cf));
+            }
+        }
+    }
+    if (STAGE == 4) {
+        auto &red = lds.red;
+        for (int off = 32; off > 0; off >>= 1) {
+            cx_t = fmax(cx_t, __shfl_xor(cx_t, off));
+            cy_t = fmax(cy_t, __shfl_xor(cy_t, off));
+            bad_t |= __shfl_xor(bad_t, off);
+        }
+        const int w = tid >> 6;
+        if ((tid & 63) == 0) { red[0][w] = cx_t; red[1][w] = cy_t; red[2][w] = (double)bad_t; }
+        __syncthreads();
+        if (tid == 0) {
+            double mx_ = 0.0, my_ = 0.0, bb = 0.0;
+            for (int k = 0; k < NT / 64; ++k) { mx_ = fmax(mx_, red[0][k]); my_ = fmax(my_, red[1][k]); bb = fmax(bb, red[2][k]); }
+            DevScalars *scw = a.sc;
+            const int nslot = scw->cur ^ 1;
+            atomicMax(&scw->cacc[nslot][0], (unsigned long long)__double_as_longlong(mx_));
+            atomicMax(&scw->cacc[nslot][1], (unsigned long long)__double_as_longlong(my_));
+            if (bb > 0.0) atomicOr(&scw->nonphys, 1);
+        }
+    }
+}
+
+template <typename real, int NT, int STAGE, bool HD, bool BG, bool SUR = false>
+__global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
+    __shared__ TileLds<real, NT> lds;
+    stage_tile<real, NT, STAGE, HD, BG, SUR>(a, blockIdx.x, blockIdx.y, lds);
+}
+
+template <typename real, int NT, int STAGE, bool HD>
+__global__ __launch_bounds__(NT) void k_stage_1d(StageArgs<real> a) {
+    __shared__ TileLds<real, NT> lds;
+    stage_tile_1d<real, NT, STAGE, HD>(a, blockIdx.x, lds);
+}
+
 template <typename real, int NT, int STAGE>
 static hipError_t launch_s(bool hd, bool bg, const StageArgs<real> &a, hipStream_t s) {
     constexpr int TX = NT - 2 * G;
+    if (a.L.ny == 1 && a.L.nx >= 2 && !bg) {
+        dim3 grid((a.L.nx + TX - 1) / TX, 1);
+        if (hd) hipLaunchKernelGGL((k_stage_1d<real, NT, STAGE, true>), grid, dim3(NT), 0, s, a);
+        else hipLaunchKernelGGL((k_stage_1d<real, NT, STAGE, false>), grid, dim3(NT), 0, s, a);
+        return hipGetLastError();
+    }
     dim3 grid((a.L.nx + TX - 1) / TX, (a.L.ny + a.ty - 1) / a.ty);
+    if (a.Rs && hd && !bg) {
+        hipLaunchKernelGGL((k_stage<real, NT, STAGE, true, false, true>), grid, dim3(NT), 0, s, a);
+        return hipGetLastError();
+    }
     if (hd && bg) hipLaunchKernelGGL((k_stage<real, NT, STAGE, true, true>), grid, dim3(NT), 0, s, a);
     else if (hd) hipLaunchKernelGGL((k_stage<real, NT, STAGE, true, false>), grid, dim3(NT), 0, s, a);
     else if (bg) hipLaunchKernelGGL((k_stage<real, NT, STAGE, false, true>), grid, dim3(NT), 0, s, a);
@@ -493,5 +748,285 @@ hipError_t launch_stage(int stage, bool hd, bool bg, const StageArgs<real> &a, h
 
 template hipError_t launch_stage<double>(int, bool, bool, const StageArgs<double> &, hipStream_t);
 template hipError_t launch_stage<float>(int, bool, bool, const StageArgs<float> &, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Plain coefficient-ratio fields (the surrogate's training target and judge).
+// The quantities are formed from the state exactly as in the stage kernel
+// (same operations, same order, no background), so a ratio computed here is
+// the one the plain stage would use at that face.
+// ---------------------------------------------------------------------------
+
+// quantity sets at cell (i, j): q = {rho~, eps~, v_x, v_y, B~_y, B~_x}
+template <typename real>
+__device__ __forceinline__ void cell_quantities(const RatioArgs<real> &a, int i, int j, real q[6]) {
+    const int64_t o = (int64_t)a.L.xoff + i + (int64_t)(j + G) * a.L.pitch;
+    const real gm1 = (real)a.gm1, igm1 = (real)a.igm1, half = (real)0.5;
+    const real rb = 0, bxb = 0, byb = 0;
+    const real rt = a.S[0][o], mx = a.S[1][o], my = a.S[2][o], et = a.S[3][o], bxt = a.S[4][o], byt = a.S[5][o];
+    const real rho = rb + rt;
+    const real irho = (real)1 / rho;
+    const real vx = mx * irho, vy = my * irho;
+    const real kin = half * (mx * vx + my * vy);
+    const real bbdot = bxb * bxt + byb * byt;
+    const real bt2 = bxt * bxt + byt * byt;
+    const real pk = gm1 * (((et - kin) - bbdot) - half * bt2);
+    q[0] = rt; q[1] = pk * igm1; q[2] = vx; q[3] = vy; q[4] = byt; q[5] = bxt;
+}
+
+// the ten plain ratios of the faces above cell (i, j): R[k] x-face set k,
+// R[5 + k] y-face set k
+template <typename real>
+__device__ __forceinline__ void cell_ratios(const RatioArgs<real> &a, int i, int j, real R[10]) {
+    real qx[6][6], qy[6][6];   // [offset -2..3][quantity]
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+        cell_quantities(a, i - 2 + m, j, qx[m]);
+        if (m == 2) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) qy[m][k] = qx[m][k];
+        } else {
+            cell_quantities(a, i, j - 2 + m, qy[m]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int kx = k == 4 ? 4 : k, ky = k == 4 ? 5 : k;   // B~_y on x faces, B~_x on y faces
+        R[k] = hd_ratio(qx[0][kx], qx[1][kx], qx[2][kx], qx[3][kx], qx[4][kx], qx[5][kx]);
+        R[5 + k] = hd_ratio(qy[0][ky], qy[1][ky], qy[2][ky], qy[3][ky], qy[4][ky], qy[5][ky]);
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(256) void k_ratio_fields(RatioArgs<real> a, float *out, int64_t pitch) {
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= a.L.nx || j >= a.L.ny) return;
+    real R[10];
+    cell_ratios(a, i, j, R);
+    const int64_t plane = pitch * a.L.ny;
+#pragma unroll
+    for (int k = 0; k < 10; ++k) out[k * plane + (int64_t)j * pitch + i] = (float)R[k];
+}
+
+template <typename real>
+hipError_t launch_ratio_fields(const RatioArgs<real> &a, float *out, int64_t pitch, hipStream_t s) {
+    dim3 grid((a.L.nx + 63) / 64, (a.L.ny + 3) / 4);
+    hipLaunchKernelGGL(k_ratio_fields<real>, grid, dim3(256), 0, s, a, out, pitch);
+    return hipGetLastError();
+}
+
+// The surrogate check: one block per tile x tile cells.  A tile falls back
+// when any of its ratio-plane values r has NOT(|r - R_plain| <= bound) (a
+// non-finite prediction always fails); then the whole tile of every plane is
+// set to -1 (plain ratio).  Comparisons are in the working precision.
+template <typename real>
+__global__ __launch_bounds__(256) void k_hd_check(RatioArgs<real> a, float *rs, int64_t pitch, double bound,
+                                                  int tile, HdDevStats *st) {
+    __shared__ double s_err[4];
+    __shared__ int s_bad[4];
+    const int ntx = (a.L.nx + tile - 1) / tile;
+    const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+    const int i0 = tx * tile, j0 = ty * tile;
+    const int wx = min(tile, a.L.nx - i0), wy = min(tile, a.L.ny - j0);
+    const int64_t plane = pitch * a.L.ny;
+    const real b = (real)bound;
+    double emax = 0.0;
+    int bad = 0;
+    for (int c = threadIdx.x; c < wx * wy; c += 256) {
+        const int i = i0 + c % wx, j = j0 + c / wx;
+        real R[10];
+        cell_ratios(a, i, j, R);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            const real e = fabs((real)rs[k * plane + (int64_t)j * pitch + i] - R[k]);
+            if (!(e <= b)) bad = 1;
+            if (isfinite(e)) emax = fmax(emax, (double)e);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        emax = fmax(emax, __shfl_xor(emax, off));
+        bad |= __shfl_xor(bad, off);
+    }
+    if ((threadIdx.x & 63) == 0) { s_err[threadIdx.x >> 6] = emax; s_bad[threadIdx.x >> 6] = bad; }
+    __syncthreads();
+    const double et = fmax(fmax(s_err[0], s_err[1]), fmax(s_err[2], s_err[3]));
+    const int bt = s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3];
+    if (threadIdx.x == 0) {
+        atomicMax(&st->err_all, (unsigned long long)__double_as_longlong(et));
+        if (bt) atomicAdd(&st->tiles_fallback, 1ull);
+        else atomicMax(&st->err_used, (unsigned long long)__double_as_longlong(et));
+    }
+    if (bt) {
+        for (int c = threadIdx.x; c < wx * wy; c += 256) {
+            const int i = i0 + c % wx, j = j0 + c / wx;
+#pragma unroll
+            for (int k = 0; k < 10; ++k) rs[k * plane + (int64_t)j * pitch + i] = -1.0f;
+        }
+    }
+}
+
+template <typename real>
+hipError_t launch_hd_check(const RatioArgs<real> &a, float *rs, int64_t pitch, double bound, int tile,
+                           HdDevStats *st, hipStream_t s) {
+    const int ntx = (a.L.nx + tile - 1) / tile, nty = (a.L.ny + tile - 1) / tile;
+    hipLaunchKernelGGL(k_hd_check<real>, dim3(ntx * nty), dim3(256), 0, s, a, rs, pitch, bound, tile, st);
+    return hipGetLastError();
+}
+
+// Network input of a state: (rho, v_x, v_y, B_x, B_y, e) per cell, then
+// (f - shift) * scale in FP32, rounded to BF16; 8 values per pixel (two zero).
+template <typename real>
+__global__ __launch_bounds__(256) void k_cnn_inputs(RatioArgs<real> a, InputNorm nm, unsigned short *x) {
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= a.L.nx || j >= a.L.ny) return;
+    const int64_t o = (int64_t)a.L.xoff + i + (int64_t)(j + G) * a.L.pitch;
+    const real rt = a.S[0][o];
+    const real irho = (real)1 / rt;
+    const float f[6] = {(float)rt, (float)(a.S[1][o] * irho), (float)(a.S[2][o] * irho), (float)a.S[4][o],
+                        (float)a.S[5][o], (float)a.S[3][o]};
+    unsigned short h[8];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) h[k] = bf16_rne((f[k] - nm.v[k]) * nm.v[6 + k]);
+    h[6] = h[7] = 0;
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    *(u32x4 *)(x + ((int64_t)j * a.L.nx + i) * 8) =
+        u32x4{h[0] | ((unsigned)h[1] << 16), h[2] | ((unsigned)h[3] << 16), h[4] | ((unsigned)h[5] << 16), 0u};
+}
+
+template <typename real>
+hipError_t launch_cnn_inputs(const RatioArgs<real> &a, const InputNorm &norm, void *x, hipStream_t s) {
+    dim3 grid((a.L.nx + 63) / 64, (a.L.ny + 3) / 4);
+    hipLaunchKernelGGL(k_cnn_inputs<real>, grid, dim3(256), 0, s, a, norm, (unsigned short *)x);
+    return hipGetLastError();
+}
+
+template hipError_t launch_ratio_fields<double>(const RatioArgs<double> &, float *, int64_t, hipStream_t);
+template hipError_t launch_ratio_fields<float>(const RatioArgs<float> &, float *, int64_t, hipStream_t);
+template hipError_t launch_hd_check<double>(const RatioArgs<double> &, float *, int64_t, double, int, HdDevStats *,
+                                            hipStream_t);
+template hipError_t launch_hd_check<float>(const RatioArgs<float> &, float *, int64_t, double, int, HdDevStats *,
+                                           hipStream_t);
+template hipError_t launch_cnn_inputs<double>(const RatioArgs<double> &, const InputNorm &, void *, hipStream_t);
+template hipError_t launch_cnn_inputs<float>(const RatioArgs<float> &, const InputNorm &, void *, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Batched persistent launch: every step of every instance in one cooperative
+// launch (all blocks co-resident, which the runtime checks at launch).  Per
+// step: each instance's dt from its own reduced wave speeds; then per stage a
+// ghost fill of all instances' stage inputs, a grid barrier, all instances'
+// tiles taken from a work queue (one atomic counter per step and stage,
+// tiles ordered most expensive first), a grid barrier.  The tile arithmetic
+// is the same device code as the per-subdomain kernels, so each instance
+// evolves bit for bit as it does alone.
+// ---------------------------------------------------------------------------
+namespace cg = cooperative_groups;
+
+__device__ __forceinline__ int bwrap(int i, int n, int periodic) {
+    if (periodic) { int r = i % n; return r < 0 ? r + n : r; }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+template <typename real, int STAGE>
+__device__ void batch_ghost_fill(const BatchArgs<real> &b, int n_blocks_threads, int gtid) {
+    const long long total = b.gbeg[b.n];
+    for (long long g = gtid; g < total; g += n_blocks_threads) {
+        // instance by binary search over the prefix offsets
+        int lo = 0, hi = b.n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (b.gbeg[mid] <= g) lo = mid; else hi = mid - 1;
+        }
+        const BatchInst<real> &I = b.inst[lo];
+        const int nx = I.L.nx, ny = I.L.ny, W = nx + 2 * G;
+        const long long gc = 2LL * G * W + 2LL * G * ny;   // ghost cells per field
+        long long m = g - b.gbeg[lo];
+        const int f = (int)(m / gc);
+        m -= (long long)f * gc;
+        int ci, rj;
+        if (m < 2LL * G * W) {
+            const int rr = (int)(m / W);
+            ci = (int)(m % W) - G;
+            rj = rr < G ? rr - G : ny + rr - G;
+        } else {
+            const long long m2 = m - 2LL * G * W;
+            rj = (int)(m2 / (2 * G));
+            const int cc = (int)(m2 % (2 * G));
+            ci = cc < G ? cc - G : nx + cc - G;
+        }
+        real *S = const_cast<real *>(I.st[STAGE - 1].S[f]);
+        const int si = bwrap(ci, nx, I.periodic_x), sj = bwrap(rj, ny, I.periodic_y);
+        S[(int64_t)I.L.xoff + ci + (int64_t)(rj + G) * I.L.pitch] =
+            S[(int64_t)I.L.xoff + si + (int64_t)(sj + G) * I.L.pitch];
+    }
+}
+
+template <typename real, int NT, int STAGE>
+__device__ void batch_stage(const BatchArgs<real> &b, int step, TileLds<real, NT> &lds, int &s_item,
+                            cg::grid_group &grid) {
+    batch_ghost_fill<real, STAGE>(b, (int)(gridDim.x * NT), (int)(blockIdx.x * NT + threadIdx.x));
+    grid.sync();
+    int *ctr = b.ctr + step * 4 + (STAGE - 1);
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = atomicAdd(ctr, 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= b.nitems) break;
+        const BatchItem w = b.items[it];
+        const BatchInst<real> &I = b.inst[w.inst];
+        if (I.oned) stage_tile_1d<real, NT, STAGE, true>(I.st[STAGE - 1], w.tx, lds);
+        else stage_tile<real, NT, STAGE, true, false>(I.st[STAGE - 1], w.tx, w.ty, lds);
+    }
+    grid.sync();
+}
+
+template <typename real, int NT>
+__global__ __launch_bounds__(NT) void k_batch(BatchArgs<real> b) {
+    __shared__ TileLds<real, NT> lds;
+    __shared__ int s_item;
+    cg::grid_group grid = cg::this_grid();
+    for (int step = 0; step < b.nsteps; ++step) {
+        if (blockIdx.x == 0)
+            for (int i = threadIdx.x; i < b.n; i += NT) step_begin_dev(b.inst[i].sc, 0.0, b.inst[i].sk);
+        grid.sync();
+        batch_stage<real, NT, 1>(b, step, lds, s_item, grid);
+        batch_stage<real, NT, 2>(b, step, lds, s_item, grid);
+        batch_stage<real, NT, 3>(b, step, lds, s_item, grid);
+        batch_stage<real, NT, 4>(b, step, lds, s_item, grid);
+        if (blockIdx.x == 0)
+            for (int i = threadIdx.x; i < b.n; i += NT) step_end_dev(b.inst[i].sc);
+        grid.sync();
+    }
+}
+
+template <typename real, int NT>
+static hipError_t launch_batch_nt(const BatchArgs<real> &b, int blocks, hipStream_t s) {
+    void *args[] = {(void *)&b};
+    return hipLaunchCooperativeKernel((const void *)k_batch<real, NT>, dim3(blocks), dim3(NT), args, 0, s);
+}
+
+template <typename real>
+hipError_t launch_batch(const BatchArgs<real> &b, int nt, int blocks, hipStream_t s) {
+    switch (nt) {
+        case 64: return launch_batch_nt<real, 64>(b, blocks, s);
+        case 128: return launch_batch_nt<real, 128>(b, blocks, s);
+        default: return launch_batch_nt<real, 256>(b, blocks, s);
+    }
+}
+
+template <typename real>
+hipError_t batch_blocks_per_cu(int nt, int *blocks) {
+    switch (nt) {
+        case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch<real, 64>, 64, 0);
+        case 128: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch<real, 128>, 128, 0);
+        default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch<real, 256>, 256, 0);
+    }
+}
+
+template hipError_t launch_batch<double>(const BatchArgs<double> &, int, int, hipStream_t);
+template hipError_t launch_batch<float>(const BatchArgs<float> &, int, int, hipStream_t);
+template hipError_t batch_blocks_per_cu<double>(int, int *);
+template hipError_t batch_blocks_per_cu<float>(int, int *);
 
 }  // namespace sacx

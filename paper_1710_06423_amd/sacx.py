@@ -34,7 +34,15 @@ EXPORTED = (
     "sacx_destroy", "sacx_set_boundaries", "sacx_init_state", "sacx_advance", "sacx_read_fields",
     "sacx_diagnostics", "sacx_halo_buffer_size", "sacx_halo_pack", "sacx_halo_unpack",
     "sacx_profile_enable", "sacx_profile_read", "sacx_set_launch", "sacx_get_launch",
+    "sacx_batch_workspace_size", "sacx_batch_create", "sacx_batch_destroy", "sacx_batch_context",
+    "sacx_batch_set_tiles", "sacx_batch_advance",
+    "sacx_cnn_buffer_sizes", "sacx_cnn_pack", "sacx_cnn_forward", "sacx_cnn_backward", "sacx_cnn_adam",
+    "sacx_cnn_inputs", "sacx_hd_ratio_fields", "sacx_surrogate_workspace_size", "sacx_hd_set_surrogate",
+    "sacx_hd_clear_surrogate", "sacx_hd_ratio_buffer", "sacx_hd_read_stats",
 )
+
+CNN_NPARAM = 23146
+CNN_PACKED_BYTES = 99840
 
 
 class Grid(ctypes.Structure):
@@ -58,7 +66,23 @@ class Diag(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("ms_stage", ctypes.c_double * 4), ("ms_halo", ctypes.c_double), ("ms_scalar", ctypes.c_double),
-                ("n_stage", ctypes.c_int64 * 4), ("n_halo", ctypes.c_int64), ("n_scalar", ctypes.c_int64)]
+                ("n_stage", ctypes.c_int64 * 4), ("n_halo", ctypes.c_int64), ("n_scalar", ctypes.c_int64),
+                ("ms_surrogate", ctypes.c_double), ("n_surrogate", ctypes.c_int64)]
+
+
+class CnnSizes(ctypes.Structure):
+    _fields_ = [("input_bytes", ctypes.c_size_t), ("act_bytes", ctypes.c_size_t),
+                ("out_bytes", ctypes.c_size_t), ("work_bytes", ctypes.c_size_t)]
+
+
+class Surrogate(ctypes.Structure):
+    _fields_ = [("d_packed", ctypes.c_void_p), ("norm", ctypes.c_float * 12), ("refresh_every", ctypes.c_int32),
+                ("tile", ctypes.c_int32), ("bound", ctypes.c_double)]
+
+
+class HdStats(ctypes.Structure):
+    _fields_ = [("refreshes", ctypes.c_int64), ("tiles_checked", ctypes.c_int64),
+                ("tiles_fallback", ctypes.c_int64), ("err_used", ctypes.c_double), ("err_all", ctypes.c_double)]
 
 
 class SacxError(RuntimeError):
@@ -100,6 +124,28 @@ def load_library():
     lib.sacx_profile_read.argtypes = [P, ctypes.POINTER(Profile)]
     lib.sacx_set_launch.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.sacx_get_launch.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.sacx_batch_workspace_size.argtypes = [ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(Params),
+                                              ctypes.POINTER(ctypes.c_size_t)]
+    lib.sacx_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(Params),
+                                      ctypes.POINTER(ctypes.c_int32), P, ctypes.c_size_t, P, ctypes.POINTER(P)]
+    lib.sacx_batch_destroy.argtypes = [P]
+    lib.sacx_batch_context.argtypes = [P, ctypes.c_int32, ctypes.POINTER(P)]
+    lib.sacx_batch_set_tiles.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.sacx_batch_advance.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
+    I32, SZ = ctypes.c_int32, ctypes.c_size_t
+    lib.sacx_cnn_buffer_sizes.argtypes = [I32, I32, I32, ctypes.POINTER(CnnSizes)]
+    lib.sacx_cnn_pack.argtypes = [P, P, P]
+    lib.sacx_cnn_forward.argtypes = [P, P, I32, I32, I32, P, P, P]
+    lib.sacx_cnn_backward.argtypes = [P, P, P, P, P, I32, I32, I32, P, SZ, P, P, P]
+    lib.sacx_cnn_adam.argtypes = [P, P, P, P, I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, P]
+    lib.sacx_cnn_inputs.argtypes = [P, ctypes.POINTER(ctypes.c_float), P]
+    lib.sacx_hd_ratio_fields.argtypes = [P, P, ctypes.c_int64]
+    lib.sacx_surrogate_workspace_size.argtypes = [P, ctypes.POINTER(SZ)]
+    lib.sacx_hd_set_surrogate.argtypes = [P, ctypes.POINTER(Surrogate), P, SZ]
+    lib.sacx_hd_clear_surrogate.argtypes = [P]
+    lib.sacx_hd_ratio_buffer.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_int64)]
+    lib.sacx_hd_read_stats.argtypes = [P, ctypes.POINTER(HdStats)]
     for n in EXPORTED:
         if n not in ("sacx_strerror", "sacx_last_error"):
             getattr(lib, n).restype = ctypes.c_int
@@ -141,14 +187,20 @@ class Solver:
     """One subdomain context (sacx_ctx) with its torch-owned workspace."""
 
     def __init__(self, grid: Grid, params: Params, bc=(PERIODIC,) * 4, device="cuda",
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, _borrow=None):
         self.lib = load_library()
+        self.owned = _borrow is None
         self.grid, self.params = grid, params
         dev = torch.device(device)
         if dev.type == "cuda" and dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.dtype = torch.float64 if grid.precision == FP64 else torch.float32
+        if _borrow is not None:
+            self.workspace = None
+            self.ctx = _borrow
+            return
         nbytes = workspace_size(grid, params)
         with torch.cuda.device(self.device):
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
@@ -177,9 +229,9 @@ class Solver:
         return s
 
     def close(self):
-        if self.ctx:
+        if self.ctx and self.owned:
             self.lib.sacx_destroy(self.ctx)
-            self.ctx = ctypes.c_void_p(None)
+        self.ctx = ctypes.c_void_p(None)
 
     def __del__(self):
         try:
@@ -268,7 +320,63 @@ class Solver:
         with torch.cuda.device(self.device):
             _check(self.lib.sacx_profile_read(self.ctx, ctypes.byref(p)), "sacx_profile_read")
         return {"ms_stage": list(p.ms_stage), "n_stage": list(p.n_stage), "ms_halo": p.ms_halo,
-                "n_halo": p.n_halo, "ms_scalar": p.ms_scalar, "n_scalar": p.n_scalar}
+                "n_halo": p.n_halo, "ms_scalar": p.ms_scalar, "n_scalar": p.n_scalar,
+                "ms_surrogate": p.ms_surrogate, "n_surrogate": p.n_surrogate}
+
+    # ------------------------------------------------ learned coefficient
+    def cnn_inputs(self, norm: Sequence[float], out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Network input image of the current state: (ny, nx, 8) BF16 (as int16 storage)."""
+        if out is None:
+            out = torch.empty((self.grid.ny, self.grid.nx, 8), dtype=torch.bfloat16, device=self.device)
+        arr = (ctypes.c_float * 12)(*[float(v) for v in norm])
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_cnn_inputs(self.ctx, arr, ctypes.c_void_p(out.data_ptr())), "sacx_cnn_inputs")
+        return out
+
+    def ratio_fields(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """Plain coefficient ratios of the current state: (10, ny, nx) float32."""
+        if out is None:
+            out = torch.empty((10, self.grid.ny, self.grid.nx), dtype=torch.float32, device=self.device)
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_hd_ratio_fields(self.ctx, ctypes.c_void_p(out.data_ptr()), self.grid.nx),
+                   "sacx_hd_ratio_fields")
+        return out
+
+    def set_surrogate(self, packed: Optional[torch.Tensor], norm: Sequence[float], refresh_every: int = 1,
+                      tile: int = 32, bound: float = 0.05):
+        """Switch the learned coefficient on (packed=None: the caller writes ratio_buffer())."""
+        n = ctypes.c_size_t(0)
+        _check(self.lib.sacx_surrogate_workspace_size(self.ctx, ctypes.byref(n)), "sacx_surrogate_workspace_size")
+        with torch.cuda.device(self.device):
+            self.sur_ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
+        self.sur_packed = packed
+        cfg = Surrogate(None if packed is None else packed.data_ptr(), (ctypes.c_float * 12)(*[float(v) for v in norm]),
+                        int(refresh_every), int(tile), float(bound))
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_hd_set_surrogate(self.ctx, ctypes.byref(cfg), ctypes.c_void_p(self.sur_ws.data_ptr()),
+                                                  n.value), "sacx_hd_set_surrogate")
+
+    def clear_surrogate(self):
+        _check(self.lib.sacx_hd_clear_surrogate(self.ctx), "sacx_hd_clear_surrogate")
+        self.sur_ws = None
+        self.sur_packed = None
+
+    def ratio_buffer(self) -> torch.Tensor:
+        """The surrogate's ratio planes as a (10, ny, nx) float32 view (writable)."""
+        ptr = ctypes.c_void_p(None)
+        pitch = ctypes.c_int64(0)
+        _check(self.lib.sacx_hd_ratio_buffer(self.ctx, ctypes.byref(ptr), ctypes.byref(pitch)), "sacx_hd_ratio_buffer")
+        off = ptr.value - self.sur_ws.data_ptr()
+        ny, nx, p = self.grid.ny, self.grid.nx, pitch.value
+        flat = self.sur_ws[off: off + 10 * p * ny * 4].view(torch.float32)
+        return flat.view(10, ny, p)[:, :, :nx]
+
+    def hd_stats(self) -> Dict:
+        st = HdStats()
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_hd_read_stats(self.ctx, ctypes.byref(st)), "sacx_hd_read_stats")
+        return {"refreshes": st.refreshes, "tiles_checked": st.tiles_checked, "tiles_fallback": st.tiles_fallback,
+                "err_used": st.err_used, "err_all": st.err_all}
 
     def set_launch(self, threads: int = 0, rows: int = 0):
         _check(self.lib.sacx_set_launch(self.ctx, int(threads), int(rows)), "sacx_set_launch")
@@ -277,3 +385,116 @@ class Solver:
         t, r = ctypes.c_int32(0), ctypes.c_int32(0)
         _check(self.lib.sacx_get_launch(self.ctx, ctypes.byref(t), ctypes.byref(r)), "sacx_get_launch")
         return t.value, r.value
+
+
+class Batch:
+    """Many independent subdomains advanced by one persistent launch
+    (sacx_batch_*).  Instance i is a borrowed context: ``batch[i]`` is a
+    Solver view of it (init_state / read_fields / diagnostics / advance)."""
+
+    def __init__(self, problems, precision=FP32, cfl=0.3, c2=DEFAULT_C2, cshk=DEFAULT_CSHK, device="cuda",
+                 stream: Optional[torch.cuda.Stream] = None, init=True):
+        self.lib = load_library()
+        n = len(problems)
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.grids = (Grid * n)(*[make_grid(p.nx, p.ny, p.x0, p.x1, p.y0, p.y1, precision, False) for p in problems])
+        self.params = (Params * n)(*[make_params(p.gamma, cfl, True, True, c2, cshk) for p in problems])
+        bc = (ctypes.c_int32 * (4 * n))(*[int(b) for p in problems for b in p.bc])
+        nbytes = ctypes.c_size_t(0)
+        _check(self.lib.sacx_batch_workspace_size(n, self.grids, self.params, ctypes.byref(nbytes)),
+               "sacx_batch_workspace_size")
+        with torch.cuda.device(dev):
+            self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+            self.b = ctypes.c_void_p(None)
+            _check(self.lib.sacx_batch_create(n, self.grids, self.params, bc, ctypes.c_void_p(self.workspace.data_ptr()),
+                                              nbytes.value, ctypes.c_void_p(self.stream.cuda_stream),
+                                              ctypes.byref(self.b)), "sacx_batch_create")
+        self.n = n
+        self.views = []
+        for i in range(n):
+            c = ctypes.c_void_p(None)
+            _check(self.lib.sacx_batch_context(self.b, i, ctypes.byref(c)), "sacx_batch_context")
+            self.views.append(Solver(self.grids[i], self.params[i], device=dev, stream=self.stream, _borrow=c))
+        if init:
+            dt = torch.float64
+            for i, p in enumerate(problems):
+                f = torch.stack([torch.from_numpy(p.fields[k]) for k in FIELDS]).to(dev, dt)
+                self.views[i].init_state(f, None, t0=p.t0)
+
+    def __len__(self):
+        return self.n
+
+    def __getitem__(self, i) -> Solver:
+        return self.views[i]
+
+    def set_tiles(self, threads: int = 0, rows=None):
+        arr = None if rows is None else (ctypes.c_int32 * self.n)(*[int(r) for r in rows])
+        _check(self.lib.sacx_batch_set_tiles(self.b, int(threads), arr), "sacx_batch_set_tiles")
+
+    def advance(self, nsteps: int, sync: bool = True):
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_batch_advance(self.b, int(nsteps), int(bool(sync))), "sacx_batch_advance")
+
+    def close(self):
+        for v in self.views:
+            v.close()
+        if self.b:
+            self.lib.sacx_batch_destroy(self.b)
+            self.b = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- network calls
+def _dp(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(None if t is None else t.data_ptr())
+
+
+def cnn_buffer_sizes(n: int, h: int, w: int) -> Dict[str, int]:
+    lib = load_library()
+    s = CnnSizes()
+    _check(lib.sacx_cnn_buffer_sizes(int(n), int(h), int(w), ctypes.byref(s)), "sacx_cnn_buffer_sizes")
+    return {"input": s.input_bytes, "act": s.act_bytes, "out": s.out_bytes, "work": s.work_bytes}
+
+
+def cnn_pack(theta: torch.Tensor, packed: torch.Tensor, stream=None):
+    lib = load_library()
+    st = stream if stream is not None else torch.cuda.current_stream(theta.device)
+    with torch.cuda.device(theta.device):
+        _check(lib.sacx_cnn_pack(_dp(theta), _dp(packed), ctypes.c_void_p(st.cuda_stream)), "sacx_cnn_pack")
+
+
+def cnn_forward(packed: torch.Tensor, x: torch.Tensor, act: torch.Tensor, out: torch.Tensor, stream=None):
+    """x: (n, h, w, 8) bf16; act: uint8 buffer; out: (n, 10, h, w) float32."""
+    lib = load_library()
+    n, h, w = x.shape[0], x.shape[1], x.shape[2]
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    with torch.cuda.device(x.device):
+        _check(lib.sacx_cnn_forward(_dp(packed), _dp(x), n, h, w, _dp(act), _dp(out), ctypes.c_void_p(st.cuda_stream)),
+               "sacx_cnn_forward")
+
+
+def cnn_backward(packed, x, act, out, target, work, grad, loss, stream=None):
+    lib = load_library()
+    n, h, w = x.shape[0], x.shape[1], x.shape[2]
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    with torch.cuda.device(x.device):
+        _check(lib.sacx_cnn_backward(_dp(packed), _dp(x), _dp(act), _dp(out), _dp(target), n, h, w, _dp(work),
+                                     work.numel() * work.element_size(), _dp(grad), _dp(loss),
+                                     ctypes.c_void_p(st.cuda_stream)), "sacx_cnn_backward")
+
+
+def cnn_adam(theta, m, v, grad, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    lib = load_library()
+    st = stream if stream is not None else torch.cuda.current_stream(theta.device)
+    with torch.cuda.device(theta.device):
+        _check(lib.sacx_cnn_adam(_dp(theta), _dp(m), _dp(v), _dp(grad), int(step), float(lr), float(beta1),
+                                 float(beta2), float(eps), ctypes.c_void_p(st.cuda_stream)), "sacx_cnn_adam")

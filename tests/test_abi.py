@@ -51,6 +51,10 @@ int main(void) {
   printf("%zu %zu %zu %zu\\n", sizeof(sacx_grid), sizeof(sacx_params), sizeof(sacx_diag), sizeof(sacx_profile));
   printf("%zu %zu %zu\\n", offsetof(sacx_grid, precision), offsetof(sacx_params, c2), offsetof(sacx_diag, steps));
   printf("%zu %zu\\n", offsetof(sacx_profile, n_stage), offsetof(sacx_diag, nonphys));
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(sacx_surrogate), offsetof(sacx_surrogate, refresh_every),
+         offsetof(sacx_surrogate, bound), sizeof(sacx_hd_stats), sizeof(sacx_cnn_sizes),
+         offsetof(sacx_profile, ms_surrogate));
+  printf("%d %d\\n", SACX_CNN_NPARAM, SACX_CNN_PACKED_BYTES);
   return 0;
 }
 """)
@@ -64,6 +68,9 @@ int main(void) {
     assert vals[6] == sx.Diag.steps.offset
     assert vals[7] == sx.Profile.n_stage.offset
     assert vals[8] == sx.Diag.nonphys.offset
+    assert vals[9:15] == [ctypes.sizeof(sx.Surrogate), sx.Surrogate.refresh_every.offset, sx.Surrogate.bound.offset,
+                          ctypes.sizeof(sx.HdStats), ctypes.sizeof(sx.CnnSizes), sx.Profile.ms_surrogate.offset]
+    assert vals[15:17] == [sx.CNN_NPARAM, sx.CNN_PACKED_BYTES]
 
 
 def test_strerror_and_codes(sx):

@@ -1,0 +1,320 @@
+"""GPU tests of the learned hyper-diffusion coefficient: the network kernels
+against the FP64 network reference (BF16 rounding points emulated), the
+ratio fields, network inputs, supplied-ratio stages and the tile check
+against the scheme oracle, the fallback, and what a trained network gains."""
+
+import math
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+import workloads as W
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def sx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1710_06423_amd import sacx
+    sacx.load_library()
+    return sacx
+
+
+@pytest.fixture(scope="module")
+def sur(sx):
+    from paper_1710_06423_amd import surrogate
+    return surrogate
+
+
+DEV = "cuda:0"
+
+
+def _to_gpu_images(x):
+    """(n, 6, h, w) float64 -> (n, h, w, 8) bf16 device tensor and the exact
+    BF16 values as float64 (n, 6, h, w) for the reference."""
+    n, c, h, w = x.shape
+    t = torch.zeros((n, h, w, 8), dtype=torch.float32)
+    t[..., :6] = torch.from_numpy(x).permute(0, 2, 3, 1).to(torch.float32)
+    tb = t.to(torch.bfloat16)
+    back = tb[..., :6].to(torch.float64).permute(0, 3, 1, 2).contiguous().numpy()
+    return tb.to(DEV).contiguous(), back
+
+
+def _f32(p):
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+
+
+def _net(sur, p32):
+    theta = torch.tensor(cnn.flatten(p32), dtype=torch.float32)
+    return sur.Network(theta, device=DEV)
+
+
+# Tolerances of the network against its reference.  Both round to BF16 at the
+# same points; what remains is FP32 accumulation (order and precision, about
+# 1e-6 relative on these sums) and the rare BF16 rounding of an activation that
+# lands on the other side of a rounding boundary (one BF16 ulp, 2^-8 relative,
+# of one value, which moves an output by far less than 1e-2).
+FWD_MAX, FWD_MEAN = 1e-2, 5e-5
+GRAD_REL = 1e-3
+
+
+@pytest.mark.parametrize("shape", [(1, 8, 32), (2, 5, 64), (1, 33, 96)])
+def test_cnn_forward_matches_reference(sx, sur, shape):
+    n, h, w = shape
+    p, x, _ = W.cnn_case(n, h, w, seed=h + w)
+    p32 = _f32(p)
+    net = _net(sur, p32)
+    xb, xr = _to_gpu_images(x)
+    out = net.forward(xb).cpu().numpy()
+    for i in range(n):
+        ref, _ = cnn.forward(p32, xr[i], bf16=True)
+        d = np.abs(out[i] - ref)
+        print(f"[cnn fwd] {shape} img {i}: max {d.max():.2e} mean {d.mean():.2e}")
+        assert d.max() <= FWD_MAX and d.mean() <= FWD_MEAN
+
+
+def test_cnn_translation_equivariance_exact(sx, sur):
+    """Periodic padding: a shifted image gives the shifted output, bit for bit
+    (every output is the same sum of the same products)."""
+    p, x, _ = W.cnn_case(1, 16, 64, seed=3)
+    net = _net(sur, _f32(p))
+    xb, _ = _to_gpu_images(x)
+    y0 = net.forward(xb).clone()
+    y1 = net.forward(torch.roll(xb, shifts=(5, -16), dims=(1, 2)).contiguous())
+    assert torch.equal(torch.roll(y0, shifts=(5, -16), dims=(2, 3)), y1)
+
+
+@pytest.mark.parametrize("shape", [(2, 6, 32), (1, 17, 64)])
+def test_cnn_gradients_match_reference(sx, sur, shape):
+    n, h, w = shape
+    p, x, t = W.cnn_case(n, h, w, seed=7 * h + w)
+    p32 = _f32(p)
+    net = _net(sur, p32)
+    xb, xr = _to_gpu_images(x)
+    tt = torch.from_numpy(t.astype(np.float32)).to(DEV).contiguous()
+    b = net._buffers(n, h, w)
+    sx.cnn_forward(net.packed, xb, b["act"], b["out"])
+    sx.cnn_backward(net.packed, xb, b["act"], b["out"], tt, b["work"], net.grad, net.loss)
+    g = net.grad.cpu().numpy().astype(np.float64)
+    loss_ref, g_ref = cnn.batch_loss_and_grads(p32, list(xr), list(t.astype(np.float32).astype(np.float64)),
+                                               bf16=True)
+    assert abs(net.loss.item() - loss_ref) <= 1e-5 * loss_ref
+    gr = cnn.flatten(g_ref)
+    o = 0
+    for l, (ci, co) in enumerate(cnn.LAYERS):
+        for name, size in (("w", co * ci * 9), ("b", co)):
+            a, r = g[o:o + size], gr[o:o + size]
+            rel = np.linalg.norm(a - r) / np.linalg.norm(r)
+            print(f"[cnn grad] {shape} {name}{l}: rel {rel:.2e}")
+            assert rel <= GRAD_REL, (name, l, rel)
+            o += size
+    # deterministic: a second backward gives the same bits
+    g1 = net.grad.clone()
+    sx.cnn_backward(net.packed, xb, b["act"], b["out"], tt, b["work"], net.grad, net.loss)
+    assert torch.equal(g1, net.grad)
+
+
+def test_cnn_adam_matches_reference(sx, sur):
+    rng = np.random.default_rng(4)
+    p = cnn.init_params(4)
+    th0 = cnn.flatten(p).astype(np.float32)
+    net = sur.Network(torch.tensor(th0), device=DEV)
+    pr = cnn.unflatten(th0.astype(np.float64))
+    m = {k: np.zeros_like(v) for k, v in pr.items()}
+    v = {k: np.zeros_like(val) for k, val in pr.items()}
+    for step in range(1, 4):
+        g = rng.normal(0, 1e-2, size=th0.size).astype(np.float32)
+        net.grad.copy_(torch.from_numpy(g))
+        sx.cnn_adam(net.theta, net.m, net.v, net.grad, step, 1e-3)
+        cnn.adam_step(pr, cnn.unflatten(g.astype(np.float64)), m, v, step, lr=1e-3)
+    d = np.abs(net.theta.cpu().numpy() - cnn.flatten(pr))
+    assert d.max() <= 1e-6
+
+
+def test_cnn_rejects_bad_shapes(sx):
+    with pytest.raises(sx.SacxError):
+        sx.cnn_buffer_sizes(1, 8, 48)
+    with pytest.raises(sx.SacxError):
+        sx.cnn_buffer_sizes(0, 8, 32)
+
+
+# ------------------------------------------------ ratio fields, inputs, check
+
+def _pair(n=96, ny=70, steps=3):
+    prob = W.orszag_tang(n, ny)
+    ref = oracle.State(prob)
+    ref.run(steps)
+    return prob, ref
+
+
+def test_ratio_fields_bitexact(sx):
+    prob, ref = _pair()
+    s = sx.Solver.from_problem(prob, device=DEV)
+    s.advance(3)
+    r = s.ratio_fields().cpu().numpy()
+    assert np.array_equal(r, ref.ratio_fields().astype(np.float32))
+
+
+def test_cnn_inputs_bitexact(sx):
+    prob, ref = _pair(64, 40, 2)
+    s = sx.Solver.from_problem(prob, device=DEV)
+    s.advance(2)
+    norm = (0.2, 0.1, -0.1, 0.0, 0.01, 0.5, 3.0, 1.5, 1.4, 3.3, 3.1, 2.0)
+    x = s.cnn_inputs(norm).to(torch.float32).cpu().numpy()
+    f = ref.f
+    irho = 1.0 / f[0]
+    raw = [f[0], f[1] * irho, f[2] * irho, f[4], f[5], f[3]]
+    for k in range(6):
+        v = (raw[k].astype(np.float32) - np.float32(norm[k])) * np.float32(norm[6 + k])
+        assert np.array_equal(x[..., k], cnn.bf16_round(v).astype(np.float32)), k
+    assert np.all(x[..., 6:] == 0)
+
+
+def test_supplied_ratios_bitexact(sx):
+    """Stages with supplied ratios (negative = plain) equal the oracle's
+    supplied-ratio scheme bit for bit."""
+    prob = W.orszag_tang(96, 64)
+    R = W.synthetic_ratio_planes(96, 64, seed=5, tile=8, frac_plain=0.3)
+    s = sx.Solver.from_problem(prob, device=DEV)
+    s.set_surrogate(None, (0.0,) * 6 + (1.0,) * 6, refresh_every=10 ** 6, tile=16, bound=math.inf)
+    s.ratio_buffer().copy_(torch.from_numpy(R))
+    s.advance(20)
+    ref = oracle.State(prob)
+    ref.advance_ext(20, R)
+    got = s.read_fields().cpu().numpy()
+    assert np.array_equal(got, ref.stacked())
+    st = s.hd_stats()
+    assert st["refreshes"] == 1 and st["tiles_fallback"] == 0
+
+
+def test_check_mask_matches_oracle(sx):
+    prob, ref = _pair(96, 70, 3)
+    rng = np.random.default_rng(9)
+    R = ref.ratio_fields().astype(np.float32)
+    rnn = R.copy()
+    tile = 20
+    for ty in range(4):
+        for tx in range(5):
+            if rng.uniform() < 0.5:
+                sl = (slice(None), slice(ty * tile, (ty + 1) * tile), slice(tx * tile, (tx + 1) * tile))
+                rnn[sl] += rng.normal(0, 0.03, size=rnn[sl].shape).astype(np.float32)
+    rnn[3, 65, 90] = np.nan
+    s = sx.Solver.from_problem(prob, device=DEV)
+    s.advance(3)
+    s.set_surrogate(None, (0.0,) * 6 + (1.0,) * 6, refresh_every=1, tile=tile, bound=0.05)
+    s.ratio_buffer().copy_(torch.from_numpy(rnn))
+    s.advance(1)
+    buf = s.ratio_buffer().cpu().numpy()
+    mask, nf, eu, ea = oracle.hd_check(ref.cfg, ref.f, rnn, 0.05, tile)
+    gm = np.zeros_like(mask)
+    for ty in range(mask.shape[0]):
+        for tx in range(mask.shape[1]):
+            blk = buf[:, ty * tile:(ty + 1) * tile, tx * tile:(tx + 1) * tile]
+            gm[ty, tx] = int(np.all(blk == -1.0))
+            if not gm[ty, tx]:
+                assert np.array_equal(blk, rnn[:, ty * tile:(ty + 1) * tile, tx * tile:(tx + 1) * tile])
+    assert np.array_equal(gm, mask)
+    st = s.hd_stats()
+    assert st["tiles_fallback"] == nf and st["tiles_checked"] == mask.size
+    assert st["err_used"] == eu and st["err_all"] == ea
+    assert 0 < nf < mask.size
+
+
+@pytest.mark.parametrize("weights", ["zero", "nan"])
+def test_bad_network_falls_back_everywhere(sx, sur, weights):
+    """Zeroed or corrupted weights: every tile falls back and the run is the
+    plain run bit for bit."""
+    prob = W.orszag_tang(128, 96)
+    plain = sx.Solver.from_problem(prob, device=DEV)
+    plain.advance(12)
+    th = torch.zeros(sx.CNN_NPARAM, dtype=torch.float32) if weights == "zero" else \
+        torch.full((sx.CNN_NPARAM,), float("nan"), dtype=torch.float32)
+    net = sur.Network(th, device=DEV)
+    s = sx.Solver.from_problem(prob, device=DEV)
+    s.set_surrogate(net.packed, sur.IDENTITY_NORM, refresh_every=4, tile=32, bound=0.05)
+    s.advance(12)
+    st = s.hd_stats()
+    assert st["refreshes"] == 3 and st["tiles_fallback"] == st["tiles_checked"] == 3 * 4 * 3
+    assert torch.equal(s.read_fields(), plain.read_fields())
+
+
+def test_surrogate_rejects_unsupported(sx):
+    s = sx.Solver.from_problem(W.brio_wu(400), device=DEV)
+    with pytest.raises(sx.SacxError):
+        s.set_surrogate(None, (0.0,) * 6 + (1.0,) * 6)
+    s2 = sx.Solver.from_problem(W.orszag_tang(48), device=DEV)
+    with pytest.raises(sx.SacxError):
+        s2.set_surrogate(None, (0.0,) * 6 + (1.0,) * 6)
+
+
+# ------------------------------------------------ training and the gain
+
+@pytest.fixture(scope="module")
+def trained(sx, sur):
+    t0 = time.time()
+    data = sur.generate(sides=(128, 192), seeds=(1, 2, 3), snap_every=10, t_end=1.5, log=print)
+    net = sur.Network(seed=0, device=DEV)
+    e0 = sur.evaluate(net, data)
+    sur.train(net, data, iters=1500, batch_pixels=1 << 17, lr=3e-3, lr_end=3e-4, log=print, log_every=500)
+    e1 = sur.evaluate(net, data)
+    torch.cuda.synchronize()
+    print(f"[train] {time.time() - t0:.1f} s, mean loss over the data {e0:.3e} -> {e1:.3e}")
+    return net, data, (e0, e1)
+
+
+def test_training_on_gpu_reduces_loss(trained):
+    """The library's own forward/backward/Adam kernels train the network:
+    the loss over the whole solver-generated data set drops."""
+    net, data, (e0, e1) = trained
+    assert e1 < 0.8 * e0
+
+
+def _rel_l2(a, b):
+    return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+
+def test_trained_network_gain(sx, sur, trained):
+    """What the trained network gains over the plain coefficient: the share of
+    face ratios it supplies within the bound (the untrained network supplies
+    none), at a stated error against the plain run (which is the oracle's
+    scheme bit for bit), and the step time."""
+    net, data, _ = trained
+    prob = W.orszag_tang(256)
+    nsteps, bound, tile, K = 60, 0.05, 32, 4
+    plain = sx.Solver.from_problem(prob, device=DEV)
+    plain.advance(2)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    plain.advance(nsteps)
+    torch.cuda.synchronize()
+    t_plain = time.time() - t0
+    res = {}
+    for name, n in (("trained", net), ("untrained", sur.Network(seed=1, device=DEV))):
+        s = sx.Solver.from_problem(prob, device=DEV)
+        s.set_surrogate(n.packed, data.norm, refresh_every=K, tile=tile, bound=bound)
+        s.advance(2)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        s.advance(nsteps)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        st = s.hd_stats()
+        kept = 1.0 - st["tiles_fallback"] / st["tiles_checked"]
+        a, b = s.read_fields(), plain.read_fields()
+        errs = [_rel_l2(a[k], b[k]) for k in range(6)]
+        res[name] = (kept, errs, dt, st)
+        print(f"[gain] {name}: kept {kept:.3f} err_used {st['err_used']:.3e} rel-L2 "
+              f"{' '.join(f'{e:.1e}' for e in errs)} time {dt * 1e3 / nsteps:.3f} ms/step "
+              f"(plain {t_plain * 1e3 / nsteps:.3f})")
+    kept_t, errs_t, _, st_t = res["trained"]
+    kept_u, _, _, _ = res["untrained"]
+    assert kept_u == 0.0
+    assert st_t["err_used"] <= bound
+    assert max(errs_t) <= 1e-3

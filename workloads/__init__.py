@@ -22,4 +22,6 @@ from .problems import (  # noqa: F401
     transpose_problem,
     batch_instances,
     cell_centres,
+    synthetic_ratio_planes,
+    cnn_case,
 )

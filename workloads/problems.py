@@ -321,3 +321,30 @@ def batch_instances(seed: int = 0, n_bw: int = 32, n_ot: int = 32) -> List[Probl
         b = float(rng.uniform(0.5, 1.5))
         out.append(orszag_tang(side, b0_scale=b))
     return out
+
+
+def synthetic_ratio_planes(nx: int, ny: int, seed: int = 0, tile: int = 8, frac_plain: float = 0.25) -> np.ndarray:
+    """Seeded coefficient-ratio planes (10, ny, nx) float32 for the supplied-ratio
+    path: values uniform in [0, 4], with a random fraction of tile x tile blocks
+    (all 10 planes) set to -1, which asks for the plain ratio there."""
+    rng = np.random.default_rng(seed)
+    r = rng.uniform(0.0, 4.0, size=(10, ny, nx)).astype(np.float32)
+    for ty in range(-(-ny // tile)):
+        for tx in range(-(-nx // tile)):
+            if rng.uniform() < frac_plain:
+                r[:, ty * tile:(ty + 1) * tile, tx * tile:(tx + 1) * tile] = -1.0
+    return r
+
+
+def cnn_case(n: int, h: int, w: int, seed: int = 0):
+    """Seeded network test case: parameters (He-scaled, small random biases),
+    input images (n, 6, h, w) and target ratio planes (n, 10, h, w) in [0, 4]."""
+    rng = np.random.default_rng(seed)
+    layers = [(6, 32), (32, 32), (32, 32), (32, 10)]
+    p = {}
+    for l, (ci, co) in enumerate(layers):
+        p[f"w{l}"] = rng.normal(0.0, math.sqrt(2.0 / (9 * ci)), size=(co, ci, 3, 3))
+        p[f"b{l}"] = rng.normal(0.0, 0.1, size=co)
+    x = rng.normal(0.0, 1.0, size=(n, 6, h, w))
+    t = rng.uniform(0.0, 4.0, size=(n, 10, h, w))
+    return p, x, t
