@@ -95,11 +95,12 @@ def _load():
                                             _P, _I, _P, _F]
             lib.orc_rhs_ext.argtypes = [ctypes.POINTER(_Cfg), _PP, ctypes.c_double, _PP, _F]
             lib.orc_hd_ratio_fields.argtypes = [ctypes.POINTER(_Cfg), _PP, _PP, _P]
+            lib.orc_hd_face_fields.argtypes = [ctypes.POINTER(_Cfg), _PP, _PP, _P, _P]
             lib.orc_hd_check.argtypes = [ctypes.POINTER(_Cfg), _PP, _F, ctypes.c_double, ctypes.c_int,
-                                         _I, _I, _P, _P]
+                                         ctypes.c_int, _I, _I, _P, _P]
             for name in ("orc_advance", "orc_wavespeed", "orc_rhs", "orc_step_patch", "orc_sums",
                          "orc_deriv_line", "orc_hd_ratio_line", "orc_abi_version", "orc_advance_ext",
-                         "orc_rhs_ext", "orc_hd_ratio_fields", "orc_hd_check"):
+                         "orc_rhs_ext", "orc_hd_ratio_fields", "orc_hd_check", "orc_hd_face_fields"):
                 getattr(lib, name).restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -283,8 +284,22 @@ def ratio_fields(cfg: _Cfg, f: Sequence[np.ndarray], bg=None) -> np.ndarray:
     return out
 
 
-def hd_check(cfg: _Cfg, f: Sequence[np.ndarray], rnn: np.ndarray, bound: float, tile: int):
-    """Surrogate check: (mask (nty, ntx) of fallback tiles, n_fallback, err_used, err_all)."""
+def face_fields(cfg: _Cfg, f: Sequence[np.ndarray], bg=None):
+    """(R, D1): plain ratios and first differences of every face, each (10, ny, nx)."""
+    lib = _load()
+    f = [_c64(a) for a in f]
+    bgp = _ptrs([_c64(a) for a in bg]) if bg is not None else None
+    R = np.zeros((10, cfg.ny, cfg.nx))
+    D1 = np.zeros((10, cfg.ny, cfg.nx))
+    rc = lib.orc_hd_face_fields(ctypes.byref(cfg), _ptrs(f), bgp, R.ctypes.data_as(_P), D1.ctypes.data_as(_P))
+    if rc != OK:
+        raise OracleError(rc, "orc_hd_face_fields")
+    return R, D1
+
+
+def hd_check(cfg: _Cfg, f: Sequence[np.ndarray], rnn: np.ndarray, bound: float, tile: int, metric: int = 0):
+    """Surrogate check: (mask (nty, ntx) of fallback tiles, n_fallback, err_used, err_all);
+    metric 0 compares ratios, 1 the flux-weighted error."""
     lib = _load()
     f = [_c64(a) for a in f]
     r = _f32_planes(rnn, cfg.nx, cfg.ny)
@@ -293,7 +308,7 @@ def hd_check(cfg: _Cfg, f: Sequence[np.ndarray], rnn: np.ndarray, bound: float, 
     nf = ctypes.c_int(0)
     eu, ea = ctypes.c_double(0), ctypes.c_double(0)
     rc = lib.orc_hd_check(ctypes.byref(cfg), _ptrs(f), r.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
-                          float(bound), int(tile), mask.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                          float(bound), int(tile), int(metric), mask.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                           ctypes.byref(nf), ctypes.byref(eu), ctypes.byref(ea))
     if rc != OK:
         raise OracleError(rc, "orc_hd_check")

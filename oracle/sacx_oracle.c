@@ -846,8 +846,9 @@ int orc_hd_ratio_line(int n, const double *q, double *R) {
  * per cfg->bc): R has 10 planes of nx*ny values, planes 0-4 the x-face sets
  * {rho~, eps~, v_x, v_y, B~_y} at faces (i+1/2, j), planes 5-9 the y-face
  * sets {rho~, eps~, v_x, v_y, B~_x} at faces (i, j+1/2).  The primitive
- * quantities are formed exactly as in the right-hand side. */
-int orc_hd_ratio_fields(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], double *R) {
+ * quantities are formed exactly as in the right-hand side.  D1 (optional,
+ * same layout) receives the first difference of each set at each face. */
+int orc_hd_face_fields(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], double *R, double *D1) {
     if (!cfg_ok(cfg) || !f || !R || cfg->nx < 2 || cfg->ny < 2) return ORC_EINVAL;
     if (cfg->background_on && !bg) return ORC_EINVAL;
     dom d;
@@ -882,6 +883,10 @@ int orc_hd_ratio_fields(const orc_cfg *cfg, double *const f[NF], double *const b
                 for (int k = 0; k < 5; ++k) {
                     R[(size_t)k * pl + (size_t)j * d.nx + i] = hd_ratio(qx[k], c, 1);
                     R[(size_t)(5 + k) * pl + (size_t)j * d.nx + i] = hd_ratio(qy[k], c, d.nxe);
+                    if (D1) {
+                        D1[(size_t)k * pl + (size_t)j * d.nx + i] = d1_at(qx[k], c, 1);
+                        D1[(size_t)(5 + k) * pl + (size_t)j * d.nx + i] = d1_at(qy[k], c, d.nxe);
+                    }
                 }
             }
     }
@@ -891,22 +896,39 @@ out:
     return rc;
 }
 
+int orc_hd_ratio_fields(const orc_cfg *cfg, double *const f[NF], double *const bg[NB], double *R) {
+    return orc_hd_face_fields(cfg, f, bg, R, NULL);
+}
+
 /* The surrogate check: the interior is cut into tiles of tile x tile cells
  * (ragged at the high edges), tile (tx, ty) covering cells
- * [tx*tile, ...) x [ty*tile, ...), row-major tile index ty*ntx + tx.  A tile
- * falls back to the plain ratio when any of its 10 face values r satisfies
- * NOT(|r - R_plain| <= bound) (a non-finite prediction always fails).
- * mask (ntx*nty ints): 1 = fallback.  err_used = max |r - R_plain| over the
- * tiles that keep the prediction, err_all = max over every finite error.
+ * [tx*tile, ...) x [ty*tile, ...), row-major tile index ty*ntx + tx.  Each
+ * face value r of the 10 planes gets an error e:
+ *   metric 0 (ratio): e = |r - R_plain|;
+ *   metric 1 (flux):  e = |r - R_plain| |d1| / D, d1 the face's first
+ *     difference of that set and D the largest |d1| of the plane over the
+ *     whole domain (e = 0 when D = 0): the error of the hyper-diffusive flux
+ *     the value produces (proportional to R d1), relative to the largest
+ *     |d1| of that quantity.
+ * A tile falls back when any of its values is not finite or has
+ * NOT(e <= bound).  mask (ntx*nty ints): 1 = fallback.  err_used = max e over
+ * the tiles that keep the prediction, err_all = max over every finite e.
  * Returns the number of fallback tiles in *nfall. */
-int orc_hd_check(const orc_cfg *cfg, double *const f[NF], const float *rnn, double bound, int tile,
+int orc_hd_check(const orc_cfg *cfg, double *const f[NF], const float *rnn, double bound, int tile, int metric,
                  int *mask, int *nfall, double *err_used, double *err_all) {
     if (!cfg_ok(cfg) || !f || !rnn || !mask || tile < 1 || cfg->background_on) return ORC_EINVAL;
+    if (metric != 0 && metric != 1) return ORC_EINVAL;
     const int nx = cfg->nx, ny = cfg->ny;
-    double *R = alloc0((size_t)10 * nx * ny);
-    if (!R) return ORC_ENOMEM;
-    int rc = orc_hd_ratio_fields(cfg, f, NULL, R);
-    if (rc) { free(R); return rc; }
+    const size_t pl = (size_t)nx * ny;
+    double *R = alloc0(10 * pl), *D1 = alloc0(10 * pl);
+    if (!R || !D1) { free(R); free(D1); return ORC_ENOMEM; }
+    int rc = orc_hd_face_fields(cfg, f, NULL, R, D1);
+    if (rc) { free(R); free(D1); return rc; }
+    double Dk[10];
+    for (int k = 0; k < 10; ++k) {
+        Dk[k] = 0.0;
+        for (size_t c = 0; c < pl; ++c) Dk[k] = dmax(Dk[k], fabs(D1[(size_t)k * pl + c]));
+    }
     const int ntx = (nx + tile - 1) / tile, nty = (ny + tile - 1) / tile;
     double eu = 0.0, ea = 0.0;
     int nf = 0;
@@ -917,9 +939,11 @@ int orc_hd_check(const orc_cfg *cfg, double *const f[NF], const float *rnn, doub
             for (int k = 0; k < 10; ++k)
                 for (int j = ty * tile; j < ny && j < (ty + 1) * tile; ++j)
                     for (int i = tx * tile; i < nx && i < (tx + 1) * tile; ++i) {
-                        size_t c = (size_t)k * nx * ny + (size_t)j * nx + i;
-                        double e = fabs((double)rnn[c] - R[c]);
-                        if (!(e <= bound)) bad = 1;
+                        size_t c = (size_t)k * pl + (size_t)j * nx + i;
+                        double r = (double)rnn[c];
+                        double e = fabs(r - R[c]);
+                        if (metric == 1) e = Dk[k] > 0.0 ? (e * fabs(D1[c])) / Dk[k] : 0.0;
+                        if (!isfinite(r) || !(e <= bound)) bad = 1;
                         if (isfinite(e)) et = dmax(et, e);
                     }
             mask[ty * ntx + tx] = bad;
@@ -931,5 +955,6 @@ int orc_hd_check(const orc_cfg *cfg, double *const f[NF], const float *rnn, doub
     if (err_used) *err_used = eu;
     if (err_all) *err_all = ea;
     free(R);
+    free(D1);
     return ORC_OK;
 }

@@ -243,3 +243,79 @@ def test_check_matches_bruteforce(oracle_lib):
         assert np.array_equal(mask, bf), (bound, tile)
         assert nf == int(bf.sum())
         assert eu <= bound
+
+
+# ------------------------------------------------ flux-weighted check
+
+def test_face_differences_x_line(oracle_lib):
+    """First differences of a line along x: 0.5 (q[i+1] - q[i]) of the embedded
+    golden spike, on every row; zero on every y face."""
+    q, _, _ = _golden_lines()["spike"]
+    prob = _x_only(q, "rho", ny=6)
+    s = oracle_lib.State(prob)
+    R, D1 = oracle_lib.face_fields(s.cfg, s.f)
+    expect = 0.5 * (np.roll(q, -1) - q)
+    for j in range(6):
+        assert np.array_equal(D1[0, j], expect)
+    assert np.all(D1[5:] == 0.0)
+    assert np.array_equal(R, s.ratio_fields())
+
+
+def _spike_case():
+    q, _, _ = _golden_lines()["spike"]       # d1 = +-0.5 only at faces 4.5, 5.5
+    prob = _x_only(q, "rho", ny=4)
+    return q, prob
+
+
+def test_flux_metric_ignores_flat_faces(oracle_lib):
+    """A wrong ratio on a face whose first difference vanishes moves no flux:
+    the flux metric keeps the tile, the ratio metric drops it."""
+    q, prob = _spike_case()
+    s = oracle_lib.State(prob)
+    R = s.ratio_fields().astype(np.float32)
+    rnn = R.copy()
+    rnn[0, 1, 9] += 3.0                      # face 9.5: d1 = 0
+    m0, nf0, _, _ = oracle_lib.hd_check(s.cfg, s.f, rnn, 0.1, 12, metric=0)
+    m1, nf1, eu1, ea1 = oracle_lib.hd_check(s.cfg, s.f, rnn, 0.1, 12, metric=1)
+    assert nf0 == 1 and nf1 == 0 and eu1 == 0.0 and ea1 == 0.0
+    # on the face with the largest |d1| the flux error is the ratio error
+    rnn2 = R.copy()
+    rnn2[0, 2, 4] += 0.25
+    _, nf, eu, ea = oracle_lib.hd_check(s.cfg, s.f, rnn2, 0.1, 12, metric=1)
+    assert nf == 1 and abs(ea - 0.25) < 1e-7
+    _, nf, eu, ea = oracle_lib.hd_check(s.cfg, s.f, rnn2, 0.3, 12, metric=1)
+    assert nf == 0 and abs(eu - 0.25) < 1e-7
+
+
+def test_flux_metric_non_finite_always_falls_back(oracle_lib):
+    q, prob = _spike_case()
+    s = oracle_lib.State(prob)
+    rnn = s.ratio_fields().astype(np.float32)
+    rnn[3, 0, 0] = np.inf                     # flat face, d1 = 0
+    for metric in (0, 1):
+        _, nf, _, _ = oracle_lib.hd_check(s.cfg, s.f, rnn, 1e30, 12, metric=metric)
+        assert nf == 1
+
+
+def test_flux_metric_matches_bruteforce(oracle_lib):
+    prob = _ot_small(30)
+    s = oracle_lib.State(prob)
+    s.run(4)
+    R, D1 = oracle_lib.face_fields(s.cfg, s.f)
+    rng = np.random.default_rng(6)
+    rnn = (R + rng.normal(0, 0.3, size=R.shape)).astype(np.float32)
+    D = np.max(np.abs(D1).reshape(10, -1), axis=1)
+    partial = 0
+    for bound, tile in [(0.01, 7), (0.2, 30), (0.5, 5), (0.8, 3)]:
+        mask, nf, eu, ea = oracle_lib.hd_check(s.cfg, s.f, rnn, bound, tile, metric=1)
+        ny, nx = R.shape[1:]
+        bf = np.zeros_like(mask)
+        for ty in range(mask.shape[0]):
+            for tx in range(mask.shape[1]):
+                sl = (slice(None), slice(ty * tile, (ty + 1) * tile), slice(tx * tile, (tx + 1) * tile))
+                e = np.abs(rnn[sl].astype(np.float64) - R[sl]) * np.abs(D1[sl]) / D[:, None, None]
+                bf[ty, tx] = int(not np.all(e <= bound))
+        assert np.array_equal(mask, bf), (bound, tile)
+        assert nf == int(bf.sum()) and eu <= bound
+        partial += 0 < nf < mask.size
+    assert partial >= 1
