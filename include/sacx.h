@@ -263,8 +263,9 @@ int sacx_batch_advance(sacx_batch *b, int32_t nsteps, int32_t sync);
  * (rho, v_x, v_y, B_x, B_y, e) per cell, normalised as (f - shift) * scale.
  * With the surrogate on, a context predicts the ratio planes every K steps,
  * compares them tile by tile with the plain ratios of the same state and
- * keeps the prediction only in tiles where every face is within a bound; the
- * other tiles, and any face given a negative value, use the plain ratio.
+ * keeps the prediction only in tiles where every face's error (ratio or
+ * flux-weighted, SACX_HD_CHECK_*) is within a bound; the other tiles, and
+ * any face given a negative value, use the plain ratio.
  * The coefficient itself keeps the exact maximum wave speed and compression
  * term.
  *
@@ -300,13 +301,14 @@ int sacx_cnn_pack(const float *d_theta, void *d_packed, void *stream);
 int sacx_cnn_forward(const void *d_packed, const void *d_x, int32_t n, int32_t h, int32_t w, void *d_act,
                      float *d_out, void *stream);
 
-/* Mean squared error of the output against d_target (same layout) into
- * *d_loss (one double, device) and its gradient with respect to every
- * parameter into d_grad (SACX_CNN_NPARAM floats, overwritten).  Sums over
- * pixels are reduced in a fixed order: results are deterministic. */
+/* Mean over all outputs of w (out - target)^2 (w = 1 when d_weight is
+ * NULL, else per-output weights in the output layout) into *d_loss (one
+ * double, device) and its gradient with respect to every parameter into
+ * d_grad (SACX_CNN_NPARAM floats, overwritten).  Sums over pixels are
+ * reduced in a fixed order: results are deterministic. */
 int sacx_cnn_backward(const void *d_packed, const void *d_x, const void *d_act, const float *d_out,
-                      const float *d_target, int32_t n, int32_t h, int32_t w, void *d_work, size_t work_bytes,
-                      float *d_grad, double *d_loss, void *stream);
+                      const float *d_target, const float *d_weight, int32_t n, int32_t h, int32_t w, void *d_work,
+                      size_t work_bytes, float *d_grad, double *d_loss, void *stream);
 
 /* One Adam update (bias-corrected, step counts from 1) of the FP32
  * parameters with moment buffers d_m, d_v (SACX_CNN_NPARAM floats each). */
@@ -318,8 +320,16 @@ int sacx_cnn_adam(float *d_theta, float *d_m, float *d_v, const float *d_grad, i
 int sacx_cnn_inputs(sacx_ctx *ctx, const float norm[12], void *d_x);
 
 /* The plain ratio planes of the context's current state, as FP32, row pitch
- * `pitch` elements, plane stride pitch * ny (the training target). */
-int sacx_hd_ratio_fields(sacx_ctx *ctx, float *d_r, int64_t pitch);
+ * `pitch` elements, plane stride pitch * ny (the training target); d_d1
+ * (optional, same layout) receives each face's first difference of its set
+ * (the hyper-diffusive flux of a face is proportional to R times it). */
+int sacx_hd_ratio_fields(sacx_ctx *ctx, float *d_r, float *d_d1, int64_t pitch);
+
+/* check metrics: the error of a predicted ratio r against the plain R at a face */
+#define SACX_HD_CHECK_RATIO 0  /* |r - R| */
+#define SACX_HD_CHECK_FLUX 1   /* |r - R| |d1| / D: d1 the face's first difference, D the largest
+                                  |d1| of that plane over the domain (0 when D = 0); the
+                                  error of the flux the value produces, relative */
 
 typedef struct sacx_surrogate {
     const void *d_packed;   /* packed network (caller-owned, valid while in use);
@@ -327,14 +337,15 @@ typedef struct sacx_surrogate {
     float norm[12];         /* input shift[6], scale[6] */
     int32_t refresh_every;  /* K >= 1: predict and check every K steps */
     int32_t tile;           /* check tile side in cells (>= 1) */
-    double bound;           /* largest |predicted - plain| a kept tile may have */
+    int32_t metric;         /* SACX_HD_CHECK_RATIO or SACX_HD_CHECK_FLUX */
+    double bound;           /* largest error a kept tile may have */
 } sacx_surrogate;
 
 typedef struct sacx_hd_stats {
     int64_t refreshes;       /* checks done */
     int64_t tiles_checked;   /* tiles compared, summed over checks */
     int64_t tiles_fallback;  /* of which fell back to the plain ratio */
-    double err_used;         /* max |predicted - plain| over kept tiles */
+    double err_used;         /* max error (per the metric) over kept tiles */
     double err_all;          /* max over every finite comparison */
 } sacx_hd_stats;
 

@@ -96,18 +96,21 @@ def forward(p: Dict[str, np.ndarray], x: np.ndarray, bf16: bool = False) -> Tupl
     return h, acts
 
 
-def loss(pred: np.ndarray, target: np.ndarray) -> float:
-    """Mean squared error over all outputs."""
-    return float(np.mean((pred - target) ** 2))
+def loss(pred: np.ndarray, target: np.ndarray, weight: np.ndarray = None) -> float:
+    """Mean over all outputs of the (weighted) squared error."""
+    w = 1.0 if weight is None else weight
+    return float(np.mean(w * (pred - target) ** 2))
 
 
 def backward(p: Dict[str, np.ndarray], acts: List[np.ndarray], target: np.ndarray,
-             bf16: bool = False, count: int = 0) -> Dict[str, np.ndarray]:
-    """Gradients of the mean squared error w.r.t. every parameter.  `count` is
-    the number of outputs the mean runs over (default: this image's)."""
+             bf16: bool = False, count: int = 0, weight: np.ndarray = None) -> Dict[str, np.ndarray]:
+    """Gradients of the (weighted) mean squared error w.r.t. every parameter.
+    `count` is the number of outputs the mean runs over (default: this
+    image's)."""
     pred = acts[-1]
     n = count if count else pred.size
-    g = 2.0 * (pred - target) / n
+    w = 1.0 if weight is None else weight
+    g = 2.0 * w * (pred - target) / n
     # d(4 sigmoid(z))/dz = pred (1 - pred / 4)
     g = g * pred * (1.0 - pred / 4.0)
     grads = {}
@@ -122,15 +125,16 @@ def backward(p: Dict[str, np.ndarray], acts: List[np.ndarray], target: np.ndarra
     return grads
 
 
-def batch_loss_and_grads(p, xs, ts, bf16: bool = False):
-    """Mean squared error over a batch of images and its parameter gradients."""
+def batch_loss_and_grads(p, xs, ts, bf16: bool = False, ws=None):
+    """(Weighted) mean squared error over a batch of images and its parameter gradients."""
     count = sum(t.size for t in ts)
     total = 0.0
     grads = {k: np.zeros_like(v) for k, v in p.items()}
-    for x, t in zip(xs, ts):
+    for i, (x, t) in enumerate(zip(xs, ts)):
+        w = None if ws is None else ws[i]
         pred, acts = forward(p, x, bf16)
-        total += float(np.sum((pred - t) ** 2))
-        g = backward(p, acts, t, bf16, count)
+        total += float(np.sum((1.0 if w is None else w) * (pred - t) ** 2))
+        g = backward(p, acts, t, bf16, count, w)
         for k in grads:
             grads[k] += g[k]
     return total / count, grads

@@ -215,8 +215,8 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 // error signal of the output layer, d(mean squared error)/dz, and per-block
 // partial sums of the squared error
 __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ out, const float *__restrict__ tgt,
-                                              int n, int h, int w, float scale, unsigned short *__restrict__ g3,
-                                              double *__restrict__ part) {
+                                              const float *__restrict__ wgt, int n, int h, int w, float scale,
+                                              unsigned short *__restrict__ g3, double *__restrict__ part) {
     __shared__ double red[4];
     const int64_t hw = (int64_t)h * w;
     const int64_t np = (int64_t)n * hw;
@@ -229,8 +229,9 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ out, con
             const int64_t i = (img * 10 + o) * hw + q;
             const float r = out[i];
             const float d = r - tgt[i];
-            s += (double)d * (double)d;
-            g[o] = ((scale * d) * r) * (1.0f - r * 0.25f);
+            const float wt = wgt ? wgt[i] : 1.0f;
+            s += (double)wt * ((double)d * (double)d);
+            g[o] = ((scale * (wt * d)) * r) * (1.0f - r * 0.25f);
         }
 #pragma unroll
         for (int o = 10; o < 16; ++o) g[o] = 0.0f;
@@ -495,8 +496,8 @@ int sacx_cnn_forward(const void *d_packed, const void *d_x, int n, int h, int w,
 }
 
 int sacx_cnn_backward(const void *d_packed, const void *d_x, const void *d_act, const float *d_out,
-                      const float *d_target, int n, int h, int w, void *d_work, size_t work_bytes, float *d_grad,
-                      double *d_loss, void *stream) {
+                      const float *d_target, const float *d_weight, int n, int h, int w, void *d_work,
+                      size_t work_bytes, float *d_grad, double *d_loss, void *stream) {
     if (!d_packed || !d_x || !d_act || !d_out || !d_target || !d_work || !d_grad || !d_loss)
         return set_error(SACX_EINVAL, "NULL buffer");
     sacx_cnn_sizes sz;
@@ -522,7 +523,7 @@ int sacx_cnn_backward(const void *d_packed, const void *d_x, const void *d_act, 
     // output layer error signal and the loss
     const double count = (double)px * 10.0;
     const int lb = (int)std::min<size_t>(2048, (px + 255) / 256);
-    k_loss<<<lb, 256, 0, s>>>(d_out, d_target, n, h, w, (float)(2.0 / count), g3, lpart);
+    k_loss<<<lb, 256, 0, s>>>(d_out, d_target, d_weight, n, h, w, (float)(2.0 / count), g3, lpart);
     HIPCHK(hipGetLastError());
     k_loss_final<<<1, 64, 0, s>>>(lpart, lb, 1.0 / count, d_loss);
     HIPCHK(hipGetLastError());

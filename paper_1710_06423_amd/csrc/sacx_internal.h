@@ -149,6 +149,7 @@ struct HdDevStats {
     unsigned long long err_used;   // IEEE bits of a non-negative double (max)
     unsigned long long err_all;
     unsigned long long pad;
+    unsigned long long dmax[10];   // per plane max |first difference| of the current check
 };
 
 // round to the nearest BF16 value, ties to even (NaN stays a quiet NaN)
@@ -192,9 +193,9 @@ struct BatchArgs {
 template <typename real>
 hipError_t launch_stage(int stage, bool hd, bool bg, const StageArgs<real> &a, hipStream_t s);
 template <typename real>
-hipError_t launch_ratio_fields(const RatioArgs<real> &a, float *out, int64_t pitch, hipStream_t s);
+hipError_t launch_ratio_fields(const RatioArgs<real> &a, float *out, float *d1, int64_t pitch, hipStream_t s);
 template <typename real>
-hipError_t launch_hd_check(const RatioArgs<real> &a, float *rs, int64_t pitch, double bound, int tile,
+hipError_t launch_hd_check(const RatioArgs<real> &a, float *rs, int64_t pitch, double bound, int tile, int metric,
                            HdDevStats *st, hipStream_t s);
 struct InputNorm {
     float v[12];   // shift[6], scale[6]

@@ -511,9 +511,9 @@ int sur_refresh(sacx_ctx *c) {
                                c->sur_pitch * ny, c->sur_pitch, c->stream));
     }
     HIPCHK(fp64 ? launch_hd_check<double>(ratio_args<double>(c), c->sur_r, c->sur_pitch, c->sur.bound, c->sur.tile,
-                                          c->sur_st, c->stream)
+                                          c->sur.metric, c->sur_st, c->stream)
                 : launch_hd_check<float>(ratio_args<float>(c), c->sur_r, c->sur_pitch, c->sur.bound, c->sur.tile,
-                                         c->sur_st, c->stream));
+                                         c->sur.metric, c->sur_st, c->stream));
     const int64_t ntx = (nx + c->sur.tile - 1) / c->sur.tile, nty = (ny + c->sur.tile - 1) / c->sur.tile;
     c->sur_refreshes += 1;
     c->sur_tiles_checked += ntx * nty;
@@ -1025,7 +1025,9 @@ __global__ void k_fill_f32(float *p, int64_t n, float v) {
 }
 
 __global__ void k_zero_stats(HdDevStats *st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *st = HdDevStats{0ull, 0ull, 0ull, 0ull};
+    unsigned long long *p = (unsigned long long *)st;
+    const int n = (int)(sizeof(HdDevStats) / sizeof(unsigned long long));
+    if (blockIdx.x == 0 && (int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
 struct SurPlan {
@@ -1073,6 +1075,8 @@ int sacx_hd_set_surrogate(sacx_ctx *ctx, const sacx_surrogate *cfg, void *d_ws, 
     if (rc) return rc;
     if (cfg->refresh_every < 1) return fail(SACX_EINVAL, "refresh_every must be >= 1");
     if (cfg->tile < 1) return fail(SACX_EINVAL, "tile must be >= 1");
+    if (cfg->metric != SACX_HD_CHECK_RATIO && cfg->metric != SACX_HD_CHECK_FLUX)
+        return fail(SACX_EINVAL, "metric must be SACX_HD_CHECK_RATIO or SACX_HD_CHECK_FLUX");
     if (!(cfg->bound >= 0.0)) return fail(SACX_EINVAL, "bound must be >= 0");
     for (int k = 0; k < 12; ++k)
         if (!std::isfinite(cfg->norm[k])) return fail(SACX_EINVAL, "input normalisation must be finite");
@@ -1150,7 +1154,7 @@ int sacx_cnn_inputs(sacx_ctx *ctx, const float norm[12], void *d_x) {
     return SACX_OK;
 }
 
-int sacx_hd_ratio_fields(sacx_ctx *ctx, float *d_r, int64_t pitch) {
+int sacx_hd_ratio_fields(sacx_ctx *ctx, float *d_r, float *d_d1, int64_t pitch) {
     if (!ctx || !d_r) return fail(SACX_EINVAL, "ctx/d_r must not be NULL");
     if (!ctx->initialized) return fail(SACX_ESTATE, "sacx_init_state has not been called");
     if (ctx->grid.background_on) return fail(SACX_EUNSUP, "ratio fields need a context without background");
@@ -1159,8 +1163,9 @@ int sacx_hd_ratio_fields(sacx_ctx *ctx, float *d_r, int64_t pitch) {
     if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
     int rc = fill_halo(ctx, ctx->U, NF, false);
     if (rc) return rc;
-    HIPCHK(ctx->grid.precision == SACX_FP64 ? launch_ratio_fields<double>(ratio_args<double>(ctx), d_r, pitch, ctx->stream)
-                                            : launch_ratio_fields<float>(ratio_args<float>(ctx), d_r, pitch, ctx->stream));
+    HIPCHK(ctx->grid.precision == SACX_FP64
+               ? launch_ratio_fields<double>(ratio_args<double>(ctx), d_r, d_d1, pitch, ctx->stream)
+               : launch_ratio_fields<float>(ratio_args<float>(ctx), d_r, d_d1, pitch, ctx->stream));
     return SACX_OK;
 }
 

@@ -75,9 +75,12 @@ class CnnSizes(ctypes.Structure):
                 ("out_bytes", ctypes.c_size_t), ("work_bytes", ctypes.c_size_t)]
 
 
+CHECK_RATIO, CHECK_FLUX = 0, 1
+
+
 class Surrogate(ctypes.Structure):
     _fields_ = [("d_packed", ctypes.c_void_p), ("norm", ctypes.c_float * 12), ("refresh_every", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("bound", ctypes.c_double)]
+                ("tile", ctypes.c_int32), ("metric", ctypes.c_int32), ("bound", ctypes.c_double)]
 
 
 class HdStats(ctypes.Structure):
@@ -136,11 +139,11 @@ def load_library():
     lib.sacx_cnn_buffer_sizes.argtypes = [I32, I32, I32, ctypes.POINTER(CnnSizes)]
     lib.sacx_cnn_pack.argtypes = [P, P, P]
     lib.sacx_cnn_forward.argtypes = [P, P, I32, I32, I32, P, P, P]
-    lib.sacx_cnn_backward.argtypes = [P, P, P, P, P, I32, I32, I32, P, SZ, P, P, P]
+    lib.sacx_cnn_backward.argtypes = [P, P, P, P, P, P, I32, I32, I32, P, SZ, P, P, P]
     lib.sacx_cnn_adam.argtypes = [P, P, P, P, I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, P]
     lib.sacx_cnn_inputs.argtypes = [P, ctypes.POINTER(ctypes.c_float), P]
-    lib.sacx_hd_ratio_fields.argtypes = [P, P, ctypes.c_int64]
+    lib.sacx_hd_ratio_fields.argtypes = [P, P, P, ctypes.c_int64]
     lib.sacx_surrogate_workspace_size.argtypes = [P, ctypes.POINTER(SZ)]
     lib.sacx_hd_set_surrogate.argtypes = [P, ctypes.POINTER(Surrogate), P, SZ]
     lib.sacx_hd_clear_surrogate.argtypes = [P]
@@ -333,17 +336,21 @@ class Solver:
             _check(self.lib.sacx_cnn_inputs(self.ctx, arr, ctypes.c_void_p(out.data_ptr())), "sacx_cnn_inputs")
         return out
 
-    def ratio_fields(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-        """Plain coefficient ratios of the current state: (10, ny, nx) float32."""
+    def ratio_fields(self, out: Optional[torch.Tensor] = None, with_d1: bool = False):
+        """Plain coefficient ratios of the current state: (10, ny, nx) float32
+        (and the face first differences, same shape, with with_d1)."""
+        shape = (10, self.grid.ny, self.grid.nx)
         if out is None:
-            out = torch.empty((10, self.grid.ny, self.grid.nx), dtype=torch.float32, device=self.device)
+            out = torch.empty(shape, dtype=torch.float32, device=self.device)
+        d1 = torch.empty(shape, dtype=torch.float32, device=self.device) if with_d1 else None
         with torch.cuda.device(self.device):
-            _check(self.lib.sacx_hd_ratio_fields(self.ctx, ctypes.c_void_p(out.data_ptr()), self.grid.nx),
-                   "sacx_hd_ratio_fields")
-        return out
+            _check(self.lib.sacx_hd_ratio_fields(self.ctx, ctypes.c_void_p(out.data_ptr()),
+                                                 ctypes.c_void_p(None if d1 is None else d1.data_ptr()),
+                                                 self.grid.nx), "sacx_hd_ratio_fields")
+        return (out, d1) if with_d1 else out
 
     def set_surrogate(self, packed: Optional[torch.Tensor], norm: Sequence[float], refresh_every: int = 1,
-                      tile: int = 32, bound: float = 0.05):
+                      tile: int = 32, bound: float = 0.05, metric: int = CHECK_FLUX):
         """Switch the learned coefficient on (packed=None: the caller writes ratio_buffer())."""
         n = ctypes.c_size_t(0)
         _check(self.lib.sacx_surrogate_workspace_size(self.ctx, ctypes.byref(n)), "sacx_surrogate_workspace_size")
@@ -351,7 +358,7 @@ class Solver:
             self.sur_ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
         self.sur_packed = packed
         cfg = Surrogate(None if packed is None else packed.data_ptr(), (ctypes.c_float * 12)(*[float(v) for v in norm]),
-                        int(refresh_every), int(tile), float(bound))
+                        int(refresh_every), int(tile), int(metric), float(bound))
         with torch.cuda.device(self.device):
             _check(self.lib.sacx_hd_set_surrogate(self.ctx, ctypes.byref(cfg), ctypes.c_void_p(self.sur_ws.data_ptr()),
                                                   n.value), "sacx_hd_set_surrogate")
@@ -482,12 +489,13 @@ def cnn_forward(packed: torch.Tensor, x: torch.Tensor, act: torch.Tensor, out: t
                "sacx_cnn_forward")
 
 
-def cnn_backward(packed, x, act, out, target, work, grad, loss, stream=None):
+def cnn_backward(packed, x, act, out, target, work, grad, loss, weight=None, stream=None):
     lib = load_library()
     n, h, w = x.shape[0], x.shape[1], x.shape[2]
     st = stream if stream is not None else torch.cuda.current_stream(x.device)
     with torch.cuda.device(x.device):
-        _check(lib.sacx_cnn_backward(_dp(packed), _dp(x), _dp(act), _dp(out), _dp(target), n, h, w, _dp(work),
+        _check(lib.sacx_cnn_backward(_dp(packed), _dp(x), _dp(act), _dp(out), _dp(target), _dp(weight), n, h, w,
+                                     _dp(work),
                                      work.numel() * work.element_size(), _dp(grad), _dp(loss),
                                      ctypes.c_void_p(st.cuda_stream)), "sacx_cnn_backward")
 

@@ -81,21 +81,22 @@ class Network:
         sx.cnn_forward(self.packed, x, b["act"], b["out"])
         return b["out"]
 
-    def loss_of(self, x: torch.Tensor, target: torch.Tensor) -> float:
-        """Mean squared error of the prediction on a batch (synchronises)."""
+    def loss_of(self, x: torch.Tensor, target: torch.Tensor, weight: Optional[torch.Tensor] = None) -> float:
+        """(Weighted) mean squared error of the prediction on a batch (synchronises)."""
         n, h, w = x.shape[:3]
         b = self._buffers(n, h, w)
         sx.cnn_forward(self.packed, x, b["act"], b["out"])
-        sx.cnn_backward(self.packed, x, b["act"], b["out"], target, b["work"], self.grad, self.loss)
+        sx.cnn_backward(self.packed, x, b["act"], b["out"], target, b["work"], self.grad, self.loss, weight)
         return float(self.loss.item())
 
-    def train_step(self, x: torch.Tensor, target: torch.Tensor, lr: float) -> torch.Tensor:
+    def train_step(self, x: torch.Tensor, target: torch.Tensor, lr: float,
+                   weight: Optional[torch.Tensor] = None) -> torch.Tensor:
         """One forward/backward/Adam step on a batch; returns the (pre-step)
         loss as a device tensor (no synchronisation)."""
         n, h, w = x.shape[:3]
         b = self._buffers(n, h, w)
         sx.cnn_forward(self.packed, x, b["act"], b["out"])
-        sx.cnn_backward(self.packed, x, b["act"], b["out"], target, b["work"], self.grad, self.loss)
+        sx.cnn_backward(self.packed, x, b["act"], b["out"], target, b["work"], self.grad, self.loss, weight)
         self.step += 1
         sx.cnn_adam(self.theta, self.m, self.v, self.grad, self.step, lr)
         self.pack()
@@ -104,11 +105,22 @@ class Network:
 
 @dataclasses.dataclass
 class Dataset:
-    """Network inputs and plain-ratio targets grouped by image size."""
+    """Network inputs, plain-ratio targets and flux weights grouped by image
+    size.  The weight of a face is (|d1| / D)^2, d1 its first difference and
+    D the largest |d1| of the plane in that snapshot: the squared error of the
+    flux-weighted check metric is the weighted squared ratio error."""
     norm: Tuple[float, ...]
     x: Dict[int, torch.Tensor]   # side -> (m, side, side, 8) bf16
     y: Dict[int, torch.Tensor]   # side -> (m, 10, side, side) float32
+    w: Dict[int, torch.Tensor]   # side -> (m, 10, side, side) float32
     meta: Dict
+
+
+def flux_weights(d1: torch.Tensor) -> torch.Tensor:
+    """(|d1| / max |d1| of each plane)^2 (0 on a plane without differences)."""
+    a = d1.abs()
+    D = a.amax(dim=(-2, -1), keepdim=True)
+    return torch.where(D > 0, a / torch.where(D > 0, D, torch.ones_like(D)), torch.zeros_like(a)) ** 2
 
 
 def input_norm(states: Sequence["sx.Solver"]) -> Tuple[float, ...]:
@@ -143,13 +155,16 @@ def generate(sides: Sequence[int] = (256, 384, 512), seeds: Sequence[int] = tupl
             p.close()
     xs: Dict[int, List[torch.Tensor]] = {}
     ys: Dict[int, List[torch.Tensor]] = {}
+    ws: Dict[int, List[torch.Tensor]] = {}
     for side in sides:
         for seed in seeds:
             s = ot_solver(side, b0s[seed], precision, device)
             k = 0
             while True:
                 xs.setdefault(side, []).append(s.cnn_inputs(norm).clone())
-                ys.setdefault(side, []).append(s.ratio_fields().clone())
+                r, d1 = s.ratio_fields(with_d1=True)
+                ys.setdefault(side, []).append(r)
+                ws.setdefault(side, []).append(flux_weights(d1))
                 k += 1
                 if max_snaps and k >= max_snaps:
                     break
@@ -160,16 +175,17 @@ def generate(sides: Sequence[int] = (256, 384, 512), seeds: Sequence[int] = tupl
                 log(f"[data] side {side} seed {seed} b0x{b0s[seed]:.3f}: {k} snapshots, t = {s.diagnostics()['t']:.3f}")
             s.close()
     return Dataset(tuple(norm), {k: torch.stack(v) for k, v in xs.items()},
-                   {k: torch.stack(v) for k, v in ys.items()},
+                   {k: torch.stack(v) for k, v in ys.items()}, {k: torch.stack(v) for k, v in ws.items()},
                    {"sides": list(sides), "seeds": list(seeds), "snap_every": snap_every, "t_end": t_end,
                     "b0": b0s})
 
 
 def train(net: Network, data: Dataset, iters: int, batch_pixels: int = 1 << 19, lr: float = 2e-3,
-          lr_end: float = 2e-4, seed: int = 0, log=None, log_every: int = 100) -> List[float]:
+          lr_end: float = 2e-4, seed: int = 0, log=None, log_every: int = 100, weighted: bool = True) -> List[float]:
     """Adam on random mini-batches (whole periodic snapshots of one size per
     step, sizes visited in proportion to their pixel counts), cosine-decayed
-    learning rate.  Returns the loss history (every log_every steps)."""
+    learning rate, flux-weighted loss by default.  Returns the loss history
+    (every log_every steps)."""
     rng = np.random.default_rng(seed)
     sides = sorted(data.x)
     weights = np.array([data.x[s].shape[0] * s * s for s in sides], dtype=np.float64)
@@ -182,8 +198,9 @@ def train(net: Network, data: Dataset, iters: int, batch_pixels: int = 1 << 19, 
         idx = torch.as_tensor(rng.choice(m, size=n, replace=False), device=data.x[side].device)
         x = data.x[side].index_select(0, idx).contiguous()
         y = data.y[side].index_select(0, idx).contiguous()
+        wt = data.w[side].index_select(0, idx).contiguous() if weighted else None
         f = 0.5 * (1 + math.cos(math.pi * it / max(1, iters - 1)))
-        loss = net.train_step(x, y, lr_end + (lr - lr_end) * f)
+        loss = net.train_step(x, y, lr_end + (lr - lr_end) * f, wt)
         if (it % log_every == 0) or it == iters - 1:
             v = float(loss.item())
             hist.append(v)
@@ -192,15 +209,16 @@ def train(net: Network, data: Dataset, iters: int, batch_pixels: int = 1 << 19, 
     return hist
 
 
-def evaluate(net: Network, data: Dataset, max_images: int = 16) -> float:
-    """Mean squared error over (up to max_images evenly spaced) snapshots of
-    every size, weighted by pixel count."""
+def evaluate(net: Network, data: Dataset, max_images: int = 16, weighted: bool = True) -> float:
+    """(Flux-weighted) mean squared error over (up to max_images evenly
+    spaced) snapshots of every size, weighted by pixel count."""
     tot, cnt = 0.0, 0
     for side in sorted(data.x):
         m = data.x[side].shape[0]
         idx = np.unique(np.linspace(0, m - 1, min(m, max_images)).astype(np.int64))
         for i in idx:
-            l = net.loss_of(data.x[side][i:i + 1], data.y[side][i:i + 1])
+            wt = data.w[side][i:i + 1] if weighted else None
+            l = net.loss_of(data.x[side][i:i + 1], data.y[side][i:i + 1], wt)
             tot += l * side * side
             cnt += side * side
     return tot / cnt

@@ -91,20 +91,25 @@ def test_cnn_translation_equivariance_exact(sx, sur):
     assert torch.equal(torch.roll(y0, shifts=(5, -16), dims=(2, 3)), y1)
 
 
-@pytest.mark.parametrize("shape", [(2, 6, 32), (1, 17, 64)])
-def test_cnn_gradients_match_reference(sx, sur, shape):
+@pytest.mark.parametrize("shape,weighted", [((2, 6, 32), False), ((1, 17, 64), False), ((2, 9, 32), True)])
+def test_cnn_gradients_match_reference(sx, sur, shape, weighted):
     n, h, w = shape
     p, x, t = W.cnn_case(n, h, w, seed=7 * h + w)
     p32 = _f32(p)
     net = _net(sur, p32)
     xb, xr = _to_gpu_images(x)
     tt = torch.from_numpy(t.astype(np.float32)).to(DEV).contiguous()
+    wt, wr = None, None
+    if weighted:
+        wn = np.random.default_rng(h).uniform(0, 1, size=t.shape).astype(np.float32) ** 2
+        wt = torch.from_numpy(wn).to(DEV).contiguous()
+        wr = list(wn.astype(np.float64))
     b = net._buffers(n, h, w)
     sx.cnn_forward(net.packed, xb, b["act"], b["out"])
-    sx.cnn_backward(net.packed, xb, b["act"], b["out"], tt, b["work"], net.grad, net.loss)
+    sx.cnn_backward(net.packed, xb, b["act"], b["out"], tt, b["work"], net.grad, net.loss, wt)
     g = net.grad.cpu().numpy().astype(np.float64)
     loss_ref, g_ref = cnn.batch_loss_and_grads(p32, list(xr), list(t.astype(np.float32).astype(np.float64)),
-                                               bf16=True)
+                                               bf16=True, ws=wr)
     assert abs(net.loss.item() - loss_ref) <= 1e-5 * loss_ref
     gr = cnn.flatten(g_ref)
     o = 0
@@ -117,7 +122,7 @@ def test_cnn_gradients_match_reference(sx, sur, shape):
             o += size
     # deterministic: a second backward gives the same bits
     g1 = net.grad.clone()
-    sx.cnn_backward(net.packed, xb, b["act"], b["out"], tt, b["work"], net.grad, net.loss)
+    sx.cnn_backward(net.packed, xb, b["act"], b["out"], tt, b["work"], net.grad, net.loss, wt)
     assert torch.equal(g1, net.grad)
 
 
@@ -158,8 +163,10 @@ def test_ratio_fields_bitexact(sx):
     prob, ref = _pair()
     s = sx.Solver.from_problem(prob, device=DEV)
     s.advance(3)
-    r = s.ratio_fields().cpu().numpy()
-    assert np.array_equal(r, ref.ratio_fields().astype(np.float32))
+    r, d1 = s.ratio_fields(with_d1=True)
+    R, D1 = oracle.face_fields(ref.cfg, ref.f)
+    assert np.array_equal(r.cpu().numpy(), R.astype(np.float32))
+    assert np.array_equal(d1.cpu().numpy(), D1.astype(np.float32))
 
 
 def test_cnn_inputs_bitexact(sx):
@@ -194,7 +201,8 @@ def test_supplied_ratios_bitexact(sx):
     assert st["refreshes"] == 1 and st["tiles_fallback"] == 0
 
 
-def test_check_mask_matches_oracle(sx):
+@pytest.mark.parametrize("metric", [0, 1])
+def test_check_mask_matches_oracle(sx, metric):
     prob, ref = _pair(96, 70, 3)
     rng = np.random.default_rng(9)
     R = ref.ratio_fields().astype(np.float32)
@@ -204,15 +212,16 @@ def test_check_mask_matches_oracle(sx):
         for tx in range(5):
             if rng.uniform() < 0.5:
                 sl = (slice(None), slice(ty * tile, (ty + 1) * tile), slice(tx * tile, (tx + 1) * tile))
-                rnn[sl] += rng.normal(0, 0.03, size=rnn[sl].shape).astype(np.float32)
+                rnn[sl] += rng.normal(0, 0.03 if metric == 0 else 0.3, size=rnn[sl].shape).astype(np.float32)
     rnn[3, 65, 90] = np.nan
+    bound = 0.05
     s = sx.Solver.from_problem(prob, device=DEV)
     s.advance(3)
-    s.set_surrogate(None, (0.0,) * 6 + (1.0,) * 6, refresh_every=1, tile=tile, bound=0.05)
+    s.set_surrogate(None, (0.0,) * 6 + (1.0,) * 6, refresh_every=1, tile=tile, bound=bound, metric=metric)
     s.ratio_buffer().copy_(torch.from_numpy(rnn))
     s.advance(1)
     buf = s.ratio_buffer().cpu().numpy()
-    mask, nf, eu, ea = oracle.hd_check(ref.cfg, ref.f, rnn, 0.05, tile)
+    mask, nf, eu, ea = oracle.hd_check(ref.cfg, ref.f, rnn, bound, tile, metric)
     gm = np.zeros_like(mask)
     for ty in range(mask.shape[0]):
         for tx in range(mask.shape[1]):
@@ -227,8 +236,8 @@ def test_check_mask_matches_oracle(sx):
     assert 0 < nf < mask.size
 
 
-@pytest.mark.parametrize("weights", ["zero", "nan"])
-def test_bad_network_falls_back_everywhere(sx, sur, weights):
+@pytest.mark.parametrize("weights,metric", [("zero", 0), ("nan", 0), ("nan", 1)])
+def test_bad_network_falls_back_everywhere(sx, sur, weights, metric):
     """Zeroed or corrupted weights: every tile falls back and the run is the
     plain run bit for bit."""
     prob = W.orszag_tang(128, 96)
@@ -238,7 +247,7 @@ def test_bad_network_falls_back_everywhere(sx, sur, weights):
         torch.full((sx.CNN_NPARAM,), float("nan"), dtype=torch.float32)
     net = sur.Network(th, device=DEV)
     s = sx.Solver.from_problem(prob, device=DEV)
-    s.set_surrogate(net.packed, sur.IDENTITY_NORM, refresh_every=4, tile=32, bound=0.05)
+    s.set_surrogate(net.packed, sur.IDENTITY_NORM, refresh_every=4, tile=32, bound=0.05, metric=metric)
     s.advance(12)
     st = s.hd_stats()
     assert st["refreshes"] == 3 and st["tiles_fallback"] == st["tiles_checked"] == 3 * 4 * 3
