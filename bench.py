@@ -11,6 +11,16 @@ Prints one JSON line: Mcell-updates/s over the timed steps, the roofline
 position of the dominant kernel (the fused stage kernel, timed live with HIP
 events on its stream) and the FP64 CPU oracle timed on a bounded sample of
 the same workload (one RK4 step on a sub-block of the same state).
+
+Other modes (one JSON line each):
+  --mode batch      64 mixed Brio-Wu / Orszag-Tang instances in one persistent
+                    launch (FP32, autotuned tiles) against the same instances
+                    run one at a time;
+  --mode surrogate  the learned hyper-diffusion coefficient: trained on
+                    solver-generated Orszag-Tang data, evaluated on an
+                    Orszag-Tang 2048^2 run at refresh intervals K = 1, 4, 16;
+  --mode copy       a device copy of known size (calibrates the HBM byte
+                    counters of a profiler run).
 """
 
 from __future__ import annotations
@@ -25,6 +35,7 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "Mcell-updates/s & % HBM roofline; plain vs FP32/batched/surrogate at equal error"
 
 
@@ -58,38 +69,55 @@ def cpu_baseline(prob, n_sample: int, cfl: float):
     }
 
 
-def main():
-    ap = argparse.ArgumentParser(description=__doc__)
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--n", type=int, default=8000, help="grid side")
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--no-hd", action="store_true", help="the paper's 'without HD' column")
-    ap.add_argument("--cpu-sample", type=int, default=3072, help="side of the oracle sub-block (0: skip)")
-    args = ap.parse_args()
+def traffic_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"k_stage_{workload}_traffic.md")
 
-    if args.gpus != 1:
-        print(f"bench.py runs one GPU's subdomain only; --gpus {args.gpus} is not supported "
-              f"(multi-GPU halo exchange is a design note, not part of this build).", file=sys.stderr)
-        sys.exit(2)
 
+def rel_l2(a, b) -> float:
+    import torch
+    a = a.to(torch.float64)
+    b = b.to(torch.float64)
+    nb = float(torch.linalg.vector_norm(b))
+    d = float(torch.linalg.vector_norm(a - b))
+    return d / nb if nb > 0 else d
+
+
+def base_record(args, metric_value, ms_step, dtype, config):
+    return {
+        "metric": METRIC,
+        "value": round(metric_value, 3),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": config,
+    }
+
+
+def run_single(args):
     import torch
     import workloads as W
     from paper_1710_06423_amd import FP32, FP64, Solver
-
-    if not torch.cuda.is_available():
-        print("bench.py needs a GPU", file=sys.stderr)
-        sys.exit(1)
+    from paper_1710_06423_amd.profiling import read_traffic
 
     n = args.n
     prec = FP64 if args.precision == "fp64" else FP32
     w = 8 if prec == FP64 else 4
     hd = not args.no_hd
+    workload = f"orszag_tang_{n}x{n}_{args.precision}_{'hd' if hd else 'nohd'}"
     log(f"[bench] generating Orszag-Tang {n}x{n}")
     prob = W.orszag_tang(n)
     log("[bench] uploading and initialising")
     s = Solver.from_problem(prob, precision=prec, hd_on=hd, cfl=0.3)
+    ref = None
+    if args.fp32_error and prec == FP32:
+        ref = Solver.from_problem(prob, precision=FP64, hd_on=hd, cfl=0.3)
     cpu = None
     if args.cpu_sample > 0:
         log(f"[bench] oracle baseline on a {args.cpu_sample}^2 sub-block")
@@ -136,38 +164,211 @@ def main():
     log(f"[bench] {ms / args.steps:.3f} ms/step; stage launches avg {avg_launch_s * 1e3:.3f} ms "
         f"(per stage {['%.3f' % x for x in per_stage]}); halo {t_comm / max(prof['n_halo'], 1):.3f} ms/exchange; "
         f"tau = ln(T_comp/T_comm) = {math.log(t_comp / t_comm) if t_comm > 0 else float('inf'):.2f}")
-    out = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "Mcell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms / args.steps, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if prec == FP64 else "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"orszag_tang_{n}x{n}_{args.precision}_{'hd' if hd else 'nohd'}",
-            "nx": n, "ny": n, "precision": args.precision, "hyper_diffusion": hd, "cfl": 0.3,
-            "halo": "3-cell, device pack/unpack, periodic self-exchange",
-            "bytes_per_cell_update": 12 * 6 * w,
-        },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
-        },
-        "cpu_baseline": cpu,
-        "phases_ms": {"stage": [round(x, 3) for x in prof["ms_stage"]], "halo": round(t_comm, 3),
-                      "scalar": round(prof["ms_scalar"], 3)},
+    tr = read_traffic(traffic_file(workload))
+    traffic = None if tr is None else round(tr["traffic_bytes_per_launch"] / avg_launch_s / 1e9, 1)
+    out = base_record(args, value, ms / args.steps, "f64" if prec == FP64 else "f32", {
+        "workload": workload,
+        "nx": n, "ny": n, "precision": args.precision, "hyper_diffusion": hd, "cfl": 0.3,
+        "halo": "3-cell, device pack/unpack, periodic self-exchange",
+        "bytes_per_cell_update": 12 * 6 * w,
+    })
+    out["roofline"] = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
     }
+    if tr is not None:
+        out["roofline"]["traffic_over_algorithmic"] = round(tr["traffic_bytes_per_launch"] / bytes_per_launch, 3)
+    out["cpu_baseline"] = cpu
+    out["phases_ms"] = {"stage": [round(x, 3) for x in prof["ms_stage"]], "halo": round(t_comm, 3),
+                        "scalar": round(prof["ms_scalar"], 3)}
+    if ref is not None:
+        log("[bench] FP64 reference run for the FP32 error")
+        ref.advance(args.warmup + args.steps)
+        a, b = s.read_fields(torch.float64), ref.read_fields(torch.float64)
+        names = ("rho", "mx", "my", "e", "bx", "by")
+        out["error_vs_fp64"] = {names[k]: float("%.3e" % rel_l2(a[k], b[k])) for k in range(6)}
+        out["error_vs_fp64"]["t"] = s.diagnostics()["t"]
+        out["error_vs_fp64"]["t_fp64"] = ref.diagnostics()["t"]
     print(json.dumps(out), flush=True)
+
+
+def run_batch(args):
+    import torch
+    import workloads as W
+    from paper_1710_06423_amd import FP32, FP64, Batch, Solver
+    from paper_1710_06423_amd.autotune import tune_batch
+
+    probs = W.batch_instances(seed=0)
+    cells = sum(p.nx * p.ny for p in probs)
+    log(f"[bench] batch of {len(probs)} instances, {cells} cells")
+    b = Batch(probs, precision=FP32)
+    t, r, trials = tune_batch(b, use_cache=False, log=log)
+    log(f"[bench] tiles: {t} threads, {r} rows")
+    b2 = Batch(probs, precision=FP32)
+    b2.set_tiles(t, [r] * len(probs))
+    if args.warmup:
+        b2.advance(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(b2.stream)
+    b2.advance(args.steps, sync=False)
+    e1.record(b2.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    value = cells * args.steps / (ms / 1e3) / 1e6
+    seq = {}
+    errs = []
+    for prec, name in ((FP32, "fp32"), (FP64, "fp64")):
+        tot = 0.0
+        for i, p in enumerate(probs):
+            s = Solver.from_problem(p, precision=prec)
+            if args.warmup:
+                s.advance(args.warmup)
+            torch.cuda.synchronize()
+            a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a0.record(s.stream)
+            s.advance(args.steps, sync=False)
+            a1.record(s.stream)
+            torch.cuda.synchronize()
+            tot += a0.elapsed_time(a1)
+            if prec == FP64:
+                x, y = b2[i].read_fields(torch.float64), s.read_fields(torch.float64)
+                errs.append(max(rel_l2(x[k], y[k]) for k in range(6)))
+            s.close()
+        seq[name] = cells * args.steps / (tot / 1e3) / 1e6
+        log(f"[bench] one at a time, {name}: {tot / args.steps:.3f} ms/step -> {seq[name]:.1f} Mcell-updates/s")
+    out = base_record(args, value, ms / args.steps, "f32", {
+        "workload": "batch64_briowu32_orszagtang32_fp32", "instances": len(probs), "cells": cells,
+        "tiles": {"threads": t, "rows2d": r},
+    })
+    out["roofline"] = None
+    out["cpu_baseline"] = None
+    out["sequential_mcell_updates_s"] = {k: round(v, 1) for k, v in seq.items()}
+    out["speedup_vs_sequential"] = {k: round(value / v, 2) for k, v in seq.items()}
+    out["max_rel_l2_vs_fp64"] = float("%.3e" % max(errs))
+    out["autotune_trials_ms"] = [[a, b_, round(c, 4)] for a, b_, c in trials]
+    print(json.dumps(out), flush=True)
+
+
+def run_surrogate(args):
+    import torch
+    import workloads as W
+    from paper_1710_06423_amd import FP64, Solver
+    from paper_1710_06423_amd import surrogate as sur
+    from paper_1710_06423_amd.sacx import CHECK_FLUX
+
+    t0 = time.time()
+    data = sur.generate(sides=(256, 384, 512), seeds=tuple(range(1, 9)), snap_every=10, t_end=3.0,
+                        max_snaps=args.max_snaps, log=log)
+    log(f"[bench] data: {sum(v.shape[0] for v in data.x.values())} snapshots in {time.time() - t0:.1f} s")
+    net = sur.Network(seed=0)
+    e0 = sur.evaluate(net, data)
+    t1 = time.time()
+    sur.train(net, data, iters=args.train_iters, batch_pixels=1 << 19, lr=2e-3, lr_end=1e-4, log=log,
+              log_every=max(1, args.train_iters // 6))
+    torch.cuda.synchronize()
+    train_s = time.time() - t1
+    e1 = sur.evaluate(net, data)
+    log(f"[bench] trained {args.train_iters} iterations in {train_s:.1f} s; loss {e0:.3e} -> {e1:.3e}")
+
+    n = args.n
+    prob = W.orszag_tang(n)
+
+    def timed(s):
+        if args.warmup:
+            s.advance(args.warmup)
+        torch.cuda.synchronize()
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record(s.stream)
+        s.advance(args.steps, sync=False)
+        a1.record(s.stream)
+        torch.cuda.synchronize()
+        return a0.elapsed_time(a1)
+
+    plain = Solver.from_problem(prob, precision=FP64)
+    ms_plain = timed(plain)
+    ref = plain.read_fields()
+    names = ("rho", "mx", "my", "e", "bx", "by")
+    runs = {}
+    for K in (1, 4, 16):
+        s = Solver.from_problem(prob, precision=FP64)
+        s.set_surrogate(net.packed, data.norm, refresh_every=K, tile=args.tile, bound=args.bound, metric=CHECK_FLUX)
+        ms = timed(s)
+        st = s.hd_stats()
+        a = s.read_fields()
+        runs[f"K{K}"] = {
+            "mcell_updates_s": round(n * n * args.steps / (ms / 1e3) / 1e6, 1),
+            "ms_per_step": round(ms / args.steps, 4),
+            "kept_tile_fraction": round(1 - st["tiles_fallback"] / st["tiles_checked"], 4),
+            "err_used": float("%.3e" % st["err_used"]),
+            "rel_l2_vs_plain": {names[k]: float("%.3e" % rel_l2(a[k], ref[k])) for k in range(6)},
+        }
+        log(f"[bench] K={K}: {runs[f'K{K}']}")
+        s.close()
+    best = max(runs.values(), key=lambda r: r["mcell_updates_s"])
+    plain_v = n * n * args.steps / (ms_plain / 1e3) / 1e6
+    out = base_record(args, best["mcell_updates_s"], best["ms_per_step"], "f64", {
+        "workload": f"orszag_tang_{n}x{n}_fp64_hd_learned_coefficient", "nx": n, "ny": n,
+        "check": {"metric": "flux", "bound": args.bound, "tile": args.tile},
+        "training": {"sides": [256, 384, 512], "seeds": list(range(1, 9)), "snap_every": 10, "t_end": 3.0,
+                     "iterations": args.train_iters, "seconds": round(train_s, 1),
+                     "loss_before": float("%.3e" % e0), "loss_after": float("%.3e" % e1)},
+    })
+    out["roofline"] = None
+    out["cpu_baseline"] = None
+    out["plain_mcell_updates_s"] = round(plain_v, 1)
+    out["runs"] = runs
+    print(json.dumps(out), flush=True)
+
+
+def run_copy(args):
+    import torch
+    nbytes = 1 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "copy", "copy_bytes": nbytes, "dispatches": 5}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default 100, surrogate 500)")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--mode", choices=["single", "batch", "surrogate", "copy"], default="single")
+    ap.add_argument("--n", type=int, default=None, help="grid side (default 8000, surrogate 2048)")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--no-hd", action="store_true", help="the paper's 'without HD' column")
+    ap.add_argument("--fp32-error", action="store_true", help="with --precision fp32: error against an FP64 run")
+    ap.add_argument("--cpu-sample", type=int, default=3072, help="side of the oracle sub-block (0: skip)")
+    ap.add_argument("--train-iters", type=int, default=6000)
+    ap.add_argument("--max-snaps", type=int, default=0)
+    ap.add_argument("--bound", type=float, default=0.05)
+    ap.add_argument("--tile", type=int, default=16)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs one GPU's subdomain only; --gpus {args.gpus} is not supported "
+              f"(multi-GPU halo exchange is a design note, not part of this build).", file=sys.stderr)
+        sys.exit(2)
+    if args.steps is None:
+        args.steps = 500 if args.mode == "surrogate" else 100
+    if args.n is None:
+        args.n = 2048 if args.mode == "surrogate" else 8000
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    {"single": run_single, "batch": run_batch, "surrogate": run_surrogate, "copy": run_copy}[args.mode](args)
 
 
 if __name__ == "__main__":

@@ -87,6 +87,7 @@ struct TileLds {
     real gx[2][3][NT];     // x-face G(v_y), G(B~_y), ring over rows (mod 3)
     real gy[2][2][NT];     // y-face G(v_x), G(B~_x), ring over faces (mod 2)
     real hx[5][NT];        // x-face fluxes H_x of row r-3
+    real ps[3][NF][NT];    // each column's last three state rows (ring over rows, mod 3)
     double red[3][NT / 64];  // stage-4 wave-speed reduction
 };
 
@@ -193,15 +194,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
             for (int f = 0; f < NF; ++f) nxt.v[f] = a.S[f][rn];
         }
         // pointwise operands of this iteration's output row j = r-3, issued
-        // now so that their latency overlaps the row's arithmetic
+        // now so that their latency overlaps the row's arithmetic.  The stage
+        // input of row j was loaded by this thread three iterations ago and
+        // is kept in the LDS ring (a second HBM read of it would miss L2:
+        // three rows of every resident block's streams exceed its capacity).
         const int j = r - G;
         const bool outrow = j >= y0 && outcol;
         const int64_t oo = (int64_t)L.xoff + c + (int64_t)(j + G) * L.pitch;
         Row6<real> pS, pU;
+        if (STAGE != 3) {
+            const int ring = (r + G) % 3;   // slot of rows r-3 and r
+            if (outrow) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) pS.v[f] = lds.ps[ring][f][tid];
+            }
+#pragma unroll
+            for (int f = 0; f < NF; ++f) lds.ps[ring][f][tid] = cur.v[f];
+        }
         if (outrow) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                if (STAGE != 3) pS.v[f] = a.S[f][oo];
                 if (STAGE == 2 || STAGE == 3) pU.v[f] = a.U[f][oo];
                 if (STAGE == 4) pU.v[f] = a.A[f][oo];
             }

@@ -1,0 +1,155 @@
+"""Summaries of rocprofv3 output for the stage kernel (text for profiles/).
+
+  python -m paper_1710_06423_amd.profiling stats  STATS_CSV BENCH_LOG OUT_MD TITLE COMMAND
+  python -m paper_1710_06423_amd.profiling traffic FETCH_CSV WRITE_CSV CFETCH_CSV CWRITE_CSV COPY_BYTES
+                                                  BENCH_LOG OUT_MD COMMANDS...
+
+`stats` turns a --kernel-trace --stats kernel summary into a table and
+compares the mean stage-kernel launch with the bench's own HIP-event timing.
+`traffic` turns two --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch)
+over the stage kernel and the same two passes over a device copy of known
+size into HBM bytes per stage launch: each counter is divided by what it
+reads per byte of the copy.  The traffic file records a hash of the stage
+kernel's sources; bench.py reports the traffic only while the hash matches.
+"""
+
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+from typing import Dict, List, Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+STAGE_SOURCES = ("csrc/sacx_stage.hip", "csrc/sacx_internal.h")
+
+
+def stage_source_hash() -> str:
+    h = hashlib.sha256()
+    for rel in STAGE_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _bench_line(path: str) -> Dict:
+    for line in reversed(open(path).read().strip().splitlines()):
+        line = line.strip()
+        if line.startswith("{"):
+            return json.loads(line)
+    raise ValueError(f"no JSON line in {path}")
+
+
+def _short(name: str) -> str:
+    return name.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+
+
+def stats_summary(stats_csv: str, bench_log: str, title: str, command: str) -> str:
+    rows = list(csv.DictReader(open(stats_csv)))
+    b = _bench_line(bench_log)
+    out = [f"# {title}", "", "Command (repository root on the GPU host):", "", "    " + command, "",
+           f"Stage kernel sources hash: {stage_source_hash()}", "",
+           "| kernel | calls | avg ms | % of GPU time |", "|---|---|---|---|"]
+    for r in rows:
+        out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} | "
+                   f"{float(r['Percentage']):.1f} |")
+    st = [r for r in rows if "k_stage" in r["Name"]]
+    if st:
+        avg = sum(float(r["TotalDurationNs"]) for r in st) / sum(int(r["Calls"]) for r in st) / 1e6
+        nl = 4 * b["steps"]
+        ev = sum(b["phases_ms"]["stage"]) / nl
+        w = 8 if b["dtype"] == "f64" else 4
+        cells = b["config"]["nx"] * b["config"]["ny"]
+        gb = 18 * w * cells / 1e9
+        out += ["", f"Mean stage-kernel launch: {avg:.3f} ms (rocprofv3, every launch including warm-up) vs "
+                    f"{ev:.3f} ms from the bench's HIP events over its timed steps (same run).",
+                f"Algorithmic bytes per stage launch: {18 * w} B x {cells / 1e6:.0f}e6 cells = {gb:.3f} GB -> "
+                f"{gb / avg * 1e3:.0f} GB/s = {gb / avg * 1e3 / 8000 * 100:.1f} % of 8 TB/s.",
+                f"Bench line of the same run: {b['value']:.0f} Mcell-updates/s, {b['ms_per_step']:.2f} ms/step, "
+                f"roofline.achieved {b['roofline']['achieved']} GB/s."]
+    return "\n".join(out) + "\n"
+
+
+def pmc_per_kernel(counter_csv: str, counter: str) -> Dict[str, List[float]]:
+    """Counter values per dispatch, grouped by kernel name."""
+    res: Dict[str, List[float]] = {}
+    for r in csv.DictReader(open(counter_csv)):
+        if r.get("Counter_Name", counter) != counter:
+            continue
+        res.setdefault(_short(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+    return res
+
+
+def _mean_of(d: Dict[str, List[float]], pattern: str) -> float:
+    vals = [v for k, vs in d.items() if re.search(pattern, k) for v in vs]
+    if not vals:
+        raise ValueError(f"no dispatch of a kernel matching {pattern!r}")
+    return sum(vals) / len(vals)
+
+
+def traffic_summary(fetch_csv: str, write_csv: str, cfetch_csv: str, cwrite_csv: str, copy_bytes: int,
+                    bench_log: str, commands: List[str], copy_pattern: str = "copyBuffer") -> str:
+    b = _bench_line(bench_log)
+    f_st = _mean_of(pmc_per_kernel(fetch_csv, "FETCH_SIZE"), "k_stage")
+    w_st = _mean_of(pmc_per_kernel(write_csv, "WRITE_SIZE"), "k_stage")
+    f_cp = _mean_of(pmc_per_kernel(cfetch_csv, "FETCH_SIZE"), copy_pattern)
+    w_cp = _mean_of(pmc_per_kernel(cwrite_csv, "WRITE_SIZE"), copy_pattern)
+    kf = f_cp * 1024.0 / copy_bytes      # counter KiB-units read per byte copied
+    kw = w_cp * 1024.0 / copy_bytes
+    fetch_b = f_st * 1024.0 / kf
+    write_b = w_st * 1024.0 / kw
+    w = 8 if b["dtype"] == "f64" else 4
+    cells = b["config"]["nx"] * b["config"]["ny"]
+    alg = 18 * w * cells
+    lines = [f"# HBM traffic of the stage kernel -- {b['config']['workload']}", "",
+             "Commands (repository root on the GPU host), one counter per run:", ""]
+    lines += ["    " + c for c in commands]
+    lines += ["", f"stage_source_hash: {stage_source_hash()}",
+              f"copy_calibration: FETCH_SIZE {f_cp:.1f} KiB and WRITE_SIZE {w_cp:.1f} KiB per copy dispatch of "
+              f"{copy_bytes} bytes -> factors {kf:.4f} (fetch) and {kw:.4f} (write) counter-KiB per KiB moved",
+              f"stage_fetch_kib_per_dispatch: {f_st:.1f}",
+              f"stage_write_kib_per_dispatch: {w_st:.1f}",
+              f"traffic_bytes_per_launch: {fetch_b + write_b:.6e}",
+              f"fetch_bytes_per_launch: {fetch_b:.6e}",
+              f"write_bytes_per_launch: {write_b:.6e}",
+              f"algorithmic_bytes_per_launch: {alg:.6e}",
+              f"traffic_over_algorithmic: {(fetch_b + write_b) / alg:.3f}"]
+    return "\n".join(lines) + "\n"
+
+
+def read_traffic(path: str) -> Optional[Dict[str, float]]:
+    """The traffic file's figures, or None when it is missing or was taken
+    from other stage-kernel sources than the current ones."""
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    kv = dict(re.findall(r"^(\w+): (\S+)", text, re.M))
+    if kv.get("stage_source_hash") != stage_source_hash():
+        return None
+    try:
+        return {k: float(kv[k]) for k in ("traffic_bytes_per_launch", "fetch_bytes_per_launch",
+                                          "write_bytes_per_launch", "algorithmic_bytes_per_launch")}
+    except (KeyError, ValueError):
+        return None
+
+
+def main(argv: List[str]):
+    if argv and argv[0] == "stats" and len(argv) == 6:
+        text = stats_summary(argv[1], argv[2], argv[4], argv[5])
+        open(argv[3], "w").write(text)
+        print(text)
+    elif argv and argv[0] == "traffic" and len(argv) >= 9:
+        text = traffic_summary(argv[1], argv[2], argv[3], argv[4], int(argv[5]), argv[6], argv[8:])
+        open(argv[7], "w").write(text)
+        print(text)
+    else:
+        print(__doc__)
+        sys.exit(2)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

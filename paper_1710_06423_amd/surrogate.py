@@ -168,7 +168,13 @@ def generate(sides: Sequence[int] = (256, 384, 512), seeds: Sequence[int] = tupl
                 k += 1
                 if max_snaps and k >= max_snaps:
                     break
-                done, t = s.advance(snap_every, t_end=t_end)
+                rc, done, t = s.advance_rc(snap_every, t_end=t_end)
+                if rc != sx.OK:
+                    # the run left the physical range: the snapshots taken so far
+                    # are of valid states; stop this run here
+                    if log:
+                        log(f"[data] side {side} seed {seed}: stopped at a non-physical state, t = {t:.3f}")
+                    break
                 if done < snap_every or t >= t_end * (1 - 1e-12):
                     break
             if log:
