@@ -348,7 +348,7 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--no-hd", action="store_true", help="the paper's 'without HD' column")
     ap.add_argument("--fp32-error", action="store_true", help="with --precision fp32: error against an FP64 run")
-    ap.add_argument("--cpu-sample", type=int, default=3072, help="side of the oracle sub-block (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=8000, help="side of the oracle sub-block (0: skip)")
     ap.add_argument("--train-iters", type=int, default=6000)
     ap.add_argument("--max-snaps", type=int, default=0)
     ap.add_argument("--bound", type=float, default=0.05)

@@ -1,6 +1,7 @@
 """Summaries of rocprofv3 output for the stage kernel (text for profiles/).
 
   python -m paper_1710_06423_amd.profiling stats  STATS_CSV BENCH_LOG OUT_MD TITLE COMMAND
+  python -m paper_1710_06423_amd.profiling sq     COUNTER_CSV BENCH_LOG OUT_MD COMMAND
   python -m paper_1710_06423_amd.profiling traffic FETCH_CSV WRITE_CSV CFETCH_CSV CWRITE_CSV COPY_BYTES
                                                   BENCH_LOG OUT_MD COMMANDS...
 
@@ -120,6 +121,35 @@ def traffic_summary(fetch_csv: str, write_csv: str, cfetch_csv: str, cwrite_csv:
     return "\n".join(lines) + "\n"
 
 
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_WAVE_CYCLES",
+               "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES")
+
+
+def sq_summary(counter_csv: str, bench_log: str, command: str) -> str:
+    """Per stage kernel: instructions per wave and the share of a wave's
+    lifetime with a VALU instruction active (both SQ counters count in the
+    same cycle units)."""
+    b = _bench_line(bench_log)
+    agg: Dict[str, Dict[str, float]] = {}
+    for r in csv.DictReader(open(counter_csv)):
+        name = _short(r["Kernel_Name"])
+        if "k_stage" not in name:
+            continue
+        agg.setdefault(name, {}).setdefault(r["Counter_Name"], 0.0)
+        agg[name][r["Counter_Name"]] += float(r["Counter_Value"])
+    lines = [f"# Instruction mix of the stage kernel -- {b['config']['workload']}", "",
+             "Command (repository root on the GPU host):", "", "    " + command, "",
+             f"Stage kernel sources hash: {stage_source_hash()}", "",
+             "| kernel | VALU / wave | LDS / wave | SALU / wave | VALU active / wave cycles | waiting on counters / wave cycles |",
+             "|---|---|---|---|---|---|"]
+    for name, d in sorted(agg.items()):
+        w = d["SQ_WAVES"]
+        lines.append(f"| `{name}` | {d['SQ_INSTS_VALU'] / w:.0f} | {d['SQ_INSTS_LDS'] / w:.0f} | "
+                     f"{d['SQ_INSTS_SALU'] / w:.0f} | {d['SQ_ACTIVE_INST_VALU'] / d['SQ_WAVE_CYCLES']:.2f} | "
+                     f"{d['SQ_WAIT_INST_ANY'] / d['SQ_WAVE_CYCLES']:.2f} |")
+    return "\n".join(lines) + "\n"
+
+
 def read_traffic(path: str) -> Optional[Dict[str, float]]:
     """The traffic file's figures, or None when it is missing or was taken
     from other stage-kernel sources than the current ones."""
@@ -140,6 +170,10 @@ def read_traffic(path: str) -> Optional[Dict[str, float]]:
 def main(argv: List[str]):
     if argv and argv[0] == "stats" and len(argv) == 6:
         text = stats_summary(argv[1], argv[2], argv[4], argv[5])
+        open(argv[3], "w").write(text)
+        print(text)
+    elif argv and argv[0] == "sq" and len(argv) == 5:
+        text = sq_summary(argv[1], argv[2], argv[4])
         open(argv[3], "w").write(text)
         print(text)
     elif argv and argv[0] == "traffic" and len(argv) >= 9:

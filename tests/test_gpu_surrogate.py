@@ -268,10 +268,10 @@ def test_surrogate_rejects_unsupported(sx):
 @pytest.fixture(scope="module")
 def trained(sx, sur):
     t0 = time.time()
-    data = sur.generate(sides=(128, 192), seeds=(1, 2, 3), snap_every=10, t_end=1.5, log=print)
+    data = sur.generate(sides=(128, 192, 256), seeds=(1, 2, 3, 4), snap_every=10, t_end=1.5, log=print)
     net = sur.Network(seed=0, device=DEV)
     e0 = sur.evaluate(net, data)
-    sur.train(net, data, iters=1500, batch_pixels=1 << 17, lr=3e-3, lr_end=3e-4, log=print, log_every=500)
+    sur.train(net, data, iters=3000, batch_pixels=1 << 18, lr=2e-3, lr_end=2e-4, log=print, log_every=1000)
     e1 = sur.evaluate(net, data)
     torch.cuda.synchronize()
     print(f"[train] {time.time() - t0:.1f} s, mean loss over the data {e0:.3e} -> {e1:.3e}")
@@ -295,8 +295,8 @@ def test_trained_network_gain(sx, sur, trained):
     none), at a stated error against the plain run (which is the oracle's
     scheme bit for bit), and the step time."""
     net, data, _ = trained
-    prob = W.orszag_tang(256)
-    nsteps, bound, tile, K = 60, 0.05, 32, 4
+    prob = W.orszag_tang(512)
+    nsteps, bound, tile, K = 100, 0.05, 16, 16
     plain = sx.Solver.from_problem(prob, device=DEV)
     plain.advance(2)
     torch.cuda.synchronize()
@@ -324,6 +324,9 @@ def test_trained_network_gain(sx, sur, trained):
               f"(plain {t_plain * 1e3 / nsteps:.3f})")
     kept_t, errs_t, _, st_t = res["trained"]
     kept_u, _, _, _ = res["untrained"]
-    assert kept_u == 0.0
+    # the trained network supplies several percent of the tiles within the
+    # flux bound (measured 9 %), the untrained one almost none (flat tiles
+    # only, measured 0.3 %); the run stays within 1e-4 of the plain run
+    assert kept_t >= 0.03 and kept_t >= 5 * kept_u
     assert st_t["err_used"] <= bound
-    assert max(errs_t) <= 1e-3
+    assert max(errs_t) <= 1e-4
