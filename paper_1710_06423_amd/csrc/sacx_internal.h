@@ -120,6 +120,10 @@ struct StageArgs {
     real *out1[NF];       // stage output (w1, w2, w3 or the new state)
     real *out2[NF];       // accumulator output (stage 2)
     const real *BG[NBG];  // static background (optional)
+    // elements from one field to the next in every buffer above (the stage
+    // kernel addresses field f of a buffer as its field 0 + f * fstride;
+    // the host checks that the buffers are laid out that way)
+    int64_t fstride;
     Layout L;
     int ty;               // output rows per block
     int nt;               // threads per block (one column each)

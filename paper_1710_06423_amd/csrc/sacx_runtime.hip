@@ -476,6 +476,7 @@ StageArgs<real> stage_args(sacx_ctx *c) {
     a.k = c->kc;
     a.hd_cross_on = c->params.hd_cross_on;
     a.sc = c->sc;
+    a.fstride = (int64_t)(((const char *)c->U[1] - (const char *)c->U[0]) / (ptrdiff_t)sizeof(real));
     for (int k = 0; k < NBG; ++k) a.BG[k] = (const real *)(c->grid.background_on ? c->BG[k] : nullptr);
     if (c->sur_on) {
         a.Rs = c->sur_r;
@@ -520,6 +521,20 @@ int sur_refresh(sacx_ctx *c) {
     return SACX_OK;
 }
 
+// the stage kernel addresses field f of a buffer as field 0 + f * fstride
+template <typename real>
+bool fields_uniform(const StageArgs<real> &a) {
+    for (int f = 1; f < NF; ++f) {
+        const int64_t o = f * a.fstride;
+        if (a.S[f] != a.S[0] + o || a.U[f] != a.U[0] + o || a.A[f] != a.A[0] + o || a.out1[f] != a.out1[0] + o ||
+            a.out2[f] != a.out2[0] + o)
+            return false;
+    }
+    for (int k = 1; k < NBG; ++k)
+        if (a.BG[0] && a.BG[k] != a.BG[0] + k * a.fstride) return false;
+    return true;
+}
+
 template <typename real>
 int run_stage(sacx_ctx *c, int stage, void *const *S, void *const *U, void *const *A, void *const *o1,
               void *const *o2) {
@@ -531,6 +546,7 @@ int run_stage(sacx_ctx *c, int stage, void *const *S, void *const *U, void *cons
         a.out1[f] = (real *)o1[f];
         a.out2[f] = (real *)(o2 ? o2[f] : o1[f]);
     }
+    if (!fields_uniform(a)) return fail(SACX_EINVAL, "internal: stage buffers are not laid out at a uniform field stride");
     HIPCHK(launch_stage<real>(stage, c->params.hd_on != 0, c->grid.background_on != 0, a, c->stream));
     return SACX_OK;
 }
@@ -1270,6 +1286,8 @@ int batch_build(sacx_batch *b) {
                 a.out1[f] = (real *)O1[st][f];
                 a.out2[f] = (real *)O2[st][f];
             }
+            if (!fields_uniform(a))
+                return fail(SACX_EINVAL, "internal: instance %d buffers are not laid out at a uniform field stride", i);
             I.st[st] = a;
         }
         I.sk.cfl = c->params.cfl;

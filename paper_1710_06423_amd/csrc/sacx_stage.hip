@@ -111,6 +111,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
     const real half = (real)0.5, two = (real)2, eight = (real)8, zero = (real)0;
 
     const Layout L = a.L;
+    const int64_t fs = a.fstride;
     const int tid = threadIdx.x;
     const int x0 = tile_x * TX;
     const int c = x0 - G + tid;
@@ -182,7 +183,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
     {
         const int64_t ro = colofs + (int64_t)(rbeg + G) * L.pitch;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) nxt.v[f] = a.S[f][ro];
+        for (int f = 0; f < NF; ++f) nxt.v[f] = a.S[0][ro + f * fs];
     }
 
     for (int r = rbeg; r <= rend; ++r) {
@@ -191,7 +192,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
         if (r < rend) {
             const int64_t rn = ro + L.pitch;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) nxt.v[f] = a.S[f][rn];
+            for (int f = 0; f < NF; ++f) nxt.v[f] = a.S[0][rn + f * fs];
         }
         // pointwise operands of this iteration's output row j = r-3, issued
         // now so that their latency overlaps the row's arithmetic.  The stage
@@ -214,8 +215,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
         if (outrow) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                if (STAGE == 2 || STAGE == 3) pU.v[f] = a.U[f][oo];
-                if (STAGE == 4) pU.v[f] = a.A[f][oo];
+                if (STAGE == 2 || STAGE == 3) pU.v[f] = a.U[0][oo + f * fs];
+                if (STAGE == 4) pU.v[f] = a.A[0][oo + f * fs];
             }
         }
         // surrogate ratios of this iteration's faces: x faces of row r-1,
@@ -234,7 +235,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
         // ================= A: row r =================
         const real rt = cur.v[0], mx = cur.v[1], my = cur.v[2], et = cur.v[3], bxt = cur.v[4], byt = cur.v[5];
         real rb = 0, eb = 0, bxb = 0, byb = 0;
-        if (BG) { rb = a.BG[0][ro]; eb = a.BG[1][ro]; bxb = a.BG[2][ro]; byb = a.BG[3][ro]; }
+        if (BG) { rb = a.BG[0][ro]; eb = a.BG[0][ro + 1 * fs]; bxb = a.BG[0][ro + 2 * fs]; byb = a.BG[0][ro + 3 * fs]; }
         const real rho = rb + rt;
         const real irho = (real)1 / rho;
         const real vx = mx * irho, vy = my * irho;
@@ -305,7 +306,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
             bgn1 = (eight * (sh_q[slot][QVY][tp1] - sh_q[slot][QVY][tm1]) - (sh_q[slot][QVY][tp2] - sh_q[slot][QVY][tm2])) * i12dx;
             // e~ of row r-2 gets -p_tb div v + sum_kl B_bk B_bl d_k v_l
             const int64_t r2 = colofs + (int64_t)((r - 2 < -G ? -G : r - 2) + G) * L.pitch;
-            const real eb2 = a.BG[1][r2], bxb2 = a.BG[2][r2], byb2 = a.BG[3][r2];
+            const real eb2 = a.BG[0][r2 + 1 * fs], bxb2 = a.BG[0][r2 + 2 * fs], byb2 = a.BG[0][r2 + 3 * fs];
             const real dxvx = bgx[0][0], dxvy = bgx[0][1];
             const real dyvx = (eight * (qw[QVX][4] - qw[QVX][2]) - (qw[QVX][5] - qw[QVX][1])) * i12dy;
             const real dyvy = (eight * (qw[QVY][4] - qw[QVY][2]) - (qw[QVY][5] - qw[QVY][1])) * i12dy;
@@ -425,28 +426,28 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
             }
             if (STAGE == 1) {
 #pragma unroll
-                for (int f = 0; f < NF; ++f) a.out1[f][oo] = pS.v[f] + hdt * K[f];
+                for (int f = 0; f < NF; ++f) a.out1[0][oo + f * fs] = pS.v[f] + hdt * K[f];
             } else if (STAGE == 2) {
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
                     const real u = pU.v[f], s = pS.v[f];
-                    a.out1[f][oo] = u + hdt * K[f];
-                    a.out2[f][oo] = (u + u) + ((s - u) + dt * K[f]);
+                    a.out1[0][oo + f * fs] = u + hdt * K[f];
+                    a.out2[0][oo + f * fs] = (u + u) + ((s - u) + dt * K[f]);
                 }
             } else if (STAGE == 3) {
 #pragma unroll
-                for (int f = 0; f < NF; ++f) a.out1[f][oo] = pU.v[f] + dt * K[f];
+                for (int f = 0; f < NF; ++f) a.out1[0][oo + f * fs] = pU.v[f] + dt * K[f];
             } else {
                 real un[6];
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
                     const real av = pU.v[f], s = pS.v[f];
                     un[f] = (s + (av - (s + s)) * third) + dt6 * K[f];
-                    a.out1[f][oo] = un[f];
+                    a.out1[0][oo + f * fs] = un[f];
                 }
                 // wave speeds of the new state (next step's dt and c_max)
                 real rb0 = 0, eb0 = 0, bxb0 = 0, byb0 = 0;
-                if (BG) { rb0 = a.BG[0][oo]; eb0 = a.BG[1][oo]; bxb0 = a.BG[2][oo]; byb0 = a.BG[3][oo]; }
+                if (BG) { rb0 = a.BG[0][oo]; eb0 = a.BG[0][oo + 1 * fs]; bxb0 = a.BG[0][oo + 2 * fs]; byb0 = a.BG[0][oo + 3 * fs]; }
                 const real r0 = rb0 + un[0];
                 const real ir0 = (real)1 / r0;
                 const real ux = un[1] * ir0, uy = un[2] * ir0;
