@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsacx.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["sacx_stage.hip", "sacx_runtime.hip", "sacx_cnn.hip"]
+SOURCES = ["sacx_stage.hip", "sacx_batch.hip", "sacx_ratio.hip", "sacx_runtime.hip", "sacx_cnn.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -1,713 +1,8 @@
-// sacx_stage.hip -- the fused RK stage kernel of the SAC MHD hot path on gfx950.
-//
-// One launch evaluates L(S) (ideal split-variable MHD fluxes differenced with
-// fourth-order central differences, plus the hyper-diffusive fluxes) for every
-// interior cell of one subdomain and applies the stage's Runge-Kutta combine
-// (paper section 2).  Stage 4 also reduces the wave speeds of the new state
-// for the next CFL time step.
-//
-// Work decomposition (MI355X: wave64, 160 KB LDS per CU, HBM-bound stencil):
-//  * a block of NT threads (one wave for NT = 64) owns TX = NT - 6 output
-//    columns; thread t holds column c = x0 - 3 + t, so the 3-cell apron on
-//    each side is computed by the 6 edge threads;
-//  * the block marches up a strip of `ty` output rows, loading each state row
-//    once (coalesced row segments, the next row prefetched while the current
-//    one is computed); quantities that only couple cells of one column (y
-//    differences, y-face hyper-diffusion windows) live in per-thread register
-//    windows, so the 3-cell y apron costs 6 warm-up rows per strip instead of
-//    an LDS tile halo;
-//  * cross-column coupling (x differences, x-face windows, the four-face
-//    averages of the cross terms) goes through small LDS row buffers;
-//  * the stage combine, and in stage 4 the wave-speed reduction, are fused in
-//    the epilogue: each evolved field is read once as a stencil input and
-//    once pointwise, then written once, so the whole RK4 step moves 12 field
-//    values per cell (the arrangement described in sacx_runtime.hip).
-//
-// Pipeline of iteration r (row r is the newest row loaded):
-//   A  : primitives and ideal fluxes of row r; publish the row to LDS;
-//        D_y F_y of row r-2 from the flux window
-//   A' : D_x F_x of row r; ideal L of row r-2; compression s of row r-1
-//   C  : x-face G = nu d1 / h of row r-1 (from the previous row buffer);
-//        y-face G of face (r-3)+1/2
-//   D  : face fluxes H_x at (c+1/2, r-3) and H_y at (c, (r-3)+1/2)
-//   E  : L(S) of row j = r-3 and the stage combine
-//
-// Arithmetic: every operation is the same IEEE operation, in the same order,
-// as in the scheme's defining sequence (the test oracle): divisions by grid
-// constants are multiplications by reciprocals computed once in FP64, no
-// multiply-add is fused (the library is built with -ffp-contract=off), and
-// the stage combine is the storage-saving RK4 arrangement.  Maxima of
-// non-negative values use the hardware max (equal values).  The
-// hyper-diffusion coefficient, a ratio of maxima of differences, amplifies
-// any rounding difference by many orders of magnitude over a run, so the
-// FP64 results are reproduced bit for bit instead of to a tolerance.
-#include <hip/hip_cooperative_groups.h>
-
-#include <algorithm>
-
-#include "sacx_internal.h"
+// sacx_stage.hip -- the fused RK stage kernel (one launch per RK stage of one
+// subdomain) and its launchers; the tile code is in sacx_tile.h.
+#include "sacx_tile.h"
 
 namespace sacx {
-
-// slots of the row buffers: the x-face quantity set {rho~, eps~, v_x, v_y,
-// B~_y} (the y-face set has B~_x in slot QB) and the totals rho, B_y
-enum { QR = 0, QE = 1, QVX = 2, QVY = 3, QB = 4, QRHO = 5, QBYT = 6, NQ = 7 };
-// flux component slots: x {rho, m_x, m_y, e, B_y}, y {rho, m_x, m_y, e, B_x}
-enum { CR = 0, CMX = 1, CMY = 2, CE = 3, CB = 4 };
-// constant class of each quantity slot: density, thermal energy, velocity, field
-__device__ __forceinline__ constexpr int qclass(int k) { return k == QR ? 0 : (k == QE ? 1 : (k == QB ? 3 : 2)); }
-
-// Hyper-diffusion coefficient ratio at the face between q2 and q3, from the
-// six values q[i-2..i+3]: max |third difference| over the 3 faces around the
-// face divided by max |first difference| over the 5 faces around it (0 when
-// the latter vanishes).
-template <typename real>
-__device__ __forceinline__ real hd_ratio(real q0, real q1, real q2, real q3, real q4, real q5) {
-    const real three = (real)3;
-    const real d3a = (q3 - q0) - three * (q2 - q1);
-    const real d3b = (q4 - q1) - three * (q3 - q2);
-    const real d3c = (q5 - q2) - three * (q4 - q3);
-    const real n = fmax(fmax(fabs(d3a), fabs(d3b)), fabs(d3c));
-    const real m = fmax(fmax(fmax(fabs(q1 - q0), fabs(q2 - q1)), fmax(fabs(q3 - q2), fabs(q4 - q3))), fabs(q5 - q4));
-    return m > (real)0 ? n / m : (real)0;
-}
-
-template <typename real>
-struct Row6 {
-    real v[NF];
-};
-
-// LDS of one tile (shared by the 2-D and 1-D tile functions, and by every
-// stage instantiation inside the batched kernel)
-template <typename real, int NT>
-struct TileLds {
-    real fx[5][NT];        // x fluxes of the newest row
-    real q[2][NQ][NT];     // row buffers (rows r and r-1)
-    real s[NT];            // compression s of row r-1
-    real gx[2][3][NT];     // x-face G(v_y), G(B~_y), ring over rows (mod 3)
-    real gy[2][2][NT];     // y-face G(v_x), G(B~_x), ring over faces (mod 2)
-    real hx[5][NT];        // x-face fluxes H_x of row r-3
-    real ps[3][NF][NT];    // each column's last three state rows (ring over rows, mod 3)
-    double red[3][NT / 64];  // stage-4 wave-speed reduction
-};
-
-// One tile of the stage: columns [tx*TX, tx*TX + TX), rows of strip ty.
-// Called by the per-subdomain kernel (one tile per block) and by the batched
-// persistent kernel (tiles of many subdomains from a work queue).
-template <typename real, int NT, int STAGE, bool HD, bool BG, bool SUR = false>
-__device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x, int tile_y, TileLds<real, NT> &lds) {
-    constexpr int TX = NT - 2 * G;
-    const DevScalars *sc = a.sc;
-    if (!sc->active) return;
-    const real dt = (real)sc->dt, hdt = (real)sc->hdt, dt6 = (real)sc->dt6;
-    real kx2[4], ky2[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) { kx2[k] = (real)sc->kx2[k]; ky2[k] = (real)sc->ky2[k]; }
-
-    const SchemeConsts &kc = a.k;
-    const real gamma = (real)kc.gamma, gm1 = (real)kc.gm1, igm1 = (real)kc.igm1;
-    const real i12dx = (real)kc.i12dx, i12dy = (real)kc.i12dy, idx = (real)kc.idx, idy = (real)kc.idy;
-    const real i2dx = (real)kc.i2dx, i2dy = (real)kc.i2dy, third = (real)kc.third;
-    const real half = (real)0.5, two = (real)2, eight = (real)8, zero = (real)0;
-
-    const Layout L = a.L;
-    const int64_t fs = a.fstride;
-    const int tid = threadIdx.x;
-    const int x0 = tile_x * TX;
-    const int c = x0 - G + tid;
-    const bool colv = c < L.nx + G;
-    const int y0 = tile_y * a.ty;
-    const int y1 = min(y0 + a.ty, L.ny);
-    const bool outcol = tid >= G && tid < NT - G && c < L.nx;
-    const bool cross = a.hd_cross_on != 0;
-
-    // clamped LDS neighbour indices (edge threads compute unused values)
-    const int tm1 = tid >= 1 ? tid - 1 : 0;
-    const int tm2 = tid >= 2 ? tid - 2 : 0;
-    const int tp1 = tid + 1 < NT ? tid + 1 : NT - 1;
-    const int tp2 = tid + 2 < NT ? tid + 2 : NT - 1;
-    const int tp3 = tid + 3 < NT ? tid + 3 : NT - 1;
-
-    auto &sh_fx = lds.fx;
-    auto &sh_q = lds.q;
-    auto &sh_s = lds.s;
-    auto &sh_gx = lds.gx;
-    auto &sh_gy = lds.gy;
-    auto &sh_hx = lds.hx;
-
-    const int64_t colofs = (int64_t)L.xoff + (colv ? c : L.nx + G - 1);
-    const int rbeg = y0 - G, rend = y1 - 1 + G;
-    // surrogate: this column's periodic image in the ratio planes
-    const int cw = SUR ? ((c % L.nx) + L.nx) % L.nx : 0;
-
-    // ---------------- per-thread windows (column-local data) ----------------
-    real qw[5][6];       // y-face set {rho~, eps~, v_x, v_y, B~_x}, rows r-5..r
-    real rbq[4], bxq[4];   // background rho_b, B_bx of rows r-3..r (background on)
-    real fyw[5][4];      // y fluxes of rows r-4..r-1
-    real dxd[2][5];      // D_x F_x of rows r-2, r-1
-    real bgx[2][2];      // D_x v_x, D_x v_y of rows r-2, r-1 (background on)
-    real kip[6];         // ideal L (+ background terms) of row r-3
-    real fmx[2][4];      // x-face means (rho, v_x, v_y, B_y) of rows r-3, r-2
-    real sw[2];          // s of rows r-3, r-2
-    real gxw[2][5];      // own x-face G of rows r-3, r-2
-    real gyp[2];         // own y-face G(v_x), G(B~_x) at face (r-4)+1/2
-    real hyp[5];         // own y-face H at face (r-4)+1/2
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-#pragma unroll
-        for (int m = 0; m < 6; ++m) qw[k][m] = 0;
-#pragma unroll
-        for (int m = 0; m < 4; ++m) fyw[k][m] = 0;
-        dxd[0][k] = dxd[1][k] = 0;
-        gxw[0][k] = gxw[1][k] = 0;
-        hyp[k] = 0;
-    }
-#pragma unroll
-    for (int k = 0; k < 6; ++k) kip[k] = 0;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) rbq[m] = bxq[m] = 0;
-#pragma unroll
-    for (int m = 0; m < 2; ++m) {
-        bgx[m][0] = bgx[m][1] = 0;
-        sw[m] = 0;
-        gyp[m] = 0;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) fmx[m][k] = 0;
-    }
-
-    double cx_t = 0.0, cy_t = 0.0;
-    int bad_t = 0;
-
-    // prefetch of the next state row
-    Row6<real> nxt;
-    {
-        const int64_t ro = colofs + (int64_t)(rbeg + G) * L.pitch;
-#pragma unroll
-        for (int f = 0; f < NF; ++f) nxt.v[f] = a.S[0][ro + f * fs];
-    }
-
-    for (int r = rbeg; r <= rend; ++r) {
-        const int64_t ro = colofs + (int64_t)(r + G) * L.pitch;
-        const Row6<real> cur = nxt;
-        if (r < rend) {
-            const int64_t rn = ro + L.pitch;
-#pragma unroll
-            for (int f = 0; f < NF; ++f) nxt.v[f] = a.S[0][rn + f * fs];
-        }
-        // pointwise operands of this iteration's output row j = r-3, issued
-        // now so that their latency overlaps the row's arithmetic.  The stage
-        // input of row j was loaded by this thread three iterations ago and
-        // is kept in the LDS ring (a second HBM read of it would miss L2:
-        // three rows of every resident block's streams exceed its capacity).
-        const int j = r - G;
-        const bool outrow = j >= y0 && outcol;
-        const int64_t oo = (int64_t)L.xoff + c + (int64_t)(j + G) * L.pitch;
-        Row6<real> pS, pU;
-        if (STAGE != 3) {
-            const int ring = (r + G) % 3;   // slot of rows r-3 and r
-            if (outrow) {
-#pragma unroll
-                for (int f = 0; f < NF; ++f) pS.v[f] = lds.ps[ring][f][tid];
-            }
-#pragma unroll
-            for (int f = 0; f < NF; ++f) lds.ps[ring][f][tid] = cur.v[f];
-        }
-        if (outrow) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                if (STAGE == 2 || STAGE == 3) pU.v[f] = a.U[0][oo + f * fs];
-                if (STAGE == 4) pU.v[f] = a.A[0][oo + f * fs];
-            }
-        }
-        // surrogate ratios of this iteration's faces: x faces of row r-1,
-        // y faces (r-3)+1/2 (periodic images)
-        float rsx[5], rsy[5];
-        if (SUR) {
-            int jx = (r - 1) % L.ny, jy = (r - 3) % L.ny;
-            jx += jx < 0 ? L.ny : 0;
-            jy += jy < 0 ? L.ny : 0;
-            const float *px_ = a.Rs + (int64_t)jx * a.rs_pitch + cw;
-            const float *py_ = a.Rs + 5 * a.rs_plane + (int64_t)jy * a.rs_pitch + cw;
-#pragma unroll
-            for (int k = 0; k < 5; ++k) { rsx[k] = px_[k * a.rs_plane]; rsy[k] = py_[k * a.rs_plane]; }
-        }
-        const int slot = r & 1, pslot = slot ^ 1;
-        // ================= A: row r =================
-        const real rt = cur.v[0], mx = cur.v[1], my = cur.v[2], et = cur.v[3], bxt = cur.v[4], byt = cur.v[5];
-        real rb = 0, eb = 0, bxb = 0, byb = 0;
-        if (BG) { rb = a.BG[0][ro]; eb = a.BG[0][ro + 1 * fs]; bxb = a.BG[0][ro + 2 * fs]; byb = a.BG[0][ro + 3 * fs]; }
-        const real rho = rb + rt;
-        const real irho = (real)1 / rho;
-        const real vx = mx * irho, vy = my * irho;
-        const real kin = half * (mx * vx + my * vy);
-        const real bbdot = bxb * bxt + byb * byt;
-        const real bt2 = bxt * bxt + byt * byt;
-        const real pk = gm1 * (((et - kin) - bbdot) - half * bt2);
-        const real pt = (pk + half * bt2) + bbdot;
-        const real eps = pk * igm1;
-        const real bxT = bxb + bxt, byT = byb + byt;
-        const real bvt = bxt * vx + byt * vy;
-        const real bvb = bxb * vx + byb * vy;
-        const real ef = et + eb + pt;
-        real fy[5];
-        sh_fx[CR][tid] = mx;
-        sh_fx[CMX][tid] = (vx * mx - (bxt * bxt + two * bxt * bxb)) + pt;
-        sh_fx[CMY][tid] = vx * my - (bxt * byt + bxt * byb + bxb * byt);
-        sh_fx[CE][tid] = ((vx * ef - bxt * bvt) - bxt * bvb) - bxb * bvt;
-        sh_fx[CB][tid] = vx * byT - bxT * vy;
-        fy[CR] = my;
-        fy[CMX] = vy * mx - (byt * bxt + byt * bxb + byb * bxt);
-        fy[CMY] = (vy * my - (byt * byt + two * byt * byb)) + pt;
-        fy[CE] = ((vy * ef - byt * bvt) - byt * bvb) - byb * bvt;
-        fy[CB] = vy * bxT - byT * vx;
-        if (HD || BG) {
-            sh_q[slot][QR][tid] = rt;
-            sh_q[slot][QE][tid] = eps;
-            sh_q[slot][QVX][tid] = vx;
-            sh_q[slot][QVY][tid] = vy;
-            sh_q[slot][QB][tid] = byt;
-            sh_q[slot][QRHO][tid] = rho;
-            sh_q[slot][QBYT][tid] = byT;
-        }
-        // D_y F_y of row r-2 (rows r-4..r)
-        real dyn[5];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            dyn[k] = (eight * (fyw[k][3] - fyw[k][1]) - (fy[k] - fyw[k][0])) * i12dy;
-            fyw[k][0] = fyw[k][1]; fyw[k][1] = fyw[k][2]; fyw[k][2] = fyw[k][3]; fyw[k][3] = fy[k];
-        }
-#pragma unroll
-        for (int k = 0; k < 5; ++k)
-#pragma unroll
-            for (int m = 0; m < 5; ++m) qw[k][m] = qw[k][m + 1];
-        qw[QR][5] = rt; qw[QE][5] = eps; qw[QVX][5] = vx; qw[QVY][5] = vy; qw[QB][5] = bxt;
-        if (BG) {
-#pragma unroll
-            for (int m = 0; m < 3; ++m) { rbq[m] = rbq[m + 1]; bxq[m] = bxq[m + 1]; }
-            rbq[3] = rb; bxq[3] = bxb;
-        }
-        __syncthreads();  // B1
-
-        // ================= A': x work on row r, ideal L of row r-2 =================
-        real dxn[5];
-#pragma unroll
-        for (int k = 0; k < 5; ++k)
-            dxn[k] = (eight * (sh_fx[k][tp1] - sh_fx[k][tm1]) - (sh_fx[k][tp2] - sh_fx[k][tm2])) * i12dx;
-        real kin6[6];
-        kin6[0] = -(dxd[0][CR] + dyn[CR]);
-        kin6[1] = -(dxd[0][CMX] + dyn[CMX]);
-        kin6[2] = -(dxd[0][CMY] + dyn[CMY]);
-        kin6[3] = -(dxd[0][CE] + dyn[CE]);
-        kin6[4] = -(zero + dyn[CB]);   // B~_x has no x flux
-        kin6[5] = -(dxd[0][CB] + zero);  // B~_y has no y flux
-        real bgn0 = 0, bgn1 = 0;
-        if (BG) {
-            bgn0 = (eight * (sh_q[slot][QVX][tp1] - sh_q[slot][QVX][tm1]) - (sh_q[slot][QVX][tp2] - sh_q[slot][QVX][tm2])) * i12dx;
-            bgn1 = (eight * (sh_q[slot][QVY][tp1] - sh_q[slot][QVY][tm1]) - (sh_q[slot][QVY][tp2] - sh_q[slot][QVY][tm2])) * i12dx;
-            // e~ of row r-2 gets -p_tb div v + sum_kl B_bk B_bl d_k v_l
-            const int64_t r2 = colofs + (int64_t)((r - 2 < -G ? -G : r - 2) + G) * L.pitch;
-            const real eb2 = a.BG[0][r2 + 1 * fs], bxb2 = a.BG[0][r2 + 2 * fs], byb2 = a.BG[0][r2 + 3 * fs];
-            const real dxvx = bgx[0][0], dxvy = bgx[0][1];
-            const real dyvx = (eight * (qw[QVX][4] - qw[QVX][2]) - (qw[QVX][5] - qw[QVX][1])) * i12dy;
-            const real dyvy = (eight * (qw[QVY][4] - qw[QVY][2]) - (qw[QVY][5] - qw[QVY][1])) * i12dy;
-            const real b2b = bxb2 * bxb2 + byb2 * byb2;
-            const real pkb = gm1 * (eb2 - half * b2b);
-            const real ptb = pkb + half * b2b;
-            const real bb = (bxb2 * bxb2 * dxvx + byb2 * byb2 * dyvy) + (bxb2 * byb2 * dxvy + byb2 * bxb2 * dyvx);
-            kin6[3] = kin6[3] + (bb - ptb * (dxvx + dyvy));
-        }
-
-        real gyn[5], hyn[5], gxn[5], fmn[4];
-        real s_new = 0;
-        if (HD) {
-            // compression s of row r-1: d_x v_x from the previous row buffer,
-            // d_y v_y from v_y of rows r and r-2
-            const real dv = (sh_q[pslot][QVX][tp1] - sh_q[pslot][QVX][tm1]) * i2dx + (qw[QVY][5] - qw[QVY][3]) * i2dy;
-            s_new = fmax(zero, -dv);
-            sh_s[tid] = s_new;
-            __syncthreads();  // B2
-
-            // ================= C: x-face G of row r-1, y-face G of face (r-3)+1/2 =================
-            const real sfx = fmax(s_new, sh_s[tp1]);
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                const int cl = qclass(k);
-                const real q2 = sh_q[pslot][k][tid], q3 = sh_q[pslot][k][tp1];
-                real R;
-                if (SUR && rsx[k] >= 0.0f)
-                    R = (real)rsx[k];
-                else
-                    R = hd_ratio(sh_q[pslot][k][tm2], sh_q[pslot][k][tm1], q2, q3, sh_q[pslot][k][tp2],
-                                 sh_q[pslot][k][tp3]);
-                const real nu = kx2[cl] * R + (real)kc.kxs[cl] * sfx;
-                gxn[k] = nu * (q3 - q2) * idx;
-            }
-            fmn[0] = half * (sh_q[pslot][QRHO][tid] + sh_q[pslot][QRHO][tp1]);
-            fmn[1] = half * (sh_q[pslot][QVX][tid] + sh_q[pslot][QVX][tp1]);
-            fmn[2] = half * (sh_q[pslot][QVY][tid] + sh_q[pslot][QVY][tp1]);
-            fmn[3] = half * (sh_q[pslot][QBYT][tid] + sh_q[pslot][QBYT][tp1]);
-            const real sfy = fmax(sw[0], sw[1]);
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                const int cl = qclass(k);
-                real R;
-                if (SUR && rsy[k] >= 0.0f)
-                    R = (real)rsy[k];
-                else
-                    R = hd_ratio(qw[k][0], qw[k][1], qw[k][2], qw[k][3], qw[k][4], qw[k][5]);
-                const real nu = ky2[cl] * R + (real)kc.kys[cl] * sfy;
-                gyn[k] = nu * (qw[k][3] - qw[k][2]) * idy;
-            }
-            const int sx = (r - 1 + 3 * 4096) % 3;   // ring slot of row r-1 (rows >= -3)
-            const int sy = (r - 3 + 2 * 4096) & 1;   // ring slot of face (r-3)+1/2
-            sh_gx[0][sx][tid] = gxn[QVY];
-            sh_gx[1][sx][tid] = gxn[QB];
-            sh_gy[0][sy][tid] = gyn[QVX];
-            sh_gy[1][sy][tid] = gyn[QB];
-            __syncthreads();  // B3
-
-            // ================= D: face fluxes of row j = r-3 =================
-            const int sxj = (r - 3 + 3 * 4096) % 3, sxj1 = (r - 2 + 3 * 4096) % 3;
-            const int syp = sy ^ 1;
-            real a4vx = 0, a4bx = 0, a4vy = 0, a4by = 0;
-            if (cross) {
-                const real q = (real)0.25;
-                a4vx = ((gyp[0] + gyn[QVX]) + (sh_gy[0][syp][tp1] + sh_gy[0][sy][tp1])) * q;
-                a4bx = ((gyp[1] + gyn[QB]) + (sh_gy[1][syp][tp1] + sh_gy[1][sy][tp1])) * q;
-                a4vy = ((sh_gx[0][sxj][tm1] + gxw[0][QVY]) + (sh_gx[0][sxj1][tm1] + gxw[1][QVY])) * q;
-                a4by = ((sh_gx[1][sxj][tm1] + gxw[0][QB]) + (sh_gx[1][sxj1][tm1] + gxw[1][QB])) * q;
-            }
-            {
-                // H_x at (c+1/2, j)
-                const real rf = fmx[0][0], vxf = fmx[0][1], vyf = fmx[0][2], byf = fmx[0][3];
-                const real txx = rf * gxw[0][QVX];
-                const real txy = half * rf * (gxw[0][QVY] + a4vx);
-                const real ez = gxw[0][QB] - a4bx;
-                sh_hx[CR][tid] = gxw[0][QR];
-                sh_hx[CMX][tid] = txx;
-                sh_hx[CMY][tid] = txy;
-                sh_hx[CE][tid] = (gxw[0][QE] + (vxf * txx + vyf * txy)) + byf * ez;
-                sh_hx[CB][tid] = ez;
-            }
-            {
-                // H_y at (c, j+1/2): rows j (qw idx 2) and j+1 (idx 3)
-                const real rj = BG ? rbq[0] + qw[QR][2] : qw[QR][2];
-                const real rj1 = BG ? rbq[1] + qw[QR][3] : qw[QR][3];
-                const real bj = BG ? bxq[0] + qw[QB][2] : qw[QB][2];
-                const real bj1 = BG ? bxq[1] + qw[QB][3] : qw[QB][3];
-                const real rf = half * (rj + rj1);
-                const real vxf = half * (qw[QVX][2] + qw[QVX][3]);
-                const real vyf = half * (qw[QVY][2] + qw[QVY][3]);
-                const real bxf = half * (bj + bj1);
-                const real tyy = rf * gyn[QVY];
-                const real tyx = half * rf * (gyn[QVX] + a4vy);
-                const real ez = a4by - gyn[QB];
-                hyn[CR] = gyn[QR];
-                hyn[CMX] = tyx;
-                hyn[CMY] = tyy;
-                hyn[CE] = (gyn[QE] + (vyf * tyy + vxf * tyx)) - bxf * ez;
-                hyn[CB] = -ez;
-            }
-        }
-        __syncthreads();  // B4 (also orders the next row's LDS writes after all reads)
-
-        // ================= E: output row j = r-3 =================
-        if (outrow) {
-            real K[6];
-#pragma unroll
-            for (int f = 0; f < 6; ++f) K[f] = kip[f];
-            if (HD) {
-                K[0] = K[0] + ((sh_hx[CR][tid] - sh_hx[CR][tm1]) * idx + (hyn[CR] - hyp[CR]) * idy);
-                K[1] = K[1] + ((sh_hx[CMX][tid] - sh_hx[CMX][tm1]) * idx + (hyn[CMX] - hyp[CMX]) * idy);
-                K[2] = K[2] + ((sh_hx[CMY][tid] - sh_hx[CMY][tm1]) * idx + (hyn[CMY] - hyp[CMY]) * idy);
-                K[3] = K[3] + ((sh_hx[CE][tid] - sh_hx[CE][tm1]) * idx + (hyn[CE] - hyp[CE]) * idy);
-                K[4] = K[4] + (zero + (hyn[CB] - hyp[CB]) * idy);
-                K[5] = K[5] + ((sh_hx[CB][tid] - sh_hx[CB][tm1]) * idx + zero);
-            }
-            if (STAGE == 1) {
-#pragma unroll
-                for (int f = 0; f < NF; ++f) a.out1[0][oo + f * fs] = pS.v[f] + hdt * K[f];
-            } else if (STAGE == 2) {
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const real u = pU.v[f], s = pS.v[f];
-                    a.out1[0][oo + f * fs] = u + hdt * K[f];
-                    a.out2[0][oo + f * fs] = (u + u) + ((s - u) + dt * K[f]);
-                }
-            } else if (STAGE == 3) {
-#pragma unroll
-                for (int f = 0; f < NF; ++f) a.out1[0][oo + f * fs] = pU.v[f] + dt * K[f];
-            } else {
-                real un[6];
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const real av = pU.v[f], s = pS.v[f];
-                    un[f] = (s + (av - (s + s)) * third) + dt6 * K[f];
-                    a.out1[0][oo + f * fs] = un[f];
-                }
-                // wave speeds of the new state (next step's dt and c_max)
-                real rb0 = 0, eb0 = 0, bxb0 = 0, byb0 = 0;
-                if (BG) { rb0 = a.BG[0][oo]; eb0 = a.BG[0][oo + 1 * fs]; bxb0 = a.BG[0][oo + 2 * fs]; byb0 = a.BG[0][oo + 3 * fs]; }
-                const real r0 = rb0 + un[0];
-                const real ir0 = (real)1 / r0;
-                const real ux = un[1] * ir0, uy = un[2] * ir0;
-                const real kn = half * (un[1] * ux + un[2] * uy);
-                const real bbd = bxb0 * un[4] + byb0 * un[5];
-                const real b2t = un[4] * un[4] + un[5] * un[5];
-                const real pkt = gm1 * (((un[3] - kn) - bbd) - half * b2t);
-                const real b2b = bxb0 * bxb0 + byb0 * byb0;
-                const real pkb = gm1 * (eb0 - half * b2b);
-                const real pkk = pkb + pkt;
-                const real bxx = bxb0 + un[4], byy = byb0 + un[5];
-                const real cf = sqrt((gamma * pkk + (bxx * bxx + byy * byy)) * ir0);
-                const bool fin = isfinite(un[0]) && isfinite(un[1]) && isfinite(un[2]) && isfinite(un[3]) &&
-                                 isfinite(un[4]) && isfinite(un[5]) && isfinite(cf);
-                if (!(r0 > (real)0) || !(pkk > (real)0) || !fin) {
-                    bad_t = 1;
-                } else {
-                    cx_t = fmax(cx_t, (double)(fabs(ux) + cf));
-                    cy_t = fmax(cy_t, (double)(fabs(uy) + cf));
-                }
-            }
-        }
-
-        // ================= end of row: advance the windows =================
-#pragma unroll
-        for (int k = 0; k < 5; ++k) { dxd[0][k] = dxd[1][k]; dxd[1][k] = dxn[k]; }
-#pragma unroll
-        for (int k = 0; k < 6; ++k) kip[k] = kin6[k];
-        if (BG) {
-            bgx[0][0] = bgx[1][0]; bgx[1][0] = bgn0;
-            bgx[0][1] = bgx[1][1]; bgx[1][1] = bgn1;
-        }
-        if (HD) {
-#pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                gxw[0][k] = gxw[1][k]; gxw[1][k] = gxn[k];
-                hyp[k] = hyn[k];
-            }
-#pragma unroll
-            for (int m = 0; m < 4; ++m) { fmx[0][m] = fmx[1][m]; fmx[1][m] = fmn[m]; }
-            sw[0] = sw[1]; sw[1] = s_new;
-            gyp[0] = gyn[QVX]; gyp[1] = gyn[QB];
-        }
-    }
-
-    if (STAGE == 4) {
-        // block reduction of the wave speeds, one atomic per block
-        auto &red = lds.red;
-        for (int off = 32; off > 0; off >>= 1) {
-            cx_t = fmax(cx_t, __shfl_xor(cx_t, off));
-            cy_t = fmax(cy_t, __shfl_xor(cy_t, off));
-            bad_t |= __shfl_xor(bad_t, off);
-        }
-        const int w = tid >> 6;
-        if ((tid & 63) == 0) { red[0][w] = cx_t; red[1][w] = cy_t; red[2][w] = (double)bad_t; }
-        __syncthreads();
-        if (tid == 0) {
-            double mx_ = 0.0, my_ = 0.0, bb = 0.0;
-            for (int k = 0; k < NT / 64; ++k) { mx_ = fmax(mx_, red[0][k]); my_ = fmax(my_, red[1][k]); bb = fmax(bb, red[2][k]); }
-            DevScalars *scw = a.sc;
-            const int nslot = scw->cur ^ 1;
-            atomicMax(&scw->cacc[nslot][0], (unsigned long long)__double_as_longlong(mx_));
-            atomicMax(&scw->cacc[nslot][1], (unsigned long long)__double_as_longlong(my_));
-            if (bb > 0.0) atomicOr(&scw->nonphys, 1);
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// One-dimensional subdomains (ny = 1, y periodic): every y difference of the
-// defining sequence is an exact zero, so the y half of the pipeline is not
-// computed; those zeros still enter the sums exactly where the defining
-// sequence adds them, so the results are the same bits as the 2-D path.
-// A tile is TX columns of the single row.
-// ---------------------------------------------------------------------------
-template <typename real, int NT, int STAGE, bool HD>
-__device__ __forceinline__ void stage_tile_1d(const StageArgs<real> &a, int tile_x, TileLds<real, NT> &lds) {
-    constexpr int TX = NT - 2 * G;
-    const DevScalars *sc = a.sc;
-    if (!sc->active) return;
-    const real dt = (real)sc->dt, hdt = (real)sc->hdt, dt6 = (real)sc->dt6;
-    real kx2[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) kx2[k] = (real)sc->kx2[k];
-    const SchemeConsts &kc = a.k;
-    const real gamma = (real)kc.gamma, gm1 = (real)kc.gm1, igm1 = (real)kc.igm1;
-    const real i12dx = (real)kc.i12dx, idx = (real)kc.idx, i2dx = (real)kc.i2dx, third = (real)kc.third;
-    const real half = (real)0.5, two = (real)2, eight = (real)8, zero = (real)0;
-    const Layout L = a.L;
-    const int tid = threadIdx.x;
-    const int c = tile_x * TX - G + tid;
-    const bool colv = c < L.nx + G;
-    const bool outcol = tid >= G && tid < NT - G && c < L.nx;
-    const int tm1 = tid >= 1 ? tid - 1 : 0;
-    const int tm2 = tid >= 2 ? tid - 2 : 0;
-    const int tp1 = tid + 1 < NT ? tid + 1 : NT - 1;
-    const int tp2 = tid + 2 < NT ? tid + 2 : NT - 1;
-    const int tp3 = tid + 3 < NT ? tid + 3 : NT - 1;
-    auto &sh_fx = lds.fx;
-    auto &sh_q = lds.q[0];
-    auto &sh_s = lds.s;
-    auto &sh_hx = lds.hx;
-    // row 0 of the subdomain (interior row)
-    const int64_t ro = (int64_t)L.xoff + (colv ? c : L.nx + G - 1) + (int64_t)G * L.pitch;
-    const int64_t oo = (int64_t)L.xoff + c + (int64_t)G * L.pitch;
-    Row6<real> pS, pU;
-    if (outcol) {
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            if (STAGE != 3) pS.v[f] = a.S[f][oo];
-            if (STAGE == 2 || STAGE == 3) pU.v[f] = a.U[f][oo];
-            if (STAGE == 4) pU.v[f] = a.A[f][oo];
-        }
-    }
-    const real rt = a.S[0][ro], mx = a.S[1][ro], my = a.S[2][ro], et = a.S[3][ro], bxt = a.S[4][ro], byt = a.S[5][ro];
-    const real rho = zero + rt;
-    const real irho = (real)1 / rho;
-    const real vx = mx * irho, vy = my * irho;
-    const real kin = half * (mx * vx + my * vy);
-    const real bbdot = zero * bxt + zero * byt;
-    const real bt2 = bxt * bxt + byt * byt;
-    const real pk = gm1 * (((et - kin) - bbdot) - half * bt2);
-    const real pt = (pk + half * bt2) + bbdot;
-    const real eps = pk * igm1;
-    const real bxT = zero + bxt, byT = zero + byt;
-    const real bvt = bxt * vx + byt * vy;
-    const real bvb = zero * vx + zero * vy;
-    const real ef = et + zero + pt;
-    sh_fx[CR][tid] = mx;
-    sh_fx[CMX][tid] = (vx * mx - (bxt * bxt + two * bxt * zero)) + pt;
-    sh_fx[CMY][tid] = vx * my - (bxt * byt + bxt * zero + zero * byt);
-    sh_fx[CE][tid] = ((vx * ef - bxt * bvt) - bxt * bvb) - zero * bvt;
-    sh_fx[CB][tid] = vx * byT - bxT * vy;
-    sh_q[QR][tid] = rt;
-    sh_q[QE][tid] = eps;
-    sh_q[QVX][tid] = vx;
-    sh_q[QVY][tid] = vy;
-    sh_q[QB][tid] = byt;
-    sh_q[QRHO][tid] = rho;
-    sh_q[QBYT][tid] = byT;
-    __syncthreads();
-    real K[6];
-    {
-        real dxn[5];
-#pragma unroll
-        for (int k = 0; k < 5; ++k)
-            dxn[k] = (eight * (sh_fx[k][tp1] - sh_fx[k][tm1]) - (sh_fx[k][tp2] - sh_fx[k][tm2])) * i12dx;
-        // D_y of any flux is an exact +0 (identical rows)
-        K[0] = -(dxn[CR] + zero);
-        K[1] = -(dxn[CMX] + zero);
-        K[2] = -(dxn[CMY] + zero);
-        K[3] = -(dxn[CE] + zero);
-        K[4] = -(zero + zero);
-        K[5] = -(dxn[CB] + zero);
-    }
-    if (HD) {
-        const real dv = (sh_q[QVX][tp1] - sh_q[QVX][tm1]) * i2dx + zero;
-        const real s_c = fmax(zero, -dv);
-        sh_s[tid] = s_c;
-        __syncthreads();
-        const real sfx = fmax(s_c, sh_s[tp1]);
-        real gx[5];
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const int cl = qclass(k);
-            const real q0 = sh_q[k][tm2], q1 = sh_q[k][tm1], q2 = sh_q[k][tid];
-            const real q3 = sh_q[k][tp1], q4 = sh_q[k][tp2], q5 = sh_q[k][tp3];
-            const real R = hd_ratio(q0, q1, q2, q3, q4, q5);
-            const real nu = kx2[cl] * R + (real)kc.kxs[cl] * sfx;
-            gx[k] = nu * (q3 - q2) * idx;
-        }
-        const real rf = half * (sh_q[QRHO][tid] + sh_q[QRHO][tp1]);
-        const real vxf = half * (sh_q[QVX][tid] + sh_q[QVX][tp1]);
-        const real vyf = half * (sh_q[QVY][tid] + sh_q[QVY][tp1]);
-        const real byf = half * (sh_q[QBYT][tid] + sh_q[QBYT][tp1]);
-        // the four-face averages of y-face G vanish exactly (G_y = +0)
-        const real txx = rf * gx[QVX];
-        const real txy = half * rf * (gx[QVY] + zero);
-        const real ez = gx[QB] - zero;
-        sh_hx[CR][tid] = gx[QR];
-        sh_hx[CMX][tid] = txx;
-        sh_hx[CMY][tid] = txy;
-        sh_hx[CE][tid] = (gx[QE] + (vxf * txx + vyf * txy)) + byf * ez;
-        sh_hx[CB][tid] = ez;
-        __syncthreads();
-        // H_y is the same on both y faces of the row: its difference is +0
-        K[0] = K[0] + ((sh_hx[CR][tid] - sh_hx[CR][tm1]) * idx + zero);
-        K[1] = K[1] + ((sh_hx[CMX][tid] - sh_hx[CMX][tm1]) * idx + zero);
-        K[2] = K[2] + ((sh_hx[CMY][tid] - sh_hx[CMY][tm1]) * idx + zero);
-        K[3] = K[3] + ((sh_hx[CE][tid] - sh_hx[CE][tm1]) * idx + zero);
-        K[4] = K[4] + (zero + zero);
-        K[5] = K[5] + ((sh_hx[CB][tid] - sh_hx[CB][tm1]) * idx + zero);
-    }
-    double cx_t = 0.0, cy_t = 0.0;
-    int bad_t = 0;
-    if (outcol) {
-        if (STAGE == 1) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) a.out1[f][oo] = pS.v[f] + hdt * K[f];
-        } else if (STAGE == 2) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                const real u = pU.v[f], s = pS.v[f];
-                a.out1[f][oo] = u + hdt * K[f];
-                a.out2[f][oo] = (u + u) + ((s - u) + dt * K[f]);
-            }
-        } else if (STAGE == 3) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) a.out1[f][oo] = pU.v[f] + dt * K[f];
-        } else {
-            real un[6];
-#pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                const real av = pU.v[f], s = pS.v[f];
-                un[f] = (s + (av - (s + s)) * third) + dt6 * K[f];
-                a.out1[f][oo] = un[f];
-            }
-            const real r0 = zero + un[0];
-            const real ir0 = (real)1 / r0;
-            const real ux = un[1] * ir0, uy = un[2] * ir0;
-            const real kn = half * (un[1] * ux + un[2] * uy);
-            const real bbd = zero * un[4] + zero * un[5];
-            const real b2t = un[4] * un[4] + un[5] * un[5];
-            const real pkt = gm1 * (((un[3] - kn) - bbd) - half * b2t);
-            const real b2b = zero * zero + zero * zero;
-            const real pkb = gm1 * (zero - half * b2b);
-            const real pkk = pkb + pkt;
-            const real bxx = zero + un[4], byy = zero + un[5];
-            const real cf = sqrt((gamma * pkk + (bxx * bxx + byy * byy)) * ir0);
-            const bool fin = isfinite(un[0]) && isfinite(un[1]) && isfinite(un[2]) && isfinite(un[3]) &&
-                             isfinite(un[4]) && isfinite(un[5]) && isfinite(cf);
-            if (!(r0 > (real)0) || !(pkk > (real)0) || !fin) {
-                bad_t = 1;
-            } else {
-                cx_t = fmax(cx_t, (double)(fabs(ux) + cf));
-                cy_t = fmax(cy_t, (double)(fabs(uy) + cf));
-            }
-        }
-    }
-    if (STAGE == 4) {
-        auto &red = lds.red;
-        for (int off = 32; off > 0; off >>= 1) {
-            cx_t = fmax(cx_t, __shfl_xor(cx_t, off));
-            cy_t = fmax(cy_t, __shfl_xor(cy_t, off));
-            bad_t |= __shfl_xor(bad_t, off);
-        }
-        const int w = tid >> 6;
-        if ((tid & 63) == 0) { red[0][w] = cx_t; red[1][w] = cy_t; red[2][w] = (double)bad_t; }
-        __syncthreads();
-        if (tid == 0) {
-            double mx_ = 0.0, my_ = 0.0, bb = 0.0;
-            for (int k = 0; k < NT / 64; ++k) { mx_ = fmax(mx_, red[0][k]); my_ = fmax(my_, red[1][k]); bb = fmax(bb, red[2][k]); }
-            DevScalars *scw = a.sc;
-            const int nslot = scw->cur ^ 1;
-            atomicMax(&scw->cacc[nslot][0], (unsigned long long)__double_as_longlong(mx_));
-            atomicMax(&scw->cacc[nslot][1], (unsigned long long)__double_as_longlong(my_));
-            if (bb > 0.0) atomicOr(&scw->nonphys, 1);
-        }
-    }
-}
 
 template <typename real, int NT, int STAGE, bool HD, bool BG, bool SUR = false>
 __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
@@ -764,359 +59,5 @@ hipError_t launch_stage(int stage, bool hd, bool bg, const StageArgs<real> &a, h
 template hipError_t launch_stage<double>(int, bool, bool, const StageArgs<double> &, hipStream_t);
 template hipError_t launch_stage<float>(int, bool, bool, const StageArgs<float> &, hipStream_t);
 
-// ---------------------------------------------------------------------------
-// Plain coefficient-ratio fields (the surrogate's training target and judge).
-// The quantities are formed from the state exactly as in the stage kernel
-// (same operations, same order, no background), so a ratio computed here is
-// the one the plain stage would use at that face.
-// ---------------------------------------------------------------------------
-
-// quantity sets at cell (i, j): q = {rho~, eps~, v_x, v_y, B~_y, B~_x}
-template <typename real>
-__device__ __forceinline__ void cell_quantities(const RatioArgs<real> &a, int i, int j, real q[6]) {
-    const int64_t o = (int64_t)a.L.xoff + i + (int64_t)(j + G) * a.L.pitch;
-    const real gm1 = (real)a.gm1, igm1 = (real)a.igm1, half = (real)0.5;
-    const real rb = 0, bxb = 0, byb = 0;
-    const real rt = a.S[0][o], mx = a.S[1][o], my = a.S[2][o], et = a.S[3][o], bxt = a.S[4][o], byt = a.S[5][o];
-    const real rho = rb + rt;
-    const real irho = (real)1 / rho;
-    const real vx = mx * irho, vy = my * irho;
-    const real kin = half * (mx * vx + my * vy);
-    const real bbdot = bxb * bxt + byb * byt;
-    const real bt2 = bxt * bxt + byt * byt;
-    const real pk = gm1 * (((et - kin) - bbdot) - half * bt2);
-    q[0] = rt; q[1] = pk * igm1; q[2] = vx; q[3] = vy; q[4] = byt; q[5] = bxt;
-}
-
-// the ten plain ratios of the faces above cell (i, j): R[k] x-face set k,
-// R[5 + k] y-face set k; D1 (optional) the first differences at those faces
-template <typename real>
-__device__ __forceinline__ void cell_ratios(const RatioArgs<real> &a, int i, int j, real R[10], real *D1 = nullptr) {
-    real qx[6][6], qy[6][6];   // [offset -2..3][quantity]
-#pragma unroll
-    for (int m = 0; m < 6; ++m) {
-        cell_quantities(a, i - 2 + m, j, qx[m]);
-        if (m == 2) {
-#pragma unroll
-            for (int k = 0; k < 6; ++k) qy[m][k] = qx[m][k];
-        } else {
-            cell_quantities(a, i, j - 2 + m, qy[m]);
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const int kx = k == 4 ? 4 : k, ky = k == 4 ? 5 : k;   // B~_y on x faces, B~_x on y faces
-        R[k] = hd_ratio(qx[0][kx], qx[1][kx], qx[2][kx], qx[3][kx], qx[4][kx], qx[5][kx]);
-        R[5 + k] = hd_ratio(qy[0][ky], qy[1][ky], qy[2][ky], qy[3][ky], qy[4][ky], qy[5][ky]);
-        if (D1) {
-            D1[k] = qx[3][kx] - qx[2][kx];
-            D1[5 + k] = qy[3][ky] - qy[2][ky];
-        }
-    }
-}
-
-// first differences of the ten sets at the faces above cell (i, j)
-template <typename real>
-__device__ __forceinline__ void cell_d1(const RatioArgs<real> &a, int i, int j, real D1[10]) {
-    real q0[6], qx[6], qy[6];
-    cell_quantities(a, i, j, q0);
-    cell_quantities(a, i + 1, j, qx);
-    cell_quantities(a, i, j + 1, qy);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const int kx = k == 4 ? 4 : k, ky = k == 4 ? 5 : k;
-        D1[k] = qx[kx] - q0[kx];
-        D1[5 + k] = qy[ky] - q0[ky];
-    }
-}
-
-template <typename real>
-__global__ __launch_bounds__(256) void k_ratio_fields(RatioArgs<real> a, float *out, float *d1, int64_t pitch) {
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= a.L.nx || j >= a.L.ny) return;
-    real R[10], D[10];
-    cell_ratios(a, i, j, R, D);
-    const int64_t plane = pitch * a.L.ny;
-#pragma unroll
-    for (int k = 0; k < 10; ++k) out[k * plane + (int64_t)j * pitch + i] = (float)R[k];
-    if (d1) {
-#pragma unroll
-        for (int k = 0; k < 10; ++k) d1[k * plane + (int64_t)j * pitch + i] = (float)D[k];
-    }
-}
-
-template <typename real>
-hipError_t launch_ratio_fields(const RatioArgs<real> &a, float *out, float *d1, int64_t pitch, hipStream_t s) {
-    dim3 grid((a.L.nx + 63) / 64, (a.L.ny + 3) / 4);
-    hipLaunchKernelGGL(k_ratio_fields<real>, grid, dim3(256), 0, s, a, out, d1, pitch);
-    return hipGetLastError();
-}
-
-// per-plane largest |first difference| over the domain (flux metric scale)
-__global__ void k_check_reset(HdDevStats *st) {
-    if (threadIdx.x < 10) st->dmax[threadIdx.x] = 0ull;
-}
-
-template <typename real>
-__global__ __launch_bounds__(256) void k_d1_max(RatioArgs<real> a, HdDevStats *st) {
-    __shared__ double red[4][10];
-    double m[10];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) m[k] = 0.0;
-    const int64_t n = (int64_t)a.L.nx * a.L.ny;
-    for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n; c += (int64_t)gridDim.x * 256) {
-        const int j = (int)(c / a.L.nx), i = (int)(c - (int64_t)j * a.L.nx);
-        real D[10];
-        cell_d1(a, i, j, D);
-#pragma unroll
-        for (int k = 0; k < 10; ++k) m[k] = fmax(m[k], (double)fabs(D[k]));
-    }
-#pragma unroll
-    for (int k = 0; k < 10; ++k)
-        for (int off = 32; off > 0; off >>= 1) m[k] = fmax(m[k], __shfl_xor(m[k], off));
-    if ((threadIdx.x & 63) == 0) {
-#pragma unroll
-        for (int k = 0; k < 10; ++k) red[threadIdx.x >> 6][k] = m[k];
-    }
-    __syncthreads();
-    if (threadIdx.x < 10) {
-        const int k = threadIdx.x;
-        const double v = fmax(fmax(red[0][k], red[1][k]), fmax(red[2][k], red[3][k]));
-        atomicMax(&st->dmax[k], (unsigned long long)__double_as_longlong(v));
-    }
-}
-
-// The surrogate check: one block per tile x tile cells.  Each ratio-plane
-// value r gets an error e = |r - R_plain| (METRIC 0) or the flux-weighted
-// e = |r - R_plain| |d1| / D (METRIC 1; d1 the face's first difference, D the
-// plane's largest |d1| over the domain, e = 0 when D = 0).  A tile falls
-// back when any value is not finite or has NOT(e <= bound); then the whole
-// tile of every plane is set to -1 (plain ratio).  Arithmetic in the working
-// precision.
-template <typename real, int METRIC>
-__global__ __launch_bounds__(256) void k_hd_check(RatioArgs<real> a, float *rs, int64_t pitch, double bound,
-                                                  int tile, HdDevStats *st) {
-    __shared__ double s_err[4];
-    __shared__ int s_bad[4];
-    const int ntx = (a.L.nx + tile - 1) / tile;
-    const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
-    const int i0 = tx * tile, j0 = ty * tile;
-    const int wx = min(tile, a.L.nx - i0), wy = min(tile, a.L.ny - j0);
-    const int64_t plane = pitch * a.L.ny;
-    const real b = (real)bound;
-    real dm[10];
-    if (METRIC == 1) {
-#pragma unroll
-        for (int k = 0; k < 10; ++k) dm[k] = (real)__longlong_as_double((long long)st->dmax[k]);
-    }
-    double emax = 0.0;
-    int bad = 0;
-    for (int c = threadIdx.x; c < wx * wy; c += 256) {
-        const int i = i0 + c % wx, j = j0 + c / wx;
-        real R[10], D[10];
-        cell_ratios(a, i, j, R, D);
-#pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            const float rv = rs[k * plane + (int64_t)j * pitch + i];
-            real e = fabs((real)rv - R[k]);
-            if (METRIC == 1) e = dm[k] > (real)0 ? (e * fabs(D[k])) / dm[k] : (real)0;
-            if (!isfinite(rv) || !(e <= b)) bad = 1;
-            if (isfinite(e)) emax = fmax(emax, (double)e);
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        emax = fmax(emax, __shfl_xor(emax, off));
-        bad |= __shfl_xor(bad, off);
-    }
-    if ((threadIdx.x & 63) == 0) { s_err[threadIdx.x >> 6] = emax; s_bad[threadIdx.x >> 6] = bad; }
-    __syncthreads();
-    const double et = fmax(fmax(s_err[0], s_err[1]), fmax(s_err[2], s_err[3]));
-    const int bt = s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3];
-    if (threadIdx.x == 0) {
-        atomicMax(&st->err_all, (unsigned long long)__double_as_longlong(et));
-        if (bt) atomicAdd(&st->tiles_fallback, 1ull);
-        else atomicMax(&st->err_used, (unsigned long long)__double_as_longlong(et));
-    }
-    if (bt) {
-        for (int c = threadIdx.x; c < wx * wy; c += 256) {
-            const int i = i0 + c % wx, j = j0 + c / wx;
-#pragma unroll
-            for (int k = 0; k < 10; ++k) rs[k * plane + (int64_t)j * pitch + i] = -1.0f;
-        }
-    }
-}
-
-template <typename real>
-hipError_t launch_hd_check(const RatioArgs<real> &a, float *rs, int64_t pitch, double bound, int tile, int metric,
-                           HdDevStats *st, hipStream_t s) {
-    const int ntx = (a.L.nx + tile - 1) / tile, nty = (a.L.ny + tile - 1) / tile;
-    if (metric == 1) {
-        hipLaunchKernelGGL(k_check_reset, dim3(1), dim3(64), 0, s, st);
-        const int64_t n = (int64_t)a.L.nx * a.L.ny;
-        const int blocks = (int)std::min<int64_t>((n + 255) / 256, 2048);
-        hipLaunchKernelGGL(k_d1_max<real>, dim3(blocks), dim3(256), 0, s, a, st);
-        hipLaunchKernelGGL((k_hd_check<real, 1>), dim3(ntx * nty), dim3(256), 0, s, a, rs, pitch, bound, tile, st);
-    } else {
-        hipLaunchKernelGGL((k_hd_check<real, 0>), dim3(ntx * nty), dim3(256), 0, s, a, rs, pitch, bound, tile, st);
-    }
-    return hipGetLastError();
-}
-
-// Network input of a state: (rho, v_x, v_y, B_x, B_y, e) per cell, then
-// (f - shift) * scale in FP32, rounded to BF16; 8 values per pixel (two zero).
-template <typename real>
-__global__ __launch_bounds__(256) void k_cnn_inputs(RatioArgs<real> a, InputNorm nm, unsigned short *x) {
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= a.L.nx || j >= a.L.ny) return;
-    const int64_t o = (int64_t)a.L.xoff + i + (int64_t)(j + G) * a.L.pitch;
-    const real rt = a.S[0][o];
-    const real irho = (real)1 / rt;
-    const float f[6] = {(float)rt, (float)(a.S[1][o] * irho), (float)(a.S[2][o] * irho), (float)a.S[4][o],
-                        (float)a.S[5][o], (float)a.S[3][o]};
-    unsigned short h[8];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) h[k] = bf16_rne((f[k] - nm.v[k]) * nm.v[6 + k]);
-    h[6] = h[7] = 0;
-    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-    *(u32x4 *)(x + ((int64_t)j * a.L.nx + i) * 8) =
-        u32x4{h[0] | ((unsigned)h[1] << 16), h[2] | ((unsigned)h[3] << 16), h[4] | ((unsigned)h[5] << 16), 0u};
-}
-
-template <typename real>
-hipError_t launch_cnn_inputs(const RatioArgs<real> &a, const InputNorm &norm, void *x, hipStream_t s) {
-    dim3 grid((a.L.nx + 63) / 64, (a.L.ny + 3) / 4);
-    hipLaunchKernelGGL(k_cnn_inputs<real>, grid, dim3(256), 0, s, a, norm, (unsigned short *)x);
-    return hipGetLastError();
-}
-
-template hipError_t launch_ratio_fields<double>(const RatioArgs<double> &, float *, float *, int64_t, hipStream_t);
-template hipError_t launch_ratio_fields<float>(const RatioArgs<float> &, float *, float *, int64_t, hipStream_t);
-template hipError_t launch_hd_check<double>(const RatioArgs<double> &, float *, int64_t, double, int, int,
-                                            HdDevStats *, hipStream_t);
-template hipError_t launch_hd_check<float>(const RatioArgs<float> &, float *, int64_t, double, int, int,
-                                           HdDevStats *, hipStream_t);
-template hipError_t launch_cnn_inputs<double>(const RatioArgs<double> &, const InputNorm &, void *, hipStream_t);
-template hipError_t launch_cnn_inputs<float>(const RatioArgs<float> &, const InputNorm &, void *, hipStream_t);
-
-// ---------------------------------------------------------------------------
-// Batched persistent launch: every step of every instance in one cooperative
-// launch (all blocks co-resident, which the runtime checks at launch).  Per
-// step: each instance's dt from its own reduced wave speeds; then per stage a
-// ghost fill of all instances' stage inputs, a grid barrier, all instances'
-// tiles taken from a work queue (one atomic counter per step and stage,
-// tiles ordered most expensive first), a grid barrier.  The tile arithmetic
-// is the same device code as the per-subdomain kernels, so each instance
-// evolves bit for bit as it does alone.
-// ---------------------------------------------------------------------------
-namespace cg = cooperative_groups;
-
-__device__ __forceinline__ int bwrap(int i, int n, int periodic) {
-    if (periodic) { int r = i % n; return r < 0 ? r + n : r; }
-    return i < 0 ? 0 : (i >= n ? n - 1 : i);
-}
-
-template <typename real, int STAGE>
-__device__ void batch_ghost_fill(const BatchArgs<real> &b, int n_blocks_threads, int gtid) {
-    const long long total = b.gbeg[b.n];
-    for (long long g = gtid; g < total; g += n_blocks_threads) {
-        // instance by binary search over the prefix offsets
-        int lo = 0, hi = b.n - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (b.gbeg[mid] <= g) lo = mid; else hi = mid - 1;
-        }
-        const BatchInst<real> &I = b.inst[lo];
-        const int nx = I.L.nx, ny = I.L.ny, W = nx + 2 * G;
-        const long long gc = 2LL * G * W + 2LL * G * ny;   // ghost cells per field
-        long long m = g - b.gbeg[lo];
-        const int f = (int)(m / gc);
-        m -= (long long)f * gc;
-        int ci, rj;
-        if (m < 2LL * G * W) {
-            const int rr = (int)(m / W);
-            ci = (int)(m % W) - G;
-            rj = rr < G ? rr - G : ny + rr - G;
-        } else {
-            const long long m2 = m - 2LL * G * W;
-            rj = (int)(m2 / (2 * G));
-            const int cc = (int)(m2 % (2 * G));
-            ci = cc < G ? cc - G : nx + cc - G;
-        }
-        real *S = const_cast<real *>(I.st[STAGE - 1].S[f]);
-        const int si = bwrap(ci, nx, I.periodic_x), sj = bwrap(rj, ny, I.periodic_y);
-        S[(int64_t)I.L.xoff + ci + (int64_t)(rj + G) * I.L.pitch] =
-            S[(int64_t)I.L.xoff + si + (int64_t)(sj + G) * I.L.pitch];
-    }
-}
-
-template <typename real, int NT, int STAGE>
-__device__ void batch_stage(const BatchArgs<real> &b, int step, TileLds<real, NT> &lds, int &s_item,
-                            cg::grid_group &grid) {
-    batch_ghost_fill<real, STAGE>(b, (int)(gridDim.x * NT), (int)(blockIdx.x * NT + threadIdx.x));
-    grid.sync();
-    int *ctr = b.ctr + step * 4 + (STAGE - 1);
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_item = atomicAdd(ctr, 1);
-        __syncthreads();
-        const int it = s_item;
-        if (it >= b.nitems) break;
-        const BatchItem w = b.items[it];
-        const BatchInst<real> &I = b.inst[w.inst];
-        if (I.oned) stage_tile_1d<real, NT, STAGE, true>(I.st[STAGE - 1], w.tx, lds);
-        else stage_tile<real, NT, STAGE, true, false>(I.st[STAGE - 1], w.tx, w.ty, lds);
-    }
-    grid.sync();
-}
-
-template <typename real, int NT>
-__global__ __launch_bounds__(NT) void k_batch(BatchArgs<real> b) {
-    __shared__ TileLds<real, NT> lds;
-    __shared__ int s_item;
-    cg::grid_group grid = cg::this_grid();
-    for (int step = 0; step < b.nsteps; ++step) {
-        if (blockIdx.x == 0)
-            for (int i = threadIdx.x; i < b.n; i += NT) step_begin_dev(b.inst[i].sc, 0.0, b.inst[i].sk);
-        grid.sync();
-        batch_stage<real, NT, 1>(b, step, lds, s_item, grid);
-        batch_stage<real, NT, 2>(b, step, lds, s_item, grid);
-        batch_stage<real, NT, 3>(b, step, lds, s_item, grid);
-        batch_stage<real, NT, 4>(b, step, lds, s_item, grid);
-        if (blockIdx.x == 0)
-            for (int i = threadIdx.x; i < b.n; i += NT) step_end_dev(b.inst[i].sc);
-        grid.sync();
-    }
-}
-
-template <typename real, int NT>
-static hipError_t launch_batch_nt(const BatchArgs<real> &b, int blocks, hipStream_t s) {
-    void *args[] = {(void *)&b};
-    return hipLaunchCooperativeKernel((const void *)k_batch<real, NT>, dim3(blocks), dim3(NT), args, 0, s);
-}
-
-template <typename real>
-hipError_t launch_batch(const BatchArgs<real> &b, int nt, int blocks, hipStream_t s) {
-    switch (nt) {
-        case 64: return launch_batch_nt<real, 64>(b, blocks, s);
-        case 128: return launch_batch_nt<real, 128>(b, blocks, s);
-        default: return launch_batch_nt<real, 256>(b, blocks, s);
-    }
-}
-
-template <typename real>
-hipError_t batch_blocks_per_cu(int nt, int *blocks) {
-    switch (nt) {
-        case 64: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch<real, 64>, 64, 0);
-        case 128: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch<real, 128>, 128, 0);
-        default: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_batch<real, 256>, 256, 0);
-    }
-}
-
-template hipError_t launch_batch<double>(const BatchArgs<double> &, int, int, hipStream_t);
-template hipError_t launch_batch<float>(const BatchArgs<float> &, int, int, hipStream_t);
-template hipError_t batch_blocks_per_cu<double>(int, int *);
-template hipError_t batch_blocks_per_cu<float>(int, int *);
 
 }  // namespace sacx
