@@ -17,15 +17,19 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsacx.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["sacx_stage.hip", "sacx_batch.hip", "sacx_ratio.hip", "sacx_runtime.hip", "sacx_cnn.hip"]
+SOURCES = ["sacx_stage.hip", "sacx_stage32.hip", "sacx_batch.hip", "sacx_batch32.hip", "sacx_ratio.hip",
+           "sacx_runtime.hip", "sacx_cnn.hip"]
+# per-file floating-point contraction: the FP32 stage and batch units contract
+# the multiply-adds written within one expression (a rule of the source alone,
+# so both kernels round an instance the same way); every other unit rounds
+# each operation on its own
+CONTRACT = {"sacx_stage32.hip": "-ffp-contract=on", "sacx_batch32.hip": "-ffp-contract=on"}
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
-    # every operation rounds once, in source order (bit-reproducible FP64 path)
-    "-ffp-contract=off",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC,
@@ -35,7 +39,7 @@ FLAGS = [
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, CONTRACT.get(src, "-ffp-contract=off"), "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)

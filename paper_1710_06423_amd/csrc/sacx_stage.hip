@@ -1,63 +1,10 @@
-// sacx_stage.hip -- the fused RK stage kernel (one launch per RK stage of one
-// subdomain) and its launchers; the tile code is in sacx_tile.h.
-#include "sacx_tile.h"
+// sacx_stage.hip -- FP64 instantiation of the fused RK stage kernel (built
+// with -ffp-contract=off: every operation rounds once, in the order of the
+// scheme's defining sequence).
+#include "sacx_stage_kernel.h"
 
 namespace sacx {
 
-template <typename real, int NT, int STAGE, bool HD, bool BG, bool SUR = false>
-__global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
-    __shared__ TileLds<real, NT> lds;
-    stage_tile<real, NT, STAGE, HD, BG, SUR>(a, blockIdx.x, blockIdx.y, lds);
-}
-
-template <typename real, int NT, int STAGE, bool HD>
-__global__ __launch_bounds__(NT) void k_stage_1d(StageArgs<real> a) {
-    __shared__ TileLds<real, NT> lds;
-    stage_tile_1d<real, NT, STAGE, HD>(a, blockIdx.x, lds);
-}
-
-template <typename real, int NT, int STAGE>
-static hipError_t launch_s(bool hd, bool bg, const StageArgs<real> &a, hipStream_t s) {
-    constexpr int TX = NT - 2 * G;
-    if (a.L.ny == 1 && a.L.nx >= 2 && !bg) {
-        dim3 grid((a.L.nx + TX - 1) / TX, 1);
-        if (hd) hipLaunchKernelGGL((k_stage_1d<real, NT, STAGE, true>), grid, dim3(NT), 0, s, a);
-        else hipLaunchKernelGGL((k_stage_1d<real, NT, STAGE, false>), grid, dim3(NT), 0, s, a);
-        return hipGetLastError();
-    }
-    dim3 grid((a.L.nx + TX - 1) / TX, (a.L.ny + a.ty - 1) / a.ty);
-    if (a.Rs && hd && !bg) {
-        hipLaunchKernelGGL((k_stage<real, NT, STAGE, true, false, true>), grid, dim3(NT), 0, s, a);
-        return hipGetLastError();
-    }
-    if (hd && bg) hipLaunchKernelGGL((k_stage<real, NT, STAGE, true, true>), grid, dim3(NT), 0, s, a);
-    else if (hd) hipLaunchKernelGGL((k_stage<real, NT, STAGE, true, false>), grid, dim3(NT), 0, s, a);
-    else if (bg) hipLaunchKernelGGL((k_stage<real, NT, STAGE, false, true>), grid, dim3(NT), 0, s, a);
-    else hipLaunchKernelGGL((k_stage<real, NT, STAGE, false, false>), grid, dim3(NT), 0, s, a);
-    return hipGetLastError();
-}
-
-template <typename real, int NT>
-static hipError_t launch_nt(int stage, bool hd, bool bg, const StageArgs<real> &a, hipStream_t s) {
-    switch (stage) {
-        case 1: return launch_s<real, NT, 1>(hd, bg, a, s);
-        case 2: return launch_s<real, NT, 2>(hd, bg, a, s);
-        case 3: return launch_s<real, NT, 3>(hd, bg, a, s);
-        default: return launch_s<real, NT, 4>(hd, bg, a, s);
-    }
-}
-
-template <typename real>
-hipError_t launch_stage(int stage, bool hd, bool bg, const StageArgs<real> &a, hipStream_t s) {
-    switch (a.nt) {
-        case 64: return launch_nt<real, 64>(stage, hd, bg, a, s);
-        case 128: return launch_nt<real, 128>(stage, hd, bg, a, s);
-        default: return launch_nt<real, 256>(stage, hd, bg, a, s);
-    }
-}
-
 template hipError_t launch_stage<double>(int, bool, bool, const StageArgs<double> &, hipStream_t);
-template hipError_t launch_stage<float>(int, bool, bool, const StageArgs<float> &, hipStream_t);
-
 
 }  // namespace sacx
