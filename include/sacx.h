@@ -125,7 +125,9 @@ int sacx_destroy(sacx_ctx *ctx);
 /* Set the boundary kind of each side (paper section 5: periodic for
  * Orszag-Tang; open for the shock tube).  Periodic sides must come in pairs
  * (x-, x+ and y-, y+), else EINVAL.  A direction with one cell must be
- * periodic.  Takes effect at the next halo fill. */
+ * periodic.  Takes effect at the next halo fill.  While a learned
+ * coefficient is set (sacx_hd_set_surrogate) only all-periodic boundaries
+ * are accepted (ESTATE otherwise). */
 int sacx_set_boundaries(sacx_ctx *ctx, const int32_t bc[4]);
 
 /* Load a state (paper section 3: the initial model configuration a process
@@ -183,6 +185,15 @@ int sacx_halo_unpack(sacx_ctx *ctx, int32_t side, const void *d_buf);
 int sacx_set_launch(sacx_ctx *ctx, int32_t threads, int32_t rows);
 int sacx_get_launch(const sacx_ctx *ctx, int32_t *threads, int32_t *rows);
 
+/* Tile kind of FP64 two-dimensional contexts with hyper-diffusion, no
+ * background and the plain coefficient: on = 1 (the default) gives every
+ * column two threads, one for the x-direction terms and one for the
+ * y-direction terms, in blocks of 2 * threads; on = 0 gives it one thread.
+ * Results are bit-identical either way; the two-thread tile holds half the
+ * per-thread state and runs two waves per SIMD.  Other contexts ignore the
+ * setting.  EINVAL unless on is 0 or 1. */
+int sacx_set_column_split(sacx_ctx *ctx, int32_t on);
+
 /* Per-phase timing on the context stream (HIP events around every launch
  * group), used to split a run into useful computation and halo exchange as in
  * the paper's cost model T = T_comp + T_comm + T_idle (section 6).
@@ -239,7 +250,9 @@ int sacx_batch_set_tiles(sacx_batch *b, int32_t threads, const int32_t *rows);
 /* Advance every instance by nsteps RK4 steps (each with its own dt) in one
  * persistent launch per 512 steps.  Every instance must have been
  * initialised (ESTATE otherwise).  With sync != 0 the call synchronises and
- * returns SACX_ENONPHYS if any instance stopped on a non-physical state. */
+ * returns SACX_ENONPHYS if any instance stopped on a non-physical state.
+ * The batch uses the plain hyper-diffusion coefficient: an instance whose
+ * context has a learned coefficient set gives SACX_EUNSUP. */
 int sacx_batch_advance(sacx_batch *b, int32_t nsteps, int32_t sync);
 
 

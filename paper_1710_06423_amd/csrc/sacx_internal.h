@@ -126,7 +126,9 @@ struct StageArgs {
     int64_t fstride;
     Layout L;
     int ty;               // output rows per block
-    int nt;               // threads per block (one column each)
+    int nt;               // columns per block (apron included)
+    int split;            // FP64 2-D hyper-diffusion tiles without background:
+                          // two threads per column (x and y roles)
     SchemeConsts k;
     int hd_cross_on;
     DevScalars *sc;

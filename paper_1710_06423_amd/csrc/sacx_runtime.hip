@@ -75,6 +75,7 @@ struct sacx_ctx {
     void *hx[2], *hy[2];
     bool initialized;
     int ty, nt;
+    int split;         // FP64 hyper-diffusion tiles: two threads per column
     double dx, dy;
     SchemeConsts kc;
     // profiling: event pairs recorded around launch groups, resolved at read
@@ -473,6 +474,7 @@ StageArgs<real> stage_args(sacx_ctx *c) {
     a.L = c->L;
     a.ty = c->ty;
     a.nt = c->nt;
+    a.split = c->split;
     a.k = c->kc;
     a.hd_cross_on = c->params.hd_cross_on;
     a.sc = c->sc;
@@ -666,6 +668,7 @@ int sacx_create(const sacx_grid *grid, const sacx_params *params, void *d_ws, si
     // FP32 with 4-wave blocks; strips of 256 rows keep the 6-row warm-up small
     c->nt = grid->background_on ? 64 : (grid->precision == SACX_FP64 ? 128 : 256);
     c->ty = default_ty(c->L, c->nt);
+    c->split = 1;
     c->dx = (grid->x1 - grid->x0) / grid->nx;
     c->dy = (grid->y1 - grid->y0) / grid->ny;
     {
@@ -730,6 +733,13 @@ int sacx_set_launch(sacx_ctx *ctx, int32_t threads, int32_t rows) {
     return SACX_OK;
 }
 
+int sacx_set_column_split(sacx_ctx *ctx, int32_t on) {
+    if (!ctx) return fail(SACX_EINVAL, "ctx must not be NULL");
+    if (on != 0 && on != 1) return fail(SACX_EINVAL, "on must be 0 or 1 (got %d)", on);
+    ctx->split = on;
+    return SACX_OK;
+}
+
 int sacx_get_launch(const sacx_ctx *ctx, int32_t *threads, int32_t *rows) {
     if (!ctx || !threads || !rows) return fail(SACX_EINVAL, "ctx/threads/rows must not be NULL");
     *threads = ctx->nt;
@@ -784,6 +794,10 @@ int sacx_set_boundaries(sacx_ctx *ctx, const int32_t bc[4]) {
         return fail(SACX_EINVAL, "periodic y boundaries must be paired");
     if (ctx->grid.nx == 1 && bc[0] != SACX_PERIODIC) return fail(SACX_EINVAL, "a one-cell direction must be periodic");
     if (ctx->grid.ny == 1 && bc[2] != SACX_PERIODIC) return fail(SACX_EINVAL, "a one-cell direction must be periodic");
+    if (ctx->sur_on)
+        for (int s = 0; s < 4; ++s)
+            if (bc[s] != SACX_PERIODIC)
+                return fail(SACX_ESTATE, "the surrogate's ratio planes are periodic: clear it before opening a boundary");
     for (int s = 0; s < 4; ++s) ctx->bc[s] = bc[s];
     return SACX_OK;
 }
@@ -1268,6 +1282,8 @@ int batch_build(sacx_batch *b) {
     std::vector<Costed> items;
     for (int i = 0; i < n; ++i) {
         sacx_ctx *c = (*b->ctx)[i];
+        if (c->sur_on)
+            return fail(SACX_EUNSUP, "instance %d has a learned coefficient set: the batch kernel uses the plain one", i);
         BatchInst<real> &I = tab[i];
         std::memset((void *)&I, 0, sizeof(I));
         void *const *S[4] = {c->U, c->B1, c->B2, c->B1};

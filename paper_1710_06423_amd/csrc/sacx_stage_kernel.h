@@ -4,7 +4,10 @@
 // sacx_stage32.hip: FP32 bulk arithmetic).
 #pragma once
 
+#include <type_traits>
+
 #include "sacx_tile.h"
+#include "sacx_tile_split.h"
 
 namespace sacx {
 
@@ -12,6 +15,13 @@ template <typename real, int NT, int STAGE, bool HD, bool BG, bool SUR = false>
 __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
     __shared__ TileLds<real, NT> lds;
     stage_tile<real, NT, STAGE, HD, BG, SUR>(a, blockIdx.x, blockIdx.y, lds);
+}
+
+// two threads per column (x and y roles), two waves per SIMD
+template <typename real, int NC, int STAGE>
+__global__ __launch_bounds__(2 * NC, 2) void k_stage_split(StageArgs<real> a) {
+    __shared__ SplitLds<real, NC> lds;
+    stage_tile_split<real, NC, STAGE>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 template <typename real, int NT, int STAGE, bool HD>
@@ -30,6 +40,12 @@ static hipError_t launch_s(bool hd, bool bg, const StageArgs<real> &a, hipStream
         return hipGetLastError();
     }
     dim3 grid((a.L.nx + TX - 1) / TX, (a.L.ny + a.ty - 1) / a.ty);
+    if constexpr (std::is_same<real, double>::value) {
+        if (a.split && hd && !bg && !a.Rs) {
+            hipLaunchKernelGGL((k_stage_split<real, NT, STAGE>), grid, dim3(2 * NT), 0, s, a);
+            return hipGetLastError();
+        }
+    }
     if (a.Rs && hd && !bg) {
         hipLaunchKernelGGL((k_stage<real, NT, STAGE, true, false, true>), grid, dim3(NT), 0, s, a);
         return hipGetLastError();

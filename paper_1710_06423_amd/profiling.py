@@ -25,7 +25,8 @@ import sys
 from typing import Dict, List, Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-STAGE_SOURCES = ("csrc/sacx_tile.h", "csrc/sacx_stage_kernel.h", "csrc/sacx_stage.hip", "csrc/sacx_internal.h")
+STAGE_SOURCES = ("csrc/sacx_tile.h", "csrc/sacx_tile_split.h", "csrc/sacx_stage_kernel.h", "csrc/sacx_stage.hip",
+                 "csrc/sacx_internal.h")
 
 
 def stage_source_hash() -> str:

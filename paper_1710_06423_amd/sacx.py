@@ -33,7 +33,7 @@ EXPORTED = (
     "sacx_abi_version", "sacx_strerror", "sacx_last_error", "sacx_workspace_size", "sacx_create",
     "sacx_destroy", "sacx_set_boundaries", "sacx_init_state", "sacx_advance", "sacx_read_fields",
     "sacx_diagnostics", "sacx_halo_buffer_size", "sacx_halo_pack", "sacx_halo_unpack",
-    "sacx_profile_enable", "sacx_profile_read", "sacx_set_launch", "sacx_get_launch",
+    "sacx_profile_enable", "sacx_profile_read", "sacx_set_launch", "sacx_get_launch", "sacx_set_column_split",
     "sacx_batch_workspace_size", "sacx_batch_create", "sacx_batch_destroy", "sacx_batch_context",
     "sacx_batch_set_tiles", "sacx_batch_advance",
     "sacx_cnn_buffer_sizes", "sacx_cnn_pack", "sacx_cnn_forward", "sacx_cnn_backward", "sacx_cnn_adam",
@@ -127,6 +127,7 @@ def load_library():
     lib.sacx_profile_read.argtypes = [P, ctypes.POINTER(Profile)]
     lib.sacx_set_launch.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
     lib.sacx_get_launch.argtypes = [P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+    lib.sacx_set_column_split.argtypes = [P, ctypes.c_int32]
     lib.sacx_batch_workspace_size.argtypes = [ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(Params),
                                               ctypes.POINTER(ctypes.c_size_t)]
     lib.sacx_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Grid), ctypes.POINTER(Params),
@@ -387,6 +388,11 @@ class Solver:
 
     def set_launch(self, threads: int = 0, rows: int = 0):
         _check(self.lib.sacx_set_launch(self.ctx, int(threads), int(rows)), "sacx_set_launch")
+
+    def set_column_split(self, on: bool):
+        """Two threads per column (x and y roles) for FP64 hyper-diffusion
+        tiles (default), or one; bit-identical results."""
+        _check(self.lib.sacx_set_column_split(self.ctx, int(bool(on))), "sacx_set_column_split")
 
     def get_launch(self):
         t, r = ctypes.c_int32(0), ctypes.c_int32(0)

@@ -347,3 +347,27 @@ def test_launch_shape_does_not_change_results(oracle_lib, shape):
     s.advance(12)
     ora = oracle_run(oracle_lib, prob, 12)
     assert_parity(oracle_lib, s.read_fields().cpu().numpy(), ora, label=f"launch {shape}")
+
+
+@pytest.mark.parametrize("shape", [(64, 7), (128, 256), (256, 33)])
+@pytest.mark.parametrize("cross", [True, False])
+def test_column_split_matches_one_thread_tiles(shape, cross):
+    """The two-threads-per-column tile (x and y roles) and the one-thread tile
+    give the same bits over every stage of several steps (time step included),
+    for block widths and strip heights that leave ragged tiles and strips, on
+    mixed open and periodic boundaries."""
+    torch = _torch()
+    from paper_1710_06423_amd import Solver
+    print(f"case: split vs one-thread {shape} cross={cross}", flush=True)
+    prob = W.random_smooth(301, 138, seed=11, bc=(W.problems.OPEN, W.problems.OPEN, 0, 0))
+    res = []
+    for split in (True, False):
+        s = Solver.from_problem(prob, hd_cross_on=cross)
+        s.set_launch(*shape)
+        s.set_column_split(split)
+        s.advance(9)
+        d = s.diagnostics()
+        res.append((s.read_fields(), d["t"], d["dt"]))
+        s.close()
+    assert torch.equal(res[0][0], res[1][0])
+    assert res[0][1] == res[1][1] and res[0][2] == res[1][2]

@@ -263,6 +263,30 @@ def test_surrogate_rejects_unsupported(sx):
         s2.set_surrogate(None, (0.0,) * 6 + (1.0,) * 6)
 
 
+def test_surrogate_state_guards(sx):
+    """The ratio planes are periodic: opening a boundary is refused while the
+    learned coefficient is set and allowed after it is cleared.  The batch
+    kernel uses the plain coefficient, so a batch whose instance has one set
+    refuses to advance."""
+    norm = (0.0,) * 6 + (1.0,) * 6
+    s = sx.Solver.from_problem(W.orszag_tang(64), device=DEV)
+    s.set_surrogate(None, norm)
+    with pytest.raises(sx.SacxError):
+        s.set_boundaries((sx.OPEN,) * 4)
+    s.clear_surrogate()
+    s.set_boundaries((sx.OPEN,) * 4)
+    with pytest.raises(sx.SacxError):
+        s.set_surrogate(None, norm)
+    b = sx.Batch([W.orszag_tang(64), W.orszag_tang(96)], precision=sx.FP64, device=DEV)
+    b[1].set_surrogate(None, norm)
+    with pytest.raises(sx.SacxError):
+        b.advance(1)
+    b[1].clear_surrogate()
+    b.advance(1)
+    assert b[0].diagnostics()["steps"] == 1 and b[1].diagnostics()["steps"] == 1
+    b.close()
+
+
 # ------------------------------------------------ training and the gain
 
 @pytest.fixture(scope="module")
