@@ -179,8 +179,11 @@ int sacx_halo_unpack(sacx_ctx *ctx, int32_t side, const void *d_buf);
 /* Launch shape of the fused stage kernel: `threads` per block (64, 128 or
  * 256; a block owns threads - 6 columns) and `rows` output rows per block
  * strip (1..4096; each strip recomputes 6 rows of halo).  0 keeps the
- * current value.  Results do not depend on the shape (bit-identical); only
- * speed does.  Used by the tile autotuner.  Contexts with background_on
+ * current value.  Until rows is set, the strip height is chosen from the
+ * device: blocks of equal work run in rounds of (compute units x resident
+ * blocks per unit), so the height minimising rounds x (rows + 6) is taken,
+ * again whenever threads or the tile kind change.  Results do not depend on
+ * the shape (bit-identical); only speed does.  Used by the tile autotuner.  Contexts with background_on
  * accept threads = 64 only (EUNSUP otherwise). */
 int sacx_set_launch(sacx_ctx *ctx, int32_t threads, int32_t rows);
 int sacx_get_launch(const sacx_ctx *ctx, int32_t *threads, int32_t *rows);

@@ -199,6 +199,8 @@ struct BatchArgs {
 template <typename real>
 hipError_t launch_stage(int stage, bool hd, bool bg, const StageArgs<real> &a, hipStream_t s);
 template <typename real>
+hipError_t stage_blocks_per_cu(int nt, bool hd, bool bg, bool split, int *blocks);
+template <typename real>
 hipError_t launch_ratio_fields(const RatioArgs<real> &a, float *out, float *d1, int64_t pitch, hipStream_t s);
 template <typename real>
 hipError_t launch_hd_check(const RatioArgs<real> &a, float *rs, int64_t pitch, double bound, int tile, int metric,

@@ -76,6 +76,7 @@ struct sacx_ctx {
     bool initialized;
     int ty, nt;
     int split;         // FP64 hyper-diffusion tiles: two threads per column
+    bool ty_auto;      // strip height chosen by auto_rows (until set explicitly)
     double dx, dy;
     SchemeConsts kc;
     // profiling: event pairs recorded around launch groups, resolved at read
@@ -153,13 +154,47 @@ Plan make_plan(const sacx_grid *g) {
     return P;
 }
 
-int default_ty(const Layout &L, int nt) {
-    // enough blocks to fill 256 CUs several times while keeping the 6-row
-    // warm-up of every strip small
+// Output rows per strip.  When the whole grid fits in one round of resident
+// blocks (slots), the strip count whose longest block (strip plus the 6-row
+// warm-up) is shortest; otherwise strips of 256 rows, halved while the launch
+// has fewer than 1024 blocks.  (Measured on MI355X at 8000^2: the FP32 kernel
+// fits one round and gains from balanced strips; the FP64 kernels take
+// several rounds and, being partly bandwidth-bound, run a part-filled last
+// round faster than a full one, so rounding the block count gains nothing
+// there while shorter strips cost warm-up rows.)
+int rows_for_slots(const Layout &L, int nt, int64_t slots) {
+    if (L.ny <= 8) return L.ny;
     const int64_t xt = (L.nx + nt - 2 * G - 1) / (nt - 2 * G);
+    int one = 0;
+    for (int64_t strips = (L.ny + 4095) / 4096; strips <= (L.ny + 7) / 8; ++strips) {
+        const int64_t ty = (L.ny + strips - 1) / strips;
+        if (ty < 8) break;
+        if (xt * ((L.ny + ty - 1) / ty) <= slots) one = (int)ty;   // later strips are shorter
+        else break;
+    }
+    // a single round, unless that needs strips longer than 1024 rows
+    if (one > 0 && one <= 1024) return one;
     int ty = 256;
     while (ty > 8 && xt * ((L.ny + ty - 1) / ty) < 1024) ty /= 2;
     return ty;
+}
+
+// the strip height for the context's current launch settings: resident
+// blocks from the device's compute units and the kernel's occupancy
+void auto_rows(sacx_ctx *c) {
+    int cus = 0, per = 0;
+    const bool fp64 = c->grid.precision == SACX_FP64;
+    const bool hd = c->params.hd_on != 0, bg = c->grid.background_on != 0;
+    hipError_t e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
+    if (e == hipSuccess)
+        e = fp64 ? stage_blocks_per_cu<double>(c->nt, hd, bg, c->split != 0, &per)
+                 : stage_blocks_per_cu<float>(c->nt, hd, bg, c->split != 0, &per);
+    if (e != hipSuccess || cus < 1 || per < 1) {
+        (void)hipGetLastError();
+        cus = 256;
+        per = 2;
+    }
+    c->ty = rows_for_slots(c->L, c->nt, (int64_t)cus * per);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -667,8 +702,8 @@ int sacx_create(const sacx_grid *grid, const sacx_params *params, void *d_ws, si
     // measured on MI355X at OT 8000^2: FP64 is best with 2-wave blocks,
     // FP32 with 4-wave blocks; strips of 256 rows keep the 6-row warm-up small
     c->nt = grid->background_on ? 64 : (grid->precision == SACX_FP64 ? 128 : 256);
-    c->ty = default_ty(c->L, c->nt);
     c->split = 1;
+    c->ty_auto = true;
     c->dx = (grid->x1 - grid->x0) / grid->nx;
     c->dy = (grid->y1 - grid->y0) / grid->ny;
     {
@@ -702,6 +737,7 @@ int sacx_create(const sacx_grid *grid, const sacx_params *params, void *d_ws, si
         return fail(SACX_EINVAL, "out of host memory");
     }
     c->ev_used = 0;
+    auto_rows(c);
     *out = c;
     return SACX_OK;
 }
@@ -729,7 +765,13 @@ int sacx_set_launch(sacx_ctx *ctx, int32_t threads, int32_t rows) {
     if (threads && threads != 64 && ctx->grid.background_on)
         return fail(SACX_EUNSUP, "background-on contexts run 64-thread blocks only");
     if (threads) ctx->nt = threads;
-    if (rows) ctx->ty = rows;
+    if (rows) {
+        ctx->ty = rows;
+        ctx->ty_auto = false;
+    } else if (threads && ctx->ty_auto) {
+        DeviceGuard dg(ctx->device);
+        auto_rows(ctx);
+    }
     return SACX_OK;
 }
 
@@ -737,6 +779,10 @@ int sacx_set_column_split(sacx_ctx *ctx, int32_t on) {
     if (!ctx) return fail(SACX_EINVAL, "ctx must not be NULL");
     if (on != 0 && on != 1) return fail(SACX_EINVAL, "on must be 0 or 1 (got %d)", on);
     ctx->split = on;
+    if (ctx->ty_auto) {
+        DeviceGuard dg(ctx->device);
+        auto_rows(ctx);
+    }
     return SACX_OK;
 }
 

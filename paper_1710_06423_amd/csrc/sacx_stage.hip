@@ -6,5 +6,6 @@
 namespace sacx {
 
 template hipError_t launch_stage<double>(int, bool, bool, const StageArgs<double> &, hipStream_t);
+template hipError_t stage_blocks_per_cu<double>(int, bool, bool, bool, int *);
 
 }  // namespace sacx

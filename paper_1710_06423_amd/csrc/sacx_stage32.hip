@@ -7,5 +7,6 @@
 namespace sacx {
 
 template hipError_t launch_stage<float>(int, bool, bool, const StageArgs<float> &, hipStream_t);
+template hipError_t stage_blocks_per_cu<float>(int, bool, bool, bool, int *);
 
 }  // namespace sacx

@@ -67,6 +67,29 @@ static hipError_t launch_nt(int stage, bool hd, bool bg, const StageArgs<real> &
     }
 }
 
+// resident blocks per compute unit of the 2-D stage kernel a launch with these
+// settings uses (stage 1; the four stages differ little in resources)
+template <typename real, int NT>
+static hipError_t blocks_per_cu_nt(bool hd, bool bg, bool split, int *blocks) {
+    if constexpr (std::is_same<real, double>::value) {
+        if (split && hd && !bg)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage_split<real, NT, 1>, 2 * NT, 0);
+    }
+    if (hd && bg) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage<real, NT, 1, true, true>, NT, 0);
+    if (hd) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage<real, NT, 1, true, false>, NT, 0);
+    if (bg) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage<real, NT, 1, false, true>, NT, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage<real, NT, 1, false, false>, NT, 0);
+}
+
+template <typename real>
+hipError_t stage_blocks_per_cu(int nt, bool hd, bool bg, bool split, int *blocks) {
+    switch (nt) {
+        case 64: return blocks_per_cu_nt<real, 64>(hd, bg, split, blocks);
+        case 128: return blocks_per_cu_nt<real, 128>(hd, bg, split, blocks);
+        default: return blocks_per_cu_nt<real, 256>(hd, bg, split, blocks);
+    }
+}
+
 template <typename real>
 hipError_t launch_stage(int stage, bool hd, bool bg, const StageArgs<real> &a, hipStream_t s) {
     switch (a.nt) {
