@@ -155,13 +155,14 @@ Plan make_plan(const sacx_grid *g) {
 }
 
 // Output rows per strip.  When the whole grid fits in one round of resident
-// blocks (slots), the strip count whose longest block (strip plus the 6-row
-// warm-up) is shortest; otherwise strips of 256 rows, halved while the launch
-// has fewer than 1024 blocks.  (Measured on MI355X at 8000^2: the FP32 kernel
-// fits one round and gains from balanced strips; the FP64 kernels take
-// several rounds and, being partly bandwidth-bound, run a part-filled last
-// round faster than a full one, so rounding the block count gains nothing
-// there while shorter strips cost warm-up rows.)
+// blocks (slots) with strips of at most 512 rows, the strip count whose
+// longest block (strip plus the 6-row warm-up) is shortest; otherwise strips
+// of 256 rows, halved while the launch has fewer than 1024 blocks.  (Measured
+// on MI355X: FP32 at 8000^2 and FP64 at 2048^2 fit one round and gain from
+// balanced strips; FP64 at 8000^2 takes several rounds and, being partly
+// bandwidth-bound, runs a part-filled last round faster than a full one, so
+// rounding the block count gains nothing there; the FP64 kernel without
+// hyper-diffusion loses 6 % with one round of 534-row strips.)
 int rows_for_slots(const Layout &L, int nt, int64_t slots) {
     if (L.ny <= 8) return L.ny;
     const int64_t xt = (L.nx + nt - 2 * G - 1) / (nt - 2 * G);
@@ -172,8 +173,7 @@ int rows_for_slots(const Layout &L, int nt, int64_t slots) {
         if (xt * ((L.ny + ty - 1) / ty) <= slots) one = (int)ty;   // later strips are shorter
         else break;
     }
-    // a single round, unless that needs strips longer than 1024 rows
-    if (one > 0 && one <= 1024) return one;
+    if (one > 0 && one <= 512) return one;
     int ty = 256;
     while (ty > 8 && xt * ((L.ny + ty - 1) / ty) < 1024) ty /= 2;
     return ty;
