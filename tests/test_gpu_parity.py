@@ -371,3 +371,24 @@ def test_column_split_matches_one_thread_tiles(shape, cross):
         s.close()
     assert torch.equal(res[0][0], res[1][0])
     assert res[0][1] == res[1][1] and res[0][2] == res[1][2]
+
+
+@pytest.mark.parametrize("shape,kind", [((2, 2), "periodic"), ((2, 5), "periodic"), ((5, 2), "periodic"),
+                                        ((3, 3), "periodic"), ((4, 7), "periodic"), ((7, 4), "periodic"),
+                                        ((6, 5), "open"), ((130, 3), "open")])
+def test_tiny_grids_parity(oracle_lib, shape, kind):
+    """Grids smaller than the stencil or a tile (one block, most threads in
+    the apron, strips shorter than the warm-up, periodic images wrapping more
+    than once) follow the oracle bit for bit with both FP64 tiles."""
+    _torch()
+    from paper_1710_06423_amd import Solver
+    print(f"case: tiny {shape} {kind}", flush=True)
+    bc = (0,) * 4 if kind == "periodic" else (W.problems.OPEN,) * 4
+    prob = W.random_smooth(*shape, seed=3, bc=bc)
+    ora = oracle_run(oracle_lib, prob, 12)
+    for split in (True, False):
+        s = Solver.from_problem(prob)
+        s.set_column_split(split)
+        s.advance(12)
+        assert_parity(oracle_lib, s.read_fields().cpu().numpy(), ora, label=f"tiny {shape} {kind} split={split}")
+        s.close()
