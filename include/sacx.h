@@ -176,15 +176,17 @@ int sacx_halo_buffer_size(const sacx_ctx *ctx, int32_t side, size_t *bytes);
 int sacx_halo_pack(sacx_ctx *ctx, int32_t side, void *d_buf);
 int sacx_halo_unpack(sacx_ctx *ctx, int32_t side, const void *d_buf);
 
-/* Launch shape of the fused stage kernel: `threads` per block (64, 128 or
- * 256; a block owns threads - 6 columns) and `rows` output rows per block
- * strip (1..4096; each strip recomputes 6 rows of halo).  0 keeps the
+/* Launch shape of the fused stage kernel: `threads` columns per block
+ * including the 6-column apron (64, 128 or 256; the one-thread tile runs
+ * that many threads per block, the FP64 split tile of sacx_set_column_split
+ * twice as many) and `rows` output rows per
+ * block strip (1..4096; each strip recomputes 6 rows of halo).  0 keeps the
  * current value.  Until rows is set, the strip height is chosen from the
- * device: blocks of equal work run in rounds of (compute units x resident
- * blocks per unit), so the height minimising rounds x (rows + 6) is taken,
- * again whenever threads or the tile kind change.  Results do not depend on
- * the shape (bit-identical); only speed does.  Used by the tile autotuner.  Contexts with background_on
- * accept threads = 64 only (EUNSUP otherwise). */
+ * device (compute units x resident blocks per unit): strips balanced to fit
+ * one round of resident blocks when that needs at most 512 rows, else 256
+ * rows (halved while there are fewer than 1024 blocks); it is chosen again
+ * whenever threads or the tile kind change.  Results do not depend on the
+ * shape (bit-identical); only speed does.  Used by the tile autotuner. */
 int sacx_set_launch(sacx_ctx *ctx, int32_t threads, int32_t rows);
 int sacx_get_launch(const sacx_ctx *ctx, int32_t *threads, int32_t *rows);
 

@@ -699,9 +699,9 @@ int sacx_create(const sacx_grid *grid, const sacx_params *params, void *d_ws, si
     c->hx[1] = c->ws + P.off_hx + P.hx_bytes;
     c->hy[0] = c->ws + P.off_hy;
     c->hy[1] = c->ws + P.off_hy + P.hy_bytes;
-    // measured on MI355X at OT 8000^2: FP64 is best with 2-wave blocks,
-    // FP32 with 4-wave blocks; strips of 256 rows keep the 6-row warm-up small
-    c->nt = grid->background_on ? 64 : (grid->precision == SACX_FP64 ? 128 : 256);
+    // measured on MI355X: FP64 is best with 128-column blocks (OT 8000^2,
+    // also with a background at 4000^2), FP32 with 256-column blocks
+    c->nt = grid->precision == SACX_FP64 ? 128 : 256;
     c->split = 1;
     c->ty_auto = true;
     c->dx = (grid->x1 - grid->x0) / grid->nx;
@@ -758,12 +758,6 @@ int sacx_set_launch(sacx_ctx *ctx, int32_t threads, int32_t rows) {
     if (threads != 0 && threads != 64 && threads != 128 && threads != 256)
         return fail(SACX_EINVAL, "threads must be 64, 128 or 256 (got %d)", threads);
     if (rows < 0 || rows > 4096) return fail(SACX_EINVAL, "rows must be in 1..4096 (got %d)", rows);
-    // Background-on contexts keep single-wave blocks: their multi-wave
-    // builds with hyper-diffusion gave wrong values in the first rows of each
-    // strip of the stage-4 launch (cause not identified; the single-wave
-    // build is verified bit-exact), so they only accept 64 threads.
-    if (threads && threads != 64 && ctx->grid.background_on)
-        return fail(SACX_EUNSUP, "background-on contexts run 64-thread blocks only");
     if (threads) ctx->nt = threads;
     if (rows) {
         ctx->ty = rows;

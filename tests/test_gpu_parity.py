@@ -323,17 +323,21 @@ def test_orszag_tang_8000_sampled_parity(oracle_lib):
     assert np.all(np.isfinite(u100))
 
 
-def test_background_contexts_use_single_wave_blocks():
-    """Background-on contexts run 64-thread blocks (the configuration their
-    bit-exact parity is established for) and refuse wider ones."""
+@pytest.mark.parametrize("nt,ty", [(64, 7), (128, 7), (128, 40), (256, 16)])
+def test_background_multiwave_parity(oracle_lib, nt, ty):
+    """Background-on contexts with one- to four-wave blocks and short strips
+    (many strip starts) follow the oracle bit for bit, HD and cross terms on:
+    an earlier build gave wrong values in the first rows of each strip with
+    multi-wave blocks, which this case would show."""
     _torch()
-    from paper_1710_06423_amd import Solver, sacx
-    prob = W.split_background(W.orszag_tang(64), 0.1, 0.1, (0.0, 0.0))
+    from paper_1710_06423_amd import Solver
+    print(f"case: background OT 200x96 launch ({nt}, {ty})", flush=True)
+    prob = W.split_background(W.orszag_tang(200, ny=96), 0.1, 0.1, (0.05, -0.02))
     s = Solver.from_problem(prob)
-    assert s.get_launch()[0] == 64
-    with pytest.raises(sacx.SacxError) as e:
-        s.set_launch(128, 0)
-    assert e.value.code == sacx.EUNSUP
+    s.set_launch(nt, ty)
+    s.advance(15)
+    ora = oracle_run(oracle_lib, prob, 15)
+    assert_parity(oracle_lib, s.read_fields().cpu().numpy(), ora, label=f"background launch ({nt}, {ty})")
 
 
 @pytest.mark.parametrize("shape", [(64, 16), (128, 8), (256, 37), (256, 256)])
