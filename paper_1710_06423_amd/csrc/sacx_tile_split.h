@@ -15,16 +15,18 @@
 // threads are the x role).  Per iteration r (row r is the newest state row):
 //   phase 1  X: primitives and x fluxes of row r, published with the state
 //               row (ring of 5 rows) and D_x F_x of row r-2
-//            Y: pointwise operands of the output row j = r-3 (HBM)
-//   phase 2  X: D_x F_x of row r, compression s of row r-1
-//            Y: y fluxes of row r, D_y F_y and ideal L of row r-2, y-face G
-//               of face (r-3)+1/2
-//   phase 3  X: x-face G of row r-1, x-face flux H_x at row j
-//            Y: y-face flux H_y at face j+1/2
-//   phase 4  Y: L(S) of row j and the stage combine (stage 4: wave speeds)
-// with barriers between phases 1-2, 2-3 and 3-4.  Every value is the same
-// IEEE operation on the same operands as in the one-thread tile, so both
-// tiles give the same bits.
+//            Y: L(S) and the stage combine of row r-4 (stage 4: its wave
+//               speeds); pointwise operands of row r-3 (HBM)
+//   phase 2  X: compression s of row r-1, coefficient ratios of its x faces
+//            Y: y-face G of face (r-3)+1/2
+//   phase 3  X: D_x F_x of row r, x-face G of row r-1, H_x at row r-3
+//            Y: y fluxes of row r, D_y F_y and ideal L of row r-2, H_y at
+//               face (r-3)+1/2
+// with a barrier after each phase; the y role's last output row follows the
+// loop.  Each role keeps its state in registers across iterations; LDS holds
+// only what the other role or a neighbouring column needs.  Every value is
+// the same IEEE operation on the same operands as in the one-thread tile, so
+// both tiles give the same bits.
 #pragma once
 
 #include "sacx_tile.h"

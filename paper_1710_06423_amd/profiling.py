@@ -11,7 +11,8 @@ compares the mean stage-kernel launch with the bench's own HIP-event timing.
 over the stage kernel and the same two passes over a device copy of known
 size into HBM bytes per stage launch: each counter is divided by what it
 reads per byte of the copy.  The traffic file records a hash of the stage
-kernel's sources; bench.py reports the traffic only while the hash matches.
+kernel's code (its sources without comments and layout); bench.py reports the
+traffic only while the hash matches.
 """
 
 from __future__ import annotations
@@ -29,11 +30,43 @@ STAGE_SOURCES = ("csrc/sacx_tile.h", "csrc/sacx_tile_split.h", "csrc/sacx_stage_
                  "csrc/sacx_internal.h")
 
 
-def stage_source_hash() -> str:
+def code_text(src: str) -> str:
+    """C++ source without its comments and with runs of white space made one
+    space (string literals are left alone), so that a change of comments or
+    layout leaves the hash of the stage kernel's code unchanged."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c == '"' or c == "'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            j = src.find("\n", i)
+            i = n if j < 0 else j
+        elif src.startswith("/*", i):
+            j = src.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def stage_source_hash(read=None) -> str:
+    """Hash of the stage kernel's code (comments and layout excluded).
+    `read(rel)` returns a source's text (default: the working tree)."""
     h = hashlib.sha256()
     for rel in STAGE_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as fh:
-            h.update(fh.read())
+        if read is None:
+            with open(os.path.join(HERE, rel)) as fh:
+                text = fh.read()
+        else:
+            text = read(rel)
+        h.update(code_text(text).encode())
     return h.hexdigest()[:16]
 
 

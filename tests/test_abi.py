@@ -134,3 +134,15 @@ def test_product_path_does_not_reference_the_oracle():
             if fn.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, fn)).read()
                 assert "import oracle" not in text and "sacx_oracle" not in text, fn
+
+
+def test_stage_code_hash_ignores_comments_and_layout():
+    """The hash that ties recorded traffic counters to the stage kernel's code
+    changes with the code, not with its comments or layout."""
+    from paper_1710_06423_amd.profiling import code_text
+    a = 'x = a * b; // one\n/* two\n three */ y  =\n  "// kept" ;'
+    b = 'x = a * b;\ny = "// kept";'
+    assert code_text(a) == 'x = a * b; y = "// kept" ;'
+    assert code_text(a).replace(" ", "") == code_text(b).replace(" ", "")
+    assert code_text("x = a * b;") != code_text("x = a + b;")
+    assert code_text("s = 'a'; // c") == "s = 'a';"
