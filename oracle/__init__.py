@@ -64,6 +64,7 @@ class _Cfg(ctypes.Structure):
         ("c2", ctypes.c_double * 4), ("cshk", ctypes.c_double * 4),
         ("bc", ctypes.c_int * 4),
         ("background_on", ctypes.c_int),
+        ("g", ctypes.c_double * 2),
     ]
 
 
@@ -135,6 +136,7 @@ def make_cfg(prob, cfl: float = 0.3, hd_on: bool = True, hd_cross_on: bool = Tru
     c.cshk = (ctypes.c_double * 4)(*cshk)
     c.bc = (ctypes.c_int * 4)(*prob.bc)
     c.background_on = int(prob.background is not None)
+    c.g = (ctypes.c_double * 2)(*getattr(prob, "g", (0.0, 0.0)))
     return c
 
 

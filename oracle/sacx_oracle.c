@@ -27,6 +27,9 @@
  *    scales with the maximum wave speed, plus a term that grows with
  *    compression (section 2);
  *  - classic fourth-order Runge-Kutta in time (section 2);
+ *  - gravity g through the sources rho g and rho g.v of section 2; with the
+ *    background taken to be in equilibrium under its own pressure and field,
+ *    what is left acts on the perturbation: rho~ g and rho~ g.v;
  *  - a CFL time step from the maximum fast speed;
  *  - halo (ghost) cells filled from periodic images or by zero-gradient
  *    copies (section 3, halo exchange; section 5 boundary conditions).
@@ -62,9 +65,10 @@ typedef struct {
     double cshk[4]; /* rho, eps, v, B */
     int bc[4];      /* x-, x+, y-, y+ */
     int background_on;
+    double g[2];    /* gravity (section 2 sources rho g, rho g.v), acting on rho~ */
 } orc_cfg;
 
-int orc_abi_version(void) { return 1; }
+int orc_abi_version(void) { return 2; }
 
 /* ------------------------------------------------------------------ */
 /* small helpers                                                       */
@@ -104,6 +108,7 @@ static int cfg_ok(const orc_cfg *c) {
     if (!(c->gamma > 1.0) || !(c->cfl > 0.0)) return 0;
     for (int s = 0; s < 4; ++s)
         if (c->bc[s] != ORC_PERIODIC && c->bc[s] != ORC_OPEN) return 0;
+    if (!isfinite(c->g[0]) || !isfinite(c->g[1])) return 0;
     if ((c->bc[0] == ORC_PERIODIC) != (c->bc[1] == ORC_PERIODIC)) return 0;
     if ((c->bc[2] == ORC_PERIODIC) != (c->bc[3] == ORC_PERIODIC)) return 0;
     return 1;
@@ -185,6 +190,8 @@ typedef struct {
     double dx, dy, gamma;
     int hd_on, hd_cross_on, bg_on;
     double c2[4], cshk[4];
+    double g[2];
+    int grav_on;
     /* optional externally supplied coefficient ratios (the surrogate's
      * prediction): 10 planes of nx*ny face values, planes 0-4 the x-face
      * sets, 5-9 the y-face sets, face (i+1/2, j) / (i, j+1/2) stored at
@@ -301,6 +308,16 @@ static int rhs_block(int nxe, int nye, double *const S[NF], double *const BG[NB]
                 double bxb = BG[B_BX][c], byb = BG[B_BY][c];
                 double bb = (bxb * bxb * dxvx + byb * byb * dyvy) + (bxb * byb * dxvy + byb * bxb * dyvx);
                 K[F_E][c] = K[F_E][c] + (bb - ptb[c] * (dxvx + dyvy));
+            }
+            if (P->grav_on) {
+                /* gravity: the sources rho g and rho g.v of section 2 less the
+                 * background's share, which its own pressure and field carry
+                 * (the equilibrium assumed for the split form), leave rho~ g
+                 * and rho~ g.v, with v the velocity of the total density */
+                double rt = S[F_RHO][c];
+                K[F_MX][c] = K[F_MX][c] + rt * P->g[0];
+                K[F_MY][c] = K[F_MY][c] + rt * P->g[1];
+                K[F_E][c] = K[F_E][c] + rt * (P->g[0] * vx[c] + P->g[1] * vy[c]);
             }
         }
     }
@@ -434,6 +451,9 @@ static void make_rhs_par(const orc_cfg *c, rhs_par *P) {
     P->hd_cross_on = c->hd_cross_on;
     P->bg_on = c->background_on;
     for (int k = 0; k < 4; ++k) { P->c2[k] = c->c2[k]; P->cshk[k] = c->cshk[k]; }
+    P->g[0] = c->g[0];
+    P->g[1] = c->g[1];
+    P->grav_on = c->g[0] != 0.0 || c->g[1] != 0.0;
     P->rext = NULL;
     P->rext_nx = c->nx;
     P->rext_ny = c->ny;

@@ -19,6 +19,8 @@ from .problems import (  # noqa: F401
     alfven_wave,
     random_smooth,
     split_background,
+    with_gravity,
+    stratified_atmosphere,
     transpose_problem,
     batch_instances,
     cell_centres,

@@ -46,6 +46,7 @@ class Problem:
     background: Optional[Dict[str, np.ndarray]] = None
     t0: float = 0.0
     meta: dict = dataclasses.field(default_factory=dict)
+    g: Tuple[float, float] = (0.0, 0.0)   # gravity (x, y)
 
     @property
     def dx(self) -> float:
@@ -282,6 +283,46 @@ def split_background(prob: Problem, rho_b: float, e_b: float, b_b=(0.0, 0.0)) ->
     return dataclasses.replace(prob, name=prob.name + "_split", fields=f, background=bg)
 
 
+def with_gravity(prob: Problem, g: Tuple[float, float]) -> Problem:
+    """The same initial state under a uniform gravity g = (g_x, g_y)."""
+    return dataclasses.replace(prob, name=prob.name + "_g", g=(float(g[0]), float(g[1])))
+
+
+def stratified_atmosphere(nx: int, ny: int, g0: float = 1.0, scale_height: float = 0.25, rho0: float = 1.0,
+                          b_b=(0.0, 0.0), amp: float = 0.02, width: float = 0.05, centre=(0.5, 0.15),
+                          gamma: float = 5.0 / 3.0, extent=(1.0, 1.0)) -> Problem:
+    """A gravitationally stratified atmosphere carrying a wave pulse, the
+    kind of medium the code exists for (section 1: waves in a strongly
+    magnetised, stratified solar atmosphere).
+
+    Background (static, in equilibrium): isothermal under g = (0, -g0) with
+    scale height H, rho_b = rho0 exp(-y/H) and p_b = rho_b g0 H, so that
+    dp_b/dy = -rho_b g0; a uniform field B_b (force-free);
+    e_b = p_b/(gamma-1) + |B_b|^2/2.  Perturbation: a Gaussian vertical
+    velocity pulse of peak `amp` times the sound speed, m~ = rho_b v,
+    e~ = rho_b v^2/2 (no pressure perturbation), rho~ = B~ = 0.
+    x periodic, y open (zero-gradient), domain [0, Lx] x [0, Ly].
+    """
+    lx, ly = extent
+    x = cell_centres(nx, 0.0, lx)
+    y = cell_centres(ny, 0.0, ly)
+    X, Y = np.meshgrid(x, y)
+    H = scale_height
+    rho_b = rho0 * np.exp(-Y / H)
+    p_b = rho_b * g0 * H
+    cs = math.sqrt(gamma * g0 * H)
+    r2 = ((X - centre[0] * lx) ** 2 + (Y - centre[1] * ly) ** 2) / width ** 2
+    vy = amp * cs * np.exp(-r2)
+    zero = np.zeros_like(X)
+    b2 = b_b[0] ** 2 + b_b[1] ** 2
+    fields = {"rho": zero.copy(), "mx": zero.copy(), "my": rho_b * vy, "e": 0.5 * rho_b * vy * vy,
+              "bx": zero.copy(), "by": zero.copy()}
+    bg = {"rho_b": rho_b, "e_b": p_b / (gamma - 1.0) + 0.5 * b2, "bx_b": np.full_like(X, b_b[0]),
+          "by_b": np.full_like(X, b_b[1])}
+    return Problem(f"stratified_{nx}x{ny}", nx, ny, 0.0, lx, 0.0, ly, gamma, (PERIODIC, PERIODIC, OPEN, OPEN),
+                   fields, bg, 0.0, {"g0": g0, "H": H, "amp": amp}, (0.0, -g0))
+
+
 def transpose_problem(prob: Problem) -> Problem:
     """Same problem with x and y exchanged (fields transposed, components swapped)."""
     f = prob.fields
@@ -300,7 +341,7 @@ def transpose_problem(prob: Problem) -> Problem:
         bg = {"rho_b": b["rho_b"].T.copy(), "e_b": b["e_b"].T.copy(),
               "bx_b": b["by_b"].T.copy(), "by_b": b["bx_b"].T.copy()}
     return Problem(prob.name + "_T", prob.ny, prob.nx, prob.y0, prob.y1, prob.x0, prob.x1,
-                   prob.gamma, bc, g, bg, prob.t0, dict(prob.meta))
+                   prob.gamma, bc, g, bg, prob.t0, dict(prob.meta), (prob.g[1], prob.g[0]))
 
 
 def batch_instances(seed: int = 0, n_bw: int = 32, n_ot: int = 32) -> List[Problem]:
