@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SACX_ABI_VERSION 1
+#define SACX_ABI_VERSION 2
 
 /* status codes */
 #define SACX_OK 0
@@ -83,6 +83,11 @@ typedef struct sacx_params {
     int32_t hd_cross_on;     /* include off-diagonal stress / e.m.f. terms */
     double c2[4];            /* ratio-term constants: density, thermal energy, velocity, field */
     double cshk[4];          /* compression-term constants, same classes */
+    double g[2];             /* gravity (x, y): the sources rho g and rho g.v of paper section 2.
+                              * With the background taken to be in equilibrium under its own
+                              * pressure and field they act on the perturbation density:
+                              * rho~ g on the momentum, rho~ g.v on the energy (v of the total
+                              * density).  {0, 0}: no gravity.  Must be finite (EINVAL). */
 } sacx_params;
 
 typedef struct sacx_diag {

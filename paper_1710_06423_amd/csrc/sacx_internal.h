@@ -64,6 +64,8 @@ struct SchemeConsts {
     double i12dx, i12dy, idx, idy, i2dx, i2dy;
     double kxs[4], kys[4];   // cshk * h_d * h_d
     double third;
+    double gx, gy;           // gravity
+    int grav;                // gravity non-zero: its sources are added
 };
 
 // constants of the time-step computation

@@ -126,6 +126,7 @@ int check_grid(const sacx_grid *g, const sacx_params *p) {
     for (int k = 0; k < 4; ++k)
         if (!(p->c2[k] >= 0.0) || !(p->cshk[k] >= 0.0) || !std::isfinite(p->c2[k]) || !std::isfinite(p->cshk[k]))
             return fail(SACX_EINVAL, "hyper-diffusion constants must be finite and >= 0");
+    if (!std::isfinite(p->g[0]) || !std::isfinite(p->g[1])) return fail(SACX_EINVAL, "gravity must be finite");
     return SACX_OK;
 }
 
@@ -723,6 +724,9 @@ int sacx_create(const sacx_grid *grid, const sacx_params *params, void *d_ws, si
             k.kys[m] = params->cshk[m] * c->dy * c->dy;
         }
         k.third = 1.0 / 3.0;
+        k.gx = params->g[0];
+        k.gy = params->g[1];
+        k.grav = params->g[0] != 0.0 || params->g[1] != 0.0;
     }
     c->initialized = false;
     c->prof_on = false;

@@ -316,6 +316,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
             const real bb = (bxb2 * bxb2 * dxvx + byb2 * byb2 * dyvy) + (bxb2 * byb2 * dxvy + byb2 * bxb2 * dyvx);
             kin6[3] = kin6[3] + (bb - ptb * (dxvx + dyvy));
         }
+        if (kc.grav) {
+            // gravity on the perturbation density of row r-2 (window index 3),
+            // after the background terms
+            const real gx = (real)kc.gx, gy = (real)kc.gy, rg = qw[QR][3];
+            kin6[1] = kin6[1] + rg * gx;
+            kin6[2] = kin6[2] + rg * gy;
+            kin6[3] = kin6[3] + rg * (gx * qw[QVX][3] + gy * qw[QVY][3]);
+        }
 
         real gyn[5], hyn[5], gxn[5], fmn[4];
         real s_new = 0;
@@ -602,6 +610,13 @@ __device__ __forceinline__ void stage_tile_1d(const StageArgs<real> &a, int tile
         K[3] = -(dxn[CE] + zero);
         K[4] = -(zero + zero);
         K[5] = -(dxn[CB] + zero);
+        if (kc.grav) {
+            // gravity on the perturbation density
+            const real gx = (real)kc.gx, gy = (real)kc.gy;
+            K[1] = K[1] + rt * gx;
+            K[2] = K[2] + rt * gy;
+            K[3] = K[3] + rt * (gx * vx + gy * vy);
+        }
     }
     if (HD) {
         const real dv = (sh_q[QVX][tp1] - sh_q[QVX][tm1]) * i2dx + zero;

@@ -53,9 +53,9 @@ struct SplitLds {
 template <typename real, int NC>
 struct SplitCommon {
     real dt, hdt, dt6, kx2[4], ky2[4];
-    real gamma, gm1, igm1, i12dx, i12dy, idx, idy, i2dx, i2dy, third;
+    real gamma, gm1, igm1, i12dx, i12dy, idx, idy, i2dx, i2dy, third, gx, gy;
     int t, c, y0, rbeg, rend, tm1, tm2, tp1, tp2, tp3;
-    bool outcol, cross;
+    bool outcol, cross, grav;
     int64_t colofs;
 
     __device__ __forceinline__ SplitCommon(const StageArgs<real> &a, int tx_, int ty_, int t_) {
@@ -70,6 +70,7 @@ struct SplitCommon {
         gamma = (real)kc.gamma; gm1 = (real)kc.gm1; igm1 = (real)kc.igm1;
         i12dx = (real)kc.i12dx; i12dy = (real)kc.i12dy; idx = (real)kc.idx; idy = (real)kc.idy;
         i2dx = (real)kc.i2dx; i2dy = (real)kc.i2dy; third = (real)kc.third;
+        gx = (real)kc.gx; gy = (real)kc.gy; grav = kc.grav != 0;
         const Layout &L = a.L;
         t = t_;
         c = tx_ * TX - G + t;
@@ -413,6 +414,13 @@ __device__ __forceinline__ void split_y(const StageArgs<real> &a, const SplitCom
             kib[3] = -(lds.dx[CE][t] + dyn[CE]);
             kib[4] = -(zero + dyn[CB]);   // B~_x has no x flux
             kib[5] = -(lds.dx[CB][t] + zero);  // B~_y has no y flux
+            if (m.grav) {
+                // gravity on the perturbation density of row r-2 (window index 3)
+                const real rg = qw[QR][3];
+                kib[1] = kib[1] + rg * m.gx;
+                kib[2] = kib[2] + rg * m.gy;
+                kib[3] = kib[3] + rg * (m.gx * qw[QVX][3] + m.gy * qw[QVY][3]);
+            }
         }
         real a4vy = 0, a4by = 0;
         if (m.cross) {

@@ -55,7 +55,7 @@ class Grid(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("hd_on", ctypes.c_int32), ("hd_cross_on", ctypes.c_int32),
-                ("c2", ctypes.c_double * 4), ("cshk", ctypes.c_double * 4)]
+                ("c2", ctypes.c_double * 4), ("cshk", ctypes.c_double * 4), ("g", ctypes.c_double * 2)]
 
 
 class Diag(ctypes.Structure):
@@ -168,9 +168,10 @@ def make_grid(nx, ny, x0, x1, y0, y1, precision=FP64, background_on=False) -> Gr
     return Grid(int(nx), int(ny), float(x0), float(x1), float(y0), float(y1), int(precision), int(bool(background_on)))
 
 
-def make_params(gamma, cfl=0.3, hd_on=True, hd_cross_on=True, c2=DEFAULT_C2, cshk=DEFAULT_CSHK) -> Params:
+def make_params(gamma, cfl=0.3, hd_on=True, hd_cross_on=True, c2=DEFAULT_C2, cshk=DEFAULT_CSHK,
+                g=(0.0, 0.0)) -> Params:
     return Params(float(gamma), float(cfl), int(bool(hd_on)), int(bool(hd_cross_on)),
-                  (ctypes.c_double * 4)(*c2), (ctypes.c_double * 4)(*cshk))
+                  (ctypes.c_double * 4)(*c2), (ctypes.c_double * 4)(*cshk), (ctypes.c_double * 2)(*g))
 
 
 def workspace_size(grid: Grid, params: Params) -> int:
@@ -222,7 +223,7 @@ class Solver:
                      cshk=DEFAULT_CSHK, device="cuda", init=True, **kw) -> "Solver":
         grid = make_grid(prob.nx, prob.ny, prob.x0, prob.x1, prob.y0, prob.y1, precision,
                          prob.background is not None)
-        params = make_params(prob.gamma, cfl, hd_on, hd_cross_on, c2, cshk)
+        params = make_params(prob.gamma, cfl, hd_on, hd_cross_on, c2, cshk, getattr(prob, "g", (0.0, 0.0)))
         s = cls(grid, params, tuple(prob.bc), device=device, **kw)
         if init:
             f = torch.stack([torch.from_numpy(prob.fields[k]) for k in FIELDS]).to(s.device)
@@ -415,7 +416,8 @@ class Batch:
         self.device = dev
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         self.grids = (Grid * n)(*[make_grid(p.nx, p.ny, p.x0, p.x1, p.y0, p.y1, precision, False) for p in problems])
-        self.params = (Params * n)(*[make_params(p.gamma, cfl, True, True, c2, cshk) for p in problems])
+        self.params = (Params * n)(*[make_params(p.gamma, cfl, True, True, c2, cshk, getattr(p, "g", (0.0, 0.0)))
+                                     for p in problems])
         bc = (ctypes.c_int32 * (4 * n))(*[int(b) for p in problems for b in p.bc])
         nbytes = ctypes.c_size_t(0)
         _check(self.lib.sacx_batch_workspace_size(n, self.grids, self.params, ctypes.byref(nbytes)),

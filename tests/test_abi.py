@@ -55,6 +55,7 @@ int main(void) {
          offsetof(sacx_surrogate, bound), sizeof(sacx_hd_stats), sizeof(sacx_cnn_sizes),
          offsetof(sacx_profile, ms_surrogate));
   printf("%d %d\\n", SACX_CNN_NPARAM, SACX_CNN_PACKED_BYTES);
+  printf("%zu\\n", offsetof(sacx_params, g));
   return 0;
 }
 """)
@@ -71,6 +72,7 @@ int main(void) {
     assert vals[9:15] == [ctypes.sizeof(sx.Surrogate), sx.Surrogate.refresh_every.offset, sx.Surrogate.bound.offset,
                           ctypes.sizeof(sx.HdStats), ctypes.sizeof(sx.CnnSizes), sx.Profile.ms_surrogate.offset]
     assert vals[15:17] == [sx.CNN_NPARAM, sx.CNN_PACKED_BYTES]
+    assert vals[17] == sx.Params.g.offset
 
 
 def test_strerror_and_codes(sx):
@@ -103,11 +105,12 @@ def test_invalid_grids_rejected(sx, bad):
     assert e.value.code == sx.EINVAL
 
 
-@pytest.mark.parametrize("bad", [dict(gamma=1.0), dict(cfl=0.0), dict(c2=(-1, 0, 0, 0)), dict(cshk=(0, float("nan"), 0, 0))])
+@pytest.mark.parametrize("bad", [dict(gamma=1.0), dict(cfl=0.0), dict(c2=(-1, 0, 0, 0)), dict(cshk=(0, float("nan"), 0, 0)),
+                                 dict(g=(float("inf"), 0.0)), dict(g=(0.0, float("nan")))])
 def test_invalid_params_rejected(sx, bad):
-    kw = dict(gamma=5 / 3, cfl=0.3, c2=sx.DEFAULT_C2, cshk=sx.DEFAULT_CSHK)
+    kw = dict(gamma=5 / 3, cfl=0.3, c2=sx.DEFAULT_C2, cshk=sx.DEFAULT_CSHK, g=(0.0, 0.0))
     kw.update(bad)
-    p = sx.make_params(kw["gamma"], kw["cfl"], True, True, kw["c2"], kw["cshk"])
+    p = sx.make_params(kw["gamma"], kw["cfl"], True, True, kw["c2"], kw["cshk"], kw["g"])
     with pytest.raises(sx.SacxError) as e:
         sx.workspace_size(sx.make_grid(8, 8, 0, 1, 0, 1), p)
     assert e.value.code == sx.EINVAL
