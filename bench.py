@@ -45,19 +45,29 @@ def log(*a):
 
 def cpu_baseline(prob, n_sample: int, cfl: float):
     """The oracle (test infrastructure) timed on one RK4 step of an
-    n_sample x n_sample sub-block of the workload's own state."""
+    n_sample x n_sample sub-block of the workload's own state (periodic
+    images across periodic edges; with a background, interior rows only)."""
     import oracle
     oracle.build(force=False)
     cfg = oracle.make_cfg(prob, cfl=cfl)
     f = [prob.fields[k] for k in oracle.FIELDS]
+    bg = None if prob.background is None else [prob.background[k] for k in oracle.BACKGROUND_FIELDS]
     # global dt / c_max of the full state (needed by the step), not timed
-    cx, cy, cmax, dt = oracle.wavespeed(cfg, f)
+    cx, cy, cmax, dt = oracle.wavespeed(cfg, f, bg)
     m = 12
-    idx = np.arange(-m, n_sample + m) % prob.nx
-    patch = [a[np.ix_(idx, idx)] for a in f]
+    ix = np.arange(-m, n_sample + m) % prob.nx
+    if bg is None:
+        iy = np.arange(-m, n_sample + m) % prob.ny
+    else:
+        n_sample = min(n_sample, prob.ny - 2 * m)
+        y0 = (prob.ny - n_sample) // 2
+        iy = np.arange(y0 - m, y0 + n_sample + m)
+        ix = np.arange(-m, n_sample + m) % prob.nx
+    patch = [a[np.ix_(iy, ix)] for a in f]
+    bgp = None if bg is None else [a[np.ix_(iy, ix)] for a in bg]
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t0 = time.perf_counter()
-    oracle.step_patch(cfg, patch, None, dt, cmax)
+    oracle.step_patch(cfg, patch, bgp, dt, cmax)
     sec = time.perf_counter() - t0
     model = "unknown CPU"
     try:
@@ -72,7 +82,7 @@ def cpu_baseline(prob, n_sample: int, cfl: float):
         "unit": "Mcell-updates/s",
         "cores": threads,
         "kind": "oracle",
-        "sample": f"one RK4 step (HD on) on a {n_sample}x{n_sample} sub-block of the OT {prob.nx}^2 "
+        "sample": f"one RK4 step (HD on) on a {n_sample}x{n_sample} sub-block of the {prob.name} "
                   f"initial state, 12-cell margin supplied; {sec:.2f} s on {threads} OpenMP threads of {model}",
     }
 
@@ -118,9 +128,10 @@ def run_single(args):
     prec = FP64 if args.precision == "fp64" else FP32
     w = 8 if prec == FP64 else 4
     hd = not args.no_hd
-    workload = f"orszag_tang_{n}x{n}_{args.precision}_{'hd' if hd else 'nohd'}"
-    log(f"[bench] generating Orszag-Tang {n}x{n}")
-    prob = W.orszag_tang(n)
+    strat = args.problem == "stratified"
+    workload = f"{args.problem}_{n}x{n}_{args.precision}_{'hd' if hd else 'nohd'}"
+    log(f"[bench] generating {args.problem} {n}x{n}")
+    prob = W.stratified_atmosphere(n, n, amp=0.05, b_b=(0.1, 0.4)) if strat else W.orszag_tang(n)
     log("[bench] uploading and initialising")
     s = Solver.from_problem(prob, precision=prec, hd_on=hd, cfl=0.3)
     ref = None
@@ -160,11 +171,13 @@ def run_single(args):
     value = cells * args.steps / (ms / 1e3) / 1e6
     # dominant kernel: the fused stage kernel (four stage instantiations).
     # algorithmic bytes: 12 field accesses x 6 fields x w per cell and step,
-    # i.e. 18 w bytes per cell per stage launch on average.
+    # i.e. 18 w bytes per cell per stage launch on average; a background adds
+    # its 4 fields, read once per stage launch.
+    acc = 12 * 6 + (16 if strat else 0)
     n_launch = sum(prof["n_stage"])
     stage_ms = sum(prof["ms_stage"])
     avg_launch_s = stage_ms / n_launch / 1e3
-    bytes_per_launch = 12 * 6 * w * cells / 4
+    bytes_per_launch = acc * w * cells / 4
     achieved = bytes_per_launch / avg_launch_s / 1e9
     per_stage = [prof["ms_stage"][k] / max(prof["n_stage"][k], 1) for k in range(4)]
     t_comp = stage_ms
@@ -177,9 +190,13 @@ def run_single(args):
     out = base_record(args, value, ms / args.steps, "f64" if prec == FP64 else "f32", {
         "workload": workload,
         "nx": n, "ny": n, "precision": args.precision, "hyper_diffusion": hd, "cfl": 0.3,
-        "halo": "3-cell, device pack/unpack, periodic self-exchange",
-        "bytes_per_cell_update": 12 * 6 * w,
+        "halo": ("3-cell; x periodic self-exchange, y open (zero-gradient fills)" if strat
+                 else "3-cell, device pack/unpack, periodic self-exchange"),
+        "bytes_per_cell_update": acc * w,
     })
+    if strat:
+        out["config"].update({"background": "isothermal hydrostatic, scale height 0.25, uniform field (0.1, 0.4)",
+                              "gravity": [0.0, -1.0], "pulse_amplitude": 0.05})
     out["roofline"] = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
@@ -193,7 +210,7 @@ def run_single(args):
     out["cpu_baseline"] = cpu
     out["phases_ms"] = {"stage": [round(x, 3) for x in prof["ms_stage"]], "halo": round(t_comm, 3),
                         "scalar": round(prof["ms_scalar"], 3)}
-    if n == 8000 and hd:
+    if n == 8000 and hd and not strat:
         # the paper's own timing of this workload, on its hardware: context only
         out["paper_context"] = {"mcell_updates_s": 39.1, "hardware": "100x NVIDIA Tesla K20c (10x10 subdomains)",
                                 "source": "Table 1, Orszag-Tang 8000^2 with hyper-diffusion, 163.6 s per 100 "
@@ -394,6 +411,8 @@ def main():
     ap.add_argument("--mode", choices=["single", "batch", "surrogate", "copy"], default="single")
     ap.add_argument("--n", type=int, default=None, help="grid side (default 8000, surrogate 2048)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--problem", choices=["orszag_tang", "stratified"], default="orszag_tang",
+                    help="single mode: Orszag-Tang, or a stratified atmosphere under gravity (background on)")
     ap.add_argument("--no-hd", action="store_true", help="the paper's 'without HD' column")
     ap.add_argument("--fp32-error", action="store_true", help="with --precision fp32: error against an FP64 run")
     ap.add_argument("--cpu-sample", type=int, default=8000, help="side of the oracle sub-block (0: skip)")

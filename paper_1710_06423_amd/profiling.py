@@ -98,10 +98,11 @@ def stats_summary(stats_csv: str, bench_log: str, title: str, command: str) -> s
         ev = sum(b["phases_ms"]["stage"]) / nl
         w = 8 if b["dtype"] == "f64" else 4
         cells = b["config"]["nx"] * b["config"]["ny"]
-        gb = 18 * w * cells / 1e9
+        per_cell = b["config"].get("bytes_per_cell_update", 72 * w) / 4   # per stage launch
+        gb = per_cell * cells / 1e9
         out += ["", f"Mean stage-kernel launch: {avg:.3f} ms (rocprofv3, every launch including warm-up) vs "
                     f"{ev:.3f} ms from the bench's HIP events over its timed steps (same run).",
-                f"Algorithmic bytes per stage launch: {18 * w} B x {cells / 1e6:.0f}e6 cells = {gb:.3f} GB -> "
+                f"Algorithmic bytes per stage launch: {per_cell:.0f} B x {cells / 1e6:.0f}e6 cells = {gb:.3f} GB -> "
                 f"{gb / avg * 1e3:.0f} GB/s = {gb / avg * 1e3 / 8000 * 100:.1f} % of 8 TB/s.",
                 f"Bench line of the same run: {b['value']:.0f} Mcell-updates/s, {b['ms_per_step']:.2f} ms/step, "
                 f"roofline.achieved {b['roofline']['achieved']} GB/s."]
