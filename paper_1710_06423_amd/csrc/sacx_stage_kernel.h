@@ -18,10 +18,10 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
 }
 
 // two threads per column (x and y roles), two waves per SIMD
-template <typename real, int NC, int STAGE>
+template <typename real, int NC, int STAGE, bool BG>
 __global__ __launch_bounds__(2 * NC, 2) void k_stage_split(StageArgs<real> a) {
-    __shared__ SplitLds<real, NC> lds;
-    stage_tile_split<real, NC, STAGE>(a, blockIdx.x, blockIdx.y, lds);
+    __shared__ SplitLds<real, NC, BG> lds;
+    stage_tile_split<real, NC, STAGE, BG>(a, blockIdx.x, blockIdx.y, lds);
 }
 
 template <typename real, int NT, int STAGE, bool HD>
@@ -41,8 +41,9 @@ static hipError_t launch_s(bool hd, bool bg, const StageArgs<real> &a, hipStream
     }
     dim3 grid((a.L.nx + TX - 1) / TX, (a.L.ny + a.ty - 1) / a.ty);
     if constexpr (std::is_same<real, double>::value) {
-        if (a.split && hd && !bg && !a.Rs) {
-            hipLaunchKernelGGL((k_stage_split<real, NT, STAGE>), grid, dim3(2 * NT), 0, s, a);
+        if (a.split && hd && !a.Rs) {
+            if (bg) hipLaunchKernelGGL((k_stage_split<real, NT, STAGE, true>), grid, dim3(2 * NT), 0, s, a);
+            else hipLaunchKernelGGL((k_stage_split<real, NT, STAGE, false>), grid, dim3(2 * NT), 0, s, a);
             return hipGetLastError();
         }
     }
@@ -72,8 +73,9 @@ static hipError_t launch_nt(int stage, bool hd, bool bg, const StageArgs<real> &
 template <typename real, int NT>
 static hipError_t blocks_per_cu_nt(bool hd, bool bg, bool split, int *blocks) {
     if constexpr (std::is_same<real, double>::value) {
-        if (split && hd && !bg)
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage_split<real, NT, 1>, 2 * NT, 0);
+        if (split && hd)
+            return bg ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage_split<real, NT, 1, true>, 2 * NT, 0)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage_split<real, NT, 1, false>, 2 * NT, 0);
     }
     if (hd && bg) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage<real, NT, 1, true, true>, NT, 0);
     if (hd) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage<real, NT, 1, true, false>, NT, 0);

@@ -1,6 +1,6 @@
 // sacx_tile_split.h -- the fused RK stage with the work of each column split
 // between two waves: one for the x-direction terms, one for the y-direction
-// terms (hyper-diffusion on, no background, plain coefficient).
+// terms (hyper-diffusion on, plain coefficient, with or without a background).
 //
 // Why: the one-thread-per-column tile holds about a hundred FP64 values of
 // sliding windows per thread, more than the 256 registers that allow two
@@ -35,13 +35,13 @@ namespace sacx {
 
 enum { SQR = 0, SQE = 1, SQVX = 2, SQVY = 3, SQB = 4, SQRHO = 5, SQBYT = 6, SQPT = 7, SNQ = 8 };
 
-template <typename real, int NC>
+template <typename real, int NC, bool BG = false>
 struct SplitLds {
     real fx[5][NC];          // x fluxes of row r
     real q[2][SNQ][NC];      // primitives of rows r, r-1 (by row parity)
     real ps[5][NF][NC];      // state rows r-4..r (ring mod 5)
     real s[3][NC];           // compression s (ring over rows mod 3)
-    real dx[5][NC];          // D_x F_x of row r-2
+    real dx[BG ? 7 : 5][NC]; // D_x F_x of row r-2 (with a background also D_x v_x, D_x v_y)
     real gx[2][3][NC];       // x-face G(v_y), G(B~_y), ring over rows (mod 3)
     real gy[2][2][NC];       // y-face G(v_x), G(B~_x), ring over faces (mod 2)
     real hx[5][NC];          // x-face fluxes H_x of row r-3
@@ -96,13 +96,10 @@ __device__ __forceinline__ int ring3(int r) { return (r + 3 * 4096) % 3; }
 
 // x role: primitives and x fluxes of the newest row, D_x F_x, compression,
 // x-face G and x-face fluxes
-template <typename real, int NC, int STAGE>
+template <typename real, int NC, int STAGE, bool BG>
 __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCommon<real, NC> &m,
-                                        SplitLds<real, NC> &lds) {
+                                        SplitLds<real, NC, BG> &lds) {
     const real half = (real)0.5, two = (real)2, eight = (real)8, zero = (real)0;
-    // the background terms of the one-thread tile, which is the same code with
-    // these zero (the operations on them are kept: they decide signed zeros)
-    const real rb = 0, eb = 0, bxb = 0, byb = 0;
     const Layout L = a.L;
     const int64_t fs = a.fstride;
     const SchemeConsts &kc = a.k;
@@ -112,8 +109,10 @@ __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCom
     real gxw[2][5];      // own x-face G of rows r-3, r-2
     real fmx[2][4];      // x-face means (rho, v_x, v_y, B_y) of rows r-3, r-2
     real vyw[2];         // v_y of rows r-2, r-1
+    real bgx[2][2];      // background on: D_x v_x, D_x v_y of rows r-2, r-1
 #pragma unroll
     for (int k = 0; k < 5; ++k) dxd[0][k] = dxd[1][k] = gxw[0][k] = gxw[1][k] = 0;
+    bgx[0][0] = bgx[0][1] = bgx[1][0] = bgx[1][1] = 0;
 #pragma unroll
     for (int k = 0; k < 4; ++k) fmx[0][k] = fmx[1][k] = 0;
     vyw[0] = vyw[1] = 0;
@@ -125,15 +124,24 @@ __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCom
     }
     lds.gy[0][0][t] = lds.gy[0][1][t] = lds.gy[1][0][t] = lds.gy[1][1][t] = 0;
 
-    // state rows r+1 and r+2 in flight
+    // state rows r+1 and r+2 in flight (with their background)
     Row6<real> n1, n2;
+    real g1[NBG], g2[NBG];
     {
         const int64_t ro = m.colofs + (int64_t)(m.rbeg + G) * L.pitch;
 #pragma unroll
         for (int f = 0; f < NF; ++f) n1.v[f] = a.S[0][ro + f * fs];
+        if (BG) {
+#pragma unroll
+            for (int f = 0; f < NBG; ++f) g1[f] = a.BG[0][ro + f * fs];
+        }
         if (m.rbeg < m.rend) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) n2.v[f] = a.S[0][ro + L.pitch + f * fs];
+            if (BG) {
+#pragma unroll
+                for (int f = 0; f < NBG; ++f) g2[f] = a.BG[0][ro + L.pitch + f * fs];
+            }
         }
     }
 
@@ -145,10 +153,23 @@ __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCom
         // ---------- phase 1: row r ----------
         const Row6<real> cur = n1;
         n1 = n2;
+        // the background terms of the one-thread tile; without a background
+        // the same code with these zero (the operations on them are kept:
+        // they decide signed zeros)
+        real rb = 0, eb = 0, bxb = 0, byb = 0;
+        if (BG) {
+            rb = g1[0]; eb = g1[1]; bxb = g1[2]; byb = g1[3];
+#pragma unroll
+            for (int f = 0; f < NBG; ++f) g1[f] = g2[f];
+        }
         if (r + 2 <= m.rend) {
             const int64_t rn = m.colofs + (int64_t)(r + 2 + G) * L.pitch;
 #pragma unroll
             for (int f = 0; f < NF; ++f) n2.v[f] = a.S[0][rn + f * fs];
+            if (BG) {
+#pragma unroll
+                for (int f = 0; f < NBG; ++f) g2[f] = a.BG[0][rn + f * fs];
+            }
         }
         const int pr = ring5(r);
 #pragma unroll
@@ -182,6 +203,10 @@ __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCom
         lds.q[slot][SQPT][t] = pt;
 #pragma unroll
         for (int k = 0; k < 5; ++k) lds.dx[k][t] = dxd[0][k];
+        if (BG) {
+            lds.dx[5][t] = bgx[0][0];
+            lds.dx[6][t] = bgx[0][1];
+        }
         __syncthreads();  // P1
 
         // ---------- phase 2: s of row r-1, coefficient ratios of its x faces ----------
@@ -203,6 +228,15 @@ __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCom
         for (int k = 0; k < 5; ++k) {
             dxd[0][k] = dxd[1][k];
             dxd[1][k] = (eight * (lds.fx[k][tp1] - lds.fx[k][tm1]) - (lds.fx[k][tp2] - lds.fx[k][tm2])) * m.i12dx;
+        }
+        if (BG) {
+            // D_x v_x, D_x v_y of row r for the background's energy terms
+            bgx[0][0] = bgx[1][0];
+            bgx[0][1] = bgx[1][1];
+            bgx[1][0] = (eight * (lds.q[slot][SQVX][tp1] - lds.q[slot][SQVX][tm1]) -
+                         (lds.q[slot][SQVX][tp2] - lds.q[slot][SQVX][tm2])) * m.i12dx;
+            bgx[1][1] = (eight * (lds.q[slot][SQVY][tp1] - lds.q[slot][SQVY][tm1]) -
+                         (lds.q[slot][SQVY][tp2] - lds.q[slot][SQVY][tm2])) * m.i12dx;
         }
         const real sfx = fmax(s_new, lds.s[s1][tp1]);
         real gxn[5];
@@ -248,9 +282,9 @@ __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCom
 
 // L(S) of output row j from the ideal part, the x-face fluxes in LDS and the
 // own y-face fluxes above (hn) and below (hp) the cell, and the stage combine
-template <typename real, int NC, int STAGE>
+template <typename real, int NC, int STAGE, bool BG>
 __device__ __forceinline__ void split_output(const StageArgs<real> &a, const SplitCommon<real, NC> &m,
-                                             SplitLds<real, NC> &lds, int j, const real (&kid)[6],
+                                             SplitLds<real, NC, BG> &lds, int j, const real (&kid)[6],
                                              const real (&hn)[5], const real (&hp)[5], const Row6<real> &pU,
                                              double &cx_t, double &cy_t, int &bad_t) {
     const real half = (real)0.5, zero = (real)0;
@@ -289,7 +323,8 @@ __device__ __forceinline__ void split_output(const StageArgs<real> &a, const Spl
             a.out1[0][oo + f * fs] = un[f];
         }
         // wave speeds of the new state (next step's dt and c_max)
-        const real rb0 = 0, eb0 = 0, bxb0 = 0, byb0 = 0;
+        real rb0 = 0, eb0 = 0, bxb0 = 0, byb0 = 0;
+        if (BG) { rb0 = a.BG[0][oo]; eb0 = a.BG[0][oo + 1 * fs]; bxb0 = a.BG[0][oo + 2 * fs]; byb0 = a.BG[0][oo + 3 * fs]; }
         const real r0 = rb0 + un[0];
         const real ir0 = (real)1 / r0;
         const real ux = un[1] * ir0, uy = un[2] * ir0;
@@ -315,11 +350,10 @@ __device__ __forceinline__ void split_output(const StageArgs<real> &a, const Spl
 
 // y role: y-face G, y fluxes, D_y F_y, the ideal L, y-face fluxes, and one
 // iteration later L(S) of the output row and the stage combine
-template <typename real, int NC, int STAGE>
+template <typename real, int NC, int STAGE, bool BG>
 __device__ __forceinline__ void split_y(const StageArgs<real> &a, const SplitCommon<real, NC> &m,
-                                        SplitLds<real, NC> &lds, double &cx_t, double &cy_t, int &bad_t) {
+                                        SplitLds<real, NC, BG> &lds, double &cx_t, double &cy_t, int &bad_t) {
     const real half = (real)0.5, two = (real)2, eight = (real)8, zero = (real)0;
-    const real eb = 0, bxb = 0, byb = 0;
     const Layout L = a.L;
     const int64_t fs = a.fstride;
     const SchemeConsts &kc = a.k;
@@ -349,7 +383,7 @@ __device__ __forceinline__ void split_y(const StageArgs<real> &a, const SplitCom
         const int sy = (r - 3 + 2 * 4096) & 1;
         // ---------- phase 1: output row r-4, operands of row r-3 ----------
         if (r - 4 >= m.y0 && m.outcol)
-            split_output<real, NC, STAGE>(a, m, lds, r - 4, kia, hb, ha, pUa, cx_t, cy_t, bad_t);
+            split_output<real, NC, STAGE, BG>(a, m, lds, r - 4, kia, hb, ha, pUa, cx_t, cy_t, bad_t);
         const int j = r - G;
         Row6<real> pUb;
         if (j >= m.y0 && m.outcol) {
@@ -363,6 +397,19 @@ __device__ __forceinline__ void split_y(const StageArgs<real> &a, const SplitCom
         __syncthreads();  // P1
 
         // ---------- phase 2: y-face G of face (r-3)+1/2 ----------
+        // background of rows r (y fluxes), r-2 (energy terms, y-face means)
+        // and r-3 (y-face means), rows below -G clamped as in the one-thread
+        // tile (those rows only feed warm-up faces); without a background the
+        // zeros of the one-thread tile
+        real eb = 0, bxb = 0, byb = 0, rb2 = 0, eb2 = 0, bxb2 = 0, byb2 = 0, rb3 = 0, bxb3 = 0;
+        if (BG) {
+            const int64_t rr = m.colofs + (int64_t)(r + G) * L.pitch;
+            const int64_t r2 = m.colofs + (int64_t)((r - 2 < -G ? -G : r - 2) + G) * L.pitch;
+            const int64_t r3 = m.colofs + (int64_t)((r - 3 < -G ? -G : r - 3) + G) * L.pitch;
+            eb = a.BG[0][rr + 1 * fs]; bxb = a.BG[0][rr + 2 * fs]; byb = a.BG[0][rr + 3 * fs];
+            rb2 = a.BG[0][r2]; eb2 = a.BG[0][r2 + 1 * fs]; bxb2 = a.BG[0][r2 + 2 * fs]; byb2 = a.BG[0][r2 + 3 * fs];
+            rb3 = a.BG[0][r3]; bxb3 = a.BG[0][r3 + 2 * fs];
+        }
         const int pr = ring5(r);
         const real rt = lds.ps[pr][0][t], bxt = lds.ps[pr][4][t];
         const real eps = lds.q[slot][SQE][t], vx = lds.q[slot][SQVX][t], vy = lds.q[slot][SQVY][t];
@@ -414,6 +461,17 @@ __device__ __forceinline__ void split_y(const StageArgs<real> &a, const SplitCom
             kib[3] = -(lds.dx[CE][t] + dyn[CE]);
             kib[4] = -(zero + dyn[CB]);   // B~_x has no x flux
             kib[5] = -(lds.dx[CB][t] + zero);  // B~_y has no y flux
+            if (BG) {
+                // e~ of row r-2 gets -p_tb div v + sum_kl B_bk B_bl d_k v_l
+                const real dxvx = lds.dx[5][t], dxvy = lds.dx[6][t];
+                const real dyvx = (eight * (qw[QVX][4] - qw[QVX][2]) - (qw[QVX][5] - qw[QVX][1])) * m.i12dy;
+                const real dyvy = (eight * (qw[QVY][4] - qw[QVY][2]) - (qw[QVY][5] - qw[QVY][1])) * m.i12dy;
+                const real b2b = bxb2 * bxb2 + byb2 * byb2;
+                const real pkb = m.gm1 * (eb2 - half * b2b);
+                const real ptb = pkb + half * b2b;
+                const real bb = (bxb2 * bxb2 * dxvx + byb2 * byb2 * dyvy) + (bxb2 * byb2 * dxvy + byb2 * bxb2 * dyvx);
+                kib[3] = kib[3] + (bb - ptb * (dxvx + dyvy));
+            }
             if (m.grav) {
                 // gravity on the perturbation density of row r-2 (window index 3)
                 const real rg = qw[QR][3];
@@ -432,10 +490,10 @@ __device__ __forceinline__ void split_y(const StageArgs<real> &a, const SplitCom
 #pragma unroll
         for (int k = 0; k < 5; ++k) ha[k] = hb[k];
         {
-            const real rj = qw[QR][2];
-            const real rj1 = qw[QR][3];
-            const real bj = qw[QB][2];
-            const real bj1 = qw[QB][3];
+            const real rj = BG ? rb3 + qw[QR][2] : qw[QR][2];
+            const real rj1 = BG ? rb2 + qw[QR][3] : qw[QR][3];
+            const real bj = BG ? bxb3 + qw[QB][2] : qw[QB][2];
+            const real bj1 = BG ? bxb2 + qw[QB][3] : qw[QB][3];
             const real rf = half * (rj + rj1);
             const real vxf = half * (qw[QVX][2] + qw[QVX][3]);
             const real vyf = half * (qw[QVY][2] + qw[QVY][3]);
@@ -454,12 +512,12 @@ __device__ __forceinline__ void split_y(const StageArgs<real> &a, const SplitCom
     }
     // the last output row (its x-face fluxes were published before P3)
     if (m.rend - G >= m.y0 && m.outcol)
-        split_output<real, NC, STAGE>(a, m, lds, m.rend - G, kia, hb, ha, pUa, cx_t, cy_t, bad_t);
+        split_output<real, NC, STAGE, BG>(a, m, lds, m.rend - G, kia, hb, ha, pUa, cx_t, cy_t, bad_t);
 }
 
-template <typename real, int NC, int STAGE>
+template <typename real, int NC, int STAGE, bool BG>
 __device__ __forceinline__ void stage_tile_split(const StageArgs<real> &a, int tile_x, int tile_y,
-                                                 SplitLds<real, NC> &lds) {
+                                                 SplitLds<real, NC, BG> &lds) {
     if (!a.sc->active) return;
     // the role is a property of the wave (NC is a multiple of 64): taking it
     // from a wave-uniform value keeps the two role loops apart in the
@@ -470,9 +528,9 @@ __device__ __forceinline__ void stage_tile_split(const StageArgs<real> &a, int t
     double cx_t = 0.0, cy_t = 0.0;
     int bad_t = 0;
     if (xrole)
-        split_x<real, NC, STAGE>(a, m, lds);
+        split_x<real, NC, STAGE, BG>(a, m, lds);
     else
-        split_y<real, NC, STAGE>(a, m, lds, cx_t, cy_t, bad_t);
+        split_y<real, NC, STAGE, BG>(a, m, lds, cx_t, cy_t, bad_t);
 
     if (STAGE == 4) {
         // block reduction of the wave speeds, one atomic per block

@@ -354,16 +354,19 @@ def test_launch_shape_does_not_change_results(oracle_lib, shape):
 
 
 @pytest.mark.parametrize("shape", [(64, 7), (128, 256), (256, 33)])
-@pytest.mark.parametrize("cross", [True, False])
-def test_column_split_matches_one_thread_tiles(shape, cross):
+@pytest.mark.parametrize("cross,background", [(True, False), (False, False), (True, True)])
+def test_column_split_matches_one_thread_tiles(shape, cross, background):
     """The two-threads-per-column tile (x and y roles) and the one-thread tile
     give the same bits over every stage of several steps (time step included),
     for block widths and strip heights that leave ragged tiles and strips, on
-    mixed open and periodic boundaries."""
+    mixed open and periodic boundaries; with a background and gravity too."""
     torch = _torch()
     from paper_1710_06423_amd import Solver
-    print(f"case: split vs one-thread {shape} cross={cross}", flush=True)
-    prob = W.random_smooth(301, 138, seed=11, bc=(W.problems.OPEN, W.problems.OPEN, 0, 0))
+    print(f"case: split vs one-thread {shape} cross={cross} background={background}", flush=True)
+    if background:
+        prob = W.stratified_atmosphere(301, 138, amp=0.08, b_b=(0.2, 0.5))
+    else:
+        prob = W.random_smooth(301, 138, seed=11, bc=(W.problems.OPEN, W.problems.OPEN, 0, 0))
     res = []
     for split in (True, False):
         s = Solver.from_problem(prob, hd_cross_on=cross)
