@@ -139,7 +139,7 @@ def traffic_summary(fetch_csv: str, write_csv: str, cfetch_csv: str, cwrite_csv:
     write_b = w_st * 1024.0 / kw
     w = 8 if b["dtype"] == "f64" else 4
     cells = b["config"]["nx"] * b["config"]["ny"]
-    alg = 18 * w * cells
+    alg = b["config"].get("bytes_per_cell_update", 72 * w) / 4 * cells   # per stage launch
     lines = [f"# HBM traffic of the stage kernel -- {b['config']['workload']}", "",
              "Commands (repository root on the GPU host), one counter per run:", ""]
     lines += ["    " + c for c in commands]
