@@ -11,8 +11,11 @@
 
 namespace sacx {
 
+// FP32 builds are held to two waves per SIMD (all but the background
+// stage-4 build fit without the bound; that one would otherwise take one
+// register too many and run one wave per SIMD at half speed)
 template <typename real, int NT, int STAGE, bool HD, bool BG, bool SUR = false>
-__global__ __launch_bounds__(NT) void k_stage(StageArgs<real> a) {
+__global__ __launch_bounds__(NT, sizeof(real) == 4 ? 2 : 1) void k_stage(StageArgs<real> a) {
     __shared__ TileLds<real, NT> lds;
     stage_tile<real, NT, STAGE, HD, BG, SUR>(a, blockIdx.x, blockIdx.y, lds);
 }
