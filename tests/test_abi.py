@@ -149,3 +149,12 @@ def test_stage_code_hash_ignores_comments_and_layout():
     assert code_text(a).replace(" ", "") == code_text(b).replace(" ", "")
     assert code_text("x = a * b;") != code_text("x = a + b;")
     assert code_text("s = 'a'; // c") == "s = 'a';"
+
+
+def test_setters_reject_null_context(sx):
+    """Host-side argument checks of the launch and tile-kind setters (no
+    device work): a NULL context is EINVAL."""
+    lib = sx.load_library()
+    assert lib.sacx_set_column_split(None, 1) == sx.EINVAL
+    assert lib.sacx_set_launch(None, 128, 64) == sx.EINVAL
+    assert lib.sacx_set_boundaries(None, None) == sx.EINVAL
