@@ -195,8 +195,8 @@ int sacx_halo_unpack(sacx_ctx *ctx, int32_t side, const void *d_buf);
 int sacx_set_launch(sacx_ctx *ctx, int32_t threads, int32_t rows);
 int sacx_get_launch(const sacx_ctx *ctx, int32_t *threads, int32_t *rows);
 
-/* Tile kind of FP64 two-dimensional contexts with hyper-diffusion, no
- * background and the plain coefficient: on = 1 (the default) gives every
+/* Tile kind of FP64 two-dimensional contexts with hyper-diffusion and the
+ * plain coefficient (with or without a background): on = 1 (the default) gives every
  * column two threads, one for the x-direction terms and one for the
  * y-direction terms, in blocks of 2 * threads; on = 0 gives it one thread.
  * Results are bit-identical either way; the two-thread tile holds half the
