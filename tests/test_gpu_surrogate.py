@@ -184,10 +184,11 @@ def test_cnn_inputs_bitexact(sx):
     assert np.all(x[..., 6:] == 0)
 
 
-def test_supplied_ratios_bitexact(sx):
+@pytest.mark.parametrize("gravity", [(0.0, 0.0), (0.3, -0.8)])
+def test_supplied_ratios_bitexact(sx, gravity):
     """Stages with supplied ratios (negative = plain) equal the oracle's
-    supplied-ratio scheme bit for bit."""
-    prob = W.orszag_tang(96, 64)
+    supplied-ratio scheme bit for bit, with and without gravity."""
+    prob = W.with_gravity(W.orszag_tang(96, 64), gravity) if any(gravity) else W.orszag_tang(96, 64)
     R = W.synthetic_ratio_planes(96, 64, seed=5, tile=8, frac_plain=0.3)
     s = sx.Solver.from_problem(prob, device=DEV)
     s.set_surrogate(None, (0.0,) * 6 + (1.0,) * 6, refresh_every=10 ** 6, tile=16, bound=math.inf)
