@@ -2,6 +2,7 @@
 
   python -m paper_1710_06423_amd.profiling stats  STATS_CSV BENCH_LOG OUT_MD TITLE COMMAND
   python -m paper_1710_06423_amd.profiling sq     COUNTER_CSV BENCH_LOG OUT_MD COMMAND
+  python -m paper_1710_06423_amd.profiling table  STATS_CSV BENCH_LOG OUT_MD TITLE COMMAND [NOTE...]
   python -m paper_1710_06423_amd.profiling traffic FETCH_CSV WRITE_CSV CFETCH_CSV CWRITE_CSV COPY_BYTES
                                                   BENCH_LOG OUT_MD COMMANDS...
 
@@ -156,6 +157,24 @@ def traffic_summary(fetch_csv: str, write_csv: str, cfetch_csv: str, cwrite_csv:
     return "\n".join(lines) + "\n"
 
 
+def table_summary(stats_csv: str, bench_log: str, title: str, command: str, notes: List[str],
+                  top: int = 16) -> str:
+    """Any kernel trace as a table (the `top` kernels by GPU time), with the
+    bench line of the same run."""
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    b = _bench_line(bench_log)
+    out = [f"# {title}", "", "Command (repository root on the GPU host):", "", "    " + command, ""]
+    out += [n for n in notes] + ([""] if notes else [])
+    out += ["| kernel | calls | avg ms | % of GPU time |", "|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.4f} | "
+                   f"{float(r['Percentage']):.1f} |")
+    out += ["", f"Bench line of the same run: workload {b['config']['workload']}, {b['value']} {b['unit']}, "
+                f"{b['ms_per_step']} ms/step over {b['steps']} steps."]
+    return "\n".join(out) + "\n"
+
+
 SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_WAVE_CYCLES",
                "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES")
 
@@ -205,6 +224,10 @@ def read_traffic(path: str) -> Optional[Dict[str, float]]:
 def main(argv: List[str]):
     if argv and argv[0] == "stats" and len(argv) == 6:
         text = stats_summary(argv[1], argv[2], argv[4], argv[5])
+        open(argv[3], "w").write(text)
+        print(text)
+    elif argv and argv[0] == "table" and len(argv) >= 6:
+        text = table_summary(argv[1], argv[2], argv[4], argv[5], argv[6:])
         open(argv[3], "w").write(text)
         print(text)
     elif argv and argv[0] == "sq" and len(argv) == 5:
