@@ -245,11 +245,20 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ out, con
     if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-__global__ void k_loss_final(const double *__restrict__ part, int nb, double inv_count, double *__restrict__ loss) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// fixed-order sum of the per-block loss partials: thread t sums partials
+// t, t + 256, ... in order, then a fixed tree over the 256 threads (one block)
+__global__ __launch_bounds__(256) void k_loss_final(const double *__restrict__ part, int nb, double inv_count,
+                                                    double *__restrict__ loss) {
+    __shared__ double red[256];
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[b];
-    *loss = s * inv_count;
+    for (int b = threadIdx.x; b < nb; b += 256) s += part[b];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] * inv_count;
 }
 
 // ------------------------------------------------------------- weight gradient
@@ -362,12 +371,25 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs a) {
     if (tid < a.cout) pp[nw + tid] = db;
 }
 
-// fixed-order sum of the per-block partials
-__global__ void k_reduce(const float *__restrict__ part, int nblocks, int np, float *__restrict__ dst) {
+// fixed-order sum of the per-block partials, in two levels: group g of
+// blockIdx.y sums blocks [g*chunk, min((g+1)*chunk, nblocks)) in order and
+// leaves its sum in the first row of its chunk; k_reduce2 then sums the group
+// sums in order.  Each column is read and written by one thread only.
+__global__ void k_reduce(float *__restrict__ part, int nblocks, int np, int chunk) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b0 = blockIdx.y * chunk;
+    if (i >= np || b0 >= nblocks) return;
+    const int b1 = min(b0 + chunk, nblocks);
+    float s = 0.0f;
+    for (int b = b0; b < b1; ++b) s += part[(int64_t)b * np + i];
+    part[(int64_t)b0 * np + i] = s;
+}
+
+__global__ void k_reduce2(const float *__restrict__ part, int nblocks, int np, int chunk, float *__restrict__ dst) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= np) return;
     float s = 0.0f;
-    for (int b = 0; b < nblocks; ++b) s += part[(int64_t)b * np + i];
+    for (int b0 = 0; b0 < nblocks; b0 += chunk) s += part[(int64_t)b0 * np + i];
     dst[i] = s;
 }
 
@@ -525,7 +547,7 @@ int sacx_cnn_backward(const void *d_packed, const void *d_x, const void *d_act, 
     const int lb = (int)std::min<size_t>(2048, (px + 255) / 256);
     k_loss<<<lb, 256, 0, s>>>(d_out, d_target, d_weight, n, h, w, (float)(2.0 / count), g3, lpart);
     HIPCHK(hipGetLastError());
-    k_loss_final<<<1, 64, 0, s>>>(lpart, lb, 1.0 / count, d_loss);
+    k_loss_final<<<1, 256, 0, s>>>(lpart, lb, 1.0 / count, d_loss);
     HIPCHK(hipGetLastError());
 
     const int rows = wgrad_rows(n, h, w);
@@ -543,8 +565,14 @@ int sacx_cnn_backward(const void *d_packed, const void *d_x, const void *d_act, 
         else k_wgrad<AC, AC><<<nbw, 256, 0, s>>>(wa);
         HIPCHK(hipGetLastError());
         const int np = cout_of(l) * cin_of(l) * 9 + cout_of(l);
-        k_reduce<<<(np + 255) / 256, 256, 0, s>>>(part, nbw, np, d_grad + woff(l));
-        HIPCHK(hipGetLastError());
+        {
+            const int chunk = std::max(1, (nbw + 63) / 64);   // at most 64 groups
+            const int groups = (nbw + chunk - 1) / chunk;
+            k_reduce<<<dim3((np + 255) / 256, groups), 256, 0, s>>>(part, nbw, np, chunk);
+            HIPCHK(hipGetLastError());
+            k_reduce2<<<(np + 255) / 256, 256, 0, s>>>(part, nbw, np, chunk, d_grad + woff(l));
+            HIPCHK(hipGetLastError());
+        }
         if (l > 0) {
             unsigned short *gn = (l % 2 == 1) ? ga : gb;
             HIPCHK(launch_conv(l, MODE_BWD, pk, gl, A[l], gn, nullptr, 0, 0, 0, n, h, w, s));
