@@ -12,7 +12,8 @@
  * subdomain; its halo ("ghost") layers are exchanged through device-side
  * pack/unpack buffers (paper section 3, the halo exchange of Fig. 1 and the
  * exchange_halo listing), with periodic self-exchange or open
- * (zero-gradient) boundaries applied locally.
+ * (zero-gradient) boundaries applied locally, or, for a domain split into
+ * subdomain contexts, filled from the neighbours before every stage.
  *
  * Conventions shared by every call
  *  - Grid: cell centred, x_i = x0 + (i + 1/2) dx, dx = (x1 - x0) / nx (same
@@ -46,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SACX_ABI_VERSION 2
+#define SACX_ABI_VERSION 3
 
 /* status codes */
 #define SACX_OK 0
@@ -60,6 +61,10 @@ extern "C" {
 /* boundary kinds */
 #define SACX_PERIODIC 0
 #define SACX_OPEN 1
+/* a side that borders another subdomain of a decomposed domain (paper
+ * section 3, Fig. 1): the library never fills its ghost cells; the caller
+ * unpacks the neighbour's strip there (sacx_halo_unpack) before every stage */
+#define SACX_EXCHANGE 2
 
 /* precisions */
 #define SACX_FP64 0
@@ -130,9 +135,11 @@ int sacx_destroy(sacx_ctx *ctx);
 /* Set the boundary kind of each side (paper section 5: periodic for
  * Orszag-Tang; open for the shock tube).  Periodic sides must come in pairs
  * (x-, x+ and y-, y+), else EINVAL.  A direction with one cell must be
- * periodic.  Takes effect at the next halo fill.  While a learned
- * coefficient is set (sacx_hd_set_surrogate) only all-periodic boundaries
- * are accepted (ESTATE otherwise). */
+ * periodic.  Takes effect at the next halo fill (the background's halos,
+ * if any, are filled again at once).  While a learned coefficient is set
+ * (sacx_hd_set_surrogate) only all-periodic boundaries are accepted (ESTATE
+ * otherwise).  EXCHANGE sides: EUNSUP with a background or with fewer than
+ * SACX_GHOST cells across; such a context steps with sacx_stage. */
 int sacx_set_boundaries(sacx_ctx *ctx, const int32_t bc[4]);
 
 /* Load a state (paper section 3: the initial model configuration a process
@@ -146,7 +153,8 @@ int sacx_init_state(sacx_ctx *ctx, const void *const *d_fields, const void *cons
                     int64_t pitch, int32_t in_precision, double t0);
 
 /* Enqueue up to nsteps RK4 steps (paper section 2; one step = 4 stages,
- * each preceded by a halo exchange).  t_end <= 0: no end time.  Otherwise
+ * each preceded by a halo exchange).  ESTATE for a context with an EXCHANGE
+ * side or while a step begun with sacx_stage is in progress.  t_end <= 0: no end time.  Otherwise
  * dt = min(dt, t_end - t) and stepping stops once t_end - t <= 1e-12 t_end.
  * A step whose start state is non-physical is not taken, and neither is any
  * later one; that state is kept.  If steps_done or t_now is non-NULL the call
@@ -172,14 +180,61 @@ int sacx_diagnostics(sacx_ctx *ctx, sacx_diag *out);
  *  side 2/3 (y-/y+): G rows x (nx + 2G) columns (x halos included, so corners
  *                    travel with the y exchange; do x before y) x 6 fields.
  * Buffer layout: [field][depth g = 0..G-1, increasing coordinate][along the side].
- * pack copies the G interior rows/columns next to `side` of the current
- * state; unpack writes the G ghost rows/columns of `side`.  For a periodic
+ * pack copies the G interior rows/columns next to `side` of the state the
+ * next stage differences (the current state between steps; during a step
+ * begun with sacx_stage, the intermediate state of the stage about to run);
+ * unpack writes the G ghost rows/columns of `side` of that same state.  For a periodic
  * neighbour, the buffer packed at x- is the one unpacked at x+.  Buffers are
  * caller-owned device memory in the context precision; sizes in bytes.
  * EUNSUP if that direction has fewer than G interior cells. */
 int sacx_halo_buffer_size(const sacx_ctx *ctx, int32_t side, size_t *bytes);
 int sacx_halo_pack(sacx_ctx *ctx, int32_t side, void *d_buf);
 int sacx_halo_unpack(sacx_ctx *ctx, int32_t side, const void *d_buf);
+
+/* Decomposed stepping (paper section 3, Fig. 1: a domain split into
+ * subdomains, one per process, whose halos are exchanged before every
+ * stage; the time step is the one of the whole domain).  Every subdomain of
+ * a domain is a context; a side that borders another subdomain is EXCHANGE.
+ * Every subdomain takes the spacing of the whole domain (sacx_set_spacing).
+ * One RK4 step of the whole domain, for stage = 1..4:
+ *   1. sacx_fill_boundaries(ctx, 0) on every subdomain;
+ *   2. for each x EXCHANGE side: the neighbour packs its facing side
+ *      (sacx_halo_pack), this context unpacks that buffer (sacx_halo_unpack);
+ *   3. sacx_fill_boundaries(ctx, 1);
+ *   4. the same for the y EXCHANGE sides (their strips carry the x halos:
+ *      the corners);
+ *   5. sacx_stage(ctx, c, ...) on every subdomain, with c at stage 1 the
+ *      maxima over all subdomains of sacx_wave_speeds.
+ * Each subdomain then evolves bit for bit as its part of the undivided
+ * domain run with sacx_advance.  No end time; a non-physical step-start
+ * state (sacx_diagnostics) stops that subdomain's steps, not the others'.
+ *
+ * sacx_fill_boundaries: fill the ghost cells of direction 0 (x, interior
+ * rows) or 1 (y, whole padded width, so after x) of the state the next stage
+ * differences, on the PERIODIC and OPEN sides (EXCHANGE sides untouched).
+ *
+ * sacx_stage: run the next stage of the step (1, 2, 3, 4, 1, ...) on the
+ * state whose ghost cells the caller completed.  At stage 1 the step begins:
+ * c_max = the x and y wave-speed maxima of the whole domain's current state
+ * (each >= 0 and finite, > 0 along a direction with more than one cell,
+ * EINVAL otherwise; NULL = this context's own); ignored at later stages.
+ * Stage 4 ends the step (t, step count, wave speeds of the new state).
+ * stage_done (optional) receives the stage that was enqueued.  ESTATE with a
+ * learned coefficient set.  Enqueued, not synchronised.
+ *
+ * sacx_wave_speeds: synchronise and return the x and y maxima of |v_d| + c_f
+ * over this context's interior cells of the current state (the step-start
+ * state while a step is in progress). */
+int sacx_fill_boundaries(sacx_ctx *ctx, int32_t direction);
+/* sacx_set_spacing: set the cell spacing (dx, dy; finite, > 0) from which
+ * the scheme's grid constants follow, in place of (x1 - x0) / nx and
+ * (y1 - y0) / ny of the context's grid.  A subdomain takes the spacing of
+ * the whole domain: its own extent over its own cell count can round
+ * differently.  EINVAL for bad values, ESTATE during a step begun with
+ * sacx_stage.  Host only; takes effect at the next step. */
+int sacx_set_spacing(sacx_ctx *ctx, double dx, double dy);
+int sacx_stage(sacx_ctx *ctx, const double c_max[2], int32_t *stage_done);
+int sacx_wave_speeds(sacx_ctx *ctx, double c_max[2]);
 
 /* Launch shape of the fused stage kernel: `threads` columns per block
  * including the 6-column apron (64, 128 or 256; the one-thread tile runs
@@ -243,7 +298,8 @@ typedef struct sacx_batch sacx_batch;
 int sacx_batch_workspace_size(int32_t n, const sacx_grid *grids, const sacx_params *params, size_t *bytes);
 
 /* Create a batch in caller-owned device memory (256-byte aligned).  bc: 4n
- * boundary kinds (x-, x+, y-, y+ per instance) or NULL for all periodic. */
+ * boundary kinds (x-, x+, y-, y+ per instance; PERIODIC or OPEN, EUNSUP for
+ * EXCHANGE) or NULL for all periodic. */
 int sacx_batch_create(int32_t n, const sacx_grid *grids, const sacx_params *params, const int32_t *bc,
                       void *d_ws, size_t ws_bytes, void *hip_stream, sacx_batch **out);
 int sacx_batch_destroy(sacx_batch *b);

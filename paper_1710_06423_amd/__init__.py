@@ -5,7 +5,8 @@ C ABI in ``include/sacx.h``); ``sacx`` is its thin ctypes binding.
 """
 
 from .sacx import (  # noqa: F401
-    FIELDS, BACKGROUND_FIELDS, PERIODIC, OPEN, FP64, FP32, GHOST,
+    FIELDS, BACKGROUND_FIELDS, PERIODIC, OPEN, EXCHANGE, FP64, FP32, GHOST,
     DEFAULT_C2, DEFAULT_CSHK, Solver, Batch, SacxError, load_library, make_grid, make_params,
     workspace_size,
 )
+from .decomposed import DecomposedSolver, even_cuts  # noqa: F401

@@ -94,6 +94,11 @@ struct sacx_ctx {
     HdDevStats *sur_st;
     int64_t sur_since;     // steps enqueued since the last refresh
     int64_t sur_refreshes, sur_tiles_checked;
+    // decomposed stepping (sacx_stage): the next RK4 stage, 0 between steps
+    int stage_next;
+    // bumped by every change a batch's instance table copies (boundaries,
+    // spacing), so that the batch rebuilds its table
+    unsigned long long gen;
 };
 
 namespace {
@@ -269,9 +274,10 @@ __global__ void k_unpack_y(FPtr<real> S, int nf, Layout L, const real *b0, const
     for (int g = 0; g < G; ++g) S.p[f][eidx(L, i - G, rg + g)] = b[((int64_t)f * G + g) * w + i];
 }
 
-// open (zero-gradient) or small-periodic (index modulo n) fills
+// open (zero-gradient) or small-periodic (index modulo n) fills; bit 0 / 1 of
+// `skip` leaves the low / high side alone (a side filled by the caller)
 template <typename real>
-__global__ void k_fill_x(FPtr<real> S, int nf, Layout L, int periodic, const DevScalars *sc) {
+__global__ void k_fill_x(FPtr<real> S, int nf, Layout L, int periodic, int skip, const DevScalars *sc) {
     if (sc && !step_active(sc)) return;
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
     const int f = blockIdx.y;
@@ -286,13 +292,13 @@ __global__ void k_fill_x(FPtr<real> S, int nf, Layout L, int periodic, const Dev
             sl = 0;
             sr = L.nx - 1;
         }
-        S.p[f][eidx(L, il, j)] = S.p[f][eidx(L, sl, j)];
-        S.p[f][eidx(L, ir, j)] = S.p[f][eidx(L, sr, j)];
+        if (!(skip & 1)) S.p[f][eidx(L, il, j)] = S.p[f][eidx(L, sl, j)];
+        if (!(skip & 2)) S.p[f][eidx(L, ir, j)] = S.p[f][eidx(L, sr, j)];
     }
 }
 
 template <typename real>
-__global__ void k_fill_y(FPtr<real> S, int nf, Layout L, int periodic, const DevScalars *sc) {
+__global__ void k_fill_y(FPtr<real> S, int nf, Layout L, int periodic, int skip, const DevScalars *sc) {
     if (sc && !step_active(sc)) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x - G;
     const int f = blockIdx.y;
@@ -307,8 +313,8 @@ __global__ void k_fill_y(FPtr<real> S, int nf, Layout L, int periodic, const Dev
             sl = 0;
             sr = L.ny - 1;
         }
-        S.p[f][eidx(L, i, jl)] = S.p[f][eidx(L, i, sl)];
-        S.p[f][eidx(L, i, jr)] = S.p[f][eidx(L, i, sr)];
+        if (!(skip & 1)) S.p[f][eidx(L, i, jl)] = S.p[f][eidx(L, i, sl)];
+        if (!(skip & 2)) S.p[f][eidx(L, i, jr)] = S.p[f][eidx(L, i, sr)];
     }
 }
 
@@ -404,6 +410,14 @@ __global__ void k_step_begin(DevScalars *sc, double t_end, StepConsts k) { step_
 
 __global__ void k_step_end(DevScalars *sc) { step_end_dev(sc); }
 
+// step start of decomposed stepping: the maxima over every subdomain replace
+// this subdomain's own, so that all subdomains take one dt and one c_max
+__global__ void k_step_begin_global(DevScalars *sc, double cx, double cy, StepConsts k) {
+    sc->cacc[sc->cur][0] = (unsigned long long)__double_as_longlong(cx);
+    sc->cacc[sc->cur][1] = (unsigned long long)__double_as_longlong(cy);
+    step_begin_dev(sc, 0.0, k);
+}
+
 // conservation sums: per-block partial sums of rows, then a fixed-order final sum
 template <typename real>
 __global__ void k_sums_partial(FPtr<real> U, Layout L, double *partials, int npart) {
@@ -466,34 +480,47 @@ FPtr<real> fptr(void *const *p, int nf) {
     return f;
 }
 
+// local boundary fill of one direction (0: x over the interior rows, 1: y over
+// the padded width, corners included, so x goes first); exchange sides are
+// left as the caller unpacked them
 template <typename real>
-int fill_halo_t(sacx_ctx *c, void *const *fields, int nf, bool gated) {
+void fill_dir_t(sacx_ctx *c, void *const *fields, int nf, bool gated, int dir) {
     const Layout &L = c->L;
     const DevScalars *sc = gated ? c->sc : nullptr;
     FPtr<real> S = fptr<real>(fields, nf);
     const int T = 256;
-    // x direction (interior rows)
-    if (c->bc[0] == SACX_PERIODIC && L.nx >= G) {
-        dim3 g((L.ny + T - 1) / T, nf, 2);
-        hipLaunchKernelGGL(k_pack_x<real>, g, dim3(T), 0, c->stream, S, nf, L, (real *)c->hx[0], (real *)c->hx[1], 2, sc);
-        // self-exchange: what x- packed becomes the x+ halo and vice versa
-        hipLaunchKernelGGL(k_unpack_x<real>, g, dim3(T), 0, c->stream, S, nf, L, (const real *)c->hx[1],
-                           (const real *)c->hx[0], 2, sc);
+    const int lo = c->bc[2 * dir], hi = c->bc[2 * dir + 1];
+    const int n = dir == 0 ? L.nx : L.ny;
+    const int along = dir == 0 ? L.ny : L.nx + 2 * G;
+    const int skip = (lo == SACX_EXCHANGE ? 1 : 0) | (hi == SACX_EXCHANGE ? 2 : 0);
+    if (skip == 3) return;
+    if (lo == SACX_PERIODIC && n >= G) {
+        // self-exchange: what the low side packed becomes the high halo and vice versa
+        void *const *h = dir == 0 ? c->hx : c->hy;
+        dim3 g((along + T - 1) / T, nf, 2);
+        if (dir == 0) {
+            hipLaunchKernelGGL(k_pack_x<real>, g, dim3(T), 0, c->stream, S, nf, L, (real *)h[0], (real *)h[1], 2, sc);
+            hipLaunchKernelGGL(k_unpack_x<real>, g, dim3(T), 0, c->stream, S, nf, L, (const real *)h[1],
+                               (const real *)h[0], 2, sc);
+        } else {
+            hipLaunchKernelGGL(k_pack_y<real>, g, dim3(T), 0, c->stream, S, nf, L, (real *)h[0], (real *)h[1], 2, sc);
+            hipLaunchKernelGGL(k_unpack_y<real>, g, dim3(T), 0, c->stream, S, nf, L, (const real *)h[1],
+                               (const real *)h[0], 2, sc);
+        }
     } else {
-        dim3 g((L.ny + T - 1) / T, nf);
-        hipLaunchKernelGGL(k_fill_x<real>, g, dim3(T), 0, c->stream, S, nf, L, c->bc[0] == SACX_PERIODIC ? 1 : 0, sc);
+        dim3 g((along + T - 1) / T, nf);
+        const int periodic = lo == SACX_PERIODIC ? 1 : 0;
+        if (dir == 0)
+            hipLaunchKernelGGL(k_fill_x<real>, g, dim3(T), 0, c->stream, S, nf, L, periodic, skip, sc);
+        else
+            hipLaunchKernelGGL(k_fill_y<real>, g, dim3(T), 0, c->stream, S, nf, L, periodic, skip, sc);
     }
-    // y direction over the padded width (corners included)
-    const int w = L.nx + 2 * G;
-    if (c->bc[2] == SACX_PERIODIC && L.ny >= G) {
-        dim3 g((w + T - 1) / T, nf, 2);
-        hipLaunchKernelGGL(k_pack_y<real>, g, dim3(T), 0, c->stream, S, nf, L, (real *)c->hy[0], (real *)c->hy[1], 2, sc);
-        hipLaunchKernelGGL(k_unpack_y<real>, g, dim3(T), 0, c->stream, S, nf, L, (const real *)c->hy[1],
-                           (const real *)c->hy[0], 2, sc);
-    } else {
-        dim3 g((w + T - 1) / T, nf);
-        hipLaunchKernelGGL(k_fill_y<real>, g, dim3(T), 0, c->stream, S, nf, L, c->bc[2] == SACX_PERIODIC ? 1 : 0, sc);
-    }
+}
+
+template <typename real>
+int fill_halo_t(sacx_ctx *c, void *const *fields, int nf, bool gated) {
+    fill_dir_t<real>(c, fields, nf, gated, 0);
+    fill_dir_t<real>(c, fields, nf, gated, 1);
     HIPCHK(hipGetLastError());
     return SACX_OK;
 }
@@ -501,6 +528,59 @@ int fill_halo_t(sacx_ctx *c, void *const *fields, int nf, bool gated) {
 int fill_halo(sacx_ctx *c, void *const *fields, int nf, bool gated) {
     return c->grid.precision == SACX_FP64 ? fill_halo_t<double>(c, fields, nf, gated)
                                           : fill_halo_t<float>(c, fields, nf, gated);
+}
+
+// the state the next stage differences: U between steps, then w1, w2, w3
+void *const *stage_input(sacx_ctx *c) {
+    switch (c->stage_next) {
+        case 1: return c->B1;
+        case 2: return c->B2;
+        case 3: return c->B1;
+        default: return c->U;
+    }
+}
+
+bool has_exchange(const sacx_ctx *c) {
+    for (int s = 0; s < 4; ++s)
+        if (c->bc[s] == SACX_EXCHANGE) return true;
+    return false;
+}
+
+// grid spacing and the scheme constants derived from it, in the same FP64
+// operations as the defining sequence
+void set_spacing(sacx_ctx *c, double dx, double dy) {
+    c->dx = dx;
+    c->dy = dy;
+    const sacx_params *params = &c->params;
+    SchemeConsts &k = c->kc;
+    k.gamma = params->gamma;
+    k.gm1 = params->gamma - 1.0;
+    k.igm1 = 1.0 / k.gm1;
+    k.i12dx = 1.0 / (12.0 * c->dx);
+    k.i12dy = 1.0 / (12.0 * c->dy);
+    k.idx = 1.0 / c->dx;
+    k.idy = 1.0 / c->dy;
+    k.i2dx = 1.0 / (2.0 * c->dx);
+    k.i2dy = 1.0 / (2.0 * c->dy);
+    for (int m = 0; m < 4; ++m) {
+        k.kxs[m] = params->cshk[m] * c->dx * c->dx;
+        k.kys[m] = params->cshk[m] * c->dy * c->dy;
+    }
+    k.third = 1.0 / 3.0;
+    k.gx = params->g[0];
+    k.gy = params->g[1];
+    k.grav = params->g[0] != 0.0 || params->g[1] != 0.0;
+}
+
+StepConsts step_consts(const sacx_ctx *c) {
+    StepConsts sk;
+    sk.cfl = c->params.cfl;
+    sk.dx = c->dx;
+    sk.dy = c->dy;
+    for (int m = 0; m < 4; ++m) sk.c2[m] = c->params.c2[m];
+    sk.ax = c->grid.nx > 1;
+    sk.ay = c->grid.ny > 1;
+    return sk;
 }
 
 template <typename real>
@@ -705,29 +785,7 @@ int sacx_create(const sacx_grid *grid, const sacx_params *params, void *d_ws, si
     c->nt = grid->precision == SACX_FP64 ? 128 : 256;
     c->split = 1;
     c->ty_auto = true;
-    c->dx = (grid->x1 - grid->x0) / grid->nx;
-    c->dy = (grid->y1 - grid->y0) / grid->ny;
-    {
-        // grid constants in the same FP64 operations as the defining sequence
-        SchemeConsts &k = c->kc;
-        k.gamma = params->gamma;
-        k.gm1 = params->gamma - 1.0;
-        k.igm1 = 1.0 / k.gm1;
-        k.i12dx = 1.0 / (12.0 * c->dx);
-        k.i12dy = 1.0 / (12.0 * c->dy);
-        k.idx = 1.0 / c->dx;
-        k.idy = 1.0 / c->dy;
-        k.i2dx = 1.0 / (2.0 * c->dx);
-        k.i2dy = 1.0 / (2.0 * c->dy);
-        for (int m = 0; m < 4; ++m) {
-            k.kxs[m] = params->cshk[m] * c->dx * c->dx;
-            k.kys[m] = params->cshk[m] * c->dy * c->dy;
-        }
-        k.third = 1.0 / 3.0;
-        k.gx = params->g[0];
-        k.gy = params->g[1];
-        k.grav = params->g[0] != 0.0 || params->g[1] != 0.0;
-    }
+    set_spacing(c, (grid->x1 - grid->x0) / grid->nx, (grid->y1 - grid->y0) / grid->ny);
     c->initialized = false;
     c->prof_on = false;
     c->sur_on = false;
@@ -830,8 +888,12 @@ int sacx_profile_read(sacx_ctx *ctx, sacx_profile *out) {
 
 int sacx_set_boundaries(sacx_ctx *ctx, const int32_t bc[4]) {
     if (!ctx || !bc) return fail(SACX_EINVAL, "ctx/bc must not be NULL");
-    for (int s = 0; s < 4; ++s)
-        if (bc[s] != SACX_PERIODIC && bc[s] != SACX_OPEN) return fail(SACX_EINVAL, "bc[%d] = %d is not a boundary kind", s, bc[s]);
+    bool exch = false;
+    for (int s = 0; s < 4; ++s) {
+        if (bc[s] != SACX_PERIODIC && bc[s] != SACX_OPEN && bc[s] != SACX_EXCHANGE)
+            return fail(SACX_EINVAL, "bc[%d] = %d is not a boundary kind", s, bc[s]);
+        exch = exch || bc[s] == SACX_EXCHANGE;
+    }
     if ((bc[0] == SACX_PERIODIC) != (bc[1] == SACX_PERIODIC))
         return fail(SACX_EINVAL, "periodic x boundaries must be paired");
     if ((bc[2] == SACX_PERIODIC) != (bc[3] == SACX_PERIODIC))
@@ -842,7 +904,20 @@ int sacx_set_boundaries(sacx_ctx *ctx, const int32_t bc[4]) {
         for (int s = 0; s < 4; ++s)
             if (bc[s] != SACX_PERIODIC)
                 return fail(SACX_ESTATE, "the surrogate's ratio planes are periodic: clear it before opening a boundary");
+    if (exch && ctx->grid.background_on)
+        return fail(SACX_EUNSUP, "exchange boundaries are not supported with a background");
+    if ((bc[0] == SACX_EXCHANGE || bc[1] == SACX_EXCHANGE) && ctx->grid.nx < G)
+        return fail(SACX_EUNSUP, "an exchange side needs at least %d cells across", G);
+    if ((bc[2] == SACX_EXCHANGE || bc[3] == SACX_EXCHANGE) && ctx->grid.ny < G)
+        return fail(SACX_EUNSUP, "an exchange side needs at least %d cells across", G);
     for (int s = 0; s < 4; ++s) ctx->bc[s] = bc[s];
+    ctx->gen += 1;
+    if (ctx->initialized && ctx->grid.background_on) {
+        // the static background's halos follow the new boundaries
+        DeviceGuard dg(ctx->device);
+        if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+        return fill_halo(ctx, ctx->BG, NBG, false);
+    }
     return SACX_OK;
 }
 
@@ -899,6 +974,7 @@ int sacx_init_state(sacx_ctx *ctx, const void *const *d_fields, const void *cons
     rc = wavespeed_into(ctx, 0);
     if (rc) return rc;
     HIPCHK(hipGetLastError());
+    ctx->stage_next = 0;
     ctx->initialized = true;
     return SACX_OK;
 }
@@ -908,6 +984,8 @@ int sacx_advance(sacx_ctx *ctx, int32_t nsteps, double t_end, int32_t *steps_don
     if (nsteps < 0) return fail(SACX_EINVAL, "nsteps must be >= 0");
     if (!std::isfinite(t_end)) return fail(SACX_EINVAL, "t_end must be finite");
     if (!ctx->initialized) return fail(SACX_ESTATE, "sacx_init_state has not been called");
+    if (has_exchange(ctx)) return fail(SACX_ESTATE, "a context with exchange boundaries steps with sacx_stage");
+    if (ctx->stage_next) return fail(SACX_ESTATE, "a step begun with sacx_stage is in progress");
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
     long long steps0 = 0;
@@ -916,14 +994,7 @@ int sacx_advance(sacx_ctx *ctx, int32_t nsteps, double t_end, int32_t *steps_don
         HIPCHK(hipMemcpyAsync(&steps0, &ctx->sc->steps, sizeof(steps0), hipMemcpyDeviceToHost, ctx->stream));
         HIPCHK(hipStreamSynchronize(ctx->stream));
     }
-    const int ax = ctx->grid.nx > 1, ay = ctx->grid.ny > 1;
-    StepConsts sk;
-    sk.cfl = ctx->params.cfl;
-    sk.dx = ctx->dx;
-    sk.dy = ctx->dy;
-    for (int m = 0; m < 4; ++m) sk.c2[m] = ctx->params.c2[m];
-    sk.ax = ax;
-    sk.ay = ay;
+    const StepConsts sk = step_consts(ctx);
     // A synchronising call enqueues in chunks and stops early once the device
     // reports that stepping ended (end time reached or non-physical state).
     const int chunk = sync ? 128 : (nsteps > 0 ? nsteps : 1);
@@ -1058,23 +1129,24 @@ static int halo_io(sacx_ctx *ctx, int32_t side, void *buf, bool pack) {
     const int T = 256;
     const int s = side & 1;
     const bool f64 = ctx->grid.precision == SACX_FP64;
+    void *const *S = stage_input(ctx);
     if (side < 2) {
         dim3 g((L.ny + T - 1) / T, NF, 1);
         if (f64) {
-            if (pack) hipLaunchKernelGGL(k_pack_x<double>, g, dim3(T), 0, ctx->stream, fptr<double>(ctx->U, NF), NF, L, (double *)buf, (double *)buf, 10 + s, (const DevScalars *)nullptr);
-            else hipLaunchKernelGGL(k_unpack_x<double>, g, dim3(T), 0, ctx->stream, fptr<double>(ctx->U, NF), NF, L, (const double *)buf, (const double *)buf, 10 + s, (const DevScalars *)nullptr);
+            if (pack) hipLaunchKernelGGL(k_pack_x<double>, g, dim3(T), 0, ctx->stream, fptr<double>(S, NF), NF, L, (double *)buf, (double *)buf, 10 + s, (const DevScalars *)nullptr);
+            else hipLaunchKernelGGL(k_unpack_x<double>, g, dim3(T), 0, ctx->stream, fptr<double>(S, NF), NF, L, (const double *)buf, (const double *)buf, 10 + s, (const DevScalars *)nullptr);
         } else {
-            if (pack) hipLaunchKernelGGL(k_pack_x<float>, g, dim3(T), 0, ctx->stream, fptr<float>(ctx->U, NF), NF, L, (float *)buf, (float *)buf, 10 + s, (const DevScalars *)nullptr);
-            else hipLaunchKernelGGL(k_unpack_x<float>, g, dim3(T), 0, ctx->stream, fptr<float>(ctx->U, NF), NF, L, (const float *)buf, (const float *)buf, 10 + s, (const DevScalars *)nullptr);
+            if (pack) hipLaunchKernelGGL(k_pack_x<float>, g, dim3(T), 0, ctx->stream, fptr<float>(S, NF), NF, L, (float *)buf, (float *)buf, 10 + s, (const DevScalars *)nullptr);
+            else hipLaunchKernelGGL(k_unpack_x<float>, g, dim3(T), 0, ctx->stream, fptr<float>(S, NF), NF, L, (const float *)buf, (const float *)buf, 10 + s, (const DevScalars *)nullptr);
         }
     } else {
         dim3 g((L.nx + 2 * G + T - 1) / T, NF, 1);
         if (f64) {
-            if (pack) hipLaunchKernelGGL(k_pack_y<double>, g, dim3(T), 0, ctx->stream, fptr<double>(ctx->U, NF), NF, L, (double *)buf, (double *)buf, 10 + s, (const DevScalars *)nullptr);
-            else hipLaunchKernelGGL(k_unpack_y<double>, g, dim3(T), 0, ctx->stream, fptr<double>(ctx->U, NF), NF, L, (const double *)buf, (const double *)buf, 10 + s, (const DevScalars *)nullptr);
+            if (pack) hipLaunchKernelGGL(k_pack_y<double>, g, dim3(T), 0, ctx->stream, fptr<double>(S, NF), NF, L, (double *)buf, (double *)buf, 10 + s, (const DevScalars *)nullptr);
+            else hipLaunchKernelGGL(k_unpack_y<double>, g, dim3(T), 0, ctx->stream, fptr<double>(S, NF), NF, L, (const double *)buf, (const double *)buf, 10 + s, (const DevScalars *)nullptr);
         } else {
-            if (pack) hipLaunchKernelGGL(k_pack_y<float>, g, dim3(T), 0, ctx->stream, fptr<float>(ctx->U, NF), NF, L, (float *)buf, (float *)buf, 10 + s, (const DevScalars *)nullptr);
-            else hipLaunchKernelGGL(k_unpack_y<float>, g, dim3(T), 0, ctx->stream, fptr<float>(ctx->U, NF), NF, L, (const float *)buf, (const float *)buf, 10 + s, (const DevScalars *)nullptr);
+            if (pack) hipLaunchKernelGGL(k_pack_y<float>, g, dim3(T), 0, ctx->stream, fptr<float>(S, NF), NF, L, (float *)buf, (float *)buf, 10 + s, (const DevScalars *)nullptr);
+            else hipLaunchKernelGGL(k_unpack_y<float>, g, dim3(T), 0, ctx->stream, fptr<float>(S, NF), NF, L, (const float *)buf, (const float *)buf, 10 + s, (const DevScalars *)nullptr);
         }
     }
     HIPCHK(hipGetLastError());
@@ -1085,6 +1157,92 @@ int sacx_halo_pack(sacx_ctx *ctx, int32_t side, void *d_buf) { return halo_io(ct
 
 int sacx_halo_unpack(sacx_ctx *ctx, int32_t side, const void *d_buf) {
     return halo_io(ctx, side, const_cast<void *>(d_buf), false);
+}
+
+// ------------------------------------------------------------------ decomposed stepping
+
+int sacx_fill_boundaries(sacx_ctx *ctx, int32_t direction) {
+    if (!ctx) return fail(SACX_EINVAL, "ctx must not be NULL");
+    if (direction != 0 && direction != 1) return fail(SACX_EINVAL, "direction must be 0 (x) or 1 (y)");
+    if (!ctx->initialized) return fail(SACX_ESTATE, "sacx_init_state has not been called");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    ProfScope ps(ctx, 4);
+    if (ctx->grid.precision == SACX_FP64) fill_dir_t<double>(ctx, stage_input(ctx), NF, false, direction);
+    else fill_dir_t<float>(ctx, stage_input(ctx), NF, false, direction);
+    HIPCHK(hipGetLastError());
+    return SACX_OK;
+}
+
+int sacx_stage(sacx_ctx *ctx, const double c_max[2], int32_t *stage_done) {
+    if (!ctx) return fail(SACX_EINVAL, "ctx must not be NULL");
+    if (!ctx->initialized) return fail(SACX_ESTATE, "sacx_init_state has not been called");
+    if (ctx->sur_on) return fail(SACX_ESTATE, "a context with a learned coefficient steps with sacx_advance");
+    if (ctx->stage_next == 0 && c_max) {
+        for (int d = 0; d < 2; ++d)
+            if (!std::isfinite(c_max[d]) || c_max[d] < 0.0) return fail(SACX_EINVAL, "c_max[%d] must be finite and >= 0", d);
+        if ((ctx->grid.nx > 1 && !(c_max[0] > 0.0)) || (ctx->grid.ny > 1 && !(c_max[1] > 0.0)))
+            return fail(SACX_EINVAL, "c_max must be > 0 along every direction with more than one cell");
+    }
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    const int s = ctx->stage_next + 1;
+    if (s == 1) {
+        ProfScope ps(ctx, 5);
+        if (c_max)
+            hipLaunchKernelGGL(k_step_begin_global, dim3(1), dim3(1), 0, ctx->stream, ctx->sc, c_max[0], c_max[1],
+                               step_consts(ctx));
+        else
+            hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, ctx->stream, ctx->sc, 0.0, step_consts(ctx));
+        HIPCHK(hipGetLastError());
+    }
+    int rc;
+    {
+        ProfScope ps(ctx, s - 1);
+        const bool f64 = ctx->grid.precision == SACX_FP64;
+        switch (s) {
+            case 1: rc = f64 ? run_stage<double>(ctx, 1, ctx->U, nullptr, nullptr, ctx->B1, nullptr)
+                             : run_stage<float>(ctx, 1, ctx->U, nullptr, nullptr, ctx->B1, nullptr); break;
+            case 2: rc = f64 ? run_stage<double>(ctx, 2, ctx->B1, ctx->U, nullptr, ctx->B2, ctx->A)
+                             : run_stage<float>(ctx, 2, ctx->B1, ctx->U, nullptr, ctx->B2, ctx->A); break;
+            case 3: rc = f64 ? run_stage<double>(ctx, 3, ctx->B2, ctx->U, nullptr, ctx->B1, nullptr)
+                             : run_stage<float>(ctx, 3, ctx->B2, ctx->U, nullptr, ctx->B1, nullptr); break;
+            default: rc = f64 ? run_stage<double>(ctx, 4, ctx->B1, nullptr, ctx->A, ctx->U, nullptr)
+                              : run_stage<float>(ctx, 4, ctx->B1, nullptr, ctx->A, ctx->U, nullptr); break;
+        }
+    }
+    if (rc) return rc;
+    if (s == 4) {
+        ProfScope ps(ctx, 5);
+        hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, ctx->stream, ctx->sc);
+        HIPCHK(hipGetLastError());
+    }
+    ctx->stage_next = s & 3;
+    if (stage_done) *stage_done = s;
+    return SACX_OK;
+}
+
+int sacx_set_spacing(sacx_ctx *ctx, double dx, double dy) {
+    if (!ctx) return fail(SACX_EINVAL, "ctx must not be NULL");
+    if (!std::isfinite(dx) || !std::isfinite(dy) || !(dx > 0.0) || !(dy > 0.0))
+        return fail(SACX_EINVAL, "dx and dy must be finite and > 0");
+    if (ctx->stage_next) return fail(SACX_ESTATE, "a step begun with sacx_stage is in progress");
+    set_spacing(ctx, dx, dy);
+    ctx->gen += 1;
+    return SACX_OK;
+}
+
+int sacx_wave_speeds(sacx_ctx *ctx, double c_max[2]) {
+    if (!ctx || !c_max) return fail(SACX_EINVAL, "ctx/c_max must not be NULL");
+    if (!ctx->initialized) return fail(SACX_ESTATE, "sacx_init_state has not been called");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    DevScalars h;
+    HIPCHK(hipMemcpyAsync(&h, ctx->sc, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    c_max[0] = __builtin_bit_cast(double, h.cacc[h.cur][0]);
+    c_max[1] = __builtin_bit_cast(double, h.cacc[h.cur][1]);
+    return SACX_OK;
 }
 
 // ------------------------------------------------------------------ surrogate
@@ -1264,6 +1422,7 @@ struct sacx_batch {
     int nt;
     std::vector<int> *rows;
     bool dirty;
+    unsigned long long gen_built;  // sum of the instance generations the table was built from
     int blocks;
 };
 
@@ -1450,6 +1609,11 @@ int sacx_batch_create(int32_t n, const sacx_grid *grids, const sacx_params *para
         if (rc) { sacx_batch_destroy(b); return rc; }
         b->ctx->push_back(c);
         if (bc) {
+            for (int k = 0; k < 4; ++k)
+                if (bc[4 * i + k] == SACX_EXCHANGE) {
+                    sacx_batch_destroy(b);
+                    return fail(SACX_EUNSUP, "instance %d: a batched instance cannot have exchange boundaries", i);
+                }
             rc = sacx_set_boundaries(c, bc + 4 * i);
             if (rc) { sacx_batch_destroy(b); return rc; }
         }
@@ -1484,13 +1648,19 @@ int sacx_batch_set_tiles(sacx_batch *b, int32_t threads, const int32_t *rows) {
 int sacx_batch_advance(sacx_batch *b, int32_t nsteps, int32_t sync) {
     if (!b) return fail(SACX_EINVAL, "batch must not be NULL");
     if (nsteps < 0) return fail(SACX_EINVAL, "nsteps must be >= 0");
-    for (sacx_ctx *c : *b->ctx)
+    unsigned long long gsum = 0;
+    for (sacx_ctx *c : *b->ctx) {
         if (!c->initialized) return fail(SACX_ESTATE, "every batch instance needs sacx_init_state first");
+        if (has_exchange(c)) return fail(SACX_ESTATE, "a batched instance cannot have exchange boundaries");
+        if (c->stage_next) return fail(SACX_ESTATE, "a batched instance has a step begun with sacx_stage in progress");
+        gsum += c->gen;
+    }
     DeviceGuard dg(b->device);
     if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the batch device");
-    if (b->dirty) {
+    if (b->dirty || gsum != b->gen_built) {
         int rc = b->precision == SACX_FP64 ? batch_build<double>(b) : batch_build<float>(b);
         if (rc) return rc;
+        b->gen_built = gsum;
     }
     const int per_launch = b->ctr_cap / 4;
     for (int done = 0; done < nsteps; done += per_launch) {

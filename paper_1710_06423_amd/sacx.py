@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsacx.so")
 
 OK, EINVAL, ENOSPC, EDEVICE, ENONPHYS, EUNSUP, ESTATE = 0, -1, -2, -3, -4, -5, -6
-PERIODIC, OPEN = 0, 1
+PERIODIC, OPEN, EXCHANGE = 0, 1, 2
 FP64, FP32 = 0, 1
 GHOST = 3
 FIELDS = ("rho", "mx", "my", "e", "bx", "by")
@@ -33,6 +33,7 @@ EXPORTED = (
     "sacx_abi_version", "sacx_strerror", "sacx_last_error", "sacx_workspace_size", "sacx_create",
     "sacx_destroy", "sacx_set_boundaries", "sacx_init_state", "sacx_advance", "sacx_read_fields",
     "sacx_diagnostics", "sacx_halo_buffer_size", "sacx_halo_pack", "sacx_halo_unpack",
+    "sacx_fill_boundaries", "sacx_stage", "sacx_wave_speeds", "sacx_set_spacing",
     "sacx_profile_enable", "sacx_profile_read", "sacx_set_launch", "sacx_get_launch", "sacx_set_column_split",
     "sacx_batch_workspace_size", "sacx_batch_create", "sacx_batch_destroy", "sacx_batch_context",
     "sacx_batch_set_tiles", "sacx_batch_advance",
@@ -123,6 +124,10 @@ def load_library():
     lib.sacx_halo_buffer_size.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)]
     lib.sacx_halo_pack.argtypes = [P, ctypes.c_int32, P]
     lib.sacx_halo_unpack.argtypes = [P, ctypes.c_int32, P]
+    lib.sacx_fill_boundaries.argtypes = [P, ctypes.c_int32]
+    lib.sacx_stage.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+    lib.sacx_wave_speeds.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
+    lib.sacx_set_spacing.argtypes = [P, ctypes.c_double, ctypes.c_double]
     lib.sacx_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.sacx_profile_read.argtypes = [P, ctypes.POINTER(Profile)]
     lib.sacx_set_launch.argtypes = [P, ctypes.c_int32, ctypes.c_int32]
@@ -316,6 +321,33 @@ class Solver:
     def halo_unpack(self, side: int, buf: torch.Tensor):
         with torch.cuda.device(self.device):
             _check(self.lib.sacx_halo_unpack(self.ctx, int(side), ctypes.c_void_p(buf.data_ptr())), "sacx_halo_unpack")
+
+    def fill_boundaries(self, direction: int):
+        """Fill the PERIODIC / OPEN ghost cells of one direction (0: x, 1: y)
+        of the state the next stage differences."""
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_fill_boundaries(self.ctx, int(direction)), "sacx_fill_boundaries")
+
+    def stage(self, c_max: Optional[Sequence[float]] = None) -> int:
+        """Enqueue the next RK4 stage; c_max (x, y) is the whole domain's
+        wave-speed maxima, used when the stage begins a step."""
+        c = None if c_max is None else (ctypes.c_double * 2)(*[float(v) for v in c_max])
+        done = ctypes.c_int32(0)
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_stage(self.ctx, c, ctypes.byref(done)), "sacx_stage")
+        return done.value
+
+    def set_spacing(self, dx: float, dy: float):
+        """Grid spacing in place of the extent over the cell count (a
+        subdomain takes the whole domain's)."""
+        _check(self.lib.sacx_set_spacing(self.ctx, float(dx), float(dy)), "sacx_set_spacing")
+
+    def wave_speeds(self):
+        """(c_x, c_y) maxima of the current state's interior (synchronises)."""
+        c = (ctypes.c_double * 2)()
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_wave_speeds(self.ctx, c), "sacx_wave_speeds")
+        return c[0], c[1]
 
     def profile_enable(self, on: bool = True):
         _check(self.lib.sacx_profile_enable(self.ctx, int(bool(on))), "sacx_profile_enable")

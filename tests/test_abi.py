@@ -158,3 +158,13 @@ def test_setters_reject_null_context(sx):
     assert lib.sacx_set_column_split(None, 1) == sx.EINVAL
     assert lib.sacx_set_launch(None, 128, 64) == sx.EINVAL
     assert lib.sacx_set_boundaries(None, None) == sx.EINVAL
+
+
+def test_stage_calls_reject_null_context(sx):
+    """Host-side argument checks of the decomposed-stepping calls."""
+    lib = sx.load_library()
+    c = (ctypes.c_double * 2)(1.0, 1.0)
+    assert lib.sacx_fill_boundaries(None, 0) == sx.EINVAL
+    assert lib.sacx_stage(None, c, None) == sx.EINVAL
+    assert lib.sacx_wave_speeds(None, c) == sx.EINVAL
+    assert lib.sacx_set_spacing(None, 0.1, 0.1) == sx.EINVAL

@@ -1,0 +1,193 @@
+"""Decomposed stepping (paper section 3, Fig. 1): a domain split into
+subdomain contexts that exchange their halo strips before every stage and
+share one time step evolves bit for bit as the undivided domain, which
+itself follows the FP64 oracle bit for bit.
+
+All subdomains run on one GPU, on one stream; the exchange buffers are what
+several GPUs would send each other.
+"""
+
+import dataclasses
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+OPEN = W.problems.OPEN
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _whole(prob, nsteps, **kw):
+    from paper_1710_06423_amd import Solver
+    s = Solver.from_problem(prob, **kw)
+    s.advance(nsteps)
+    f = s.read_fields()
+    d = s.diagnostics()
+    s.close()
+    return f, d
+
+
+def _decomposed(prob, xcuts, ycuts, nsteps, **kw):
+    from paper_1710_06423_amd import DecomposedSolver
+    dec = DecomposedSolver(prob, xcuts, ycuts, **kw)
+    dec.advance(nsteps)
+    f = dec.read_fields()
+    d = dec.diagnostics()
+    dec.close()
+    return f, d
+
+
+def _check(torch, prob, xcuts, ycuts, nsteps, label, **kw):
+    print(f"case: {label} cuts x {xcuts} y {ycuts} steps {nsteps} {kw}", flush=True)
+    ref, dref = _whole(prob, nsteps, **kw)
+    got, dgot = _decomposed(prob, xcuts, ycuts, nsteps, **kw)
+    nd = int((got != ref).sum())
+    print(f"[decomposed] {label}: {nd} elements differ", flush=True)
+    assert nd == 0, label
+    for row in dgot:
+        for d in row:
+            assert d["steps"] == dref["steps"] and d["t"] == dref["t"] and d["dt"] == dref["dt"]
+    return got
+
+
+@pytest.mark.parametrize("xcuts,ycuts", [
+    ([0, 50, 128], [0, 40, 96]),          # 2 x 2 as in the paper's figure, uneven
+    ([0, 128], [0, 31, 64, 96]),          # strips along y, x periodic locally
+    ([0, 3, 70, 128], [0, 96]),           # strips along x, one of 3 columns (the halo depth)
+    ([0, 40, 80, 128], [0, 30, 66, 96]),  # 3 x 3
+])
+def test_periodic_orszag_tang(xcuts, ycuts):
+    torch = _torch()
+    _check(torch, W.orszag_tang(128, ny=96), xcuts, ycuts, 12, "OT periodic")
+
+
+def test_periodic_matches_oracle(oracle_lib):
+    """The decomposed run against the oracle directly."""
+    torch = _torch()
+    prob = W.orszag_tang(96, ny=80)
+    got = _check(torch, prob, [0, 33, 96], [0, 47, 80], 15, "OT vs oracle").cpu().numpy()
+    ora = oracle_lib.State(prob)
+    ora.run(15)
+    assert np.array_equal(got, ora.stacked())
+
+
+@pytest.mark.parametrize("bc", [(OPEN, OPEN, 0, 0), (0, 0, OPEN, OPEN), (OPEN,) * 4])
+def test_open_boundaries(bc):
+    """Open outer sides with exchange sides inside (the corners of a y strip
+    come from an x exchange next to an open fill)."""
+    torch = _torch()
+    prob = W.random_smooth(90, 70, seed=5, bc=bc)
+    _check(torch, prob, [0, 41, 90], [0, 33, 70], 10, f"random smooth bc {bc}")
+
+
+def test_brio_wu_pieces():
+    """A 1-D shock tube cut into three pieces (open ends)."""
+    torch = _torch()
+    _check(torch, W.brio_wu(800), [0, 250, 551, 800], [0, 1], 40, "Brio-Wu")
+
+
+@pytest.mark.parametrize("variant", ["no_hd", "no_cross", "gravity", "one_thread_tile"])
+def test_scheme_variants(variant):
+    torch = _torch()
+    prob = W.orszag_tang(100, ny=72)
+    kw = {}
+    if variant == "no_hd":
+        kw = dict(hd_on=False)
+    elif variant == "no_cross":
+        kw = dict(hd_cross_on=False)
+    elif variant == "gravity":
+        prob = W.with_gravity(prob, (0.3, -0.8))
+    if variant != "one_thread_tile":
+        _check(torch, prob, [0, 45, 100], [0, 36, 72], 10, variant, **kw)
+        return
+    # the one-thread tile in every subdomain and in the undivided run
+    from paper_1710_06423_amd import DecomposedSolver, Solver
+    s = Solver.from_problem(prob)
+    s.set_column_split(False)
+    s.advance(10)
+    ref = s.read_fields()
+    dec = DecomposedSolver(prob, [0, 45, 100], [0, 36, 72])
+    for row in dec.subs:
+        for sub in row:
+            sub.set_column_split(False)
+    dec.advance(10)
+    assert torch.equal(dec.read_fields(), ref)
+
+
+def test_fp32_decomposed_equals_undivided():
+    """FP32 bulk: the decomposed run equals the undivided FP32 run bit for
+    bit (the FP64 time step is the same, every cell sees the same inputs)."""
+    torch = _torch()
+    from paper_1710_06423_amd import FP32
+    _check(torch, W.orszag_tang(128, ny=80), [0, 64, 128], [0, 37, 80], 12, "OT FP32", precision=FP32)
+
+
+def test_stage_calls_reject_misuse():
+    """Argument and order checks of the stage-level calls."""
+    torch = _torch()
+    from paper_1710_06423_amd import EXCHANGE, Solver, SacxError, Batch
+    from paper_1710_06423_amd import sacx
+    prob = W.orszag_tang(32)
+    s = Solver.from_problem(prob)
+
+    def code(fn, *a):
+        with pytest.raises(SacxError) as e:
+            fn(*a)
+        return e.value.code
+
+    assert code(s.fill_boundaries, 2) == sacx.EINVAL
+    assert code(s.set_boundaries, (3, 0, 0, 0)) == sacx.EINVAL
+    assert code(s.set_boundaries, (0, EXCHANGE, 0, 0)) == sacx.EINVAL   # periodic sides come in pairs
+    assert code(s.stage, (float("nan"), 1.0)) == sacx.EINVAL
+    assert code(s.stage, (0.0, 1.0)) == sacx.EINVAL
+    s.set_boundaries((EXCHANGE,) * 4)
+    assert code(s.advance, 1) == sacx.ESTATE
+    s.set_boundaries((0,) * 4)
+    assert s.stage(None) == 1                 # a step begun stage by stage ...
+    assert code(s.advance, 1) == sacx.ESTATE  # ... must be finished that way
+    s.fill_boundaries(0)
+    s.fill_boundaries(1)
+    assert s.stage(None) == 2
+    for st in (3, 4):
+        s.fill_boundaries(0)
+        s.fill_boundaries(1)
+        assert s.stage((123.0, 456.0)) == st   # c_max is only read at stage 1
+    s.advance(1)
+    assert s.diagnostics()["steps"] == 2
+    s.close()
+    # a background cannot have exchange sides; a small direction neither
+    bg = Solver.from_problem(W.stratified_atmosphere(16, 20))
+    assert code(bg.set_boundaries, (0, 0, EXCHANGE, EXCHANGE)) == sacx.EUNSUP
+    bg.close()
+    thin = Solver.from_problem(W.orszag_tang(2, ny=16))
+    assert code(thin.set_boundaries, (EXCHANGE, EXCHANGE, 0, 0)) == sacx.EUNSUP
+    thin.close()
+    with pytest.raises(SacxError) as e:
+        Batch([dataclasses.replace(W.orszag_tang(32), bc=(EXCHANGE,) * 4)])
+    assert e.value.code == sacx.EUNSUP
+
+
+def test_stage_by_stage_equals_advance():
+    """A single context stepped stage by stage with its own boundary fills
+    and its own wave speeds equals sacx_advance."""
+    torch = _torch()
+    from paper_1710_06423_amd import Solver
+    prob = W.random_smooth(60, 44, seed=9, bc=(OPEN, OPEN, 0, 0))
+    a = Solver.from_problem(prob)
+    a.advance(8)
+    b = Solver.from_problem(prob)
+    for _ in range(8):
+        for _st in range(4):
+            b.fill_boundaries(0)
+            b.fill_boundaries(1)
+            b.stage(None)
+    assert torch.equal(a.read_fields(), b.read_fields())
+    assert a.diagnostics()["t"] == b.diagnostics()["t"]

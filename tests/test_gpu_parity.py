@@ -59,7 +59,7 @@ def test_library_loads_on_gpu():
     torch = _torch()
     from paper_1710_06423_amd import load_library
     lib = load_library()
-    assert lib.sacx_abi_version() == 2
+    assert lib.sacx_abi_version() == 3
     assert torch.cuda.get_device_properties(0).gcnArchName.startswith("gfx950")
 
 
