@@ -11,20 +11,54 @@
 
 namespace sacx {
 
+// The chip hands consecutive blocks of a launch to its 8 XCDs in turn (the
+// linear block index modulo 8), each XCD with its own L2.  The blocks are
+// renumbered so that tiles that are neighbours in row-major order run on one
+// XCD and fetch the apron columns they share into one L2: RUN > 0 gives each
+// XCD runs of RUN neighbouring tiles while the launch keeps its row-major
+// progress (blocks past the last whole group of 8 runs keep their index);
+// RUN == 0 gives each XCD one contiguous run of n/8 tiles.  Either is a
+// bijection of the block indices, so every tile is still computed once.
+// Measured at Orszag-Tang 8000^2 (three runs each): the FP32 one-thread tile
+// is 2.8 % faster with one contiguous run (1.6 % with runs of 4); the FP64
+// split tile 0.8 % faster with runs of 4 and 6 % slower with one contiguous run.
+constexpr int kXcds = 8;
+
+template <int RUN>
+__device__ __forceinline__ void xcd_tile(int &tx, int &ty) {
+    const int gx = (int)gridDim.x;
+    const int n = gx * (int)gridDim.y;
+    const int b = (int)blockIdx.x + (int)blockIdx.y * gx;
+    const int x = b % kXcds, i = b / kXcds;
+    int l;
+    if (RUN == 0) {
+        const int q = n / kXcds, r = n % kXcds;
+        l = x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+    } else {
+        l = b < n - n % (kXcds * RUN) ? ((i / RUN) * kXcds + x) * RUN + i % RUN : b;
+    }
+    tx = l % gx;
+    ty = l / gx;
+}
+
 // FP32 builds are held to two waves per SIMD (all but the background
 // stage-4 build fit without the bound; that one would otherwise take one
 // register too many and run one wave per SIMD at half speed)
 template <typename real, int NT, int STAGE, bool HD, bool BG, bool SUR = false>
 __global__ __launch_bounds__(NT, sizeof(real) == 4 ? 2 : 1) void k_stage(StageArgs<real> a) {
     __shared__ TileLds<real, NT> lds;
-    stage_tile<real, NT, STAGE, HD, BG, SUR>(a, blockIdx.x, blockIdx.y, lds);
+    int tx, ty;
+    xcd_tile<0>(tx, ty);
+    stage_tile<real, NT, STAGE, HD, BG, SUR>(a, tx, ty, lds);
 }
 
 // two threads per column (x and y roles), two waves per SIMD
 template <typename real, int NC, int STAGE, bool BG>
 __global__ __launch_bounds__(2 * NC, 2) void k_stage_split(StageArgs<real> a) {
     __shared__ SplitLds<real, NC, BG> lds;
-    stage_tile_split<real, NC, STAGE, BG>(a, blockIdx.x, blockIdx.y, lds);
+    int tx, ty;
+    xcd_tile<4>(tx, ty);
+    stage_tile_split<real, NC, STAGE, BG>(a, tx, ty, lds);
 }
 
 template <typename real, int NT, int STAGE, bool HD>
