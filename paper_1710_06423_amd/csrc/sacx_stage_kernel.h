@@ -19,9 +19,12 @@ namespace sacx {
 // progress (blocks past the last whole group of 8 runs keep their index);
 // RUN == 0 gives each XCD one contiguous run of n/8 tiles.  Either is a
 // bijection of the block indices, so every tile is still computed once.
-// Measured at Orszag-Tang 8000^2 (three runs each): the FP32 one-thread tile
-// is 2.8 % faster with one contiguous run (1.6 % with runs of 4); the FP64
-// split tile 0.8 % faster with runs of 4 and 6 % slower with one contiguous run.
+// Measured at 8000^2 against no renumbering (two or three runs each): FP32
+// tiles are 2.7 % (Orszag-Tang) and 3.9 % (stratified) faster with one
+// contiguous run, and no faster with runs of 4; FP64 tiles are faster with
+// runs of 4 (split tile 0.8 %, the tile without hyper-diffusion 2.8 %) and
+// slower with one contiguous run (6 % and 4 %).  FP64 kernels take 4 and FP32
+// kernels 0.
 constexpr int kXcds = 8;
 
 template <int RUN>
@@ -48,7 +51,7 @@ template <typename real, int NT, int STAGE, bool HD, bool BG, bool SUR = false>
 __global__ __launch_bounds__(NT, sizeof(real) == 4 ? 2 : 1) void k_stage(StageArgs<real> a) {
     __shared__ TileLds<real, NT> lds;
     int tx, ty;
-    xcd_tile<0>(tx, ty);
+    xcd_tile<sizeof(real) == 4 ? 0 : 4>(tx, ty);
     stage_tile<real, NT, STAGE, HD, BG, SUR>(a, tx, ty, lds);
 }
 
