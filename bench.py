@@ -19,6 +19,12 @@ Other modes (one JSON line each):
   --mode surrogate  the learned hyper-diffusion coefficient: trained on
                     solver-generated Orszag-Tang data, evaluated on an
                     Orszag-Tang 2048^2 run at refresh intervals K = 1, 4, 16;
+  --mode decomposed the same workload split into px x py subdomain contexts
+                    on the one GPU (--split, default 2x2), stepped stage by
+                    stage with a halo exchange between them before every
+                    stage and a device max of the wave speeds per step,
+                    beside the undivided run (the cost of the exchange path;
+                    the results are compared bit for bit);
   --mode copy       a device copy of known size (calibrates the HBM byte
                     counters of a profiler run).
 """
@@ -226,6 +232,72 @@ def run_single(args):
     print(json.dumps(out), flush=True)
 
 
+def run_decomposed(args):
+    import torch
+    import workloads as W
+    from paper_1710_06423_amd import FP32, FP64, DecomposedSolver, Solver, even_cuts
+
+    n = args.n
+    px, py = (int(v) for v in args.split.lower().split("x"))
+    prec = FP64 if args.precision == "fp64" else FP32
+    log(f"[bench] generating orszag_tang {n}x{n}, split {px}x{py}")
+    prob = W.orszag_tang(n)
+    dec = DecomposedSolver(prob, even_cuts(n, px), even_cuts(n, py), precision=prec)
+    one = Solver.from_problem(prob, precision=prec)
+    del prob
+    subs = [s for row in dec.subs for s in row]
+    stream = one.stream
+    log(f"[bench] warmup {args.warmup} steps")
+    dec.advance(args.warmup)
+    one.advance(args.warmup)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    for s in subs:
+        s.profile_enable(True)
+    log(f"[bench] timing {args.steps} decomposed steps")
+    ms_dec = timed(lambda: dec.advance(args.steps))
+    profs = [s.profile_read() for s in subs]
+    for s in subs:
+        s.profile_enable(False)
+    log(f"[bench] timing {args.steps} undivided steps")
+    ms_one = timed(lambda: one.advance(args.steps, sync=False))
+    diags = [s.diagnostics() for s in subs] + [one.diagnostics()]
+    if any(d["nonphys"] or d["steps"] != args.warmup + args.steps for d in diags):
+        log(f"[bench] run failed: {diags}")
+        sys.exit(1)
+    same = bool(torch.equal(dec.read_fields(torch.float64), one.read_fields(torch.float64)))
+    cells = n * n
+    value = cells * args.steps / (ms_dec / 1e3) / 1e6
+    stage_ms = sum(sum(p["ms_stage"]) for p in profs)
+    halo_ms = sum(p["ms_halo"] for p in profs)
+    log(f"[bench] decomposed {ms_dec / args.steps:.3f} ms/step, undivided {ms_one / args.steps:.3f}; "
+        f"stage kernels {stage_ms / args.steps:.3f}, halo fills and exchange {halo_ms / args.steps:.3f} ms/step; "
+        f"bit-identical: {same}")
+    out = base_record(args, value, ms_dec / args.steps, "f64" if prec == FP64 else "f32", {
+        "workload": f"orszag_tang_{n}x{n}_{args.precision}_hd_decomposed_{px}x{py}",
+        "nx": n, "ny": n, "precision": args.precision, "hyper_diffusion": True, "cfl": 0.3,
+        "subdomains": [px, py],
+        "halo": "3-cell; every side exchanged with a neighbour subdomain (periodic images included) "
+                "through device pack/unpack buffers before every stage",
+    })
+    out["undivided"] = {"value": round(cells * args.steps / (ms_one / 1e3) / 1e6, 3),
+                        "ms_per_step": round(ms_one / args.steps, 4)}
+    out["overhead_vs_undivided"] = round(ms_dec / ms_one - 1.0, 4)
+    out["phases_ms"] = {"stage": round(stage_ms, 3), "halo": round(halo_ms, 3),
+                        "tau": round(math.log(stage_ms / halo_ms), 3) if halo_ms > 0 else None}
+    out["bit_identical_to_undivided"] = same
+    print(json.dumps(out), flush=True)
+
+
 def run_batch(args):
     import torch
     import workloads as W
@@ -408,7 +480,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 100, surrogate 500)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["single", "batch", "surrogate", "copy"], default="single")
+    ap.add_argument("--mode", choices=["single", "batch", "surrogate", "decomposed", "copy"], default="single")
+    ap.add_argument("--split", default="2x2", help="decomposed mode: subdomains along x and y, e.g. 2x2")
     ap.add_argument("--n", type=int, default=None, help="grid side (default 8000, surrogate 2048)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--problem", choices=["orszag_tang", "stratified"], default="orszag_tang",
@@ -435,7 +508,8 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
-    {"single": run_single, "batch": run_batch, "surrogate": run_surrogate, "copy": run_copy}[args.mode](args)
+    {"single": run_single, "batch": run_batch, "surrogate": run_surrogate, "decomposed": run_decomposed,
+     "copy": run_copy}[args.mode](args)
 
 
 if __name__ == "__main__":

@@ -204,7 +204,9 @@ int sacx_halo_unpack(sacx_ctx *ctx, int32_t side, const void *d_buf);
  *   4. the same for the y EXCHANGE sides (their strips carry the x halos:
  *      the corners);
  *   5. sacx_stage(ctx, c, ...) on every subdomain, with c at stage 1 the
- *      maxima over all subdomains of sacx_wave_speeds.
+ *      maxima over all subdomains: on the host from sacx_wave_speeds, or
+ *      on the device by sacx_wave_speeds_max into one zeroed array (the
+ *      stand-in of an all-reduce(max); no synchronisation).
  * Each subdomain then evolves bit for bit as its part of the undivided
  * domain run with sacx_advance.  No end time; a non-physical step-start
  * state (sacx_diagnostics) stops that subdomain's steps, not the others'.
@@ -216,15 +218,25 @@ int sacx_halo_unpack(sacx_ctx *ctx, int32_t side, const void *d_buf);
  * sacx_stage: run the next stage of the step (1, 2, 3, 4, 1, ...) on the
  * state whose ghost cells the caller completed.  At stage 1 the step begins:
  * c_max = the x and y wave-speed maxima of the whole domain's current state
- * (each >= 0 and finite, > 0 along a direction with more than one cell,
- * EINVAL otherwise; NULL = this context's own); ignored at later stages.
+ * (each >= 0 and finite, > 0 along a direction with more than one cell;
+ * NULL = this context's own); ignored at later stages.  c_max_on_device = 0:
+ * c_max is host memory, read during the call, EINVAL for bad values; 1: it
+ * is 2 device doubles (8-byte aligned), read on the stream when the step
+ * begins, and a bad value stops this subdomain's stepping as a non-physical
+ * state does (sacx_diagnostics reports it).
  * Stage 4 ends the step (t, step count, wave speeds of the new state).
  * stage_done (optional) receives the stage that was enqueued.  ESTATE with a
  * learned coefficient set.  Enqueued, not synchronised.
  *
  * sacx_wave_speeds: synchronise and return the x and y maxima of |v_d| + c_f
  * over this context's interior cells of the current state (the step-start
- * state while a step is in progress). */
+ * state while a step is in progress).
+ *
+ * sacx_wave_speeds_max: enqueue d_c_max[d] = max(d_c_max[d], this context's
+ * maxima) on a device array of 2 doubles (8-byte aligned) that holds
+ * non-negative values, e.g. zeros written before the first context of the
+ * step.  ESTATE during a step.  Contexts on different streams must order
+ * these updates before every stage 1 that reads the array. */
 int sacx_fill_boundaries(sacx_ctx *ctx, int32_t direction);
 /* sacx_set_spacing: set the cell spacing (dx, dy; finite, > 0) from which
  * the scheme's grid constants follow, in place of (x1 - x0) / nx and
@@ -233,8 +245,9 @@ int sacx_fill_boundaries(sacx_ctx *ctx, int32_t direction);
  * differently.  EINVAL for bad values, ESTATE during a step begun with
  * sacx_stage.  Host only; takes effect at the next step. */
 int sacx_set_spacing(sacx_ctx *ctx, double dx, double dy);
-int sacx_stage(sacx_ctx *ctx, const double c_max[2], int32_t *stage_done);
+int sacx_stage(sacx_ctx *ctx, const double *c_max, int32_t c_max_on_device, int32_t *stage_done);
 int sacx_wave_speeds(sacx_ctx *ctx, double c_max[2]);
+int sacx_wave_speeds_max(sacx_ctx *ctx, double *d_c_max);
 
 /* Launch shape of the fused stage kernel: `threads` columns per block
  * including the 6-column apron (64, 128 or 256; the one-thread tile runs
@@ -263,7 +276,9 @@ int sacx_set_column_split(sacx_ctx *ctx, int32_t on);
  * group), used to split a run into useful computation and halo exchange as in
  * the paper's cost model T = T_comp + T_comm + T_idle (section 6).
  *  ms_stage[s] / n_stage[s]: the fused stage-s kernel (s = 0..3 for stages 1..4);
- *  ms_halo / n_halo: halo pack + unpack (or boundary fill) before each stage;
+ *  ms_halo / n_halo: halo pack + unpack (or boundary fill) before each stage,
+ *                    and each sacx_fill_boundaries, sacx_halo_pack and
+ *                    sacx_halo_unpack call;
  *  ms_scalar / n_scalar: the one-thread time-step kernels;
  *  ms_surrogate / n_surrogate: surrogate refreshes (prediction and check).
  * sacx_profile_enable(ctx, 1) resets the accumulators and starts recording;

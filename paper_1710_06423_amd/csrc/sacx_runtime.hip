@@ -411,11 +411,28 @@ __global__ void k_step_begin(DevScalars *sc, double t_end, StepConsts k) { step_
 __global__ void k_step_end(DevScalars *sc) { step_end_dev(sc); }
 
 // step start of decomposed stepping: the maxima over every subdomain replace
-// this subdomain's own, so that all subdomains take one dt and one c_max
-__global__ void k_step_begin_global(DevScalars *sc, double cx, double cy, StepConsts k) {
+// this subdomain's own, so that all subdomains take one dt and one c_max.
+// From a device array (dc != nullptr) the values are checked here: one that
+// is not finite, negative, or zero along a direction with more than one cell
+// stops stepping like a non-physical state.
+__global__ void k_step_begin_global(DevScalars *sc, double cx, double cy, const double *dc, StepConsts k) {
+    if (dc) {
+        cx = dc[0];
+        cy = dc[1];
+        const bool ok = isfinite(cx) && isfinite(cy) && cx >= 0.0 && cy >= 0.0 && (!k.ax || cx > 0.0) &&
+                        (!k.ay || cy > 0.0);
+        if (!ok) sc->nonphys = 1;
+    }
     sc->cacc[sc->cur][0] = (unsigned long long)__double_as_longlong(cx);
     sc->cacc[sc->cur][1] = (unsigned long long)__double_as_longlong(cy);
     step_begin_dev(sc, 0.0, k);
+}
+
+// the device stand-in of an all-reduce(max) over subdomains: this context's
+// maxima of the current state into a caller array (non-negative doubles
+// order as their bit patterns)
+__global__ void k_speeds_max(const DevScalars *sc, unsigned long long *dc) {
+    if (threadIdx.x < 2) atomicMax(&dc[threadIdx.x], sc->cacc[sc->cur][threadIdx.x]);
 }
 
 // conservation sums: per-block partial sums of rows, then a fixed-order final sum
@@ -1126,6 +1143,7 @@ static int halo_io(sacx_ctx *ctx, int32_t side, void *buf, bool pack) {
         return fail(SACX_EUNSUP, "halo exchange needs at least %d cells across", G);
     DeviceGuard dg(ctx->device);
     if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    ProfScope ps(ctx, 4);
     const int T = 256;
     const int s = side & 1;
     const bool f64 = ctx->grid.precision == SACX_FP64;
@@ -1174,11 +1192,15 @@ int sacx_fill_boundaries(sacx_ctx *ctx, int32_t direction) {
     return SACX_OK;
 }
 
-int sacx_stage(sacx_ctx *ctx, const double c_max[2], int32_t *stage_done) {
+int sacx_stage(sacx_ctx *ctx, const double *c_max, int32_t c_max_on_device, int32_t *stage_done) {
     if (!ctx) return fail(SACX_EINVAL, "ctx must not be NULL");
+    if (c_max_on_device != 0 && c_max_on_device != 1) return fail(SACX_EINVAL, "c_max_on_device must be 0 or 1");
+    if (c_max_on_device && !c_max) return fail(SACX_EINVAL, "a device c_max must not be NULL");
+    if (c_max_on_device && ((uintptr_t)c_max % alignof(double)))
+        return fail(SACX_EINVAL, "a device c_max must be 8-byte aligned");
     if (!ctx->initialized) return fail(SACX_ESTATE, "sacx_init_state has not been called");
     if (ctx->sur_on) return fail(SACX_ESTATE, "a context with a learned coefficient steps with sacx_advance");
-    if (ctx->stage_next == 0 && c_max) {
+    if (ctx->stage_next == 0 && c_max && !c_max_on_device) {
         for (int d = 0; d < 2; ++d)
             if (!std::isfinite(c_max[d]) || c_max[d] < 0.0) return fail(SACX_EINVAL, "c_max[%d] must be finite and >= 0", d);
         if ((ctx->grid.nx > 1 && !(c_max[0] > 0.0)) || (ctx->grid.ny > 1 && !(c_max[1] > 0.0)))
@@ -1189,9 +1211,12 @@ int sacx_stage(sacx_ctx *ctx, const double c_max[2], int32_t *stage_done) {
     const int s = ctx->stage_next + 1;
     if (s == 1) {
         ProfScope ps(ctx, 5);
-        if (c_max)
-            hipLaunchKernelGGL(k_step_begin_global, dim3(1), dim3(1), 0, ctx->stream, ctx->sc, c_max[0], c_max[1],
+        if (c_max_on_device)
+            hipLaunchKernelGGL(k_step_begin_global, dim3(1), dim3(1), 0, ctx->stream, ctx->sc, 0.0, 0.0, c_max,
                                step_consts(ctx));
+        else if (c_max)
+            hipLaunchKernelGGL(k_step_begin_global, dim3(1), dim3(1), 0, ctx->stream, ctx->sc, c_max[0], c_max[1],
+                               (const double *)nullptr, step_consts(ctx));
         else
             hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(1), 0, ctx->stream, ctx->sc, 0.0, step_consts(ctx));
         HIPCHK(hipGetLastError());
@@ -1229,6 +1254,19 @@ int sacx_set_spacing(sacx_ctx *ctx, double dx, double dy) {
     if (ctx->stage_next) return fail(SACX_ESTATE, "a step begun with sacx_stage is in progress");
     set_spacing(ctx, dx, dy);
     ctx->gen += 1;
+    return SACX_OK;
+}
+
+int sacx_wave_speeds_max(sacx_ctx *ctx, double *d_c_max) {
+    if (!ctx || !d_c_max) return fail(SACX_EINVAL, "ctx/d_c_max must not be NULL");
+    if ((uintptr_t)d_c_max % alignof(double)) return fail(SACX_EINVAL, "d_c_max must be 8-byte aligned");
+    if (!ctx->initialized) return fail(SACX_ESTATE, "sacx_init_state has not been called");
+    if (ctx->stage_next) return fail(SACX_ESTATE, "a step begun with sacx_stage is in progress");
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    hipLaunchKernelGGL(k_speeds_max, dim3(1), dim3(64), 0, ctx->stream, (const DevScalars *)ctx->sc,
+                       (unsigned long long *)d_c_max);
+    HIPCHK(hipGetLastError());
     return SACX_OK;
 }
 

@@ -3,11 +3,12 @@ Fig. 1: the initial configuration divided into sub-regions, each advanced by
 its own process with 'halo' layers exchanged through buffers before every
 stage, and one time step for the whole domain).
 
-Here every subdomain lives on the same GPU and the exchange is a device
-buffer that one context packs and its neighbour unpacks; on several GPUs the
-same buffers would travel between devices.  Each step takes the wave-speed
-maxima over all subdomains (the step's only global reduction), then runs the
-four stages, each after the x and then the y halo exchange.  The subdomains
+Here every subdomain lives on the same GPU and stream, and the exchange is a
+device buffer that one context packs and its neighbour unpacks; on several
+GPUs the same buffers would travel between devices.  Each step takes the
+wave-speed maxima over all subdomains (the step's only global reduction, a
+device max here, an all-reduce(max) on several GPUs), then runs the four
+stages, each after the x and then the y halo exchange.  The subdomains
 evolve bit for bit as their parts of the undivided domain.
 """
 
@@ -53,6 +54,8 @@ class DecomposedSolver:
                 s.init_state(f, None, t0=prob.t0)
                 row.append(s)
             self.subs.append(row)
+        # the whole domain's wave-speed maxima, reduced on the device
+        self.cmax = torch.zeros(2, dtype=torch.float64, device=self.subs[0][0].device)
         # buffers[b][a][side]: what subdomain (a, b) packs at `side`
         self.buffers = [[{side: s.halo_buffer(side) for side in range(4) if self._sides(a, b)[side] == EXCHANGE}
                          for a, s in enumerate(row)] for b, row in enumerate(self.subs)]
@@ -105,9 +108,19 @@ class DecomposedSolver:
                 cx, cy = max(cx, x), max(cy, y)
         return cx, cy
 
-    def advance(self, nsteps: int):
+    def advance(self, nsteps: int, device_max: bool = True):
+        """nsteps RK4 steps of the whole domain.  device_max: the maxima over
+        the subdomains are reduced on the device (no synchronisation), else
+        read back and reduced on the host."""
         for _ in range(nsteps):
-            c = self.wave_speeds()
+            if device_max:
+                self.cmax.zero_()
+                for row in self.subs:
+                    for s in row:
+                        s.wave_speeds_max(self.cmax)
+                c = self.cmax
+            else:
+                c = self.wave_speeds()
             for _stage in range(4):
                 for row in self.subs:
                     for s in row:

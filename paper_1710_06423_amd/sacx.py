@@ -33,7 +33,7 @@ EXPORTED = (
     "sacx_abi_version", "sacx_strerror", "sacx_last_error", "sacx_workspace_size", "sacx_create",
     "sacx_destroy", "sacx_set_boundaries", "sacx_init_state", "sacx_advance", "sacx_read_fields",
     "sacx_diagnostics", "sacx_halo_buffer_size", "sacx_halo_pack", "sacx_halo_unpack",
-    "sacx_fill_boundaries", "sacx_stage", "sacx_wave_speeds", "sacx_set_spacing",
+    "sacx_fill_boundaries", "sacx_stage", "sacx_wave_speeds", "sacx_wave_speeds_max", "sacx_set_spacing",
     "sacx_profile_enable", "sacx_profile_read", "sacx_set_launch", "sacx_get_launch", "sacx_set_column_split",
     "sacx_batch_workspace_size", "sacx_batch_create", "sacx_batch_destroy", "sacx_batch_context",
     "sacx_batch_set_tiles", "sacx_batch_advance",
@@ -125,7 +125,8 @@ def load_library():
     lib.sacx_halo_pack.argtypes = [P, ctypes.c_int32, P]
     lib.sacx_halo_unpack.argtypes = [P, ctypes.c_int32, P]
     lib.sacx_fill_boundaries.argtypes = [P, ctypes.c_int32]
-    lib.sacx_stage.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]
+    lib.sacx_stage.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    lib.sacx_wave_speeds_max.argtypes = [P, P]
     lib.sacx_wave_speeds.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     lib.sacx_set_spacing.argtypes = [P, ctypes.c_double, ctypes.c_double]
     lib.sacx_profile_enable.argtypes = [P, ctypes.c_int32]
@@ -328,14 +329,31 @@ class Solver:
         with torch.cuda.device(self.device):
             _check(self.lib.sacx_fill_boundaries(self.ctx, int(direction)), "sacx_fill_boundaries")
 
-    def stage(self, c_max: Optional[Sequence[float]] = None) -> int:
+    def stage(self, c_max=None) -> int:
         """Enqueue the next RK4 stage; c_max (x, y) is the whole domain's
-        wave-speed maxima, used when the stage begins a step."""
-        c = None if c_max is None else (ctypes.c_double * 2)(*[float(v) for v in c_max])
+        wave-speed maxima, used when the stage begins a step: a pair of
+        floats, or a float64 device tensor of 2 elements read on the stream."""
         done = ctypes.c_int32(0)
+        if isinstance(c_max, torch.Tensor):
+            if c_max.dtype != torch.float64 or c_max.numel() != 2 or c_max.device != self.device:
+                raise ValueError(f"c_max must be 2 float64 values on {self.device}")
+            c, on_dev = ctypes.c_void_p(c_max.data_ptr()), 1
+        elif c_max is None:
+            c, on_dev = None, 0
+        else:
+            arr = (ctypes.c_double * 2)(*[float(v) for v in c_max])
+            c, on_dev = ctypes.cast(arr, ctypes.c_void_p), 0
         with torch.cuda.device(self.device):
-            _check(self.lib.sacx_stage(self.ctx, c, ctypes.byref(done)), "sacx_stage")
+            _check(self.lib.sacx_stage(self.ctx, c, on_dev, ctypes.byref(done)), "sacx_stage")
         return done.value
+
+    def wave_speeds_max(self, c_max: torch.Tensor):
+        """Enqueue c_max = max(c_max, this context's maxima) on a float64
+        device tensor of 2 elements."""
+        if c_max.dtype != torch.float64 or c_max.numel() != 2 or c_max.device != self.device:
+            raise ValueError(f"c_max must be 2 float64 values on {self.device}")
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_wave_speeds_max(self.ctx, ctypes.c_void_p(c_max.data_ptr())), "sacx_wave_speeds_max")
 
     def set_spacing(self, dx: float, dy: float):
         """Grid spacing in place of the extent over the cell count (a

@@ -165,6 +165,7 @@ def test_stage_calls_reject_null_context(sx):
     lib = sx.load_library()
     c = (ctypes.c_double * 2)(1.0, 1.0)
     assert lib.sacx_fill_boundaries(None, 0) == sx.EINVAL
-    assert lib.sacx_stage(None, c, None) == sx.EINVAL
+    assert lib.sacx_stage(None, c, 0, None) == sx.EINVAL
     assert lib.sacx_wave_speeds(None, c) == sx.EINVAL
+    assert lib.sacx_wave_speeds_max(None, c) == sx.EINVAL
     assert lib.sacx_set_spacing(None, 0.1, 0.1) == sx.EINVAL

@@ -35,20 +35,20 @@ def _whole(prob, nsteps, **kw):
     return f, d
 
 
-def _decomposed(prob, xcuts, ycuts, nsteps, **kw):
+def _decomposed(prob, xcuts, ycuts, nsteps, device_max=True, **kw):
     from paper_1710_06423_amd import DecomposedSolver
     dec = DecomposedSolver(prob, xcuts, ycuts, **kw)
-    dec.advance(nsteps)
+    dec.advance(nsteps, device_max=device_max)
     f = dec.read_fields()
     d = dec.diagnostics()
     dec.close()
     return f, d
 
 
-def _check(torch, prob, xcuts, ycuts, nsteps, label, **kw):
-    print(f"case: {label} cuts x {xcuts} y {ycuts} steps {nsteps} {kw}", flush=True)
+def _check(torch, prob, xcuts, ycuts, nsteps, label, device_max=True, **kw):
+    print(f"case: {label} cuts x {xcuts} y {ycuts} steps {nsteps} device_max={device_max} {kw}", flush=True)
     ref, dref = _whole(prob, nsteps, **kw)
-    got, dgot = _decomposed(prob, xcuts, ycuts, nsteps, **kw)
+    got, dgot = _decomposed(prob, xcuts, ycuts, nsteps, device_max=device_max, **kw)
     nd = int((got != ref).sum())
     print(f"[decomposed] {label}: {nd} elements differ", flush=True)
     assert nd == 0, label
@@ -69,11 +69,13 @@ def test_periodic_orszag_tang(xcuts, ycuts):
     _check(torch, W.orszag_tang(128, ny=96), xcuts, ycuts, 12, "OT periodic")
 
 
-def test_periodic_matches_oracle(oracle_lib):
-    """The decomposed run against the oracle directly."""
+@pytest.mark.parametrize("device_max", [True, False])
+def test_periodic_matches_oracle(oracle_lib, device_max):
+    """The decomposed run against the oracle directly, with the maxima over
+    the subdomains reduced on the device or on the host."""
     torch = _torch()
     prob = W.orszag_tang(96, ny=80)
-    got = _check(torch, prob, [0, 33, 96], [0, 47, 80], 15, "OT vs oracle").cpu().numpy()
+    got = _check(torch, prob, [0, 33, 96], [0, 47, 80], 15, "OT vs oracle", device_max=device_max).cpu().numpy()
     ora = oracle_lib.State(prob)
     ora.run(15)
     assert np.array_equal(got, ora.stacked())
@@ -162,6 +164,22 @@ def test_stage_calls_reject_misuse():
         assert s.stage((123.0, 456.0)) == st   # c_max is only read at stage 1
     s.advance(1)
     assert s.diagnostics()["steps"] == 2
+    lib = s.lib
+    c = torch.zeros(2, dtype=torch.float64, device=s.device)
+    assert lib.sacx_stage(s.ctx, None, 1, None) == sacx.EINVAL          # a device c_max must be given
+    assert lib.sacx_stage(s.ctx, c.data_ptr() + 4, 1, None) == sacx.EINVAL   # misaligned
+    assert lib.sacx_stage(s.ctx, c.data_ptr(), 2, None) == sacx.EINVAL
+    # the device max equals the host read-back
+    s.wave_speeds_max(c)
+    assert tuple(c.cpu().tolist()) == s.wave_speeds()
+    # a bad device value stops this subdomain's stepping, reported as non-physical
+    c.fill_(float("nan"))
+    for _ in range(4):
+        s.fill_boundaries(0)
+        s.fill_boundaries(1)
+        s.stage(c)
+    d = s.diagnostics()
+    assert d["nonphys"] and d["steps"] == 2
     s.close()
     # a background cannot have exchange sides; a small direction neither
     bg = Solver.from_problem(W.stratified_atmosphere(16, 20))
