@@ -26,7 +26,8 @@ Other modes (one JSON line each):
                     beside the undivided run (the cost of the exchange path;
                     the results are compared bit for bit);
   --mode copy       a device copy of known size (calibrates the HBM byte
-                    counters of a profiler run).
+                    counters of a profiler run), and the streaming rate of a
+                    plain elementwise kernel (b = a + 3c, 3 x 4 GiB).
 """
 
 from __future__ import annotations
@@ -470,8 +471,24 @@ def run_copy(args):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / 5
     gbs = 2 * nbytes / (ms / 1e3) / 1e9
+    del src, dst
+    # the streaming rate a plain elementwise kernel attains: b = a + 3 c over
+    # three 4 GiB float64 arrays (2 reads, 1 write per element), best of 5
+    n = 1 << 29
+    a = torch.zeros(n, dtype=torch.float64, device="cuda")
+    c = torch.zeros_like(a)
+    b = torch.empty_like(a)
+    best = float("inf")
+    for _ in range(6):
+        e0.record()
+        torch.add(a, c, alpha=3.0, out=b)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    tgbs = 3 * 8 * n / (best / 1e3) / 1e9
     print(json.dumps({"mode": "copy", "copy_bytes": nbytes, "dispatches": 5, "ms_per_copy": round(ms, 4),
-                      "read_plus_write_gb_s": round(gbs, 1), "fraction_of_8tb_s": round(gbs / HBM_PEAK_GBS, 4)}),
+                      "read_plus_write_gb_s": round(gbs, 1), "fraction_of_8tb_s": round(gbs / HBM_PEAK_GBS, 4),
+                      "triad_gb_s": round(tgbs, 1), "triad_fraction_of_8tb_s": round(tgbs / HBM_PEAK_GBS, 4)}),
           flush=True)
 
 
