@@ -152,6 +152,27 @@ int sacx_set_boundaries(sacx_ctx *ctx, const int32_t bc[4]);
 int sacx_init_state(sacx_ctx *ctx, const void *const *d_fields, const void *const *d_bg,
                     int64_t pitch, int32_t in_precision, double t0);
 
+/* The paper's verification problems (section 5), generated on the device
+ * in place of sacx_init_state, evaluated at the cell centres of the
+ * context's grid (x_i = x0 + (i + 1/2) dx), gamma from the parameters:
+ *  SACX_PROBLEM_ORSZAG_TANG: rho = 25/(36 pi), p = 5/(12 pi),
+ *    v = (-sin y, sin x), B = B0 (-sin y, sin 2x), B0 = prm[0]/sqrt(4 pi)
+ *    (nprm 0 or 1, default prm[0] = 1); all boundaries PERIODIC.  The
+ *    standard vortex is the grid [0, 2 pi]^2 with gamma = 5/3.
+ *  SACX_PROBLEM_BRIO_WU: the shock tube, left of the middle of the domain
+ *    rho = p = s_l, B = (0.75, 1), right rho = 0.125 s_r, p = 0.1 s_r,
+ *    B = (0.75, -1), v = 0 (prm = {s_l, s_r}, nprm 0 to 2, default 1, each
+ *    > 0).  Along y (field components swapped) when nx = 1 < ny, else along
+ *    x; OPEN ends, PERIODIC across.  The standard tube is [0, 1], gamma = 2.
+ * Sets those boundaries (as sacx_set_boundaries, with its errors), then
+ * continues as sacx_init_state (time t0, step count reset).  EINVAL for an
+ * unknown kind or bad parameters, EUNSUP with a background.  The sines come
+ * from the device's sin: a cell may differ from a host evaluation in the
+ * last bit.  Enqueued on the stream. */
+#define SACX_PROBLEM_ORSZAG_TANG 0
+#define SACX_PROBLEM_BRIO_WU 1
+int sacx_init_problem(sacx_ctx *ctx, int32_t kind, const double *prm, int32_t nprm, double t0);
+
 /* Enqueue up to nsteps RK4 steps (paper section 2; one step = 4 stages,
  * each preceded by a halo exchange).  ESTATE for a context with an EXCHANGE
  * side or while a step begun with sacx_stage is in progress.  t_end <= 0: no end time.  Otherwise

@@ -336,6 +336,46 @@ __global__ void k_import(FPtr<real> D, CPtr<T> src, int nf, Layout L, int64_t pi
     for (int f = 0; f < nf; ++f) D.p[f][eidx(L, i, j)] = (real)src.p[f][(int64_t)j * pitch + i];
 }
 
+// the verification problems evaluated at the cell centres x0 + (i + 1/2) hx,
+// y0 + (j + 1/2) hy (the operations in the order the conserved variables are
+// defined: e = p/(gamma-1) + rho |v|^2/2 + |B|^2/2)
+template <typename real>
+__global__ void k_init_problem(FPtr<real> D, Layout L, int kind, double x0, double hx, double y0, double hy,
+                               double mid, int along_y, double gamma, double p0, double p1) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    if (i >= L.nx) return;
+    const double x = x0 + ((double)i + 0.5) * hx, y = y0 + ((double)j + 0.5) * hy;
+    double rho, vx, vy, p, bx, by;
+    if (kind == SACX_PROBLEM_ORSZAG_TANG) {
+        const double pi = 3.141592653589793;   // the double nearest pi
+        const double b0 = p0 / sqrt(4.0 * pi);
+        rho = 25.0 / (36.0 * pi);
+        p = 5.0 / (12.0 * pi);
+        vx = -sin(y);
+        vy = sin(x);
+        bx = -b0 * sin(y);
+        by = b0 * sin(2.0 * x);
+    } else {
+        const bool left = (along_y ? y : x) < mid;
+        rho = left ? 1.0 * p0 : 0.125 * p1;
+        p = left ? 1.0 * p0 : 0.1 * p1;
+        vx = 0.0;
+        vy = 0.0;
+        const double bn = 0.75, bt = left ? 1.0 : -1.0;
+        bx = along_y ? bt : bn;
+        by = along_y ? bn : bt;
+    }
+    const double e = p / (gamma - 1.0) + 0.5 * rho * (vx * vx + vy * vy) + 0.5 * (bx * bx + by * by);
+    const int64_t o = eidx(L, i, j);
+    D.p[0][o] = (real)rho;
+    D.p[1][o] = (real)(rho * vx);
+    D.p[2][o] = (real)(rho * vy);
+    D.p[3][o] = (real)e;
+    D.p[4][o] = (real)bx;
+    D.p[5][o] = (real)by;
+}
+
 template <typename real, typename T>
 __global__ void k_export(FPtr<real> Sx, MPtr<T> dst, uint32_t mask, Layout L, int64_t pitch) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -938,6 +978,21 @@ int sacx_set_boundaries(sacx_ctx *ctx, const int32_t bc[4]) {
     return SACX_OK;
 }
 
+// after the evolved fields (and background) are in place: scalars, halos
+// and the first wave-speed reduction
+static int finish_init(sacx_ctx *ctx, double t0) {
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, ctx->stream, ctx->sc, t0);
+    int rc = fill_halo(ctx, ctx->U, NF, false);
+    if (rc) return rc;
+    rc = wavespeed_into(ctx, 0);
+    if (rc) return rc;
+    HIPCHK(hipGetLastError());
+    ctx->stage_next = 0;
+    ctx->initialized = true;
+    return SACX_OK;
+}
+
 int sacx_init_state(sacx_ctx *ctx, const void *const *d_fields, const void *const *d_bg, int64_t pitch,
                     int32_t in_precision, double t0) {
     if (!ctx || !d_fields) return fail(SACX_EINVAL, "ctx/fields must not be NULL");
@@ -984,16 +1039,43 @@ int sacx_init_state(sacx_ctx *ctx, const void *const *d_fields, const void *cons
         int rc = fill_halo(ctx, ctx->BG, NBG, false);
         if (rc) return rc;
     }
-    HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_reset_scalars, dim3(1), dim3(1), 0, ctx->stream, ctx->sc, t0);
-    int rc = fill_halo(ctx, ctx->U, NF, false);
+    return finish_init(ctx, t0);
+}
+
+int sacx_init_problem(sacx_ctx *ctx, int32_t kind, const double *prm, int32_t nprm, double t0) {
+    if (!ctx) return fail(SACX_EINVAL, "ctx must not be NULL");
+    if (kind != SACX_PROBLEM_ORSZAG_TANG && kind != SACX_PROBLEM_BRIO_WU) return fail(SACX_EINVAL, "unknown problem %d", kind);
+    const int maxp = kind == SACX_PROBLEM_ORSZAG_TANG ? 1 : 2;
+    if (nprm < 0 || nprm > maxp) return fail(SACX_EINVAL, "problem %d takes at most %d parameters", kind, maxp);
+    if (nprm > 0 && !prm) return fail(SACX_EINVAL, "prm must not be NULL when nprm > 0");
+    if (!std::isfinite(t0)) return fail(SACX_EINVAL, "t0 must be finite");
+    if (ctx->grid.background_on) return fail(SACX_EUNSUP, "the problem generators set no background");
+    const double p0 = nprm >= 1 ? prm[0] : 1.0, p1 = nprm >= 2 ? prm[1] : 1.0;
+    if (!std::isfinite(p0) || !std::isfinite(p1)) return fail(SACX_EINVAL, "parameters must be finite");
+    if (kind == SACX_PROBLEM_BRIO_WU && (!(p0 > 0.0) || !(p1 > 0.0)))
+        return fail(SACX_EINVAL, "the shock tube's scale factors must be > 0");
+    const sacx_grid &g = ctx->grid;
+    const int along_y = kind == SACX_PROBLEM_BRIO_WU && g.nx == 1 && g.ny > 1;
+    int32_t bc[4] = {SACX_PERIODIC, SACX_PERIODIC, SACX_PERIODIC, SACX_PERIODIC};
+    if (kind == SACX_PROBLEM_BRIO_WU) {
+        if (along_y) bc[2] = bc[3] = SACX_OPEN;
+        else bc[0] = bc[1] = SACX_OPEN;
+    }
+    int rc = sacx_set_boundaries(ctx, bc);
     if (rc) return rc;
-    rc = wavespeed_into(ctx, 0);
-    if (rc) return rc;
-    HIPCHK(hipGetLastError());
-    ctx->stage_next = 0;
-    ctx->initialized = true;
-    return SACX_OK;
+    DeviceGuard dg(ctx->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the context device");
+    const double hx = (g.x1 - g.x0) / g.nx, hy = (g.y1 - g.y0) / g.ny;
+    const double mid = along_y ? (g.y0 + g.y1) * 0.5 : (g.x0 + g.x1) * 0.5;
+    const Layout &L = ctx->L;
+    dim3 grd((L.nx + 255) / 256, L.ny);
+    if (g.precision == SACX_FP64)
+        hipLaunchKernelGGL(k_init_problem<double>, grd, dim3(256), 0, ctx->stream, fptr<double>(ctx->U, NF), L, kind,
+                           g.x0, hx, g.y0, hy, mid, along_y, ctx->params.gamma, p0, p1);
+    else
+        hipLaunchKernelGGL(k_init_problem<float>, grd, dim3(256), 0, ctx->stream, fptr<float>(ctx->U, NF), L, kind,
+                           g.x0, hx, g.y0, hy, mid, along_y, ctx->params.gamma, p0, p1);
+    return finish_init(ctx, t0);
 }
 
 int sacx_advance(sacx_ctx *ctx, int32_t nsteps, double t_end, int32_t *steps_done, double *t_now) {

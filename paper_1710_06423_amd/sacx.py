@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libsacx.so")
 
 OK, EINVAL, ENOSPC, EDEVICE, ENONPHYS, EUNSUP, ESTATE = 0, -1, -2, -3, -4, -5, -6
 PERIODIC, OPEN, EXCHANGE = 0, 1, 2
+PROBLEM_ORSZAG_TANG, PROBLEM_BRIO_WU = 0, 1
 FP64, FP32 = 0, 1
 GHOST = 3
 FIELDS = ("rho", "mx", "my", "e", "bx", "by")
@@ -31,7 +32,7 @@ DEFAULT_CSHK = (0.5, 0.5, 0.5, 0.5)
 
 EXPORTED = (
     "sacx_abi_version", "sacx_strerror", "sacx_last_error", "sacx_workspace_size", "sacx_create",
-    "sacx_destroy", "sacx_set_boundaries", "sacx_init_state", "sacx_advance", "sacx_read_fields",
+    "sacx_destroy", "sacx_set_boundaries", "sacx_init_state", "sacx_init_problem", "sacx_advance", "sacx_read_fields",
     "sacx_diagnostics", "sacx_halo_buffer_size", "sacx_halo_pack", "sacx_halo_unpack",
     "sacx_fill_boundaries", "sacx_stage", "sacx_wave_speeds", "sacx_wave_speeds_max", "sacx_set_spacing",
     "sacx_profile_enable", "sacx_profile_read", "sacx_set_launch", "sacx_get_launch", "sacx_set_column_split",
@@ -117,6 +118,8 @@ def load_library():
     lib.sacx_set_boundaries.argtypes = [P, ctypes.POINTER(ctypes.c_int32)]
     lib.sacx_init_state.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.c_int64, ctypes.c_int32,
                                     ctypes.c_double]
+    lib.sacx_init_problem.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32,
+                                      ctypes.c_double]
     lib.sacx_advance.argtypes = [P, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(ctypes.c_int32),
                                  ctypes.POINTER(ctypes.c_double)]
     lib.sacx_read_fields.argtypes = [P, ctypes.POINTER(P), ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32]
@@ -270,6 +273,14 @@ class Solver:
         with torch.cuda.device(self.device):
             _check(self.lib.sacx_init_state(self.ctx, _ptrs([fields[k] for k in range(6)]), bgp,
                                             fields.shape[2], prec, float(t0)), "sacx_init_state")
+
+    def init_problem(self, kind: int, prm: Sequence[float] = (), t0: float = 0.0):
+        """Generate a verification problem on the device (sacx_init_problem):
+        PROBLEM_ORSZAG_TANG (prm: B0 scale) or PROBLEM_BRIO_WU (prm: left and
+        right scale); sets that problem's boundaries."""
+        arr = (ctypes.c_double * max(len(prm), 1))(*[float(v) for v in prm])
+        with torch.cuda.device(self.device):
+            _check(self.lib.sacx_init_problem(self.ctx, int(kind), arr, len(prm), float(t0)), "sacx_init_problem")
 
     def advance(self, nsteps: int, t_end: float = 0.0, sync: bool = True):
         """Enqueue nsteps; with sync, return (steps_done, t) and raise on a non-physical stop."""

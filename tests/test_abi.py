@@ -169,3 +169,4 @@ def test_stage_calls_reject_null_context(sx):
     assert lib.sacx_wave_speeds(None, c) == sx.EINVAL
     assert lib.sacx_wave_speeds_max(None, c) == sx.EINVAL
     assert lib.sacx_set_spacing(None, 0.1, 0.1) == sx.EINVAL
+    assert lib.sacx_init_problem(None, 0, None, 0, 0.0) == sx.EINVAL
