@@ -25,6 +25,10 @@ Other modes (one JSON line each):
                     stage and a device max of the wave speeds per step,
                     beside the undivided run (the cost of the exchange path;
                     the results are compared bit for bit);
+  --mode graph      an n x n Orszag-Tang grid (default 1024) stepped by eager
+                    launches and by replays of a HIP graph of --graph-steps
+                    captured steps (small grids are launch-bound); the two
+                    runs end bit-identical;
   --mode copy       a device copy of known size (calibrates the HBM byte
                     counters of a profiler run), and the streaming rate of a
                     plain elementwise kernel (b = a + 3c, 3 x 4 GiB).
@@ -243,11 +247,11 @@ def run_decomposed(args):
     prec = FP64 if args.precision == "fp64" else FP32
     log(f"[bench] generating orszag_tang {n}x{n}, split {px}x{py}")
     prob = W.orszag_tang(n)
-    dec = DecomposedSolver(prob, even_cuts(n, px), even_cuts(n, py), precision=prec)
-    one = Solver.from_problem(prob, precision=prec)
+    stream = torch.cuda.Stream()
+    dec = DecomposedSolver(prob, even_cuts(n, px), even_cuts(n, py), precision=prec, stream=stream)
+    one = Solver.from_problem(prob, precision=prec, stream=stream)
     del prob
     subs = [s for row in dec.subs for s in row]
-    stream = one.stream
     log(f"[bench] warmup {args.warmup} steps")
     dec.advance(args.warmup)
     one.advance(args.warmup)
@@ -269,10 +273,15 @@ def run_decomposed(args):
     profs = [s.profile_read() for s in subs]
     for s in subs:
         s.profile_enable(False)
+    g = max(1, min(args.graph_steps, args.steps))
+    reps = args.steps // g
+    log(f"[bench] capturing {g} decomposed steps into a graph, timing {reps} replays")
+    graph = dec.graph(g)
+    ms_graph = timed(lambda: [graph.replay() for _ in range(reps)]) * args.steps / (reps * g)
     log(f"[bench] timing {args.steps} undivided steps")
-    ms_one = timed(lambda: one.advance(args.steps, sync=False))
+    ms_one = timed(lambda: one.advance(args.steps + reps * g, sync=False)) * args.steps / (args.steps + reps * g)
     diags = [s.diagnostics() for s in subs] + [one.diagnostics()]
-    if any(d["nonphys"] or d["steps"] != args.warmup + args.steps for d in diags):
+    if any(d["nonphys"] or d["steps"] != args.warmup + args.steps + reps * g for d in diags):
         log(f"[bench] run failed: {diags}")
         sys.exit(1)
     same = bool(torch.equal(dec.read_fields(torch.float64), one.read_fields(torch.float64)))
@@ -293,9 +302,63 @@ def run_decomposed(args):
     out["undivided"] = {"value": round(cells * args.steps / (ms_one / 1e3) / 1e6, 3),
                         "ms_per_step": round(ms_one / args.steps, 4)}
     out["overhead_vs_undivided"] = round(ms_dec / ms_one - 1.0, 4)
+    out["graph"] = {"steps_per_graph": g, "ms_per_step": round(ms_graph / args.steps, 4),
+                    "value": round(cells * args.steps / (ms_graph / 1e3) / 1e6, 3),
+                    "overhead_vs_undivided": round(ms_graph / ms_one - 1.0, 4)}
     out["phases_ms"] = {"stage": round(stage_ms, 3), "halo": round(halo_ms, 3),
                         "tau": round(math.log(stage_ms / halo_ms), 3) if halo_ms > 0 else None}
     out["bit_identical_to_undivided"] = same
+    print(json.dumps(out), flush=True)
+
+
+def run_graph(args):
+    import torch
+    import workloads as W
+    from paper_1710_06423_amd import FP32, FP64, Solver
+
+    n = args.n
+    prec = FP64 if args.precision == "fp64" else FP32
+    g = max(1, min(args.graph_steps, args.steps))
+    reps = max(1, args.steps // g)
+    steps = reps * g
+    log(f"[bench] orszag_tang {n}x{n} {args.precision}: eager vs a graph of {g} steps x {reps}")
+    prob = W.orszag_tang(n)
+    stream = torch.cuda.Stream()
+    eager = Solver.from_problem(prob, precision=prec, stream=stream)
+    graphed = Solver.from_problem(prob, precision=prec, stream=stream)
+    del prob
+    eager.advance(args.warmup)
+    graphed.advance(args.warmup)
+    graph = graphed.graph(g)
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record(stream)
+        fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b)
+
+    ms_eager = timed(lambda: eager.advance(steps, sync=False))
+    ms_graph = timed(lambda: [graph.replay() for _ in range(reps)])
+    de, dg = eager.diagnostics(), graphed.diagnostics()
+    if de["nonphys"] or dg["nonphys"] or de["steps"] != dg["steps"] or de["steps"] != args.warmup + steps:
+        log(f"[bench] run failed: {de} {dg}")
+        sys.exit(1)
+    same = bool(torch.equal(eager.read_fields(torch.float64), graphed.read_fields(torch.float64)))
+    cells = n * n
+    value = cells * steps / (ms_graph / 1e3) / 1e6
+    log(f"[bench] eager {ms_eager / steps:.4f} ms/step, graph {ms_graph / steps:.4f} ms/step; bit-identical: {same}")
+    out = base_record(args, value, ms_graph / steps, "f64" if prec == FP64 else "f32", {
+        "workload": f"orszag_tang_{n}x{n}_{args.precision}_hd_graph{g}",
+        "nx": n, "ny": n, "precision": args.precision, "hyper_diffusion": True, "cfl": 0.3,
+        "steps_per_graph": g,
+    })
+    out["steps"] = steps
+    out["eager"] = {"value": round(cells * steps / (ms_eager / 1e3) / 1e6, 3), "ms_per_step": round(ms_eager / steps, 4)}
+    out["speedup_vs_eager"] = round(ms_eager / ms_graph, 4)
+    out["bit_identical_to_eager"] = same
     print(json.dumps(out), flush=True)
 
 
@@ -497,9 +560,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 100, surrogate 500)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["single", "batch", "surrogate", "decomposed", "copy"], default="single")
+    ap.add_argument("--mode", choices=["single", "batch", "surrogate", "decomposed", "graph", "copy"],
+                    default="single")
     ap.add_argument("--split", default="2x2", help="decomposed mode: subdomains along x and y, e.g. 2x2")
-    ap.add_argument("--n", type=int, default=None, help="grid side (default 8000, surrogate 2048)")
+    ap.add_argument("--graph-steps", type=int, default=10, help="graph and decomposed modes: steps per captured graph")
+    ap.add_argument("--n", type=int, default=None, help="grid side (default 8000, surrogate 2048, graph 1024)")
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--problem", choices=["orszag_tang", "stratified"], default="orszag_tang",
                     help="single mode: Orszag-Tang, or a stratified atmosphere under gravity (background on)")
@@ -519,14 +584,14 @@ def main():
     if args.steps is None:
         args.steps = 500 if args.mode == "surrogate" else 100
     if args.n is None:
-        args.n = 2048 if args.mode == "surrogate" else 8000
+        args.n = {"surrogate": 2048, "graph": 1024}.get(args.mode, 8000)
 
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     {"single": run_single, "batch": run_batch, "surrogate": run_surrogate, "decomposed": run_decomposed,
-     "copy": run_copy}[args.mode](args)
+     "graph": run_graph, "copy": run_copy}[args.mode](args)
 
 
 if __name__ == "__main__":

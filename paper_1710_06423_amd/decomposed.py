@@ -12,11 +12,12 @@ stages, each after the x and then the y halo exchange.  The subdomains
 evolve bit for bit as their parts of the undivided domain.
 """
 
-from typing import List, Sequence
+from typing import List, Optional, Sequence
 
 import torch
 
-from .sacx import EXCHANGE, FIELDS, FP64, OPEN, PERIODIC, Solver, make_grid, make_params, DEFAULT_C2, DEFAULT_CSHK
+from .sacx import (EXCHANGE, FIELDS, FP64, OPEN, PERIODIC, Solver, StepGraph, make_grid, make_params, DEFAULT_C2,
+                   DEFAULT_CSHK)
 
 
 def even_cuts(n: int, parts: int) -> List[int]:
@@ -28,7 +29,8 @@ class DecomposedSolver:
     """The subdomains of one problem and their exchange buffers."""
 
     def __init__(self, prob, xcuts: Sequence[int], ycuts: Sequence[int], precision=FP64, cfl=0.3, hd_on=True,
-                 hd_cross_on=True, c2=DEFAULT_C2, cshk=DEFAULT_CSHK, device="cuda"):
+                 hd_cross_on=True, c2=DEFAULT_C2, cshk=DEFAULT_CSHK, device="cuda",
+                 stream: Optional[torch.cuda.Stream] = None):
         if prob.background is not None:
             raise ValueError("exchange boundaries do not support a background")
         xcuts, ycuts = list(xcuts), list(ycuts)
@@ -46,7 +48,7 @@ class DecomposedSolver:
                 i0, i1, j0, j1 = xcuts[a], xcuts[a + 1], ycuts[b], ycuts[b + 1]
                 grid = make_grid(i1 - i0, j1 - j0, prob.x0 + i0 * dx, prob.x0 + i1 * dx, prob.y0 + j0 * dy,
                                  prob.y0 + j1 * dy, precision, False)
-                s = Solver(grid, params, self._sides(a, b), device=device)
+                s = Solver(grid, params, self._sides(a, b), device=device, stream=stream)
                 # the whole domain's spacing: the subdomain's extent over its
                 # cell count can round differently
                 s.set_spacing(dx, dy)
@@ -54,8 +56,12 @@ class DecomposedSolver:
                 s.init_state(f, None, t0=prob.t0)
                 row.append(s)
             self.subs.append(row)
+        # every subdomain works on one stream, and so does the driver's own
+        # device work (the maxima array)
+        self.stream = self.subs[0][0].stream
         # the whole domain's wave-speed maxima, reduced on the device
-        self.cmax = torch.zeros(2, dtype=torch.float64, device=self.subs[0][0].device)
+        with torch.cuda.stream(self.stream):
+            self.cmax = torch.zeros(2, dtype=torch.float64, device=self.subs[0][0].device)
         # buffers[b][a][side]: what subdomain (a, b) packs at `side`
         self.buffers = [[{side: s.halo_buffer(side) for side in range(4) if self._sides(a, b)[side] == EXCHANGE}
                          for a, s in enumerate(row)] for b, row in enumerate(self.subs)]
@@ -112,27 +118,44 @@ class DecomposedSolver:
         """nsteps RK4 steps of the whole domain.  device_max: the maxima over
         the subdomains are reduced on the device (no synchronisation), else
         read back and reduced on the host."""
-        for _ in range(nsteps):
-            if device_max:
-                self.cmax.zero_()
-                for row in self.subs:
-                    for s in row:
-                        s.wave_speeds_max(self.cmax)
-                c = self.cmax
-            else:
-                c = self.wave_speeds()
-            for _stage in range(4):
-                for row in self.subs:
-                    for s in row:
-                        s.fill_boundaries(0)
-                self._exchange(0)
-                for row in self.subs:
-                    for s in row:
-                        s.fill_boundaries(1)
-                self._exchange(1)
-                for row in self.subs:
-                    for s in row:
-                        s.stage(c)
+        with torch.cuda.stream(self.stream):
+            for _ in range(nsteps):
+                self._step(device_max)
+
+    def _step(self, device_max: bool):
+        """Enqueue one step of the whole domain."""
+        if device_max:
+            self.cmax.zero_()
+            for row in self.subs:
+                for s in row:
+                    s.wave_speeds_max(self.cmax)
+            c = self.cmax
+        else:
+            c = self.wave_speeds()
+        for _stage in range(4):
+            for row in self.subs:
+                for s in row:
+                    s.fill_boundaries(0)
+            self._exchange(0)
+            for row in self.subs:
+                for s in row:
+                    s.fill_boundaries(1)
+            self._exchange(1)
+            for row in self.subs:
+                for s in row:
+                    s.stage(c)
+
+    def graph(self, nsteps: int) -> StepGraph:
+        """nsteps steps of the whole domain (device maxima) captured into one
+        HIP graph: every fill, pack, unpack, maximum and stage launch of
+        every subdomain replayed as one graph launch.  Needs the subdomains
+        on a stream of their own (DecomposedSolver(..., stream=...))."""
+
+        def enqueue():
+            for _ in range(nsteps):
+                self._step(True)
+
+        return StepGraph(enqueue, self.stream)
 
     def read_fields(self, dtype: torch.dtype = torch.float64) -> torch.Tensor:
         out = None

@@ -8,6 +8,7 @@ this module succeeds but every call raises -- there is no fallback path.
 
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 from typing import Dict, Optional, Sequence
@@ -253,6 +254,22 @@ class Solver:
         except Exception:
             pass
 
+    @contextlib.contextmanager
+    def _shared(self):
+        """Order the device tensors a call shares with the library when the
+        caller's current stream is not the context's: the context's stream
+        first waits for the caller's (inputs it produced, outputs it just
+        allocated and cleared), and the caller's stream then waits for the
+        context's (results it will read).  The tensors stay the caller's."""
+        cur = torch.cuda.current_stream(self.device)
+        same = cur.cuda_stream == self.stream.cuda_stream
+        if not same:
+            self.stream.wait_stream(cur)
+        with torch.cuda.device(self.device):
+            yield
+        if not same:
+            cur.wait_stream(self.stream)
+
     def set_boundaries(self, bc):
         arr = (ctypes.c_int32 * 4)(*[int(b) for b in bc])
         _check(self.lib.sacx_set_boundaries(self.ctx, arr), "sacx_set_boundaries")
@@ -270,7 +287,7 @@ class Solver:
         if bg is not None:
             bg = bg.to(fields.dtype).contiguous()
             bgp = _ptrs([bg[k] for k in range(4)])
-        with torch.cuda.device(self.device):
+        with self._shared():
             _check(self.lib.sacx_init_state(self.ctx, _ptrs([fields[k] for k in range(6)]), bgp,
                                             fields.shape[2], prec, float(t0)), "sacx_init_state")
 
@@ -308,7 +325,7 @@ class Solver:
     def read_fields(self, dtype: torch.dtype = torch.float64, mask: int = 0x3F) -> torch.Tensor:
         out = torch.zeros((6, self.grid.ny, self.grid.nx), dtype=dtype, device=self.device)
         prec = FP64 if dtype == torch.float64 else FP32
-        with torch.cuda.device(self.device):
+        with self._shared():
             _check(self.lib.sacx_read_fields(self.ctx, _ptrs([out[k] for k in range(6)]), self.grid.nx, mask, prec),
                    "sacx_read_fields")
         return out
@@ -327,11 +344,11 @@ class Solver:
                            device=self.device)
 
     def halo_pack(self, side: int, buf: torch.Tensor):
-        with torch.cuda.device(self.device):
+        with self._shared():
             _check(self.lib.sacx_halo_pack(self.ctx, int(side), ctypes.c_void_p(buf.data_ptr())), "sacx_halo_pack")
 
     def halo_unpack(self, side: int, buf: torch.Tensor):
-        with torch.cuda.device(self.device):
+        with self._shared():
             _check(self.lib.sacx_halo_unpack(self.ctx, int(side), ctypes.c_void_p(buf.data_ptr())), "sacx_halo_unpack")
 
     def fill_boundaries(self, direction: int):
@@ -354,7 +371,7 @@ class Solver:
         else:
             arr = (ctypes.c_double * 2)(*[float(v) for v in c_max])
             c, on_dev = ctypes.cast(arr, ctypes.c_void_p), 0
-        with torch.cuda.device(self.device):
+        with self._shared():
             _check(self.lib.sacx_stage(self.ctx, c, on_dev, ctypes.byref(done)), "sacx_stage")
         return done.value
 
@@ -363,7 +380,7 @@ class Solver:
         device tensor of 2 elements."""
         if c_max.dtype != torch.float64 or c_max.numel() != 2 or c_max.device != self.device:
             raise ValueError(f"c_max must be 2 float64 values on {self.device}")
-        with torch.cuda.device(self.device):
+        with self._shared():
             _check(self.lib.sacx_wave_speeds_max(self.ctx, ctypes.c_void_p(c_max.data_ptr())), "sacx_wave_speeds_max")
 
     def set_spacing(self, dx: float, dy: float):
@@ -380,6 +397,19 @@ class Solver:
 
     def profile_enable(self, on: bool = True):
         _check(self.lib.sacx_profile_enable(self.ctx, int(bool(on))), "sacx_profile_enable")
+        self._profiling = bool(on)
+
+    def graph(self, nsteps: int) -> "StepGraph":
+        """nsteps RK4 steps captured into a HIP graph; each replay advances
+        the state by nsteps as advance(nsteps, sync=False) would.  Needs a
+        context on its own stream (Solver(..., stream=torch.cuda.Stream()))
+        and profiling off; without a learned coefficient, whose refresh
+        schedule lives on the host."""
+        if getattr(self, "_profiling", False):
+            raise ValueError("turn profiling off before capturing")
+        if getattr(self, "sur_ws", None) is not None:
+            raise ValueError("a context with a learned coefficient cannot be captured")
+        return StepGraph(lambda: self.advance(nsteps, sync=False), self.stream)
 
     def profile_read(self) -> Dict:
         p = Profile()
@@ -395,7 +425,7 @@ class Solver:
         if out is None:
             out = torch.empty((self.grid.ny, self.grid.nx, 8), dtype=torch.bfloat16, device=self.device)
         arr = (ctypes.c_float * 12)(*[float(v) for v in norm])
-        with torch.cuda.device(self.device):
+        with self._shared():
             _check(self.lib.sacx_cnn_inputs(self.ctx, arr, ctypes.c_void_p(out.data_ptr())), "sacx_cnn_inputs")
         return out
 
@@ -406,7 +436,7 @@ class Solver:
         if out is None:
             out = torch.empty(shape, dtype=torch.float32, device=self.device)
         d1 = torch.empty(shape, dtype=torch.float32, device=self.device) if with_d1 else None
-        with torch.cuda.device(self.device):
+        with self._shared():
             _check(self.lib.sacx_hd_ratio_fields(self.ctx, ctypes.c_void_p(out.data_ptr()),
                                                  ctypes.c_void_p(None if d1 is None else d1.data_ptr()),
                                                  self.grid.nx), "sacx_hd_ratio_fields")
@@ -422,7 +452,7 @@ class Solver:
         self.sur_packed = packed
         cfg = Surrogate(None if packed is None else packed.data_ptr(), (ctypes.c_float * 12)(*[float(v) for v in norm]),
                         int(refresh_every), int(tile), int(metric), float(bound))
-        with torch.cuda.device(self.device):
+        with self._shared():
             _check(self.lib.sacx_hd_set_surrogate(self.ctx, ctypes.byref(cfg), ctypes.c_void_p(self.sur_ws.data_ptr()),
                                                   n.value), "sacx_hd_set_surrogate")
 
@@ -530,6 +560,28 @@ class Batch:
 
 
 # ---------------------------------------------------------------- network calls
+class StepGraph:
+    """A fixed piece of enqueued work (steps of a context, or of a decomposed
+    domain) captured once into a HIP graph through torch.cuda.CUDAGraph and
+    replayed: one launch of the graph in place of every kernel launch of the
+    piece, for launch-bound runs (small grids, the many small exchange
+    kernels of a decomposed domain).  The capture enqueues nothing; each
+    replay does the work on the captured stream."""
+
+    def __init__(self, enqueue, stream: torch.cuda.Stream):
+        if stream is None or stream.cuda_stream == 0:
+            raise ValueError("graph capture needs the work on a stream of its own, not the default stream")
+        self.stream = stream
+        self.graph = torch.cuda.CUDAGraph()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(self.graph, stream=stream, capture_error_mode="thread_local"):
+            enqueue()
+
+    def replay(self):
+        with torch.cuda.stream(self.stream):
+            self.graph.replay()
+
+
 def _dp(t: Optional[torch.Tensor]):
     return ctypes.c_void_p(None if t is None else t.data_ptr())
 
