@@ -187,7 +187,8 @@ int sacx_advance(sacx_ctx *ctx, int32_t nsteps, double t_end, int32_t *steps_don
 /* Copy the interior of the evolved fields selected by field_mask (bit k =
  * field k) into caller device buffers d_out[k] (pitch in elements), converted
  * to out_precision.  Entries of d_out for unselected fields are ignored.
- * Enqueued on the stream (paper section 5: snapshots at fixed times). */
+ * During a step begun with sacx_stage these are the fields at the step's
+ * start.  Enqueued on the stream (paper section 5: snapshots at fixed times). */
 int sacx_read_fields(sacx_ctx *ctx, void *const *d_out, int64_t pitch, uint32_t field_mask,
                      int32_t out_precision);
 
