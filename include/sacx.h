@@ -75,7 +75,9 @@ extern "C" {
 
 typedef struct sacx_grid {
     int32_t nx, ny;          /* interior cells of this subdomain */
-    double x0, x1, y0, y1;   /* physical extent of this subdomain */
+    double x0, x1, y0, y1;   /* physical extent of this subdomain; the cell spacing is
+                                (x1 - x0) / nx and (y1 - y0) / ny unless sacx_set_spacing
+                                replaces it */
     int32_t precision;       /* SACX_FP64 or SACX_FP32: storage and bulk arithmetic;
                                 time step and conservation sums are always FP64 */
     int32_t background_on;   /* 1: static background arrays are present */
@@ -98,7 +100,7 @@ typedef struct sacx_params {
 typedef struct sacx_diag {
     double t;                /* current time */
     double dt;               /* time step of the last step taken */
-    double c_x, c_y, c_max;  /* max(|v_d| + c_f) of the current state */
+    double c_x, c_y, c_max;  /* max(|v_d| + c_f) over this context's cells of the current state */
     double sums[6];          /* sum over the interior of each evolved field times dx dy (FP64) */
     int64_t steps;           /* steps taken since sacx_init_state */
     int32_t nonphys;         /* 1 if the current state is non-physical */
