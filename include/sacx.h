@@ -273,6 +273,33 @@ int sacx_stage(sacx_ctx *ctx, const double *c_max, int32_t c_max_on_device, int3
 int sacx_wave_speeds(sacx_ctx *ctx, double c_max[2]);
 int sacx_wave_speeds_max(sacx_ctx *ctx, double *d_c_max);
 
+/* A decomposed domain stepped natively: px x py subdomain contexts (row
+ * major, subdomain (a, b) at subs[a + b px], x increasing with a, y with b)
+ * whose halos the library exchanges itself, in the order described above,
+ * with the maxima reduced on the device.  Requirements (EINVAL otherwise):
+ * every context initialised (ESTATE otherwise), on one device and one
+ * stream, with equal precision, scheme parameters and grid spacing; every
+ * side that borders another subdomain is EXCHANGE, and so is the facing side
+ * of the neighbour across every EXCHANGE side (across the domain's edge the
+ * neighbour is the subdomain at the other end: a periodic domain); facing
+ * strips have equal lengths.  A context of a domain is still the caller's
+ * (destroy the domain first); its own calls keep working.
+ *  sacx_domain_buffer_size: bytes of caller device memory the domain needs
+ *    (one strip per EXCHANGE side and the maxima); host arithmetic.
+ *  sacx_domain_create: d_buf (256-byte aligned, ENOSPC if smaller) must
+ *    outlive the domain.
+ *  sacx_domain_advance: enqueue nsteps steps of every subdomain on their
+ *    stream (no synchronisation); ESTATE while a subdomain has a step begun
+ *    with sacx_stage in progress.  A subdomain stopped by a non-physical state
+ *    stays stopped (sacx_diagnostics); the others go on.
+ *  sacx_domain_destroy: releases the host object (NULL is a no-op). */
+typedef struct sacx_domain sacx_domain;
+int sacx_domain_buffer_size(int32_t px, int32_t py, sacx_ctx *const *subs, size_t *bytes);
+int sacx_domain_create(int32_t px, int32_t py, sacx_ctx *const *subs, void *d_buf, size_t buf_bytes,
+                       sacx_domain **out);
+int sacx_domain_advance(sacx_domain *d, int32_t nsteps);
+int sacx_domain_destroy(sacx_domain *d);
+
 /* Launch shape of the fused stage kernel: `threads` columns per block
  * including the 6-column apron (64, 128 or 256; the one-thread tile runs
  * that many threads per block, the FP64 split tile of sacx_set_column_split

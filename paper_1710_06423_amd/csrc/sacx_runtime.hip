@@ -33,6 +33,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "sacx_internal.h"
@@ -1800,6 +1801,203 @@ int sacx_batch_advance(sacx_batch *b, int32_t nsteps, int32_t sync) {
             int np = 0;
             HIPCHK(hipMemcpy(&np, &c->sc->nonphys, sizeof(int), hipMemcpyDeviceToHost));
             if (np) return fail(SACX_ENONPHYS, "a batch instance reached a non-physical state");
+        }
+    }
+    return SACX_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ decomposed domain
+
+namespace {
+
+__global__ void k_zero_doubles(double *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0;
+}
+
+constexpr size_t kDomainAlign = 256;
+
+// the neighbour across `side` of subdomain (a, b) in a px x py layout,
+// wrapping around the domain (a periodic image is a neighbour too)
+int domain_neighbour(int px, int py, int a, int b, int side) {
+    switch (side) {
+        case 0: return ((a - 1 + px) % px) + b * px;
+        case 1: return ((a + 1) % px) + b * px;
+        case 2: return a + ((b - 1 + py) % py) * px;
+        default: return a + ((b + 1) % py) * px;
+    }
+}
+
+bool domain_edge(int px, int py, int a, int b, int side) {
+    switch (side) {
+        case 0: return a == 0;
+        case 1: return a == px - 1;
+        case 2: return b == 0;
+        default: return b == py - 1;
+    }
+}
+
+}  // namespace
+
+struct sacx_domain {
+    int px, py;
+    std::vector<sacx_ctx *> *subs;            // row-major, px x py
+    std::vector<std::array<void *, 4>> *buf;  // per subdomain and side: the strip it packs (exchange sides)
+    std::vector<std::array<int, 4>> *nbr;     // per subdomain and side: the neighbour (exchange sides)
+    double *cmax;                             // the whole domain's wave-speed maxima (device)
+};
+
+extern "C" {
+
+// checks shared by the size query and creation; on success *bytes is the
+// caller memory the domain needs
+static int domain_check(int32_t px, int32_t py, sacx_ctx *const *subs, size_t *bytes) {
+    if (px < 1 || py < 1 || (int64_t)px * py > 65536) return fail(SACX_EINVAL, "px, py must be >= 1 (at most 65536 subdomains)");
+    if (!subs || !bytes) return fail(SACX_EINVAL, "subs/bytes must not be NULL");
+    const int n = px * py;
+    for (int i = 0; i < n; ++i) {
+        if (!subs[i]) return fail(SACX_EINVAL, "subdomain %d is NULL", i);
+        for (int j = 0; j < i; ++j)
+            if (subs[j] == subs[i]) return fail(SACX_EINVAL, "subdomain %d appears twice", i);
+    }
+    const sacx_ctx *c0 = subs[0];
+    size_t total = kDomainAlign;  // the maxima
+    for (int b = 0; b < py; ++b)
+        for (int a = 0; a < px; ++a) {
+            const int i = a + b * px;
+            const sacx_ctx *c = subs[i];
+            if (!c->initialized) return fail(SACX_ESTATE, "subdomain %d has no state (sacx_init_state)", i);
+            if (c->device != c0->device || c->stream != c0->stream)
+                return fail(SACX_EINVAL, "subdomain %d is not on the device and stream of subdomain 0", i);
+            if (c->grid.precision != c0->grid.precision) return fail(SACX_EINVAL, "subdomain %d has another precision", i);
+            if (std::memcmp(&c->params, &c0->params, sizeof(sacx_params)) != 0)
+                return fail(SACX_EINVAL, "subdomain %d has other scheme parameters", i);
+            if (c->dx != c0->dx || c->dy != c0->dy)
+                return fail(SACX_EINVAL, "subdomain %d has another grid spacing (sacx_set_spacing)", i);
+            if (c->sur_on) return fail(SACX_ESTATE, "subdomain %d has a learned coefficient", i);
+            for (int side = 0; side < 4; ++side) {
+                const bool edge = domain_edge(px, py, a, b, side);
+                if (c->bc[side] != SACX_EXCHANGE) {
+                    if (!edge) return fail(SACX_EINVAL, "subdomain %d side %d borders a subdomain but is not EXCHANGE", i, side);
+                    continue;
+                }
+                const sacx_ctx *nb = subs[domain_neighbour(px, py, a, b, side)];
+                if (nb->bc[side ^ 1] != SACX_EXCHANGE)
+                    return fail(SACX_EINVAL, "subdomain %d side %d: the neighbour's facing side is not EXCHANGE", i, side);
+                if ((side < 2 && nb->grid.ny != c->grid.ny) || (side >= 2 && nb->grid.nx != c->grid.nx))
+                    return fail(SACX_EINVAL, "subdomain %d side %d: the neighbour's strip has another length", i, side);
+                size_t sb = 0;
+                int rc = sacx_halo_buffer_size(c, side, &sb);
+                if (rc) return rc;
+                total += round_up(sb, kDomainAlign);
+            }
+        }
+    *bytes = total;
+    return SACX_OK;
+}
+
+int sacx_domain_buffer_size(int32_t px, int32_t py, sacx_ctx *const *subs, size_t *bytes) {
+    return domain_check(px, py, subs, bytes);
+}
+
+int sacx_domain_create(int32_t px, int32_t py, sacx_ctx *const *subs, void *d_buf, size_t buf_bytes, sacx_domain **out) {
+    if (!out) return fail(SACX_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    size_t need = 0;
+    int rc = domain_check(px, py, subs, &need);
+    if (rc) return rc;
+    if (!d_buf) return fail(SACX_EINVAL, "buffer pointer is NULL");
+    if (((uintptr_t)d_buf) % kDomainAlign) return fail(SACX_EINVAL, "buffer must be 256-byte aligned");
+    if (buf_bytes < need) return fail(SACX_ENOSPC, "buffer has %zu bytes, %zu needed", buf_bytes, need);
+    sacx_domain *d = new (std::nothrow) sacx_domain();
+    if (!d) return fail(SACX_EINVAL, "out of host memory");
+    d->px = px;
+    d->py = py;
+    d->subs = new (std::nothrow) std::vector<sacx_ctx *>(subs, subs + (size_t)px * py);
+    d->buf = new (std::nothrow) std::vector<std::array<void *, 4>>((size_t)px * py);
+    d->nbr = new (std::nothrow) std::vector<std::array<int, 4>>((size_t)px * py);
+    if (!d->subs || !d->buf || !d->nbr) {
+        sacx_domain_destroy(d);
+        return fail(SACX_EINVAL, "out of host memory");
+    }
+    char *p = (char *)d_buf;
+    d->cmax = (double *)p;
+    p += kDomainAlign;
+    for (int b = 0; b < py; ++b)
+        for (int a = 0; a < px; ++a) {
+            const int i = a + b * px;
+            for (int side = 0; side < 4; ++side) {
+                (*d->buf)[i][side] = nullptr;
+                (*d->nbr)[i][side] = -1;
+                if (subs[i]->bc[side] != SACX_EXCHANGE) continue;
+                size_t sb = 0;
+                sacx_halo_buffer_size(subs[i], side, &sb);
+                (*d->buf)[i][side] = p;
+                (*d->nbr)[i][side] = domain_neighbour(px, py, a, b, side);
+                p += round_up(sb, kDomainAlign);
+            }
+        }
+    *out = d;
+    return SACX_OK;
+}
+
+int sacx_domain_destroy(sacx_domain *d) {
+    if (!d) return SACX_OK;
+    delete d->subs;
+    delete d->buf;
+    delete d->nbr;
+    delete d;
+    return SACX_OK;
+}
+
+// one direction's exchange: every subdomain packs its exchange strips, then
+// unpacks the strips its neighbours packed facing it
+static int domain_exchange(sacx_domain *d, int dir) {
+    const int n = d->px * d->py;
+    for (int i = 0; i < n; ++i)
+        for (int side = 2 * dir; side < 2 * dir + 2; ++side)
+            if ((*d->buf)[i][side]) {
+                int rc = sacx_halo_pack((*d->subs)[i], side, (*d->buf)[i][side]);
+                if (rc) return rc;
+            }
+    for (int i = 0; i < n; ++i)
+        for (int side = 2 * dir; side < 2 * dir + 2; ++side)
+            if ((*d->buf)[i][side]) {
+                const int j = (*d->nbr)[i][side];
+                int rc = sacx_halo_unpack((*d->subs)[i], side, (*d->buf)[j][side ^ 1]);
+                if (rc) return rc;
+            }
+    return SACX_OK;
+}
+
+int sacx_domain_advance(sacx_domain *d, int32_t nsteps) {
+    if (!d) return fail(SACX_EINVAL, "domain must not be NULL");
+    if (nsteps < 0) return fail(SACX_EINVAL, "nsteps must be >= 0");
+    const int n = d->px * d->py;
+    for (int i = 0; i < n; ++i) {
+        const sacx_ctx *c = (*d->subs)[i];
+        if (c->stage_next) return fail(SACX_ESTATE, "subdomain %d has a step in progress", i);
+        if (c->sur_on) return fail(SACX_ESTATE, "subdomain %d has a learned coefficient", i);
+    }
+    sacx_ctx *c0 = (*d->subs)[0];
+    DeviceGuard dg(c0->device);
+    if (!dg.ok) return fail(SACX_EDEVICE, "cannot select the domain's device");
+    for (int step = 0; step < nsteps; ++step) {
+        hipLaunchKernelGGL(k_zero_doubles, dim3(1), dim3(64), 0, c0->stream, d->cmax, 2);
+        HIPCHK(hipGetLastError());
+        int rc;
+        for (int i = 0; i < n; ++i)
+            if ((rc = sacx_wave_speeds_max((*d->subs)[i], d->cmax))) return rc;
+        for (int s = 0; s < 4; ++s) {
+            for (int i = 0; i < n; ++i)
+                if ((rc = sacx_fill_boundaries((*d->subs)[i], 0))) return rc;
+            if ((rc = domain_exchange(d, 0))) return rc;
+            for (int i = 0; i < n; ++i)
+                if ((rc = sacx_fill_boundaries((*d->subs)[i], 1))) return rc;
+            if ((rc = domain_exchange(d, 1))) return rc;
+            for (int i = 0; i < n; ++i)
+                if ((rc = sacx_stage((*d->subs)[i], d->cmax, 1, nullptr))) return rc;
         }
     }
     return SACX_OK;

@@ -14,10 +14,12 @@ evolve bit for bit as their parts of the undivided domain.
 
 from typing import List, Optional, Sequence
 
+import ctypes
+
 import torch
 
-from .sacx import (EXCHANGE, FIELDS, FP64, OPEN, PERIODIC, Solver, StepGraph, make_grid, make_params, DEFAULT_C2,
-                   DEFAULT_CSHK)
+from .sacx import (EXCHANGE, FIELDS, FP64, OPEN, PERIODIC, Solver, StepGraph, _check, load_library, make_grid,
+                   make_params, DEFAULT_C2, DEFAULT_CSHK)
 
 
 def even_cuts(n: int, parts: int) -> List[int]:
@@ -62,9 +64,24 @@ class DecomposedSolver:
         # the whole domain's wave-speed maxima, reduced on the device
         with torch.cuda.stream(self.stream):
             self.cmax = torch.zeros(2, dtype=torch.float64, device=self.subs[0][0].device)
-        # buffers[b][a][side]: what subdomain (a, b) packs at `side`
+        # buffers[b][a][side]: what subdomain (a, b) packs at `side` (the
+        # Python-driven path)
         self.buffers = [[{side: s.halo_buffer(side) for side in range(4) if self._sides(a, b)[side] == EXCHANGE}
                          for a, s in enumerate(row)] for b, row in enumerate(self.subs)]
+        # the library's own domain object (the native path): subdomain (a, b)
+        # at a + b px, its strips and maxima in one caller-owned buffer
+        self.lib = load_library()
+        arr = (ctypes.c_void_p * (self.px * self.py))(*[s.ctx.value for row in self.subs for s in row])
+        self._subs_arr = arr
+        nbytes = ctypes.c_size_t(0)
+        _check(self.lib.sacx_domain_buffer_size(self.px, self.py, arr, ctypes.byref(nbytes)), "sacx_domain_buffer_size")
+        with torch.cuda.stream(self.stream):
+            self.domain_buf = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=self.subs[0][0].device)
+        base = self.domain_buf.data_ptr()
+        off = (-base) % 256
+        self.domain = ctypes.c_void_p(None)
+        _check(self.lib.sacx_domain_create(self.px, self.py, arr, ctypes.c_void_p(base + off), nbytes.value,
+                                           ctypes.byref(self.domain)), "sacx_domain_create")
 
     def _sides(self, a: int, b: int):
         """Boundary kinds of subdomain (a, b): EXCHANGE towards a neighbour
@@ -114,10 +131,16 @@ class DecomposedSolver:
                 cx, cy = max(cx, x), max(cy, y)
         return cx, cy
 
-    def advance(self, nsteps: int, device_max: bool = True):
-        """nsteps RK4 steps of the whole domain.  device_max: the maxima over
-        the subdomains are reduced on the device (no synchronisation), else
-        read back and reduced on the host."""
+    def advance(self, nsteps: int, device_max: bool = True, native: bool = True):
+        """nsteps RK4 steps of the whole domain.  native: the library's domain
+        object drives every launch (sacx_domain_advance); otherwise this class
+        does, through the stage-level calls, with the maxima over the
+        subdomains reduced on the device (device_max) or read back and
+        reduced on the host."""
+        if native and device_max:
+            with torch.cuda.device(self.subs[0][0].device):
+                _check(self.lib.sacx_domain_advance(self.domain, int(nsteps)), "sacx_domain_advance")
+            return
         with torch.cuda.stream(self.stream):
             for _ in range(nsteps):
                 self._step(device_max)
@@ -146,16 +169,11 @@ class DecomposedSolver:
                     s.stage(c)
 
     def graph(self, nsteps: int) -> StepGraph:
-        """nsteps steps of the whole domain (device maxima) captured into one
-        HIP graph: every fill, pack, unpack, maximum and stage launch of
+        """nsteps steps of the whole domain (the native path) captured into
+        one HIP graph: every fill, pack, unpack, maximum and stage launch of
         every subdomain replayed as one graph launch.  Needs the subdomains
         on a stream of their own (DecomposedSolver(..., stream=...))."""
-
-        def enqueue():
-            for _ in range(nsteps):
-                self._step(True)
-
-        return StepGraph(enqueue, self.stream)
+        return StepGraph(lambda: self.advance(nsteps), self.stream)
 
     def read_fields(self, dtype: torch.dtype = torch.float64) -> torch.Tensor:
         out = None
@@ -171,6 +189,15 @@ class DecomposedSolver:
         return [[s.diagnostics() for s in row] for row in self.subs]
 
     def close(self):
+        if getattr(self, "domain", None):
+            self.lib.sacx_domain_destroy(self.domain)
+            self.domain = ctypes.c_void_p(None)
         for row in self.subs:
             for s in row:
                 s.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

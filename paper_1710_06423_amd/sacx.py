@@ -36,6 +36,7 @@ EXPORTED = (
     "sacx_destroy", "sacx_set_boundaries", "sacx_init_state", "sacx_init_problem", "sacx_advance", "sacx_read_fields",
     "sacx_diagnostics", "sacx_halo_buffer_size", "sacx_halo_pack", "sacx_halo_unpack",
     "sacx_fill_boundaries", "sacx_stage", "sacx_wave_speeds", "sacx_wave_speeds_max", "sacx_set_spacing",
+    "sacx_domain_buffer_size", "sacx_domain_create", "sacx_domain_advance", "sacx_domain_destroy",
     "sacx_profile_enable", "sacx_profile_read", "sacx_set_launch", "sacx_get_launch", "sacx_set_column_split",
     "sacx_batch_workspace_size", "sacx_batch_create", "sacx_batch_destroy", "sacx_batch_context",
     "sacx_batch_set_tiles", "sacx_batch_advance",
@@ -131,6 +132,11 @@ def load_library():
     lib.sacx_fill_boundaries.argtypes = [P, ctypes.c_int32]
     lib.sacx_stage.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.sacx_wave_speeds_max.argtypes = [P, P]
+    lib.sacx_domain_buffer_size.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(P), ctypes.POINTER(ctypes.c_size_t)]
+    lib.sacx_domain_create.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(P), P, ctypes.c_size_t,
+                                       ctypes.POINTER(P)]
+    lib.sacx_domain_advance.argtypes = [P, ctypes.c_int32]
+    lib.sacx_domain_destroy.argtypes = [P]
     lib.sacx_wave_speeds.argtypes = [P, ctypes.POINTER(ctypes.c_double)]
     lib.sacx_set_spacing.argtypes = [P, ctypes.c_double, ctypes.c_double]
     lib.sacx_profile_enable.argtypes = [P, ctypes.c_int32]

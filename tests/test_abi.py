@@ -170,3 +170,8 @@ def test_stage_calls_reject_null_context(sx):
     assert lib.sacx_wave_speeds_max(None, c) == sx.EINVAL
     assert lib.sacx_set_spacing(None, 0.1, 0.1) == sx.EINVAL
     assert lib.sacx_init_problem(None, 0, None, 0, 0.0) == sx.EINVAL
+    n = ctypes.c_size_t(0)
+    assert lib.sacx_domain_buffer_size(0, 1, None, ctypes.byref(n)) == sx.EINVAL
+    assert lib.sacx_domain_buffer_size(1, 1, None, ctypes.byref(n)) == sx.EINVAL
+    assert lib.sacx_domain_advance(None, 1) == sx.EINVAL
+    assert lib.sacx_domain_destroy(None) == 0

@@ -35,20 +35,21 @@ def _whole(prob, nsteps, **kw):
     return f, d
 
 
-def _decomposed(prob, xcuts, ycuts, nsteps, device_max=True, **kw):
+def _decomposed(prob, xcuts, ycuts, nsteps, device_max=True, native=True, **kw):
     from paper_1710_06423_amd import DecomposedSolver
     dec = DecomposedSolver(prob, xcuts, ycuts, **kw)
-    dec.advance(nsteps, device_max=device_max)
+    dec.advance(nsteps, device_max=device_max, native=native)
     f = dec.read_fields()
     d = dec.diagnostics()
     dec.close()
     return f, d
 
 
-def _check(torch, prob, xcuts, ycuts, nsteps, label, device_max=True, **kw):
-    print(f"case: {label} cuts x {xcuts} y {ycuts} steps {nsteps} device_max={device_max} {kw}", flush=True)
+def _check(torch, prob, xcuts, ycuts, nsteps, label, device_max=True, native=True, **kw):
+    print(f"case: {label} cuts x {xcuts} y {ycuts} steps {nsteps} device_max={device_max} native={native} {kw}",
+          flush=True)
     ref, dref = _whole(prob, nsteps, **kw)
-    got, dgot = _decomposed(prob, xcuts, ycuts, nsteps, device_max=device_max, **kw)
+    got, dgot = _decomposed(prob, xcuts, ycuts, nsteps, device_max=device_max, native=native, **kw)
     nd = int((got != ref).sum())
     print(f"[decomposed] {label}: {nd} elements differ", flush=True)
     assert nd == 0, label
@@ -64,9 +65,12 @@ def _check(torch, prob, xcuts, ycuts, nsteps, label, device_max=True, **kw):
     ([0, 3, 70, 128], [0, 96]),           # strips along x, one of 3 columns (the halo depth)
     ([0, 40, 80, 128], [0, 30, 66, 96]),  # 3 x 3
 ])
-def test_periodic_orszag_tang(xcuts, ycuts):
+@pytest.mark.parametrize("native", [True, False])
+def test_periodic_orszag_tang(xcuts, ycuts, native):
+    """Through the library's domain object (native) and through the
+    stage-level calls driven from Python."""
     torch = _torch()
-    _check(torch, W.orszag_tang(128, ny=96), xcuts, ycuts, 12, "OT periodic")
+    _check(torch, W.orszag_tang(128, ny=96), xcuts, ycuts, 12, "OT periodic", native=native)
 
 
 @pytest.mark.parametrize("device_max", [True, False])
@@ -90,10 +94,60 @@ def test_open_boundaries(bc):
     _check(torch, prob, [0, 41, 90], [0, 33, 70], 10, f"random smooth bc {bc}")
 
 
-def test_brio_wu_pieces():
+@pytest.mark.parametrize("native", [True, False])
+def test_brio_wu_pieces(native):
     """A 1-D shock tube cut into three pieces (open ends)."""
     torch = _torch()
-    _check(torch, W.brio_wu(800), [0, 250, 551, 800], [0, 1], 40, "Brio-Wu")
+    _check(torch, W.brio_wu(800), [0, 250, 551, 800], [0, 1], 40, "Brio-Wu", native=native)
+
+
+def test_domain_object_rejects_bad_layouts():
+    """sacx_domain_* argument checks: sides and strips that do not match, a
+    short or misaligned buffer, a step in progress."""
+    torch = _torch()
+    import ctypes
+    from paper_1710_06423_amd import EXCHANGE, OPEN, Solver, sacx
+    lib = sacx.load_library()
+    prob = W.orszag_tang(64, ny=40)
+
+    def sub(nx, ny, bc):
+        g = sacx.make_grid(nx, ny, 0.0, 1.0, 0.0, 1.0)
+        s = Solver(g, sacx.make_params(5 / 3), bc)
+        f = torch.stack([torch.from_numpy(prob.fields[k][:ny, :nx].copy()) for k in W.FIELDS]).cuda()
+        s.init_state(f)
+        return s
+
+    def size(subs, px, py):
+        arr = (ctypes.c_void_p * len(subs))(*[s.ctx.value for s in subs])
+        n = ctypes.c_size_t(0)
+        return lib.sacx_domain_buffer_size(px, py, arr, ctypes.byref(n)), n.value, arr
+
+    x2 = (EXCHANGE, EXCHANGE, 0, 0)
+    a, b = sub(32, 40, x2), sub(32, 40, x2)
+    rc, need, arr = size([a, b], 2, 1)
+    assert rc == sacx.OK and need > 0
+    buf = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    base = buf.data_ptr() + (-buf.data_ptr()) % 256
+    d = ctypes.c_void_p(None)
+    assert lib.sacx_domain_create(2, 1, arr, ctypes.c_void_p(base), need - 8, ctypes.byref(d)) == sacx.ENOSPC
+    assert lib.sacx_domain_create(2, 1, arr, ctypes.c_void_p(base + 8), need, ctypes.byref(d)) == sacx.EINVAL
+    assert lib.sacx_domain_create(2, 1, arr, ctypes.c_void_p(base), need, ctypes.byref(d)) == sacx.OK
+    a.stage(None)                                 # a step begun by hand ...
+    assert lib.sacx_domain_advance(d, 1) == sacx.ESTATE
+    for _ in range(3):
+        a.fill_boundaries(0)
+        a.fill_boundaries(1)
+        a.stage(None)                             # ... and finished
+    assert lib.sacx_domain_advance(d, 1) == sacx.OK
+    assert lib.sacx_domain_destroy(d) == sacx.OK
+    # an interior side that is not EXCHANGE; strips of different lengths; the same context twice
+    c = sub(32, 40, (OPEN, OPEN, 0, 0))
+    assert size([a, c], 2, 1)[0] == sacx.EINVAL
+    e = sub(32, 24, x2)
+    assert size([a, e], 2, 1)[0] == sacx.EINVAL
+    assert size([a, a], 2, 1)[0] == sacx.EINVAL
+    assert lib.sacx_domain_advance(None, 1) == sacx.EINVAL
+    assert lib.sacx_domain_destroy(None) == sacx.OK
 
 
 @pytest.mark.parametrize("variant", ["no_hd", "no_cross", "gravity", "one_thread_tile"])
