@@ -64,6 +64,7 @@ def _check(torch, prob, xcuts, ycuts, nsteps, label, device_max=True, native=Tru
     ([0, 128], [0, 31, 64, 96]),          # strips along y, x periodic locally
     ([0, 3, 70, 128], [0, 96]),           # strips along x, one of 3 columns (the halo depth)
     ([0, 40, 80, 128], [0, 30, 66, 96]),  # 3 x 3
+    ([0, 128], [0, 96]),                  # one subdomain: no exchange side at all
 ])
 @pytest.mark.parametrize("native", [True, False])
 def test_periodic_orszag_tang(xcuts, ycuts, native):
@@ -88,10 +89,12 @@ def test_periodic_matches_oracle(oracle_lib, device_max):
 @pytest.mark.parametrize("bc", [(OPEN, OPEN, 0, 0), (0, 0, OPEN, OPEN), (OPEN,) * 4])
 def test_open_boundaries(bc):
     """Open outer sides with exchange sides inside (the corners of a y strip
-    come from an x exchange next to an open fill)."""
+    come from an x exchange next to an open fill), and the same domain as a
+    single subdomain."""
     torch = _torch()
     prob = W.random_smooth(90, 70, seed=5, bc=bc)
     _check(torch, prob, [0, 41, 90], [0, 33, 70], 10, f"random smooth bc {bc}")
+    _check(torch, prob, [0, 90], [0, 70], 10, f"random smooth bc {bc}, one subdomain")
 
 
 @pytest.mark.parametrize("native", [True, False])
