@@ -282,15 +282,17 @@ int sacx_wave_speeds_max(sacx_ctx *ctx, double *d_c_max);
  * side that borders another subdomain is EXCHANGE, and so is the facing side
  * of the neighbour across every EXCHANGE side (across the domain's edge the
  * neighbour is the subdomain at the other end: a periodic domain); facing
- * strips have equal lengths.  A context of a domain is still the caller's
- * (destroy the domain first); its own calls keep working.
+ * strips have equal lengths; at most 4096 subdomains.  A context of a
+ * domain is still the caller's (destroy the domain first); its own calls
+ * keep working.
  *  sacx_domain_buffer_size: bytes of caller device memory the domain needs
  *    (one strip per EXCHANGE side and the maxima); host arithmetic.
  *  sacx_domain_create: d_buf (256-byte aligned, ENOSPC if smaller) must
  *    outlive the domain.
  *  sacx_domain_advance: enqueue nsteps steps of every subdomain on their
  *    stream (no synchronisation); ESTATE while a subdomain has a step begun
- *    with sacx_stage in progress.  A subdomain stopped by a non-physical state
+ *    with sacx_stage in progress or has other boundary kinds than when the
+ *    domain was created.  A subdomain stopped by a non-physical state
  *    stays stopped (sacx_diagnostics); the others go on.
  *  sacx_domain_destroy: releases the host object (NULL is a no-op). */
 typedef struct sacx_domain sacx_domain;

@@ -1845,6 +1845,7 @@ struct sacx_domain {
     std::vector<sacx_ctx *> *subs;            // row-major, px x py
     std::vector<std::array<void *, 4>> *buf;  // per subdomain and side: the strip it packs (exchange sides)
     std::vector<std::array<int, 4>> *nbr;     // per subdomain and side: the neighbour (exchange sides)
+    std::vector<std::array<int, 4>> *bc;      // per subdomain: the boundary kinds the layout was checked with
     double *cmax;                             // the whole domain's wave-speed maxima (device)
 };
 
@@ -1853,7 +1854,7 @@ extern "C" {
 // checks shared by the size query and creation; on success *bytes is the
 // caller memory the domain needs
 static int domain_check(int32_t px, int32_t py, sacx_ctx *const *subs, size_t *bytes) {
-    if (px < 1 || py < 1 || (int64_t)px * py > 65536) return fail(SACX_EINVAL, "px, py must be >= 1 (at most 65536 subdomains)");
+    if (px < 1 || py < 1 || (int64_t)px * py > 4096) return fail(SACX_EINVAL, "px, py must be >= 1 (at most 4096 subdomains)");
     if (!subs || !bytes) return fail(SACX_EINVAL, "subs/bytes must not be NULL");
     const int n = px * py;
     for (int i = 0; i < n; ++i) {
@@ -1917,7 +1918,8 @@ int sacx_domain_create(int32_t px, int32_t py, sacx_ctx *const *subs, void *d_bu
     d->subs = new (std::nothrow) std::vector<sacx_ctx *>(subs, subs + (size_t)px * py);
     d->buf = new (std::nothrow) std::vector<std::array<void *, 4>>((size_t)px * py);
     d->nbr = new (std::nothrow) std::vector<std::array<int, 4>>((size_t)px * py);
-    if (!d->subs || !d->buf || !d->nbr) {
+    d->bc = new (std::nothrow) std::vector<std::array<int, 4>>((size_t)px * py);
+    if (!d->subs || !d->buf || !d->nbr || !d->bc) {
         sacx_domain_destroy(d);
         return fail(SACX_EINVAL, "out of host memory");
     }
@@ -1930,6 +1932,7 @@ int sacx_domain_create(int32_t px, int32_t py, sacx_ctx *const *subs, void *d_bu
             for (int side = 0; side < 4; ++side) {
                 (*d->buf)[i][side] = nullptr;
                 (*d->nbr)[i][side] = -1;
+                (*d->bc)[i][side] = subs[i]->bc[side];
                 if (subs[i]->bc[side] != SACX_EXCHANGE) continue;
                 size_t sb = 0;
                 sacx_halo_buffer_size(subs[i], side, &sb);
@@ -1947,6 +1950,7 @@ int sacx_domain_destroy(sacx_domain *d) {
     delete d->subs;
     delete d->buf;
     delete d->nbr;
+    delete d->bc;
     delete d;
     return SACX_OK;
 }
@@ -1978,6 +1982,9 @@ int sacx_domain_advance(sacx_domain *d, int32_t nsteps) {
     for (int i = 0; i < n; ++i) {
         const sacx_ctx *c = (*d->subs)[i];
         if (c->stage_next) return fail(SACX_ESTATE, "subdomain %d has a step in progress", i);
+        for (int side = 0; side < 4; ++side)
+            if (c->bc[side] != (*d->bc)[i][side])
+                return fail(SACX_ESTATE, "subdomain %d changed its boundaries after the domain was created", i);
         if (c->sur_on) return fail(SACX_ESTATE, "subdomain %d has a learned coefficient", i);
     }
     sacx_ctx *c0 = (*d->subs)[0];

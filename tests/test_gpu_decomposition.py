@@ -142,6 +142,10 @@ def test_domain_object_rejects_bad_layouts():
         a.fill_boundaries(1)
         a.stage(None)                             # ... and finished
     assert lib.sacx_domain_advance(d, 1) == sacx.OK
+    b.set_boundaries((EXCHANGE, EXCHANGE, OPEN, OPEN))   # no longer the layout the domain checked
+    assert lib.sacx_domain_advance(d, 1) == sacx.ESTATE
+    b.set_boundaries(x2)
+    assert lib.sacx_domain_advance(d, 1) == sacx.OK
     assert lib.sacx_domain_destroy(d) == sacx.OK
     # an interior side that is not EXCHANGE; strips of different lengths; the same context twice
     c = sub(32, 40, (OPEN, OPEN, 0, 0))
