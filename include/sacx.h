@@ -177,8 +177,9 @@ int sacx_init_problem(sacx_ctx *ctx, int32_t kind, const double *prm, int32_t np
 
 /* Enqueue up to nsteps RK4 steps (paper section 2; one step = 4 stages,
  * each preceded by a halo exchange).  ESTATE for a context with an EXCHANGE
- * side or while a step begun with sacx_stage is in progress.  t_end <= 0: no end time.  Otherwise
- * dt = min(dt, t_end - t) and stepping stops once t_end - t <= 1e-12 t_end.
+ * side or while a step begun with sacx_stage is in progress.  t_end <= 0: no
+ * end time.  Otherwise dt = min(dt, t_end - t) and stepping stops once
+ * t_end - t <= 1e-12 t_end.
  * A step whose start state is non-physical is not taken, and neither is any
  * later one; that state is kept.  If steps_done or t_now is non-NULL the call
  * synchronises the stream, fills them (steps taken by this call, current
@@ -207,9 +208,10 @@ int sacx_diagnostics(sacx_ctx *ctx, sacx_diag *out);
  * pack copies the G interior rows/columns next to `side` of the state the
  * next stage differences (the current state between steps; during a step
  * begun with sacx_stage, the intermediate state of the stage about to run);
- * unpack writes the G ghost rows/columns of `side` of that same state.  For a periodic
- * neighbour, the buffer packed at x- is the one unpacked at x+.  Buffers are
- * caller-owned device memory in the context precision; sizes in bytes.
+ * unpack writes the G ghost rows/columns of `side` of that same state.  For
+ * a periodic neighbour, the buffer packed at x- is the one unpacked at x+.
+ * Buffers are caller-owned device memory in the context precision; sizes in
+ * bytes.
  * EUNSUP if that direction has fewer than G interior cells. */
 int sacx_halo_buffer_size(const sacx_ctx *ctx, int32_t side, size_t *bytes);
 int sacx_halo_pack(sacx_ctx *ctx, int32_t side, void *d_buf);
