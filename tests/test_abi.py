@@ -5,6 +5,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -175,3 +176,23 @@ def test_stage_calls_reject_null_context(sx):
     assert lib.sacx_domain_buffer_size(1, 1, None, ctypes.byref(n)) == sx.EINVAL
     assert lib.sacx_domain_advance(None, 1) == sx.EINVAL
     assert lib.sacx_domain_destroy(None) == 0
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built HIP library the binding raises; nothing falls back
+    to another implementation."""
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_1710_06423_amd.sacx as sx\n"
+        "sx.LIB_PATH = %r\n"
+        "sx._lib = None\n"
+        "try:\n"
+        "    sx.load_library()\n"
+        "except RuntimeError as e:\n"
+        "    print('raised:', e)\n"
+        "    sys.exit(0)\n"
+        "sys.exit(1)\n"
+    ) % (ROOT, str(tmp_path / "libsacx.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, (r.stdout, r.stderr)
+    assert "missing" in r.stdout
