@@ -1955,23 +1955,66 @@ int sacx_domain_destroy(sacx_domain *d) {
     return SACX_OK;
 }
 
+// both strips of one direction of a context's stage input in one launch
+// (the two-sided form of the pack / unpack kernels): b0 for the low side,
+// b1 for the high side
+static int halo_io_both(sacx_ctx *ctx, int dir, void *b0, void *b1, bool pack) {
+    ProfScope ps(ctx, 4);
+    const Layout &L = ctx->L;
+    const int T = 256;
+    void *const *S = stage_input(ctx);
+    const bool f64 = ctx->grid.precision == SACX_FP64;
+    const int along = dir == 0 ? L.ny : L.nx + 2 * G;
+    dim3 g((along + T - 1) / T, NF, 2);
+    const DevScalars *none = nullptr;
+    if (dir == 0) {
+        if (f64) {
+            if (pack) hipLaunchKernelGGL(k_pack_x<double>, g, dim3(T), 0, ctx->stream, fptr<double>(S, NF), NF, L, (double *)b0, (double *)b1, 2, none);
+            else hipLaunchKernelGGL(k_unpack_x<double>, g, dim3(T), 0, ctx->stream, fptr<double>(S, NF), NF, L, (const double *)b0, (const double *)b1, 2, none);
+        } else {
+            if (pack) hipLaunchKernelGGL(k_pack_x<float>, g, dim3(T), 0, ctx->stream, fptr<float>(S, NF), NF, L, (float *)b0, (float *)b1, 2, none);
+            else hipLaunchKernelGGL(k_unpack_x<float>, g, dim3(T), 0, ctx->stream, fptr<float>(S, NF), NF, L, (const float *)b0, (const float *)b1, 2, none);
+        }
+    } else {
+        if (f64) {
+            if (pack) hipLaunchKernelGGL(k_pack_y<double>, g, dim3(T), 0, ctx->stream, fptr<double>(S, NF), NF, L, (double *)b0, (double *)b1, 2, none);
+            else hipLaunchKernelGGL(k_unpack_y<double>, g, dim3(T), 0, ctx->stream, fptr<double>(S, NF), NF, L, (const double *)b0, (const double *)b1, 2, none);
+        } else {
+            if (pack) hipLaunchKernelGGL(k_pack_y<float>, g, dim3(T), 0, ctx->stream, fptr<float>(S, NF), NF, L, (float *)b0, (float *)b1, 2, none);
+            else hipLaunchKernelGGL(k_unpack_y<float>, g, dim3(T), 0, ctx->stream, fptr<float>(S, NF), NF, L, (const float *)b0, (const float *)b1, 2, none);
+        }
+    }
+    HIPCHK(hipGetLastError());
+    return SACX_OK;
+}
+
 // one direction's exchange: every subdomain packs its exchange strips, then
-// unpacks the strips its neighbours packed facing it
+// unpacks the strips its neighbours packed facing it (both sides of the
+// direction in one launch where both are exchange sides)
 static int domain_exchange(sacx_domain *d, int dir) {
     const int n = d->px * d->py;
-    for (int i = 0; i < n; ++i)
-        for (int side = 2 * dir; side < 2 * dir + 2; ++side)
-            if ((*d->buf)[i][side]) {
-                int rc = sacx_halo_pack((*d->subs)[i], side, (*d->buf)[i][side]);
-                if (rc) return rc;
-            }
-    for (int i = 0; i < n; ++i)
-        for (int side = 2 * dir; side < 2 * dir + 2; ++side)
-            if ((*d->buf)[i][side]) {
-                const int j = (*d->nbr)[i][side];
-                int rc = sacx_halo_unpack((*d->subs)[i], side, (*d->buf)[j][side ^ 1]);
-                if (rc) return rc;
-            }
+    const int lo = 2 * dir, hi = 2 * dir + 1;
+    for (int i = 0; i < n; ++i) {
+        sacx_ctx *c = (*d->subs)[i];
+        void *const *b = (*d->buf)[i].data();
+        int rc = SACX_OK;
+        if (b[lo] && b[hi]) rc = halo_io_both(c, dir, b[lo], b[hi], true);
+        else if (b[lo]) rc = sacx_halo_pack(c, lo, b[lo]);
+        else if (b[hi]) rc = sacx_halo_pack(c, hi, b[hi]);
+        if (rc) return rc;
+    }
+    for (int i = 0; i < n; ++i) {
+        sacx_ctx *c = (*d->subs)[i];
+        void *const *b = (*d->buf)[i].data();
+        // the strip a side receives is the one its neighbour packed facing it
+        void *from_lo = b[lo] ? (*d->buf)[(*d->nbr)[i][lo]][hi] : nullptr;
+        void *from_hi = b[hi] ? (*d->buf)[(*d->nbr)[i][hi]][lo] : nullptr;
+        int rc = SACX_OK;
+        if (from_lo && from_hi) rc = halo_io_both(c, dir, from_lo, from_hi, false);
+        else if (from_lo) rc = sacx_halo_unpack(c, lo, from_lo);
+        else if (from_hi) rc = sacx_halo_unpack(c, hi, from_hi);
+        if (rc) return rc;
+    }
     return SACX_OK;
 }
 
