@@ -77,3 +77,27 @@ def test_graph_needs_its_own_stream_and_no_profiling():
     t.graph(1).replay()
     torch.cuda.synchronize()
     assert t.diagnostics()["steps"] == 1
+
+
+def test_tensors_shared_across_streams_are_ordered():
+    """A context on its own stream reads inputs that kernels on the caller's
+    stream have just produced, and hands back outputs the caller's stream
+    reads at once: the binding orders the two streams both ways."""
+    torch = _torch()
+    from paper_1710_06423_amd import Solver
+    prob = W.orszag_tang(512, ny=384)
+    ref = Solver.from_problem(prob)
+    ref.advance(3)
+    side = Solver.from_problem(prob, stream=torch.cuda.Stream(), init=False)
+    host = torch.stack([torch.from_numpy(prob.fields[k]) for k in W.FIELDS])
+    for rep in range(3):
+        # produced by a chain of kernels on the caller's (default) stream,
+        # each exact (scaling by powers of two), so f equals the host arrays
+        f = host.cuda() * 2.0
+        for _ in range(20):
+            f = f * 1.0
+        f = f * 0.5
+        side.init_state(f)
+        side.advance(3, sync=False)
+        out = side.read_fields()
+        assert torch.equal(out * 1.0, ref.read_fields()), rep
