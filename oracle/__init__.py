@@ -24,7 +24,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sacx_oracle.c")
-_LIB = os.path.join(_HERE, "libsacx_oracle.so")
+# SACX_ORACLE_LIB points the tests at another build of the same source (the
+# mutation test builds copies with planted mistakes and runs the pins on them)
+_LIB = os.environ.get("SACX_ORACLE_LIB") or os.path.join(_HERE, "libsacx_oracle.so")
 
 FIELDS = ("rho", "mx", "my", "e", "bx", "by")
 BACKGROUND_FIELDS = ("rho_b", "e_b", "bx_b", "by_b")
@@ -36,6 +38,15 @@ ENOMEM = -7
 
 PERIODIC = 0
 OPEN = 1
+
+# Arithmetic forms of the scheme (see sacx_oracle.c).  PAPER defines the
+# oracle: classic RK4 combined as printed from four kept right-hand sides,
+# every division written as a division.  LOWSTORE is the algebraically equal
+# four-array arrangement with reciprocals of the grid constants, rho and
+# gamma - 1; a device implementation that follows that operation sequence can
+# be compared with it bit for bit.  The CPU pins tie the two together.
+PAPER = 0
+LOWSTORE = 1
 
 # Hyper-diffusion constants (our choice; the paper gives none).  Order of the
 # classes: density, thermal energy, velocity, magnetic field.
@@ -65,6 +76,7 @@ class _Cfg(ctypes.Structure):
         ("bc", ctypes.c_int * 4),
         ("background_on", ctypes.c_int),
         ("g", ctypes.c_double * 2),
+        ("form", ctypes.c_int),
     ]
 
 
@@ -124,7 +136,7 @@ def _c64(a) -> np.ndarray:
 
 def make_cfg(prob, cfl: float = 0.3, hd_on: bool = True, hd_cross_on: bool = True,
              c2: Sequence[float] = DEFAULT_C2, cshk: Sequence[float] = DEFAULT_CSHK,
-             gamma: Optional[float] = None) -> _Cfg:
+             gamma: Optional[float] = None, form: int = PAPER) -> _Cfg:
     c = _Cfg()
     c.nx, c.ny = prob.nx, prob.ny
     c.x0, c.x1, c.y0, c.y1 = prob.x0, prob.x1, prob.y0, prob.y1
@@ -137,6 +149,9 @@ def make_cfg(prob, cfl: float = 0.3, hd_on: bool = True, hd_cross_on: bool = Tru
     c.bc = (ctypes.c_int * 4)(*prob.bc)
     c.background_on = int(prob.background is not None)
     c.g = (ctypes.c_double * 2)(*getattr(prob, "g", (0.0, 0.0)))
+    if form not in (PAPER, LOWSTORE):
+        raise ValueError(f"unknown arithmetic form {form!r}")
+    c.form = form
     return c
 
 
@@ -144,9 +159,10 @@ class State:
     """An oracle run: the problem, the scheme constants and the current state."""
 
     def __init__(self, prob, cfl: float = 0.3, hd_on: bool = True, hd_cross_on: bool = True,
-                 c2: Sequence[float] = DEFAULT_C2, cshk: Sequence[float] = DEFAULT_CSHK):
+                 c2: Sequence[float] = DEFAULT_C2, cshk: Sequence[float] = DEFAULT_CSHK,
+                 form: int = PAPER):
         self.prob = prob
-        self.cfg = make_cfg(prob, cfl, hd_on, hd_cross_on, c2, cshk)
+        self.cfg = make_cfg(prob, cfl, hd_on, hd_cross_on, c2, cshk, form=form)
         self.f = [_c64(prob.fields[k]).copy() for k in FIELDS]
         self.bg = None
         if prob.background is not None:

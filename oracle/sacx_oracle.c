@@ -56,6 +56,27 @@ enum { C_RHO = 0, C_EPS = 1, C_V = 2, C_B = 3 };
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENONPHYS = -4, ORC_ENOMEM = -7 };
 enum { ORC_PERIODIC = 0, ORC_OPEN = 1 };
 
+/* Two arithmetic forms of the same scheme.
+ *
+ * ORC_FORM_PAPER defines the oracle: classic RK4 combined as printed,
+ * U+ = U + dt/6 (K1 + 2 K2 + 2 K3 + K4) from four kept right-hand sides, and
+ * every division of the scheme (by 12h, 2h, h, rho, gamma - 1) done as a
+ * division.
+ *
+ * ORC_FORM_LOWSTORE is an algebraically equal rearrangement that needs only
+ * four state arrays (U, the stage input S, an accumulator A, and the current
+ * K): the same stage inputs, the final combine as
+ *   A = 2U + ((S1 - U) + dt K2),   U+ = S3 + (A - 2 S3)/3 + dt/6 K4,
+ * and divisions by grid constants, by rho and by gamma - 1 done as
+ * multiplications by a reciprocal formed once.  It is a second, fixed IEEE
+ * operation sequence: the hyper-diffusion coefficient (a ratio of maxima)
+ * amplifies rounding-order differences from one step to the next, so two
+ * algebraically equal forms drift apart far above 1e-12 within 100 steps of a
+ * shock-forming run.  A device implementation that follows this sequence
+ * exactly can be compared with it bit for bit; the CPU tests tie it to the
+ * paper form (many steps without hyper-diffusion, a few with it). */
+enum { ORC_FORM_PAPER = 0, ORC_FORM_LOWSTORE = 1 };
+
 typedef struct {
     int nx, ny;
     double x0, x1, y0, y1;
@@ -66,9 +87,10 @@ typedef struct {
     int bc[4];      /* x-, x+, y-, y+ */
     int background_on;
     double g[2];    /* gravity (section 2 sources rho g, rho g.v), acting on rho~ */
+    int form;       /* ORC_FORM_PAPER (the definition) or ORC_FORM_LOWSTORE */
 } orc_cfg;
 
-int orc_abi_version(void) { return 2; }
+int orc_abi_version(void) { return 3; }
 
 /* ------------------------------------------------------------------ */
 /* small helpers                                                       */
@@ -109,6 +131,7 @@ static int cfg_ok(const orc_cfg *c) {
     for (int s = 0; s < 4; ++s)
         if (c->bc[s] != ORC_PERIODIC && c->bc[s] != ORC_OPEN) return 0;
     if (!isfinite(c->g[0]) || !isfinite(c->g[1])) return 0;
+    if (c->form != ORC_FORM_PAPER && c->form != ORC_FORM_LOWSTORE) return 0;
     if ((c->bc[0] == ORC_PERIODIC) != (c->bc[1] == ORC_PERIODIC)) return 0;
     if ((c->bc[2] == ORC_PERIODIC) != (c->bc[3] == ORC_PERIODIC)) return 0;
     return 1;
@@ -148,14 +171,22 @@ static void fill_ghosts_one(double *a, int nx, int ny, const int bc[4]) {
 }
 
 /* ------------------------------------------------------------------ */
-/* the fourth-order central difference (section 2)                     */
-/*   D f_i = [8 (f_{i+1} - f_{i-1}) - (f_{i+2} - f_{i-2})] / (12 h)     */
-/* (every division by a grid constant is a multiplication by its       */
-/* reciprocal, computed once: 1/(12h), 1/(2h), 1/h, 1/(gamma-1))        */
+/* x / d: a division in the paper form; in the low-storage form a      */
+/* multiplication by the reciprocal inv_d = 1/d formed once            */
 /* ------------------------------------------------------------------ */
 
-static double d4(const double *f, ptrdiff_t i, ptrdiff_t st, double inv12h) {
-    return (8.0 * (f[i + st] - f[i - st]) - (f[i + 2 * st] - f[i - 2 * st])) * inv12h;
+static double over(int paper, double x, double d, double inv_d) {
+    return paper ? x / d : x * inv_d;
+}
+
+/* ------------------------------------------------------------------ */
+/* the fourth-order central difference (section 2)                     */
+/*   D f_i = [8 (f_{i+1} - f_{i-1}) - (f_{i+2} - f_{i-2})] / (12 h)     */
+/* h12 = 12 h, inv12h = 1/(12 h)                                       */
+/* ------------------------------------------------------------------ */
+
+static double d4(int paper, const double *f, ptrdiff_t i, ptrdiff_t st, double h12, double inv12h) {
+    return over(paper, 8.0 * (f[i + st] - f[i - st]) - (f[i + 2 * st] - f[i - 2 * st]), h12, inv12h);
 }
 
 /* ------------------------------------------------------------------ */
@@ -188,6 +219,7 @@ static double hd_ratio(const double *q, ptrdiff_t i, ptrdiff_t st) {
 
 typedef struct {
     double dx, dy, gamma;
+    int paper;      /* 1: ORC_FORM_PAPER arithmetic, 0: ORC_FORM_LOWSTORE */
     int hd_on, hd_cross_on, bg_on;
     double c2[4], cshk[4];
     double g[2];
@@ -217,11 +249,13 @@ static double ratio_or_ext(const rhs_par *P, int plane, int i, int j, const doub
 static int rhs_block(int nxe, int nye, double *const S[NF], double *const BG[NB],
                      const rhs_par *P, double cmax, double *const K[NF]) {
     const size_t n = (size_t)nxe * nye;
+    const int pf = P->paper;
     const double gm1 = P->gamma - 1.0;
     const double igm1 = 1.0 / gm1;
     const double dx = P->dx, dy = P->dy;
-    const double i12dx = 1.0 / (12.0 * dx), i12dy = 1.0 / (12.0 * dy);
-    const double i2dx = 1.0 / (2.0 * dx), i2dy = 1.0 / (2.0 * dy);
+    const double h12x = 12.0 * dx, h12y = 12.0 * dy, h2x = 2.0 * dx, h2y = 2.0 * dy;
+    const double i12dx = 1.0 / h12x, i12dy = 1.0 / h12y;
+    const double i2dx = 1.0 / h2x, i2dy = 1.0 / h2y;
     const double idx = 1.0 / dx, idy = 1.0 / dy;
     int rc = ORC_OK;
 
@@ -252,7 +286,7 @@ static int rhs_block(int nxe, int nye, double *const S[NF], double *const BG[NB]
             double bxt = S[F_BX][c], byt = S[F_BY][c];
             double r = rb + rt;
             double ir = 1.0 / r;
-            double ux = mx * ir, uy = my * ir;
+            double ux = over(pf, mx, r, ir), uy = over(pf, my, r, ir);
             double kin = 0.5 * (mx * ux + my * uy);          /* rho v^2 / 2 */
             double bbdot = bxb * bxt + byb * byt;            /* B_b . B~ */
             double bt2 = bxt * bxt + byt * byt;              /* |B~|^2 */
@@ -261,7 +295,7 @@ static int rhs_block(int nxe, int nye, double *const S[NF], double *const BG[NB]
             bxT[c] = bxb + bxt; byT[c] = byb + byt;
             pkt[c] = pk;
             ptt[c] = (pk + 0.5 * bt2) + bbdot;                /* p~_t */
-            epst[c] = pk * igm1;                              /* thermal energy perturbation */
+            epst[c] = over(pf, pk, gm1, igm1);                /* thermal energy perturbation */
             if (P->bg_on) {
                 double b2b = bxb * bxb + byb * byb;
                 double pkb = gm1 * (eb - 0.5 * b2b);
@@ -297,14 +331,16 @@ static int rhs_block(int nxe, int nye, double *const S[NF], double *const BG[NB]
                 continue;
             }
             for (int k = 0; k < NF; ++k) {
-                double ddx = d4(Fx[k], (ptrdiff_t)c, 1, i12dx);
-                double ddy = d4(Fy[k], (ptrdiff_t)c, nxe, i12dy);
+                double ddx = d4(pf, Fx[k], (ptrdiff_t)c, 1, h12x, i12dx);
+                double ddy = d4(pf, Fy[k], (ptrdiff_t)c, nxe, h12y, i12dy);
                 K[k][c] = -(ddx + ddy);
             }
             if (P->bg_on) {
                 /* e~ gets -p_tb div v + sum_kl B_bk B_bl d_k v_l (non-conservative) */
-                double dxvx = d4(vx, (ptrdiff_t)c, 1, i12dx), dyvy = d4(vy, (ptrdiff_t)c, nxe, i12dy);
-                double dxvy = d4(vy, (ptrdiff_t)c, 1, i12dx), dyvx = d4(vx, (ptrdiff_t)c, nxe, i12dy);
+                double dxvx = d4(pf, vx, (ptrdiff_t)c, 1, h12x, i12dx);
+                double dyvy = d4(pf, vy, (ptrdiff_t)c, nxe, h12y, i12dy);
+                double dxvy = d4(pf, vy, (ptrdiff_t)c, 1, h12x, i12dx);
+                double dyvx = d4(pf, vx, (ptrdiff_t)c, nxe, h12y, i12dy);
                 double bxb = BG[B_BX][c], byb = BG[B_BY][c];
                 double bb = (bxb * bxb * dxvx + byb * byb * dyvy) + (bxb * byb * dxvy + byb * bxb * dyvx);
                 K[F_E][c] = K[F_E][c] + (bb - ptb[c] * (dxvx + dyvy));
@@ -329,7 +365,7 @@ static int rhs_block(int nxe, int nye, double *const S[NF], double *const BG[NB]
     for (int j = 1; j < nye - 1; ++j) {
         for (int i = 1; i < nxe - 1; ++i) {
             size_t c = (size_t)i + (size_t)j * nxe;
-            double dv = (vx[c + 1] - vx[c - 1]) * i2dx + (vy[c + nxe] - vy[c - nxe]) * i2dy;
+            double dv = over(pf, vx[c + 1] - vx[c - 1], h2x, i2dx) + over(pf, vy[c + nxe] - vy[c - nxe], h2y, i2dy);
             s[c] = dmax(0.0, -dv);
         }
     }
@@ -350,7 +386,7 @@ static int rhs_block(int nxe, int nye, double *const S[NF], double *const BG[NB]
                 for (int k = 0; k < 5; ++k) {
                     double R = ratio_or_ext(P, k, i, j, qx[k], (ptrdiff_t)c, 1);
                     double nu = P->c2[cls[k]] * dx * cmax * R + P->cshk[cls[k]] * dx * dx * sf;
-                    Gx[k][c] = nu * d1_at(qx[k], (ptrdiff_t)c, 1) * idx;
+                    Gx[k][c] = over(pf, nu * d1_at(qx[k], (ptrdiff_t)c, 1), dx, idx);
                 }
             }
         }
@@ -362,7 +398,7 @@ static int rhs_block(int nxe, int nye, double *const S[NF], double *const BG[NB]
                 for (int k = 0; k < 5; ++k) {
                     double R = ratio_or_ext(P, 5 + k, i, j, qy[k], (ptrdiff_t)c, nxe);
                     double nu = P->c2[cls[k]] * dy * cmax * R + P->cshk[cls[k]] * dy * dy * sf;
-                    Gy[k][c] = nu * d1_at(qy[k], (ptrdiff_t)c, nxe) * idy;
+                    Gy[k][c] = over(pf, nu * d1_at(qy[k], (ptrdiff_t)c, nxe), dy, idy);
                 }
             }
         }
@@ -429,7 +465,7 @@ static int rhs_block(int nxe, int nye, double *const S[NF], double *const BG[NB]
         for (int i = G; i < nxe - G; ++i) {
             size_t c = (size_t)i + (size_t)j * nxe;
             for (int k = 0; k < NF; ++k) {
-                double hd = (Hx[k][c] - Hx[k][c - 1]) * idx + (Hy[k][c] - Hy[k][c - nxe]) * idy;
+                double hd = over(pf, Hx[k][c] - Hx[k][c - 1], dx, idx) + over(pf, Hy[k][c] - Hy[k][c - nxe], dy, idy);
                 K[k][c] = K[k][c] + hd;
             }
         }
@@ -447,6 +483,7 @@ static void make_rhs_par(const orc_cfg *c, rhs_par *P) {
     P->dx = (c->x1 - c->x0) / c->nx;
     P->dy = (c->y1 - c->y0) / c->ny;
     P->gamma = c->gamma;
+    P->paper = c->form == ORC_FORM_PAPER;
     P->hd_on = c->hd_on;
     P->hd_cross_on = c->hd_cross_on;
     P->bg_on = c->background_on;
@@ -468,6 +505,7 @@ static void make_rhs_par(const orc_cfg *c, rhs_par *P) {
 
 static int wavespeed_ext(const orc_cfg *cfg, double *const U[NF], double *const BG[NB],
                          int nxe, int i0, int i1, int j0, int j1, double out[3]) {
+    const int pf = cfg->form == ORC_FORM_PAPER;
     const double gm1 = cfg->gamma - 1.0;
     double cx = 0.0, cy = 0.0;
     int bad = 0;
@@ -481,7 +519,7 @@ static int wavespeed_ext(const orc_cfg *cfg, double *const U[NF], double *const 
             double bxt = U[F_BX][c], byt = U[F_BY][c];
             double r = rb + rt;
             double ir = 1.0 / r;
-            double ux = mx * ir, uy = my * ir;
+            double ux = over(pf, mx, r, ir), uy = over(pf, my, r, ir);
             double kin = 0.5 * (mx * ux + my * uy);
             double bbdot = bxb * bxt + byb * byt;
             double bt2 = bxt * bxt + byt * byt;
@@ -490,7 +528,7 @@ static int wavespeed_ext(const orc_cfg *cfg, double *const U[NF], double *const 
             double pkb = gm1 * (eb - 0.5 * b2b);
             double pk = pkb + pkt;
             double bx = bxb + bxt, by = byb + byt;
-            double cf = sqrt((cfg->gamma * pk + (bx * bx + by * by)) * ir);
+            double cf = sqrt(over(pf, cfg->gamma * pk + (bx * bx + by * by), r, ir));
             int finite = isfinite(rt) && isfinite(mx) && isfinite(my) && isfinite(et) &&
                          isfinite(bxt) && isfinite(byt) && isfinite(cf);
             if (!(r > 0.0) || !(pk > 0.0) || !finite) { bad = 1; continue; }
@@ -524,13 +562,13 @@ typedef struct {
     orc_cfg cfg;
     rhs_par par;
     int nx, ny, nxe, nye;
-    block U, S, A, K[1];
+    block U, S, A, K[4];   /* A: low-storage form only; K[1..3]: paper form only */
     double *BG[NB];
 } dom;
 
 static void dom_free(dom *d) {
     block_free(&d->U); block_free(&d->S); block_free(&d->A);
-    block_free(&d->K[0]);
+    for (int s = 0; s < 4; ++s) block_free(&d->K[s]);
     for (int k = 0; k < NB; ++k) { free(d->BG[k]); d->BG[k] = NULL; }
 }
 
@@ -542,8 +580,12 @@ static int dom_init(dom *d, const orc_cfg *cfg, double *const f[NF], double *con
     d->nxe = cfg->nx + 2 * G; d->nye = cfg->ny + 2 * G;
     int rc = block_alloc(&d->U, d->nxe, d->nye);
     if (!rc) rc = block_alloc(&d->S, d->nxe, d->nye);
-    if (!rc) rc = block_alloc(&d->A, d->nxe, d->nye);
     if (!rc) rc = block_alloc(&d->K[0], d->nxe, d->nye);
+    if (cfg->form == ORC_FORM_PAPER) {
+        for (int s = 1; s < 4 && !rc; ++s) rc = block_alloc(&d->K[s], d->nxe, d->nye);
+    } else if (!rc) {
+        rc = block_alloc(&d->A, d->nxe, d->nye);
+    }
     if (!rc && cfg->background_on) {
         for (int k = 0; k < NB; ++k) {
             d->BG[k] = alloc0((size_t)d->nxe * d->nye);
@@ -577,55 +619,72 @@ static void fill_block(dom *d, block *b) {
     for (int k = 0; k < NF; ++k) fill_ghosts_one(b->f[k], d->nx, d->ny, d->cfg.bc);
 }
 
-/* one classic RK4 step (section 2), K_s = L(S_{s-1}):
- *   S1 = U + dt/2 K1
- *   S2 = U + dt/2 K2,   A = 2U + ((S1 - U) + dt K2)
- *   S3 = U + dt K3
- *   U+ = S3 + (A - 2 S3)/3 + dt/6 K4
- * which is U + dt/6 (K1 + 2 K2 + 2 K3 + K4) rearranged so that only U, S, A
- * and the current K are needed (the GPU keeps four state arrays); a state
- * with L = 0 is reproduced exactly.  The halo is refilled before every L.
- * This arrangement is fixed here because the hyper-diffusion coefficient
- * (a ratio of maxima) amplifies rounding differences: two arithmetically
- * different but algebraically equal orderings drift apart far above 1e-12
- * within 100 steps, so the device path reproduces this exact sequence of
- * IEEE operations (no fused multiply-add on either side). */
-static void rk_stage_combine(dom *d, int stage, double dt, const block *K) {
-    const double hdt = 0.5 * dt, dt6 = dt / 6.0, third = 1.0 / 3.0;
+/* One classic RK4 step (section 2).  With K_s the right-hand side of the
+ * s-th stage input (the halo refilled before every L):
+ *   K1 = L(U),  K2 = L(U + dt/2 K1),  K3 = L(U + dt/2 K2),  K4 = L(U + dt K3)
+ *   U+ = U + dt/6 (K1 + 2 K2 + 2 K3 + K4)
+ * The paper form keeps the four K and combines them as written.  The
+ * low-storage form builds the same stage inputs and folds the combine into
+ *   A = 2U + ((S1 - U) + dt K2)       (stage 2, while S1 is still held)
+ *   U+ = S3 + (A - 2 S3)/3 + dt/6 K4  (stage 4)
+ * which is the same polynomial in dt (A - 2 S3 = dt (K1 + 2 K2 - 2 K3)/2, so
+ * U+ = U + dt K3 + dt (K1 + 2 K2 - 2 K3)/6 + dt K4/6). */
+static void rk_stage_input(dom *d, int stage, double dt, const block *K) {
+    /* S_stage = U + c dt K_stage, c = 1/2, 1/2, 1 for stages 1-3 */
+    const double c = stage == 3 ? dt : 0.5 * dt;
     for (int k = 0; k < NF; ++k) {
-        double *u = d->U.f[k], *s = d->S.f[k], *acc = d->A.f[k];
-        const double *kk = K->f[k];
+        const double *u = d->U.f[k], *kk = K->f[k];
+        double *s = d->S.f[k], *acc = d->A.f[k];
 #pragma omp parallel for schedule(static)
         for (int j = G; j < d->nye - G; ++j)
             for (int i = G; i < d->nxe - G; ++i) {
-                size_t c = (size_t)i + (size_t)j * d->nxe;
-                if (stage == 1) {
-                    s[c] = u[c] + hdt * kk[c];
-                } else if (stage == 2) {
-                    double s1 = s[c];
-                    s[c] = u[c] + hdt * kk[c];
-                    acc[c] = (u[c] + u[c]) + ((s1 - u[c]) + dt * kk[c]);
-                } else if (stage == 3) {
-                    s[c] = u[c] + dt * kk[c];
-                } else {
-                    u[c] = (s[c] + (acc[c] - (s[c] + s[c])) * third) + dt6 * kk[c];
-                }
+                size_t q = (size_t)i + (size_t)j * d->nxe;
+                if (stage == 2 && acc) acc[q] = (u[q] + u[q]) + ((s[q] - u[q]) + dt * kk[q]);
+                s[q] = u[q] + c * kk[q];
+            }
+    }
+}
+
+static void rk_final_paper(dom *d, double dt) {
+    const double dt6 = dt / 6.0;
+    for (int k = 0; k < NF; ++k) {
+        double *u = d->U.f[k];
+        const double *k1 = d->K[0].f[k], *k2 = d->K[1].f[k], *k3 = d->K[2].f[k], *k4 = d->K[3].f[k];
+#pragma omp parallel for schedule(static)
+        for (int j = G; j < d->nye - G; ++j)
+            for (int i = G; i < d->nxe - G; ++i) {
+                size_t q = (size_t)i + (size_t)j * d->nxe;
+                u[q] = u[q] + dt6 * (((k1[q] + 2.0 * k2[q]) + 2.0 * k3[q]) + k4[q]);
+            }
+    }
+}
+
+static void rk_final_lowstore(dom *d, double dt) {
+    const double dt6 = dt / 6.0, third = 1.0 / 3.0;
+    for (int k = 0; k < NF; ++k) {
+        double *u = d->U.f[k];
+        const double *s = d->S.f[k], *acc = d->A.f[k], *kk = d->K[0].f[k];
+#pragma omp parallel for schedule(static)
+        for (int j = G; j < d->nye - G; ++j)
+            for (int i = G; i < d->nxe - G; ++i) {
+                size_t q = (size_t)i + (size_t)j * d->nxe;
+                u[q] = (s[q] + (acc[q] - (s[q] + s[q])) * third) + dt6 * kk[q];
             }
     }
 }
 
 static int dom_step(dom *d, double dt, double cmax) {
-    int rc;
-    fill_block(d, &d->U);
-    rc = rhs_block(d->nxe, d->nye, d->U.f, d->BG, &d->par, cmax, d->K[0].f);
-    if (rc) return rc;
-    rk_stage_combine(d, 1, dt, &d->K[0]);
-    for (int stage = 2; stage <= 4; ++stage) {
-        fill_block(d, &d->S);
-        rc = rhs_block(d->nxe, d->nye, d->S.f, d->BG, &d->par, cmax, d->K[0].f);
+    const int paper = d->cfg.form == ORC_FORM_PAPER;
+    for (int stage = 1; stage <= 4; ++stage) {
+        block *in = stage == 1 ? &d->U : &d->S;
+        block *K = paper ? &d->K[stage - 1] : &d->K[0];
+        fill_block(d, in);
+        int rc = rhs_block(d->nxe, d->nye, in->f, d->BG, &d->par, cmax, K->f);
         if (rc) return rc;
-        rk_stage_combine(d, stage, dt, &d->K[0]);
+        if (stage < 4) rk_stage_input(d, stage, dt, K);
     }
+    if (paper) rk_final_paper(d, dt);
+    else rk_final_lowstore(d, dt);
     return ORC_OK;
 }
 
@@ -767,7 +826,8 @@ int orc_step_patch(const orc_cfg *cfg, int px, int py, double *const f[NF], doub
                     BGl[l][k][(size_t)i + (size_t)j * w] = bg[k][(size_t)(i + o) + (size_t)(j + o) * px];
     }
     /* stage inputs: level 0 is U itself; the combine follows dom_step's
-     * arrangement exactly (S1, S2 and A from U, then S3, then U+) */
+     * arithmetic exactly in either form (S1, S2 [and A] from U, then S3,
+     * then U+ from the four K [or from S3, A and K4]) */
     for (int k = 0; k < NF; ++k) memcpy(Sb[0].f[k], f[k], sizeof(double) * (size_t)px * py);
     {
         const double hdt = 0.5 * dt, dt6 = dt / 6.0, third = 1.0 / 3.0;
@@ -795,10 +855,20 @@ int orc_step_patch(const orc_cfg *cfg, int px, int py, double *const f[NF], doub
                         } else if (l == 2) {
                             Sb[3].f[k][(size_t)i + (size_t)j * wn] = u + dt * kk;
                         } else {
-                            /* level 3 block is the S3 block; A sits on level 2 (offset G more) */
-                            double s3 = Sb[3].f[k][ck];
-                            double acc = Ab.f[k][(size_t)(i + 2 * G) + (size_t)(j + 2 * G) * (px - 4 * G)];
-                            out[k][(size_t)i + (size_t)j * wn] = (s3 + (acc - (s3 + s3)) * third) + dt6 * kk;
+                            /* level 3 block is the S3 block; A sits on level 2 (offset G more);
+                             * K of level m at this cell is at offset (4 - m) G in its block */
+                            double r;
+                            if (cfg->form == ORC_FORM_PAPER) {
+                                double k1 = Kb[0].f[k][(size_t)(i + 4 * G) + (size_t)(j + 4 * G) * px];
+                                double k2 = Kb[1].f[k][(size_t)(i + 3 * G) + (size_t)(j + 3 * G) * (px - 2 * G)];
+                                double k3 = Kb[2].f[k][(size_t)(i + 2 * G) + (size_t)(j + 2 * G) * (px - 4 * G)];
+                                r = u + dt6 * (((k1 + 2.0 * k2) + 2.0 * k3) + kk);
+                            } else {
+                                double s3 = Sb[3].f[k][ck];
+                                double acc = Ab.f[k][(size_t)(i + 2 * G) + (size_t)(j + 2 * G) * (px - 4 * G)];
+                                r = (s3 + (acc - (s3 + s3)) * third) + dt6 * kk;
+                            }
+                            out[k][(size_t)i + (size_t)j * wn] = r;
                         }
                     }
         }
@@ -840,8 +910,7 @@ int orc_deriv_line(int n, const double *q, double h, double *out) {
     double *e = alloc0((size_t)n + 2 * G);
     if (!e) return ORC_ENOMEM;
     for (int i = -G; i < n + G; ++i) e[i + G] = q[imod(i, n)];
-    const double inv12h = 1.0 / (12.0 * h);
-    for (int i = 0; i < n; ++i) out[i] = d4(e, i + G, 1, inv12h);
+    for (int i = 0; i < n; ++i) out[i] = d4(1, e, i + G, 1, 12.0 * h, 0.0);
     free(e);
     return ORC_OK;
 }
@@ -879,6 +948,7 @@ int orc_hd_face_fields(const orc_cfg *cfg, double *const f[NF], double *const bg
     double *vx = alloc0(n), *vy = alloc0(n), *eps = alloc0(n);
     if (!vx || !vy || !eps) { rc = ORC_ENOMEM; goto out; }
     {
+        const int pf = cfg->form == ORC_FORM_PAPER;
         const double gm1 = cfg->gamma - 1.0, igm1 = 1.0 / gm1;
         for (size_t c = 0; c < n; ++c) {
             double rb = 0.0, bxb = 0.0, byb = 0.0;
@@ -887,12 +957,12 @@ int orc_hd_face_fields(const orc_cfg *cfg, double *const f[NF], double *const bg
             double bxt = d.U.f[F_BX][c], byt = d.U.f[F_BY][c];
             double r = rb + rt;
             double ir = 1.0 / r;
-            double ux = mx * ir, uy = my * ir;
+            double ux = over(pf, mx, r, ir), uy = over(pf, my, r, ir);
             double kin = 0.5 * (mx * ux + my * uy);
             double bbdot = bxb * bxt + byb * byt;
             double bt2 = bxt * bxt + byt * byt;
             double pk = gm1 * (((et - kin) - bbdot) - 0.5 * bt2);
-            vx[c] = ux; vy[c] = uy; eps[c] = pk * igm1;
+            vx[c] = ux; vy[c] = uy; eps[c] = over(pf, pk, gm1, igm1);
         }
         double *qx[5] = {d.U.f[F_RHO], eps, vx, vy, d.U.f[F_BY]};
         double *qy[5] = {d.U.f[F_RHO], eps, vx, vy, d.U.f[F_BX]};

@@ -58,7 +58,7 @@ def test_batch_fp64_matches_oracle(oracle_lib):
     b = Batch(probs, precision=FP64)
     b.advance(12)
     for i, p in enumerate(probs):
-        ora = oracle_lib.State(p)
+        ora = oracle_lib.State(p, form=oracle_lib.LOWSTORE)
         ora.run(12)
         got = b[i].read_fields().cpu().numpy()
         assert np.array_equal(got, ora.stacked()), i
@@ -113,7 +113,7 @@ def test_batch_64_mixed_workload(oracle_lib):
         a, c = b[i].read_fields().cpu().numpy(), s.read_fields().cpu().numpy()
         assert np.array_equal(a, c), i
     for i in (3, 35):
-        ora = oracle_lib.State(probs[i])
+        ora = oracle_lib.State(probs[i], form=oracle_lib.LOWSTORE)
         ora.run(100)
         got = b[i].read_fields().cpu().numpy()
         errs = [oracle_lib.rel_l2(got[k], ora.stacked()[k]) for k in range(6)]

@@ -81,7 +81,7 @@ def test_periodic_matches_oracle(oracle_lib, device_max):
     torch = _torch()
     prob = W.orszag_tang(96, ny=80)
     got = _check(torch, prob, [0, 33, 96], [0, 47, 80], 15, "OT vs oracle", device_max=device_max).cpu().numpy()
-    ora = oracle_lib.State(prob)
+    ora = oracle_lib.State(prob, form=oracle_lib.LOWSTORE)
     ora.run(15)
     assert np.array_equal(got, ora.stacked())
 

@@ -22,7 +22,7 @@ def _torch():
 
 
 def _exact(oracle_lib, got, prob, nsteps, label, **kw):
-    ora = oracle_lib.State(prob, **kw)
+    ora = oracle_lib.State(prob, form=oracle_lib.LOWSTORE, **kw)
     ora.run(nsteps)
     ref = ora.stacked()
     nd = int(np.sum(got != ref))
@@ -106,7 +106,7 @@ def test_fp32_stratified_error(oracle_lib):
     _torch()
     from paper_1710_06423_amd import Solver, FP32
     prob = W.stratified_atmosphere(128, 160, amp=0.05, b_b=(0.1, 0.4))
-    ora = oracle_lib.State(prob)
+    ora = oracle_lib.State(prob, form=oracle_lib.LOWSTORE)
     ora.run(40)
     ref = ora.stacked()
     s = Solver.from_problem(prob, precision=FP32)

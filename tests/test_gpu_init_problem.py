@@ -45,7 +45,7 @@ def test_orszag_tang_generator(oracle_lib, n, ny, b0):
     s.advance(12)
     run = W.Problem("ot_device", prob.nx, prob.ny, prob.x0, prob.x1, prob.y0, prob.y1, prob.gamma, prob.bc,
                     {k: got[i].copy() for i, k in enumerate(W.FIELDS)}, None, 0.0, {}, prob.g)
-    ora = oracle_lib.State(run)
+    ora = oracle_lib.State(run, form=oracle_lib.LOWSTORE)
     ora.run(12)
     assert np.array_equal(s.read_fields().cpu().numpy(), ora.stacked())
 
@@ -64,7 +64,7 @@ def test_brio_wu_generator_bit_exact(oracle_lib, n, scales, along_y):
     s.init_problem(PROBLEM_BRIO_WU, scales)
     assert np.array_equal(s.read_fields().cpu().numpy(), prob.stacked())
     s.advance(30)
-    ora = oracle_lib.State(prob)
+    ora = oracle_lib.State(prob, form=oracle_lib.LOWSTORE)
     ora.run(30)
     assert np.array_equal(s.read_fields().cpu().numpy(), ora.stacked())
 

@@ -3,8 +3,13 @@
 FP64 bar: relative L2 per field <= 1e-12 after the whole run, at sizes that
 span several 250-column tiles and row strips with a ragged tail.  Because the
 hyper-diffusion coefficient amplifies rounding differences, the FP64 device
-path reproduces the oracle's sequence of IEEE operations; these tests also
-require bit-for-bit equality (exact=True).
+path reproduces the IEEE operation sequence of the oracle's low-storage form
+(the four-array RK4 arrangement with reciprocals), and these tests require
+bit-for-bit equality with it (exact=True).  The CPU pins tie that form to the
+oracle's paper form (textbook RK4 combine, divisions as written); the
+`test_paper_form_*` cases below compare the device with the paper form
+directly, where rounding is not amplified: many steps without
+hyper-diffusion, a few with it.
 """
 
 import math
@@ -37,7 +42,7 @@ def gpu_run(prob, nsteps, t_end=0.0, **kw):
 
 
 def oracle_run(oracle, prob, nsteps, t_end=0.0, **kw):
-    s = oracle.State(prob, **kw)
+    s = oracle.State(prob, form=oracle.LOWSTORE, **kw)
     s.run(nsteps, t_end)
     return s
 
@@ -61,6 +66,29 @@ def test_library_loads_on_gpu():
     lib = load_library()
     assert lib.sacx_abi_version() == 3
     assert torch.cuda.get_device_properties(0).gcnArchName.startswith("gfx950")
+
+
+@pytest.mark.parametrize("hd_on,nsteps", [(False, 100), (True, 3)])
+def test_paper_form_orszag_tang(oracle_lib, hd_on, nsteps):
+    """OT 256 x 192 against the oracle's paper form: 100 steps without
+    hyper-diffusion, 3 with it, relative L2 per field <= 1e-12."""
+    print(f"case: paper form OT 256x192 hd={hd_on} steps={nsteps}", flush=True)
+    prob = W.orszag_tang(256, ny=192)
+    s, out, done, t = gpu_run(prob, nsteps, hd_on=hd_on)
+    ora = oracle_lib.State(prob, hd_on=hd_on, form=oracle_lib.PAPER)
+    ora.run(nsteps)
+    assert done == nsteps and abs(t - ora.t) <= 1e-13 * ora.t
+    assert_parity(oracle_lib, out, ora, label=f"paper form OT256x192 hd={hd_on}", exact=False)
+
+
+def test_paper_form_brio_wu(oracle_lib):
+    """Brio-Wu 800 with hyper-diffusion, 3 steps, against the paper form."""
+    print("case: paper form brio_wu 800 3 steps", flush=True)
+    prob = W.brio_wu(800)
+    s, out, done, t = gpu_run(prob, 3)
+    ora = oracle_lib.State(prob, form=oracle_lib.PAPER)
+    ora.run(3)
+    assert_parity(oracle_lib, out, ora, label="paper form BW-800 3 steps", exact=False)
 
 
 def test_brio_wu_800_parity(oracle_lib):
@@ -155,7 +183,7 @@ def test_conservation_sums(oracle_lib):
     d0 = s.diagnostics()
     s.advance(50)
     d1 = s.diagnostics()
-    cfg = oracle_lib.make_cfg(prob)
+    cfg = oracle_lib.make_cfg(prob, form=oracle_lib.LOWSTORE)
     ref0 = oracle_lib.sums(cfg, [prob.fields[k] for k in W.FIELDS])
     absum = oracle_lib.sums(cfg, [np.abs(prob.fields[k]) for k in W.FIELDS])
     assert np.allclose(d0["sums"], ref0, rtol=1e-13, atol=1e-13 * absum.max())
@@ -182,7 +210,7 @@ def test_wave_speeds_match_oracle(oracle_lib):
     prob = W.orszag_tang(200, ny=120)
     s = Solver.from_problem(prob)
     d = s.diagnostics()
-    cx, cy, cmax, dt = oracle_lib.State(prob).wavespeed()
+    cx, cy, cmax, dt = oracle_lib.State(prob, form=oracle_lib.LOWSTORE).wavespeed()
     assert d["c_x"] == cx and d["c_y"] == cy
     s.advance(1)
     assert s.diagnostics()["dt"] == dt
@@ -295,7 +323,7 @@ def test_orszag_tang_8000_sampled_parity(oracle_lib):
     print("case: OT 8000 sampled step 99 -> 100", flush=True)
     prob = W.orszag_tang(n)
     s = Solver.from_problem(prob)
-    cfg = oracle_lib.make_cfg(prob)
+    cfg = oracle_lib.make_cfg(prob, form=oracle_lib.LOWSTORE)
     del prob
     done, t = s.advance(99)
     assert done == 99

@@ -154,7 +154,7 @@ def test_cnn_rejects_bad_shapes(sx):
 
 def _pair(n=96, ny=70, steps=3):
     prob = W.orszag_tang(n, ny)
-    ref = oracle.State(prob)
+    ref = oracle.State(prob, form=oracle.LOWSTORE)
     ref.run(steps)
     return prob, ref
 
@@ -194,7 +194,7 @@ def test_supplied_ratios_bitexact(sx, gravity):
     s.set_surrogate(None, (0.0,) * 6 + (1.0,) * 6, refresh_every=10 ** 6, tile=16, bound=math.inf)
     s.ratio_buffer().copy_(torch.from_numpy(R))
     s.advance(20)
-    ref = oracle.State(prob)
+    ref = oracle.State(prob, form=oracle.LOWSTORE)
     ref.advance_ext(20, R)
     got = s.read_fields().cpu().numpy()
     assert np.array_equal(got, ref.stacked())

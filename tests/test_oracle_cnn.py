@@ -110,6 +110,37 @@ def test_adam_first_step_moves_by_lr():
     assert np.allclose(p["w"], [0.99, -1.99, 2.99], atol=1e-15)
 
 
+def test_adam_bias_correction_with_constant_gradient():
+    """A constant gradient g gives m_t = (1 - b1^t) g and v_t = (1 - b2^t) g^2,
+    so with bias correction (and eps = 0) every step, not only the first,
+    moves the weight by exactly lr * sign(g).  A wrong power of b1 or b2 in
+    the correction fails from t = 2 on."""
+    p = {"w": np.array([1.0, -2.0])}
+    g = {"w": np.array([0.3, -5.0])}
+    m = {"w": np.zeros(2)}
+    v = {"w": np.zeros(2)}
+    for t in range(1, 6):
+        before = p["w"].copy()
+        cnn.adam_step(p, g, m, v, t, lr=0.125, b1=0.75, b2=0.5, eps=0.0)
+        assert np.allclose(p["w"] - before, [-0.125, 0.125], rtol=0, atol=1e-15), t
+
+
+def test_adam_steps_two_and_three_hand_computed():
+    """Gradients 1, -1, 2 with b1 = b2 = 1/2, lr = 1/10, eps = 0, from w = 0:
+    t = 1: m = 1/2, v = 1/2, corrected 1 and 1: w = -1/10;
+    t = 2: m = 1/4 - 1/2 = -1/4, v = 1/4 + 1/2 = 3/4, corrected by 3/4:
+           m^ = -1/3, v^ = 1: w = -1/10 + 1/30;
+    t = 3: m = -1/8 + 1 = 7/8, v = 3/8 + 2 = 19/8, corrected by 7/8:
+           m^ = 1, v^ = 19/7: w = -1/10 + 1/30 - (1/10) sqrt(7/19)."""
+    p = {"w": np.zeros(1)}
+    m = {"w": np.zeros(1)}
+    v = {"w": np.zeros(1)}
+    want = [-0.1, -0.1 + 1.0 / 30.0, -0.1 + 1.0 / 30.0 - 0.1 * np.sqrt(7.0 / 19.0)]
+    for t, gv in enumerate((1.0, -1.0, 2.0), start=1):
+        cnn.adam_step(p, {"w": np.array([gv])}, m, v, t, lr=0.1, b1=0.5, b2=0.5, eps=0.0)
+        assert abs(p["w"][0] - want[t - 1]) <= 1e-15, (t, p["w"][0], want[t - 1])
+
+
 def test_training_reduces_loss():
     rng = np.random.default_rng(7)
     p = cnn.init_params(7)

@@ -555,24 +555,3 @@ def test_hyper_viscosity_stress_is_symmetric(oracle_lib):
     assert big > 0
     assert np.max(np.abs(full[1][inner])) < 1e-2 * big
     assert np.max(np.abs(full[2][inner])) < 1e-2 * big
-
-
-def test_rk4_arrangement_is_classic_rk4(oracle_lib):
-    """One oracle step equals U + dt/6 (K1 + 2K2 + 2K3 + K4) with the stages
-    S1 = U + dt/2 K1, S2 = U + dt/2 K2, S3 = U + dt K3 built here from
-    separate right-hand-side evaluations (to rounding, one step)."""
-    for prob in (W.orszag_tang(48), W.brio_wu(200)):
-        s = oracle_lib.State(prob)
-        cx, cy, cmax, dt = s.wavespeed()
-        cfg = s.cfg
-        U = prob.stacked()
-        K1 = oracle_lib.rhs(cfg, list(U), None, cmax)
-        K2 = oracle_lib.rhs(cfg, list(U + 0.5 * dt * K1), None, cmax)
-        K3 = oracle_lib.rhs(cfg, list(U + 0.5 * dt * K2), None, cmax)
-        K4 = oracle_lib.rhs(cfg, list(U + dt * K3), None, cmax)
-        text = U + dt / 6 * (K1 + 2 * K2 + 2 * K3 + K4)
-        s.run(1)
-        assert s.last[0] == dt
-        got = s.stacked()
-        scale = np.maximum(np.max(np.abs(U), axis=(1, 2), keepdims=True), np.max(np.abs(text - U)))
-        assert np.max(np.abs(got - text) / scale) < 1e-14

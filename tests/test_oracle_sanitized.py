@@ -1,8 +1,8 @@
 """The oracle's C source under AddressSanitizer and UndefinedBehaviorSanitizer
 (CPU only): a small C driver compiled together with the oracle runs every
 entry point on grids from smaller than the stencil to a few tiles, with
-periodic, open and mixed boundaries, a background with gravity, and the
-cross terms on and off.  Any out-of-bounds access, leak, use after free or
+periodic, open and mixed boundaries, a background with gravity, the cross
+terms on and off, in both arithmetic forms.  Any out-of-bounds access, leak, use after free or
 undefined operation aborts the driver."""
 
 import os
@@ -42,7 +42,7 @@ static void fill(int nx, int ny, double *f[NF], double *bg[NB], int background, 
         }
 }
 
-static int run(int nx, int ny, int b0, int b2, int background, int cross, int seed) {
+static int run(int nx, int ny, int b0, int b2, int background, int cross, int seed, int form) {
     orc_cfg c;
     memset(&c, 0, sizeof(c));
     c.nx = nx; c.ny = ny; c.x0 = 0; c.x1 = 1; c.y0 = 0; c.y1 = 1;
@@ -50,6 +50,7 @@ static int run(int nx, int ny, int b0, int b2, int background, int cross, int se
     for (int m = 0; m < 4; ++m) { c.c2[m] = 0.02; c.cshk[m] = 0.5; }
     c.bc[0] = c.bc[1] = b0; c.bc[2] = c.bc[3] = b2;
     c.background_on = background;
+    c.form = form;
     if (background) { c.g[0] = 0.1; c.g[1] = -0.5; }
     size_t n = (size_t)nx * ny;
     double *f[NF], *K[NF], *bg[NB];
@@ -96,12 +97,13 @@ int main(void) {
         {6, 5, 1, 1, 0, 1}, {40, 1, 1, 0, 0, 1}, {1, 33, 0, 1, 0, 1}, {30, 26, 0, 0, 0, 1},
         {27, 31, 1, 0, 0, 0}, {26, 28, 0, 1, 1, 1}, {29, 25, 1, 1, 1, 1},
     };
-    for (size_t i = 0; i < sizeof(cases) / sizeof(cases[0]); ++i) {
-        const int *q = cases[i];
-        int rc = run(q[0], q[1], q[2], q[3], q[4], q[5], (int)i);
-        printf("case %dx%d bc %d/%d bg %d cross %d: %d\n", q[0], q[1], q[2], q[3], q[4], q[5], rc);
-        if (rc) return 1;
-    }
+    for (int form = ORC_FORM_PAPER; form <= ORC_FORM_LOWSTORE; ++form)
+        for (size_t i = 0; i < sizeof(cases) / sizeof(cases[0]); ++i) {
+            const int *q = cases[i];
+            int rc = run(q[0], q[1], q[2], q[3], q[4], q[5], (int)i, form);
+            printf("form %d case %dx%d bc %d/%d bg %d cross %d: %d\n", form, q[0], q[1], q[2], q[3], q[4], q[5], rc);
+            if (rc) return 1;
+        }
     double line[16], out[16], R[16];
     for (int i = 0; i < 16; ++i) line[i] = sin(0.4 * i);
     if (orc_deriv_line(16, line, 0.1, out) || orc_hd_ratio_line(16, line, R)) return 1;
