@@ -380,6 +380,7 @@ def run_batch(args):
     b = Batch(probs, precision=FP32)
     t, r, trials = tune_batch(b, use_cache=False, log=log)
     log(f"[bench] tiles: {t} threads, {r} rows")
+    b.close()
     b2 = Batch(probs, precision=FP32)
     b2.set_tiles(t, [r] * len(probs))
     if args.warmup:
@@ -413,6 +414,7 @@ def run_batch(args):
             s.close()
         seq[name] = cells * args.steps / (tot / 1e3) / 1e6
         log(f"[bench] one at a time, {name}: {tot / args.steps:.3f} ms/step -> {seq[name]:.1f} Mcell-updates/s")
+    b2.close()
     out = base_record(args, value, ms / args.steps, "f32", {
         "workload": "batch64_briowu32_orszagtang32_fp32", "instances": len(probs), "cells": cells,
         "tiles": {"threads": t, "rows2d": r},

@@ -131,7 +131,9 @@ int sacx_workspace_size(const sacx_grid *grid, const sacx_params *params, size_t
 int sacx_create(const sacx_grid *grid, const sacx_params *params, void *d_ws, size_t ws_bytes,
                 void *hip_stream, sacx_ctx **out);
 
-/* Release a context (does not touch the workspace memory). NULL is a no-op. */
+/* Release a context: waits for the work queued on its stream (so the caller
+ * may free the workspace once this returns), then frees the host object; the
+ * workspace memory itself is not touched.  NULL is a no-op. */
 int sacx_destroy(sacx_ctx *ctx);
 
 /* Set the boundary kind of each side (paper section 5: periodic for
@@ -372,6 +374,8 @@ int sacx_batch_workspace_size(int32_t n, const sacx_grid *grids, const sacx_para
  * EXCHANGE) or NULL for all periodic. */
 int sacx_batch_create(int32_t n, const sacx_grid *grids, const sacx_params *params, const int32_t *bc,
                       void *d_ws, size_t ws_bytes, void *hip_stream, sacx_batch **out);
+/* Release a batch and its instance contexts, after the work queued on its
+ * stream has finished.  NULL is a no-op. */
 int sacx_batch_destroy(sacx_batch *b);
 
 /* The context of instance i (owned by the batch, valid until destroy). */

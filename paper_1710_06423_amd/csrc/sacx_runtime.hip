@@ -864,6 +864,12 @@ int sacx_create(const sacx_grid *grid, const sacx_params *params, void *d_ws, si
 
 int sacx_destroy(sacx_ctx *ctx) {
     if (!ctx) return SACX_OK;
+    {
+        // the caller frees the workspace after this call: the work queued
+        // on it must be finished first
+        DeviceGuard dg(ctx->device);
+        (void)hipStreamSynchronize(ctx->stream);
+    }
     if (ctx->ev_pool) {
         for (hipEvent_t e : *ctx->ev_pool) (void)hipEventDestroy(e);
         delete ctx->ev_pool;
@@ -1689,6 +1695,10 @@ int sacx_batch_workspace_size(int32_t n, const sacx_grid *grids, const sacx_para
 
 int sacx_batch_destroy(sacx_batch *b) {
     if (!b) return SACX_OK;
+    {
+        DeviceGuard dg(b->device);
+        (void)hipStreamSynchronize(b->stream);
+    }
     if (b->ctx)
         for (sacx_ctx *c : *b->ctx) sacx_destroy(c);
     delete b->ctx;

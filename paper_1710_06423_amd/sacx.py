@@ -8,9 +8,11 @@ this module succeeds but every call raises -- there is no fallback path.
 
 from __future__ import annotations
 
+import atexit
 import contextlib
 import ctypes
 import os
+import weakref
 from typing import Dict, Optional, Sequence
 
 import torch
@@ -99,6 +101,20 @@ class SacxError(RuntimeError):
 
 
 _lib = None
+
+# Contexts and batches still open: closed at interpreter exit, while the HIP
+# runtime is still up (Python's exit handlers run before the C library's),
+# so no library handle is released during the runtime's own teardown.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def load_library():
@@ -223,7 +239,10 @@ class Solver:
             self.ctx = _borrow
             return
         nbytes = workspace_size(grid, params)
-        with torch.cuda.device(self.device):
+        # allocated on the context's stream: the caching allocator hands the
+        # block back to that stream's pool when it is freed, so a later
+        # allocation there is ordered after the context's queued kernels
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.ctx = ctypes.c_void_p(None)
         with torch.cuda.device(self.device):
@@ -231,6 +250,7 @@ class Solver:
                                         ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
                                         ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.ctx)),
                    "sacx_create")
+        _live.add(self)
         self.set_boundaries(bc)
         self.dtype = torch.float64 if grid.precision == FP64 else torch.float32
 
@@ -250,8 +270,11 @@ class Solver:
         return s
 
     def close(self):
+        """Destroy the context; its queued work finishes first (sacx_destroy
+        waits for the stream), then the workspace can be freed."""
         if self.ctx and self.owned:
-            self.lib.sacx_destroy(self.ctx)
+            with torch.cuda.device(self.device):
+                self.lib.sacx_destroy(self.ctx)
         self.ctx = ctypes.c_void_p(None)
 
     def __del__(self):
@@ -271,10 +294,14 @@ class Solver:
         same = cur.cuda_stream == self.stream.cuda_stream
         if not same:
             self.stream.wait_stream(cur)
-        with torch.cuda.device(self.device):
-            yield
-        if not same:
-            cur.wait_stream(self.stream)
+        try:
+            with torch.cuda.device(self.device):
+                yield
+        finally:
+            # also when the call failed: it may have enqueued work before
+            # returning its error
+            if not same:
+                cur.wait_stream(self.stream)
 
     def set_boundaries(self, bc):
         arr = (ctypes.c_int32 * 4)(*[int(b) for b in bc])
@@ -346,8 +373,12 @@ class Solver:
     def halo_buffer(self, side: int) -> torch.Tensor:
         n = ctypes.c_size_t(0)
         _check(self.lib.sacx_halo_buffer_size(self.ctx, int(side), ctypes.byref(n)), "sacx_halo_buffer_size")
-        return torch.zeros(n.value // (8 if self.grid.precision == FP64 else 4), dtype=self.dtype,
-                           device=self.device)
+        buf = torch.zeros(n.value // (8 if self.grid.precision == FP64 else 4), dtype=self.dtype,
+                          device=self.device)
+        # the context's stream uses it too: its block is not reused before
+        # the work queued there when it is freed has finished
+        buf.record_stream(self.stream)
+        return buf
 
     def halo_pack(self, side: int, buf: torch.Tensor):
         with self._shared():
@@ -453,7 +484,7 @@ class Solver:
         """Switch the learned coefficient on (packed=None: the caller writes ratio_buffer())."""
         n = ctypes.c_size_t(0)
         _check(self.lib.sacx_surrogate_workspace_size(self.ctx, ctypes.byref(n)), "sacx_surrogate_workspace_size")
-        with torch.cuda.device(self.device):
+        with torch.cuda.device(self.device), torch.cuda.stream(self.stream):
             self.sur_ws = torch.empty(n.value, dtype=torch.uint8, device=self.device)
         self.sur_packed = packed
         cfg = Surrogate(None if packed is None else packed.data_ptr(), (ctypes.c_float * 12)(*[float(v) for v in norm]),
@@ -519,12 +550,14 @@ class Batch:
         nbytes = ctypes.c_size_t(0)
         _check(self.lib.sacx_batch_workspace_size(n, self.grids, self.params, ctypes.byref(nbytes)),
                "sacx_batch_workspace_size")
-        with torch.cuda.device(dev):
+        with torch.cuda.device(dev), torch.cuda.stream(self.stream):
             self.workspace = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+        with torch.cuda.device(dev):
             self.b = ctypes.c_void_p(None)
             _check(self.lib.sacx_batch_create(n, self.grids, self.params, bc, ctypes.c_void_p(self.workspace.data_ptr()),
                                               nbytes.value, ctypes.c_void_p(self.stream.cuda_stream),
                                               ctypes.byref(self.b)), "sacx_batch_create")
+        _live.add(self)
         self.n = n
         self.views = []
         for i in range(n):
@@ -552,10 +585,12 @@ class Batch:
             _check(self.lib.sacx_batch_advance(self.b, int(nsteps), int(bool(sync))), "sacx_batch_advance")
 
     def close(self):
+        """Destroy the batch (its queued work finishes first)."""
         for v in self.views:
             v.close()
         if self.b:
-            self.lib.sacx_batch_destroy(self.b)
+            with torch.cuda.device(self.device):
+                self.lib.sacx_batch_destroy(self.b)
             self.b = ctypes.c_void_p(None)
 
     def __del__(self):

@@ -101,3 +101,22 @@ def test_tensors_shared_across_streams_are_ordered():
         side.advance(3, sync=False)
         out = side.read_fields()
         assert torch.equal(out * 1.0, ref.read_fields()), rep
+
+
+def test_closing_a_context_with_queued_work_keeps_fresh_allocations_intact():
+    """A context on its own stream is closed, and its workspace dropped,
+    while steps are still queued: closing waits for them, and the freed
+    block goes back to the context stream's pool, so a tensor allocated and
+    filled right afterwards on the caller's stream keeps its values."""
+    torch = _torch()
+    from paper_1710_06423_amd import Solver
+    prob = W.orszag_tang(512, ny=512)
+    for rep in range(3):
+        s = Solver.from_problem(prob, stream=torch.cuda.Stream())
+        nbytes = s.workspace.numel()
+        s.advance(20, sync=False)
+        s.close()
+        del s
+        x = torch.full((nbytes,), 7, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        assert int((x != 7).sum()) == 0, rep
