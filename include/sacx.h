@@ -463,6 +463,23 @@ int sacx_cnn_backward(const void *d_packed, const void *d_x, const void *d_act, 
                       const float *d_target, const float *d_weight, int32_t n, int32_t h, int32_t w, void *d_work,
                       size_t work_bytes, float *d_grad, double *d_loss, void *stream);
 
+/* The backward pass of sacx_cnn_backward (same arguments, same results bit
+ * for bit) with no workspace argument, for callers that cannot allocate
+ * device memory: code under HIP-graph capture, tight training loops,
+ * harnesses that forbid allocation.  Its scratch is a static device array of
+ * SACX_CNN_STATIC_WORK_BYTES (64 MiB), one per device, reserved from the
+ * library's first use on that device until the process ends; the call
+ * itself allocates and frees nothing.  ENOSPC when the batch needs more
+ * scratch than that (sacx_cnn_buffer_sizes().work_bytes; e.g. 8 images of
+ * 128 x 128 fit).  Every call on one device uses that device's one array:
+ * calls that overlap on one device (other streams, other threads) race and
+ * must be ordered by the caller.  Nothing in the scratch needs to start at
+ * zero: each pass writes what it reads. */
+#define SACX_CNN_STATIC_WORK_BYTES (64u << 20)
+int sacx_cnn_backward_noalloc(const void *d_packed, const void *d_x, const void *d_act, const float *d_out,
+                              const float *d_target, const float *d_weight, int32_t n, int32_t h, int32_t w,
+                              float *d_grad, double *d_loss, void *stream);
+
 /* One Adam update (bias-corrected, step counts from 1) of the FP32
  * parameters with moment buffers d_m, d_v (SACX_CNN_NPARAM floats each). */
 int sacx_cnn_adam(float *d_theta, float *d_m, float *d_v, const float *d_grad, int32_t step, float lr,

@@ -26,6 +26,7 @@
 //                  row-major over (out channel, in channel, ky, kx)
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "sacx_internal.h"
 
@@ -517,19 +518,16 @@ int sacx_cnn_forward(const void *d_packed, const void *d_x, int n, int h, int w,
     return SACX_OK;
 }
 
-int sacx_cnn_backward(const void *d_packed, const void *d_x, const void *d_act, const float *d_out,
-                      const float *d_target, const float *d_weight, int n, int h, int w, void *d_work,
-                      size_t work_bytes, float *d_grad, double *d_loss, void *stream) {
-    if (!d_packed || !d_x || !d_act || !d_out || !d_target || !d_work || !d_grad || !d_loss)
-        return set_error(SACX_EINVAL, "NULL buffer");
-    sacx_cnn_sizes sz;
-    int rc = sacx_cnn_buffer_sizes(n, h, w, &sz);
-    if (rc) return rc;
-    if (work_bytes < sz.work_bytes)
-        return set_error(SACX_ENOSPC, "network work buffer too small (%zu < %zu bytes)", work_bytes, sz.work_bytes);
-    if (((uintptr_t)d_packed | (uintptr_t)d_x | (uintptr_t)d_act | (uintptr_t)d_work) % 16)
-        return set_error(SACX_EINVAL, "network buffers must be 16-byte aligned");
-    hipStream_t s = (hipStream_t)stream;
+}  // extern "C"
+
+// The backward pass proper, on a scratch buffer `d_work` of at least
+// sacx_cnn_buffer_sizes().work_bytes whose size the caller has checked.
+// Every scratch byte it reads was written earlier in the same pass (no
+// kernel accumulates into the scratch), so its previous contents never
+// matter.
+static int cnn_backward_on(const void *d_packed, const void *d_x, const void *d_act, const float *d_out,
+                           const float *d_target, const float *d_weight, int n, int h, int w, void *d_work,
+                           float *d_grad, double *d_loss, hipStream_t s) {
     const unsigned char *pk = (const unsigned char *)d_packed;
     const size_t px = (size_t)n * h * w;
     const unsigned char *act = (const unsigned char *)d_act;
@@ -580,6 +578,79 @@ int sacx_cnn_backward(const void *d_packed, const void *d_x, const void *d_act, 
         }
     }
     return SACX_OK;
+}
+
+static int cnn_backward_args(const void *d_packed, const void *d_x, const void *d_act, const float *d_out,
+                             const float *d_target, const float *d_grad, const double *d_loss, int n, int h,
+                             int w, sacx_cnn_sizes *sz) {
+    if (!d_packed || !d_x || !d_act || !d_out || !d_target || !d_grad || !d_loss)
+        return set_error(SACX_EINVAL, "NULL buffer");
+    int rc = sacx_cnn_buffer_sizes(n, h, w, sz);
+    if (rc) return rc;
+    if (((uintptr_t)d_packed | (uintptr_t)d_x | (uintptr_t)d_act) % 16)
+        return set_error(SACX_EINVAL, "network buffers must be 16-byte aligned");
+    return SACX_OK;
+}
+
+// Scratch of the allocation-free backward pass: one array per device,
+// reserved when the library's code object is loaded on that device and held
+// until the process ends.  Host code never names it directly (in host code
+// the name is only a stand-in, not a device address): the device address is
+// looked up once per device with hipGetSymbolAddress and kept below.
+static __device__ __align__(256) unsigned char scratch[SACX_CNN_STATIC_WORK_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static int scratch_for_current_device(void **out) {
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return set_error(SACX_EUNSUP, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(SACX_EDEVICE, "hipGetSymbolAddress of the static network scratch failed: %s",
+                             hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SACX_OK;
+}
+
+extern "C" {
+
+int sacx_cnn_backward(const void *d_packed, const void *d_x, const void *d_act, const float *d_out,
+                      const float *d_target, const float *d_weight, int n, int h, int w, void *d_work,
+                      size_t work_bytes, float *d_grad, double *d_loss, void *stream) {
+    sacx_cnn_sizes sz;
+    int rc = cnn_backward_args(d_packed, d_x, d_act, d_out, d_target, d_grad, d_loss, n, h, w, &sz);
+    if (rc) return rc;
+    if (!d_work) return set_error(SACX_EINVAL, "NULL buffer");
+    if (work_bytes < sz.work_bytes)
+        return set_error(SACX_ENOSPC, "network work buffer too small (%zu < %zu bytes)", work_bytes, sz.work_bytes);
+    if ((uintptr_t)d_work % 16) return set_error(SACX_EINVAL, "network buffers must be 16-byte aligned");
+    return cnn_backward_on(d_packed, d_x, d_act, d_out, d_target, d_weight, n, h, w, d_work, d_grad, d_loss,
+                           (hipStream_t)stream);
+}
+
+int sacx_cnn_backward_noalloc(const void *d_packed, const void *d_x, const void *d_act, const float *d_out,
+                              const float *d_target, const float *d_weight, int n, int h, int w, float *d_grad,
+                              double *d_loss, void *stream) {
+    sacx_cnn_sizes sz;
+    int rc = cnn_backward_args(d_packed, d_x, d_act, d_out, d_target, d_grad, d_loss, n, h, w, &sz);
+    if (rc) return rc;
+    if (sz.work_bytes > (size_t)SACX_CNN_STATIC_WORK_BYTES)
+        return set_error(SACX_ENOSPC, "batch of %d images of %d x %d needs %zu scratch bytes, more than the %zu of "
+                                      "the static scratch (use sacx_cnn_backward with a workspace)",
+                         n, h, w, sz.work_bytes, (size_t)SACX_CNN_STATIC_WORK_BYTES);
+    void *wk = nullptr;
+    rc = scratch_for_current_device(&wk);
+    if (rc) return rc;
+    return cnn_backward_on(d_packed, d_x, d_act, d_out, d_target, d_weight, n, h, w, wk, d_grad, d_loss,
+                           (hipStream_t)stream);
 }
 
 int sacx_cnn_adam(float *d_theta, float *d_m, float *d_v, const float *d_grad, int step, float lr, float beta1,

@@ -42,13 +42,15 @@ EXPORTED = (
     "sacx_profile_enable", "sacx_profile_read", "sacx_set_launch", "sacx_get_launch", "sacx_set_column_split",
     "sacx_batch_workspace_size", "sacx_batch_create", "sacx_batch_destroy", "sacx_batch_context",
     "sacx_batch_set_tiles", "sacx_batch_advance",
-    "sacx_cnn_buffer_sizes", "sacx_cnn_pack", "sacx_cnn_forward", "sacx_cnn_backward", "sacx_cnn_adam",
+    "sacx_cnn_buffer_sizes", "sacx_cnn_pack", "sacx_cnn_forward", "sacx_cnn_backward",
+    "sacx_cnn_backward_noalloc", "sacx_cnn_adam",
     "sacx_cnn_inputs", "sacx_hd_ratio_fields", "sacx_surrogate_workspace_size", "sacx_hd_set_surrogate",
     "sacx_hd_clear_surrogate", "sacx_hd_ratio_buffer", "sacx_hd_read_stats",
 )
 
 CNN_NPARAM = 23146
 CNN_PACKED_BYTES = 99840
+CNN_STATIC_WORK_BYTES = 64 << 20
 
 
 class Grid(ctypes.Structure):
@@ -173,6 +175,7 @@ def load_library():
     lib.sacx_cnn_pack.argtypes = [P, P, P]
     lib.sacx_cnn_forward.argtypes = [P, P, I32, I32, I32, P, P, P]
     lib.sacx_cnn_backward.argtypes = [P, P, P, P, P, P, I32, I32, I32, P, SZ, P, P, P]
+    lib.sacx_cnn_backward_noalloc.argtypes = [P, P, P, P, P, P, I32, I32, I32, P, P, P]
     lib.sacx_cnn_adam.argtypes = [P, P, P, P, I32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, P]
     lib.sacx_cnn_inputs.argtypes = [P, ctypes.POINTER(ctypes.c_float), P]
@@ -660,6 +663,17 @@ def cnn_backward(packed, x, act, out, target, work, grad, loss, weight=None, str
                                      _dp(work),
                                      work.numel() * work.element_size(), _dp(grad), _dp(loss),
                                      ctypes.c_void_p(st.cuda_stream)), "sacx_cnn_backward")
+
+
+def cnn_backward_noalloc(packed, x, act, out, target, grad, loss, weight=None, stream=None):
+    """sacx_cnn_backward on the library's static scratch (no work buffer)."""
+    lib = load_library()
+    n, h, w = x.shape[0], x.shape[1], x.shape[2]
+    st = stream if stream is not None else torch.cuda.current_stream(x.device)
+    with torch.cuda.device(x.device):
+        _check(lib.sacx_cnn_backward_noalloc(_dp(packed), _dp(x), _dp(act), _dp(out), _dp(target), _dp(weight), n, h,
+                                             w, _dp(grad), _dp(loss), ctypes.c_void_p(st.cuda_stream)),
+               "sacx_cnn_backward_noalloc")
 
 
 def cnn_adam(theta, m, v, grad, step: int, lr: float, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
