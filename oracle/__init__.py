@@ -55,7 +55,10 @@ DEFAULT_CSHK = (0.5, 0.5, 0.5, 0.5)
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C11, OpenMP, no FMA contraction)."""
+    """Compile the oracle with gcc (plain C11, OpenMP, no FMA contraction),
+    the 3-D oracle beside it."""
+    from . import oracle3d
+    oracle3d.build(force=force)
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",

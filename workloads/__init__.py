@@ -27,3 +27,15 @@ from .problems import (  # noqa: F401
     synthetic_ratio_planes,
     cnn_case,
 )
+from .problems3d import (  # noqa: F401,E402
+    Problem3,
+    FIELDS3,
+    conserved3,
+    orszag_tang_3d,
+    uniform_3d,
+    entropy_wave_3d,
+    entropy_wave_3d_exact,
+    random_smooth_3d,
+    embed_2d,
+    extract_2d,
+)
