@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libsacx.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["sacx_stage.hip", "sacx_stage32.hip", "sacx_batch.hip", "sacx_batch32.hip", "sacx_ratio.hip",
+SOURCES = ["sacx_stage.hip", "sacx_stage32.hip", "sacx_batch.hip", "sacx_batch32.hip", "sacx_ratio.hip", "sacx3.hip",
            "sacx_runtime.hip", "sacx_cnn.hip"]
 # per-file floating-point contraction: the FP32 stage and batch units contract
 # the multiply-adds written within one expression (a rule of the source alone,

@@ -11,6 +11,7 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "sacx.h")
+HEADERS = sorted(os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h"))
 
 
 @pytest.fixture(scope="module")
@@ -24,17 +25,21 @@ def sx():
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(sacx_\w+)\s*\(", text, re.M)))
+    """Every function declared in any header under include/."""
+    names = set()
+    for h in HEADERS:
+        names |= set(re.findall(r"^\s*(?:int|const char \*)\s*(sacx3?_\w+)\s*\(", open(h).read(), re.M))
+    return sorted(names)
 
 
 def test_every_declared_symbol_is_exported(sx):
+    from paper_1710_06423_amd import sacx3
     lib = sx.load_library()
     names = declared_functions()
     assert len(names) >= 16
     for n in names:
         assert hasattr(lib, n), n
-    assert set(names) == set(sx.EXPORTED)
+    assert set(names) == set(sx.EXPORTED) | set(sacx3.EXPORTED3)
 
 
 def test_abi_version_matches_header(sx):
@@ -196,3 +201,79 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, (r.stdout, r.stderr)
     assert "missing" in r.stdout
+
+
+# ------------------------------------------------------------ 3-D contexts
+
+def test_3d_struct_layout_matches_header(sx, tmp_path):
+    from paper_1710_06423_amd import sacx3
+    src = tmp_path / "layout3.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "sacx3.h"
+int main(void) {
+  printf("%zu %zu %zu\\n", sizeof(sacx3_grid), sizeof(sacx3_params), sizeof(sacx3_diag));
+  printf("%zu %zu %zu %zu\\n", offsetof(sacx3_grid, x0), offsetof(sacx3_params, c2), offsetof(sacx3_diag, sums),
+         offsetof(sacx3_diag, nonphys));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout3"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), "-o", str(exe), str(src)], check=True)
+    got = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    want = [ctypes.sizeof(sacx3.Grid3), ctypes.sizeof(sacx3.Params3), ctypes.sizeof(sacx3.Diag3),
+            sacx3.Grid3.x0.offset, sacx3.Params3.c2.offset, sacx3.Diag3.sums.offset, sacx3.Diag3.nonphys.offset]
+    assert [int(v) for v in got] == want
+
+
+def test_3d_workspace_size_arithmetic(sx):
+    """Four state arrays of 8 fields, and with hyper-diffusion 21 face arrays,
+    each (nz + 6) planes of (ny + 6) rows of a 256-byte-rounded pitch."""
+    from paper_1710_06423_amd import sacx3
+    g = sacx3.make_grid3(37, 21, 19, (0, 1, 0, 1, 0, 1))
+    on = sacx3.workspace_size3(g, sacx3.make_params3(5 / 3))
+    off = sacx3.workspace_size3(g, sacx3.make_params3(5 / 3, hd_on=False))
+    pitch = ((32 + 37 + 3 + 31) // 32) * 32
+    field = ((pitch * 27 * 25 + 31) // 32) * 32 * 8
+    assert on - off == 21 * field
+    assert off >= 32 * field and off < 32 * field + (1 << 17)
+
+
+@pytest.mark.parametrize("bad", [dict(nx=0), dict(nz=-1), dict(nx=1, ny=1, nz=1), dict(x1=0.0),
+                                 dict(nx=1200, ny=1200, nz=1200)])
+def test_3d_invalid_grids_rejected(sx, bad):
+    from paper_1710_06423_amd import sacx3
+    kw = dict(nx=8, ny=8, nz=8, x1=1.0)
+    kw.update(bad)
+    g = sacx3.make_grid3(kw["nx"], kw["ny"], kw["nz"], (0.0, kw["x1"], 0.0, 1.0, 0.0, 1.0))
+    with pytest.raises(sx.SacxError) as e:
+        sacx3.workspace_size3(g, sacx3.make_params3(5 / 3))
+    assert e.value.code in (sx.EINVAL, sx.EUNSUP)
+
+
+def test_3d_calls_reject_null_context(sx):
+    from paper_1710_06423_amd import sacx3
+    lib = sacx3.load_library()
+    bc = (ctypes.c_int32 * 6)(*([0] * 6))
+    assert lib.sacx3_set_boundaries(None, bc) == sx.EINVAL
+    assert lib.sacx3_advance(None, 1, 0.0, None, None) == sx.EINVAL
+    assert lib.sacx3_read_fields(None, None, 1, 1, 1) == sx.EINVAL
+    assert lib.sacx3_diagnostics(None, None) == sx.EINVAL
+    assert lib.sacx3_set_launch(None, 4) == sx.EINVAL
+    assert lib.sacx3_destroy(None) == sx.OK
+
+
+def test_3d_create_rejects_bad_workspace_without_touching_the_device(sx):
+    from paper_1710_06423_amd import sacx3
+    lib = sacx3.load_library()
+    g = sacx3.make_grid3(8, 8, 8, (0, 1, 0, 1, 0, 1))
+    p = sacx3.make_params3(5 / 3)
+    need = sacx3.workspace_size3(g, p)
+    out = ctypes.c_void_p(None)
+    assert lib.sacx3_create(ctypes.byref(g), ctypes.byref(p), None, need, None, ctypes.byref(out)) == sx.EINVAL
+    assert lib.sacx3_create(ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(256 * 7 + 8), need, None,
+                            ctypes.byref(out)) == sx.EINVAL
+    assert lib.sacx3_create(ctypes.byref(g), ctypes.byref(p), ctypes.c_void_p(256 * 7), need - 1, None,
+                            ctypes.byref(out)) == sx.ENOSPC
+    assert not out.value
