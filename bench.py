@@ -10,7 +10,13 @@ CFL 0.3, FP64 (default) or FP32 bulk arithmetic.  A step is one full RK4 step
 Prints one JSON line: Mcell-updates/s over the timed steps, the roofline
 position of the dominant kernel (the fused stage kernel, timed live with HIP
 events on its stream) and the FP64 CPU oracle timed on a bounded sample of
-the same workload (one RK4 step on a sub-block of the same state).
+the same workload (one RK4 step on a sub-block of the same state, on all
+host threads and, in a child process, on one).  The default run also carries
+the metric's comparison under "compare": FP32 bulk arithmetic on the same
+workload (error against the FP64 run), the batched launch of 64 mixed
+instances (sampled instances against the oracle) and the learned coefficient
+on Orszag-Tang 2048^2 (error against the plain FP64 path); --no-extras skips
+them.
 
 Other modes (one JSON line each):
   --mode batch      64 mixed Brio-Wu / Orszag-Tang instances in one persistent
@@ -29,6 +35,8 @@ Other modes (one JSON line each):
                     launches and by replays of a HIP graph of --graph-steps
                     captured steps (small grids are launch-bound); the two
                     runs end bit-identical;
+  --mode 3d         the 3-D scheme: Orszag-Tang carried into z on an n^3
+                    grid (default 512^3), FP64, hyper-diffusion on;
   --mode copy       a device copy of known size (calibrates the HBM byte
                     counters of a profiler run), and the streaming rate of a
                     plain elementwise kernel (b = a + 3c, 3 x 4 GiB).
@@ -129,6 +137,139 @@ def base_record(args, metric_value, ms_step, dtype, config):
     }
 
 
+def oracle_one_thread(n_sample: int):
+    """The oracle at one thread on an n_sample^2 sub-block of the headline
+    state, in a child process (OMP_NUM_THREADS is read when the OpenMP
+    runtime starts), started before this process touches the GPU."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--mode", "oracle-sample", "--n", "8000",
+                        "--cpu-sample", str(n_sample)], capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip()[-400:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def run_oracle_sample(args):
+    import workloads as W
+    out = cpu_baseline(W.orszag_tang(args.n), args.cpu_sample, 0.3)
+    out["nproc"] = os.cpu_count()
+    print(json.dumps(out), flush=True)
+
+
+def timed_advance(s, steps, warmup):
+    import torch
+    if warmup:
+        s.advance(warmup)
+    torch.cuda.synchronize()
+    a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a0.record(s.stream)
+    s.advance(steps, sync=False)
+    a1.record(s.stream)
+    torch.cuda.synchronize()
+    return a0.elapsed_time(a1)
+
+
+def sub_fp32(args, ref_fields, t_ref):
+    """FP32 bulk arithmetic on the headline workload, same warm-up and timed
+    steps; per-field relative L2 against the FP64 run's final state."""
+    import torch
+    import workloads as W
+    from paper_1710_06423_amd import FP32, Solver
+    s = Solver.from_problem(W.orszag_tang(args.n), precision=FP32, cfl=0.3)
+    ms = timed_advance(s, args.steps, args.warmup)
+    a = s.read_fields(torch.float64)
+    t = s.diagnostics()["t"]
+    s.close()
+    names = ("rho", "mx", "my", "e", "bx", "by")
+    return {"mcell_updates_s": round(args.n * args.n * args.steps / (ms / 1e3) / 1e6, 1),
+            "ms_per_step": round(ms / args.steps, 4), "dtype": "f32 bulk, f64 dt and sums",
+            "roofline_frac_algorithmic": round(288 * args.n * args.n * args.steps / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "rel_l2_vs_fp64": {names[k]: float("%.3e" % rel_l2(a[k], ref_fields[k])) for k in range(6)},
+            "steps_compared": args.warmup + args.steps, "t": t, "t_fp64": t_ref}
+
+
+def sub_batch(args):
+    """64 mixed instances in one persistent launch (FP32, autotuned tiles),
+    100 steps; sampled instances against the FP64 oracle."""
+    import torch
+    import oracle
+    import workloads as W
+    from paper_1710_06423_amd import FP32, Batch
+    from paper_1710_06423_amd.autotune import tune_batch
+    probs = W.batch_instances(seed=0)
+    cells = sum(p.nx * p.ny for p in probs)
+    b = Batch(probs, precision=FP32)
+    t, r, _ = tune_batch(b, use_cache=False, log=lambda *a: None)
+    b.close()
+    b = Batch(probs, precision=FP32)
+    b.set_tiles(t, [r] * len(probs))
+    steps = 100
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(b.stream)
+    b.advance(steps, sync=False)
+    e1.record(b.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    # sampled against the oracle: the two smallest tubes and the two smallest boxes
+    bw = sorted((i for i, p in enumerate(probs) if p.ny == 1), key=lambda i: probs[i].nx)[:2]
+    ot = sorted((i for i, p in enumerate(probs) if p.ny > 1), key=lambda i: probs[i].nx * probs[i].ny)[:2]
+    oracle.build(force=False)
+    errs = {}
+    for i in bw + ot:
+        got = b[i].read_fields(torch.float64).cpu().numpy()
+        ref = oracle.State(probs[i], form=oracle.LOWSTORE)
+        ref.run(steps)
+        want = ref.stacked()
+        errs[f"{'briowu' if probs[i].ny == 1 else 'orszag_tang'}_{probs[i].nx}x{probs[i].ny}"] = float(
+            "%.3e" % max(oracle.rel_l2(got[k], want[k]) for k in range(6)))
+    b.close()
+    return {"mcell_updates_s": round(cells * steps / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms / steps, 4),
+            "instances": len(probs), "cells": cells, "steps": steps, "tiles": {"threads": t, "rows2d": r},
+            "dtype": "f32 bulk, f64 dt and sums", "sampled_max_rel_l2_vs_oracle": errs}
+
+
+def sub_surrogate(args, log_every=1000):
+    """The learned coefficient on Orszag-Tang 2048^2, 500 steps, refresh
+    every 16 steps, flux bound 0.05: trained on solver-generated data by the
+    library's own kernels, against the plain FP64 path."""
+    import workloads as W
+    from paper_1710_06423_amd import FP64, Solver
+    from paper_1710_06423_amd import surrogate as sur
+    from paper_1710_06423_amd.sacx import CHECK_FLUX
+    t0 = time.time()
+    data = sur.generate(sides=(256, 384, 512), seeds=tuple(range(1, 9)), snap_every=10, t_end=3.0, log=lambda *a: None)
+    gen_s = time.time() - t0
+    net = sur.Network(seed=0)
+    t1 = time.time()
+    sur.train(net, data, iters=6000, batch_pixels=1 << 19, lr=2e-3, lr_end=1e-4, log=lambda *a: None,
+              log_every=log_every)
+    train_s = time.time() - t1
+    n, steps, K, bound = 2048, 500, 16, 0.05
+    prob = W.orszag_tang(n)
+    plain = Solver.from_problem(prob, precision=FP64)
+    ms_plain = timed_advance(plain, steps, 2)
+    ref = plain.read_fields()
+    plain.close()
+    s = Solver.from_problem(prob, precision=FP64)
+    s.set_surrogate(net.packed, data.norm, refresh_every=K, tile=16, bound=bound, metric=CHECK_FLUX)
+    ms = timed_advance(s, steps, 2)
+    st = s.hd_stats()
+    a = s.read_fields()
+    s.close()
+    names = ("rho", "mx", "my", "e", "bx", "by")
+    return {"workload": f"orszag_tang_{n}x{n}_fp64_hd_learned_coefficient", "steps": steps, "refresh_every": K,
+            "bound": bound, "check": "flux, 16^2 tiles",
+            "mcell_updates_s": round(n * n * steps / (ms / 1e3) / 1e6, 1),
+            "plain_mcell_updates_s": round(n * n * steps / (ms_plain / 1e3) / 1e6, 1),
+            "fallback_tile_fraction": round(st["tiles_fallback"] / max(st["tiles_checked"], 1), 4),
+            "err_used": float("%.3e" % st["err_used"]),
+            "rel_l2_vs_plain_fp64": {names[k]: float("%.3e" % rel_l2(a[k], ref[k])) for k in range(6)},
+            "training": {"snapshots": int(sum(v.shape[0] for v in data.x.values())), "generate_s": round(gen_s, 1),
+                         "iterations": 6000, "train_s": round(train_s, 1)}}
+
+
 def run_single(args):
     import torch
     import workloads as W
@@ -226,6 +367,26 @@ def run_single(args):
         out["paper_context"] = {"mcell_updates_s": 39.1, "hardware": "100x NVIDIA Tesla K20c (10x10 subdomains)",
                                 "source": "Table 1, Orszag-Tang 8000^2 with hyper-diffusion, 163.6 s per 100 "
                                           "iterations; precision not stated"}
+    extras = args.mode == "single" and not args.no_extras and n == 8000 and hd and not strat and prec == FP64
+    if extras:
+        # the metric's comparison: FP32, batched and learned forms beside the
+        # plain FP64 path (each at its stated error), and the oracle at one thread
+        t_ref = diag["t"]
+        fields = s.read_fields()
+        s.close()
+        subs = {}
+        for name, fn in (("fp32_8000", lambda: sub_fp32(args, fields, t_ref)), ("batch64", lambda: sub_batch(args)),
+                         ("learned_coefficient_2048_k16", lambda: sub_surrogate(args))):
+            log(f"[bench] sub-record {name}")
+            try:
+                subs[name] = fn()
+            except Exception as e:  # recorded, so the headline line still prints
+                subs[name] = {"error": f"{type(e).__name__}: {e}"}
+            log(f"[bench] {name}: {subs[name]}")
+        del fields
+        out["compare"] = subs
+        if args.one_thread is not None:
+            out["cpu_baseline_1thread"] = args.one_thread
     if ref is not None:
         log("[bench] FP64 reference run for the FP32 error")
         ref.advance(args.warmup + args.steps)
@@ -525,6 +686,65 @@ def run_surrogate(args):
     print(json.dumps(out), flush=True)
 
 
+def run_3d(args):
+    """The 3-D scheme: Orszag-Tang carried into z (eps = 0.2) on an n^3 grid,
+    periodic, FP64, hyper-diffusion on, CFL 0.3.  A step is 4 stages, each a
+    face-quantity launch and a fused stage launch after the ghost fills."""
+    import torch
+    import workloads as W
+    from paper_1710_06423_amd.sacx3 import Solver3
+
+    n = args.n
+    log(f"[bench] generating orszag_tang_3d {n}^3")
+    prob = W.orszag_tang_3d(n)
+    s = Solver3.from_problem(prob, cfl=0.3)
+    del prob
+    cpu = None
+    if args.cpu_sample > 0:
+        from oracle import oracle3d as O3
+        O3.build(force=False)
+        m = min(args.cpu_sample, 128)
+        sample = W.orszag_tang_3d(m)
+        st = O3.State3(sample, form=O3.LOWSTORE)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t0 = time.perf_counter()
+        st.run(1)
+        sec = time.perf_counter() - t0
+        cpu = {"value": m ** 3 / sec / 1e6, "unit": "Mcell-updates/s", "cores": threads, "kind": "oracle",
+               "sample": f"one RK4 step (HD on) of orszag_tang_3d at {m}^3; {sec:.2f} s on {threads} OpenMP threads"}
+        log(f"[bench] oracle: {cpu['value']:.3f} Mcell-updates/s")
+    if args.warmup:
+        s.advance(args.warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.advance(args.steps, sync=False)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    d = s.diagnostics()
+    s.close()
+    if d["nonphys"] or d["steps"] != args.warmup + args.steps:
+        log(f"[bench] run failed: {d}")
+        sys.exit(1)
+    cells = n ** 3
+    value = cells * args.steps / (ms / 1e3) / 1e6
+    # algorithmic bytes: 12 field accesses x 8 fields x 8 B per cell and step
+    alg = 12 * 8 * 8
+    achieved = alg * cells / (ms / args.steps / 1e3) / 1e9
+    log(f"[bench] 3-D {n}^3: {ms / args.steps:.3f} ms/step, {value:.1f} Mcell-updates/s, {achieved:.0f} GB/s algorithmic")
+    out = base_record(args, value, ms / args.steps, "f64", {
+        "workload": f"orszag_tang_3d_{n}^3_fp64_hd", "nx": n, "ny": n, "nz": n, "precision": "fp64",
+        "hyper_diffusion": True, "cfl": 0.3, "bytes_per_cell_update": alg,
+        "kernels": "per stage: k3_faces (face quantities to HBM) + k3_stage (fused RHS and combine)",
+    })
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                       "scope": "whole step (both launches of every stage, ghost fills, dt)"}
+    out["cpu_baseline"] = cpu
+    print(json.dumps(out), flush=True)
+
+
 def run_copy(args):
     """A 1 GiB device-to-device copy, five times: the dispatches a profiler run
     calibrates its byte counters with, and the achievable HBM bandwidth."""
@@ -568,7 +788,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 100, surrogate 500)")
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--mode", choices=["single", "batch", "surrogate", "decomposed", "graph", "copy"],
+    ap.add_argument("--mode", choices=["single", "batch", "surrogate", "decomposed", "graph", "copy", "3d",
+                                       "oracle-sample"],
                     default="single")
     ap.add_argument("--split", default="2x2", help="decomposed mode: subdomains along x and y, e.g. 2x2")
     ap.add_argument("--graph-steps", type=int, default=10, help="graph and decomposed modes: steps per captured graph")
@@ -583,7 +804,12 @@ def main():
     ap.add_argument("--max-snaps", type=int, default=0)
     ap.add_argument("--bound", type=float, default=0.05)
     ap.add_argument("--tile", type=int, default=16)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="single mode: only the headline (no FP32 / batch / learned-coefficient sub-records)")
     args = ap.parse_args()
+    if args.mode == "oracle-sample":
+        run_oracle_sample(args)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs one GPU's subdomain only; --gpus {args.gpus} is not supported "
@@ -592,14 +818,19 @@ def main():
     if args.steps is None:
         args.steps = 500 if args.mode == "surrogate" else 100
     if args.n is None:
-        args.n = {"surrogate": 2048, "graph": 1024}.get(args.mode, 8000)
+        args.n = {"surrogate": 2048, "graph": 1024, "3d": 512}.get(args.mode, 8000)
 
+    args.one_thread = None
+    if args.mode == "single" and not args.no_extras and args.cpu_sample > 0 and args.n == 8000:
+        # before anything initialises the GPU
+        log("[bench] oracle at one thread on a 1000^2 sub-block")
+        args.one_thread = oracle_one_thread(1000)
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     {"single": run_single, "batch": run_batch, "surrogate": run_surrogate, "decomposed": run_decomposed,
-     "graph": run_graph, "copy": run_copy}[args.mode](args)
+     "graph": run_graph, "copy": run_copy, "3d": run_3d}[args.mode](args)
 
 
 if __name__ == "__main__":

@@ -546,7 +546,7 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
                 // keeps the G loads of later faces from being hoisted into
                 // the registers of earlier ones)
                 double ah[NF3], bh[NF3];
-#pragma unroll
+#pragma unroll 1
                 for (int side = 0; side < 2; ++side) {
                     const int xx = x - 1 + side;          // face between xx and xx + 1
                     const int lb = bx - 1 + side;         // LDS column of xx
@@ -576,7 +576,7 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
                     for (int f = 0; f < NF3; ++f) ah[f] = side == 0 ? h.h[f] : (h.h[f] - ah[f]) * kc.ih[0];
                     __builtin_amdgcn_sched_barrier(0);
                 }
-#pragma unroll
+#pragma unroll 1
                 for (int side = 0; side < 2; ++side) {
                     const int yy = y - 1 + side;
                     const int lb = by - 1 + side;
