@@ -11,92 +11,193 @@
 namespace sacx {
 
 // ---------------------------------------------------------------------------
-// Batched persistent launch: every step of every instance in one cooperative
-// launch (all blocks co-resident, which the runtime checks at launch).  Per
-// step: each instance's dt from its own reduced wave speeds; then per stage a
-// ghost fill of all instances' stage inputs, a grid barrier, all instances'
-// tiles taken from a work queue (one atomic counter per step and stage,
-// tiles ordered most expensive first), a grid barrier.  The tile arithmetic
-// is the same device code as the per-subdomain kernels, so each instance
-// evolves bit for bit as it does alone.
+// Batched persistent launch: every step of every instance in one launch with
+// all blocks resident (a cooperative launch, which the runtime checks).
+//
+// The instances are split into one group per XCD (balanced by cost on the
+// host), and each group's work is one queue taken in order through its own
+// counter by the blocks of that XCD (a block reads the XCD it runs on from
+// the XCC_ID hardware register).  A queue's entries are, for each global
+// stage g = 4 step + (stage - 1) of the launch, its per-stage list: instance
+// by instance (most expensive first) the F_i pieces of the ghost fill of the
+// instance's stage input (a fill by one block would hold up the instance's
+// tiles for hundreds of microseconds), then its tiles (most expensive
+// first); after the last stage, one entry per instance closes its last step.
+// Each instance keeps two completion counters, and an entry waits only for
+// its own instance:
+//   fill piece (i, g): all tiles of (i, g - 1) done -> tiles[i] >= T_i g
+//                 (piece 0 of a step's first stage also ends the previous
+//                 step and computes this step's dt from the instance's own
+//                 reduced wave speeds)
+//   tile  (i, g): the fill of (i, g) done           -> fills[i] >= F_i (g + 1)
+// so an instance's next stage starts as soon as its own tiles are done,
+// while other instances are still in their previous stage: no grid barrier,
+// and no partly filled round of tiles before one.  Every dependency points
+// to an earlier entry of the same queue and every block is resident, so
+// some block can always proceed.
+//
+// Everything an instance reads and writes during the launch stays in one
+// XCD, whose L2 every block of the queue shares: a finished entry's waves
+// wait for their stores to reach L2, then one thread increments the counter
+// (an L2 atomic); a waiting thread polls the counter in L2, and after it
+// every wave acquires at agent scope, which invalidates its compute unit's
+// L1, before reading the instance's data.  (Kernel boundaries make the data
+// visible to the other XCDs and the host.)  No L2 write-back is needed per
+// entry.
+//
+// Every wait is bounded (spin_limit polls): one that exceeds it raises the
+// abort flag, every block leaves its queue, and the host reports the error;
+// so does a queue with work whose XCD has no block of the launch.  The tile
+// arithmetic is the device code of the per-subdomain kernels, so each
+// instance evolves bit for bit as it does alone.
 // ---------------------------------------------------------------------------
-namespace cg = cooperative_groups;
 
 __device__ __forceinline__ int bwrap(int i, int n, int periodic) {
     if (periodic) { int r = i % n; return r < 0 ? r + n : r; }
     return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
-template <typename real, int STAGE>
-__device__ void batch_ghost_fill(const BatchArgs<real> &b, int n_blocks_threads, int gtid) {
-    const long long total = b.gbeg[b.n];
-    for (long long g = gtid; g < total; g += n_blocks_threads) {
-        // instance by binary search over the prefix offsets
-        int lo = 0, hi = b.n - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (b.gbeg[mid] <= g) lo = mid; else hi = mid - 1;
-        }
-        const BatchInst<real> &I = b.inst[lo];
-        const int nx = I.L.nx, ny = I.L.ny, W = nx + 2 * G;
-        const long long gc = 2LL * G * W + 2LL * G * ny;   // ghost cells per field
-        long long m = g - b.gbeg[lo];
-        const int f = (int)(m / gc);
-        m -= (long long)f * gc;
+// one piece of the ghost fill of an instance's stage input, by one block:
+// periodic images or zero-gradient copies of cells (every source is a cell,
+// corners included); the pieces split the instance's ghost cells evenly
+template <typename real, int NT>
+__device__ void batch_inst_fill(const BatchInst<real> &I, int stage, int piece) {
+    const int nx = I.L.nx, ny = I.L.ny, W = nx + 2 * G;
+    const int gc = 2 * G * W + 2 * G * ny;   // ghost cells per field
+    const int g0 = piece * kBatchFillPiece, g1 = min(NF * gc, g0 + kBatchFillPiece);
+    for (int g = g0 + (int)threadIdx.x; g < g1; g += NT) {
+        const int f = g / gc;
+        const int m = g - f * gc;
         int ci, rj;
-        if (m < 2LL * G * W) {
-            const int rr = (int)(m / W);
-            ci = (int)(m % W) - G;
+        if (m < 2 * G * W) {
+            const int rr = m / W;
+            ci = m % W - G;
             rj = rr < G ? rr - G : ny + rr - G;
         } else {
-            const long long m2 = m - 2LL * G * W;
-            rj = (int)(m2 / (2 * G));
-            const int cc = (int)(m2 % (2 * G));
+            const int m2 = m - 2 * G * W;
+            rj = m2 / (2 * G);
+            const int cc = m2 % (2 * G);
             ci = cc < G ? cc - G : nx + cc - G;
         }
-        real *S = const_cast<real *>(I.st[STAGE - 1].S[f]);
+        real *S = const_cast<real *>(I.st[stage - 1].S[f]);
         const int si = bwrap(ci, nx, I.periodic_x), sj = bwrap(rj, ny, I.periodic_y);
         S[(int64_t)I.L.xoff + ci + (int64_t)(rj + G) * I.L.pitch] =
             S[(int64_t)I.L.xoff + si + (int64_t)(sj + G) * I.L.pitch];
     }
 }
 
-template <typename real, int NT, int STAGE>
-__device__ void batch_stage(const BatchArgs<real> &b, int step, TileLds<real, NT> &lds, int &s_item,
-                            cg::grid_group &grid) {
-    batch_ghost_fill<real, STAGE>(b, (int)(gridDim.x * NT), (int)(blockIdx.x * NT + threadIdx.x));
-    grid.sync();
-    int *ctr = b.ctr + step * 4 + (STAGE - 1);
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_item = atomicAdd(ctr, 1);
-        __syncthreads();
-        const int it = s_item;
-        if (it >= b.nitems) break;
-        const BatchItem w = b.items[it];
-        const BatchInst<real> &I = b.inst[w.inst];
-        if (I.oned) stage_tile_1d<real, NT, STAGE, true>(I.st[STAGE - 1], w.tx, lds);
-        else stage_tile<real, NT, STAGE, true, false>(I.st[STAGE - 1], w.tx, w.ty, lds);
+// wait (one thread) until the L2 counter *p >= target; 0 if the wait was abandoned
+__device__ __forceinline__ int batch_wait(int *p, int target, int *abort_flag, int spin_limit) {
+    int spins = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return 0;
+        if (++spins > spin_limit) {
+            __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return 0;
+        }
+        __builtin_amdgcn_s_sleep(8);
     }
-    grid.sync();
+    return 1;
+}
+
+template <typename real, int NT>
+__device__ __forceinline__ void batch_tile(const BatchInst<real> &I, const BatchItem &w, int stage,
+                                           TileLds<real, NT> &lds) {
+    if (I.oned) {
+        switch (stage) {
+            case 1: stage_tile_1d<real, NT, 1, true>(I.st[0], w.tx, lds); break;
+            case 2: stage_tile_1d<real, NT, 2, true>(I.st[1], w.tx, lds); break;
+            case 3: stage_tile_1d<real, NT, 3, true>(I.st[2], w.tx, lds); break;
+            default: stage_tile_1d<real, NT, 4, true>(I.st[3], w.tx, lds); break;
+        }
+    } else {
+        switch (stage) {
+            case 1: stage_tile<real, NT, 1, true, false>(I.st[0], w.tx, w.ty, lds); break;
+            case 2: stage_tile<real, NT, 2, true, false>(I.st[1], w.tx, w.ty, lds); break;
+            case 3: stage_tile<real, NT, 3, true, false>(I.st[2], w.tx, w.ty, lds); break;
+            default: stage_tile<real, NT, 4, true, false>(I.st[3], w.tx, w.ty, lds); break;
+        }
+    }
 }
 
 template <typename real, int NT>
 __global__ __launch_bounds__(NT, sizeof(real) == 4 ? 2 : 1) void k_batch(BatchArgs<real> b) {
     __shared__ TileLds<real, NT> lds;
-    __shared__ int s_item;
-    cg::grid_group grid = cg::this_grid();
-    for (int step = 0; step < b.nsteps; ++step) {
-        if (blockIdx.x == 0)
-            for (int i = threadIdx.x; i < b.n; i += NT) step_begin_dev(b.inst[i].sc, 0.0, b.inst[i].sk);
-        grid.sync();
-        batch_stage<real, NT, 1>(b, step, lds, s_item, grid);
-        batch_stage<real, NT, 2>(b, step, lds, s_item, grid);
-        batch_stage<real, NT, 3>(b, step, lds, s_item, grid);
-        batch_stage<real, NT, 4>(b, step, lds, s_item, grid);
-        if (blockIdx.x == 0)
-            for (int i = threadIdx.x; i < b.n; i += NT) step_end_dev(b.inst[i].sc);
-        grid.sync();
+    __shared__ int s_item, s_ok;
+    int *const abort_flag = b.sync + BATCH_ABORT;
+    int *const fills = b.sync + BATCH_SYNC0;
+    int *const tiles = b.sync + BATCH_SYNC0 + b.n;
+    unsigned xcc;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID, 0, 4)" : "=s"(xcc));
+    const int x = (int)xcc;
+    // every queue with work needs a block on its XCD
+    if (threadIdx.x == 0) {
+        if (x < kBatchQueues) atomicAdd(b.sync + BATCH_BLOCKS0 + x, 1);
+        else __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    cooperative_groups::this_grid().sync();
+    if (threadIdx.x == 0) {
+        int ok = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+        for (int k = 0; k < kBatchQueues; ++k)
+            if (b.qlen[k] > 0 && __hip_atomic_load(b.sync + BATCH_BLOCKS0 + k, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT) == 0)
+                ok = 0;
+        if (!ok) __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_ok = ok;
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    int *const queue = b.sync + BATCH_QUEUE0 + x;
+    const int qlen = b.qlen[x];
+    const int body = b.nsteps * 4 * qlen;   // entries before the closing ones
+    const int total = body + (b.ioff[x + 1] - b.ioff[x]);
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+        __syncthreads();
+        const int q = s_item;
+        if (q >= total) break;
+        int g, inst, kind;
+        BatchItem w{0, 0, 0, 0};
+        if (q < body) {
+            g = q / qlen;
+            w = b.items[b.qoff[x] + q - g * qlen];
+            inst = w.inst;
+            kind = w.kind;
+        } else {
+            g = 4 * b.nsteps;
+            inst = b.qinst[b.ioff[x] + q - body];
+            kind = -1;   // closes the instance's last step
+        }
+        const BatchInst<real> &I = b.inst[inst];
+        if (threadIdx.x == 0)
+            s_ok = kind == BATCH_TILE ? batch_wait(fills + inst, I.nfill * (g + 1), abort_flag, b.spin_limit)
+                                      : batch_wait(tiles + inst, I.ntiles * g, abort_flag, b.spin_limit);
+        __syncthreads();
+        if (!s_ok) break;
+        // this compute unit's L1 may hold lines of the instance from before
+        // the entries just waited for: every wave acquires at agent scope,
+        // which invalidates the L1 (a workgroup-scope invalidate does not:
+        // all of a workgroup's waves share one L1)
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        const int stage = (g & 3) + 1;
+        if (kind == BATCH_TILE) {
+            batch_tile<real, NT>(I, w, stage, lds);
+        } else if (kind == BATCH_FILL) {
+            if (stage == 1 && w.tx == 0 && threadIdx.x == 0) {
+                if (g > 0) step_end_dev(I.sc);
+                step_begin_dev(I.sc, 0.0, I.sk);
+            }
+            batch_inst_fill<real, NT>(I, stage, w.tx);
+        } else if (threadIdx.x == 0) {
+            step_end_dev(I.sc);
+        }
+        // every wave's stores of the entry have reached L2 (the block barrier
+        // alone does not wait for them), then one thread publishes the entry
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (threadIdx.x == 0 && kind >= 0)
+            __hip_atomic_fetch_add(kind == BATCH_TILE ? tiles + inst : fills + inst, 1, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 

@@ -179,22 +179,44 @@ struct BatchInst {
     Layout L;
     int periodic_x, periodic_y;
     int oned;                // ny == 1: one-dimensional tiles
+    int ntiles;              // tiles of one stage
+    int nfill;               // ghost-fill pieces of one stage
     int pad;
 };
 
+// ghost cells (all fields) per ghost-fill piece of a batched instance
+constexpr int kBatchFillPiece = 2048;
+
+// an entry of the per-stage work list: one piece (tx) of the ghost fill of an
+// instance's stage input (kind BATCH_FILL; piece 0 of a step's first stage
+// also takes the step's time step) or one tile of its stage (kind BATCH_TILE)
+enum { BATCH_TILE = 0, BATCH_FILL = 1 };
 struct BatchItem {
-    int inst, tx, ty, pad;   // a tile of one instance
+    int inst, tx, ty, kind;
 };
+
+// The batch's work is split into one queue per XCD (instances assigned to
+// queues by cost); a block serves the queue of the XCD it runs on.
+constexpr int kBatchQueues = 8;
+
+// Batch synchronisation words: the abort flag of a dependency wait that
+// exceeded its bound (sticky), per queue its work counter and the count of
+// blocks serving it, then per instance the count of completed ghost fills and
+// of completed tiles.  All but the abort flag are zeroed before every launch.
+enum { BATCH_ABORT = 0, BATCH_QUEUE0 = 1, BATCH_BLOCKS0 = 1 + kBatchQueues, BATCH_SYNC0 = 1 + 2 * kBatchQueues };
 
 template <typename real>
 struct BatchArgs {
     const BatchInst<real> *inst;
     int n;
-    const BatchItem *items;  // tiles of all instances, most expensive first
-    int nitems;
-    const long long *gbeg;   // n + 1 prefix offsets of ghost cells x fields
-    int *ctr;                // work-queue counters, one per (step, stage), zero at launch
+    const BatchItem *items;  // per queue one stage's work list (per instance its fill, then its tiles), queue after queue
+    const int *qinst;        // the instances of each queue, queue after queue
+    int qoff[kBatchQueues];  // first entry of each queue's list in items
+    int qlen[kBatchQueues];  // entries of each queue's list
+    int ioff[kBatchQueues + 1];  // prefix offsets of the queues' instances in qinst
+    int *sync;               // BATCH_SYNC0 + 2 n words
     int nsteps;
+    int spin_limit;          // bound of a dependency wait (polls)
 };
 
 // host-side launchers (defined in the .hip units)

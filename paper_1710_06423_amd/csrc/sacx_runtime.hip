@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstdarg>
 #include <cmath>
 #include <cstdio>
@@ -1540,10 +1541,10 @@ struct sacx_batch {
     hipStream_t stream;
     std::vector<sacx_ctx *> *ctx;
     char *tab;          // BatchInst array
-    long long *gbeg;    // n + 1
-    int *ctr;           // work-queue counters
-    int ctr_cap;
+    int *sync;          // abort flag, queue counters, per-instance completion counters
     BatchItem *items;
+    int *qinst;         // instances of each XCD queue
+    int qoff[kBatchQueues], qlen[kBatchQueues], ioff[kBatchQueues + 1];
     int items_cap;
     int nitems;
     int nt;
@@ -1555,21 +1556,32 @@ struct sacx_batch {
 
 namespace {
 
-constexpr int kBatchCtr = 4 * 512;  // counters for up to 512 steps per launch
+// polls of a batch dependency wait before it gives up (about a second);
+// SACX_BATCH_SPIN_LIMIT replaces it (a debugging knob: 0 makes every wait
+// that is not already satisfied abort the launch)
+constexpr int kBatchSpinLimit = 1 << 20;
 constexpr size_t kInstBytes = sizeof(BatchInst<double>) > sizeof(BatchInst<float>) ? sizeof(BatchInst<double>)
                                                                                     : sizeof(BatchInst<float>);
 
+// ghost-fill pieces of one stage of a batched instance
+int batch_fill_pieces(const sacx_grid &g) {
+    const int64_t cells = (int64_t)NF * (2LL * G * (g.nx + 2 * G) + 2LL * G * g.ny);
+    return (int)((cells + kBatchFillPiece - 1) / kBatchFillPiece);
+}
+
+// entries of one stage's work lists (tiles of at most 58 columns, the
+// narrowest tile, and one row; fill pieces)
 int64_t batch_items_bound(int n, const sacx_grid *g) {
     int64_t t = 0;
     for (int i = 0; i < n; ++i) {
         const int64_t xt = (g[i].nx + 57) / 58;
-        t += g[i].ny == 1 ? xt : xt * g[i].ny;
+        t += (g[i].ny == 1 ? xt : xt * g[i].ny) + batch_fill_pieces(g[i]);
     }
     return t;
 }
 
 struct BatchPlan {
-    size_t off_tab, off_gbeg, off_ctr, off_items, off_inst, total;
+    size_t off_tab, off_sync, off_items, off_qinst, off_inst, total;
     std::vector<size_t> inst_off, inst_bytes;
 };
 
@@ -1589,9 +1601,9 @@ int batch_plan(int n, const sacx_grid *grids, const sacx_params *params, BatchPl
     }
     size_t off = 0;
     P->off_tab = off; off += round_up((size_t)n * kInstBytes, kAlign);
-    P->off_gbeg = off; off += round_up((size_t)(n + 1) * sizeof(long long), kAlign);
-    P->off_ctr = off; off += round_up((size_t)kBatchCtr * sizeof(int), kAlign);
+    P->off_sync = off; off += round_up((size_t)(BATCH_SYNC0 + 2 * n) * sizeof(int), kAlign);
     P->off_items = off; off += round_up((size_t)batch_items_bound(n, grids) * sizeof(BatchItem), kAlign);
+    P->off_qinst = off; off += round_up((size_t)n * sizeof(int), kAlign);
     P->off_inst = off;
     for (int i = 0; i < n; ++i) { P->inst_off[i] = off; off += round_up(P->inst_bytes[i], kAlign); }
     P->total = off;
@@ -1607,9 +1619,9 @@ int batch_build(sacx_batch *b) {
     const int n = b->n;
     const int TX = b->nt - 2 * G;
     std::vector<BatchInst<real>> tab(n);
-    std::vector<long long> gbeg(n + 1, 0);
     struct Costed { int64_t cost; BatchItem it; };
-    std::vector<Costed> items;
+    std::vector<std::vector<Costed>> tiles(n);
+    std::vector<int64_t> icost(n, 0);
     for (int i = 0; i < n; ++i) {
         sacx_ctx *c = (*b->ctx)[i];
         if (c->sur_on)
@@ -1647,27 +1659,52 @@ int batch_build(sacx_batch *b) {
         I.periodic_x = c->bc[0] == SACX_PERIODIC;
         I.periodic_y = c->bc[2] == SACX_PERIODIC;
         I.oned = (c->grid.ny == 1 && c->grid.nx >= 2) ? 1 : 0;
-        const long long W = c->L.nx + 2 * G;
-        gbeg[i + 1] = gbeg[i] + (long long)NF * (2LL * G * W + 2LL * G * c->L.ny);
         const int xt = (c->L.nx + TX - 1) / TX;
         if (I.oned) {
-            for (int x = 0; x < xt; ++x) items.push_back({1, {i, x, 0, 0}});
+            for (int x = 0; x < xt; ++x) tiles[i].push_back({1, {i, x, 0, BATCH_TILE}});
         } else {
             const int ty = (*b->rows)[i];
             const int yt = (c->L.ny + ty - 1) / ty;
             for (int y = 0; y < yt; ++y) {
                 const int rows = std::min(ty, c->L.ny - y * ty);
-                for (int x = 0; x < xt; ++x) items.push_back({(int64_t)rows + 2 * G, {i, x, y, 0}});
+                for (int x = 0; x < xt; ++x) tiles[i].push_back({(int64_t)rows + 2 * G, {i, x, y, BATCH_TILE}});
             }
         }
+        std::stable_sort(tiles[i].begin(), tiles[i].end(), [](const Costed &p, const Costed &q) { return p.cost > q.cost; });
+        I.ntiles = (int)tiles[i].size();
+        I.nfill = batch_fill_pieces(c->grid);
+        for (const Costed &t : tiles[i]) icost[i] += t.cost;
     }
-    std::stable_sort(items.begin(), items.end(), [](const Costed &p, const Costed &q) { return p.cost > q.cost; });
-    if ((int64_t)items.size() > b->items_cap) return fail(SACX_ENOSPC, "batch work list exceeds its bound");
-    std::vector<BatchItem> flat(items.size());
-    for (size_t k = 0; k < items.size(); ++k) flat[k] = items[k].it;
+    // instances to the XCD queues, most expensive first to the least loaded
+    // queue; each queue's list: its instances most expensive first, each its
+    // fill pieces then its tiles
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int p, int q) { return icost[p] > icost[q]; });
+    std::vector<std::vector<int>> group(kBatchQueues);
+    std::vector<int64_t> load(kBatchQueues, 0);
+    for (int i : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        group[k].push_back(i);
+        load[k] += icost[i];
+    }
+    std::vector<BatchItem> flat;
+    std::vector<int> qinst;
+    for (int k = 0; k < kBatchQueues; ++k) {
+        b->qoff[k] = (int)flat.size();
+        b->ioff[k] = (int)qinst.size();
+        for (int i : group[k]) {
+            qinst.push_back(i);
+            for (int k2 = 0; k2 < tab[i].nfill; ++k2) flat.push_back({i, k2, 0, BATCH_FILL});
+            for (const Costed &t : tiles[i]) flat.push_back(t.it);
+        }
+        b->qlen[k] = (int)flat.size() - b->qoff[k];
+    }
+    b->ioff[kBatchQueues] = (int)qinst.size();
+    if ((int64_t)flat.size() > b->items_cap) return fail(SACX_ENOSPC, "batch work list exceeds its bound");
     b->nitems = (int)flat.size();
+    HIPCHK(hipMemcpyAsync(b->qinst, qinst.data(), sizeof(int) * n, hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipMemcpyAsync(b->tab, tab.data(), sizeof(BatchInst<real>) * n, hipMemcpyHostToDevice, b->stream));
-    HIPCHK(hipMemcpyAsync(b->gbeg, gbeg.data(), sizeof(long long) * (n + 1), hipMemcpyHostToDevice, b->stream));
     HIPCHK(hipMemcpyAsync(b->items, flat.data(), sizeof(BatchItem) * flat.size(), hipMemcpyHostToDevice, b->stream));
     // host vectors go out of scope: finish the copies first
     HIPCHK(hipStreamSynchronize(b->stream));
@@ -1678,6 +1715,19 @@ int batch_build(sacx_batch *b) {
     b->blocks = per_cu * cus;
     b->dirty = false;
     return SACX_OK;
+}
+
+template <typename real>
+void batch_args(const sacx_batch *b, int nsteps, int spin, BatchArgs<real> *a) {
+    a->inst = (const BatchInst<real> *)b->tab;
+    a->n = b->n;
+    a->items = b->items;
+    a->qinst = b->qinst;
+    for (int k = 0; k < kBatchQueues; ++k) { a->qoff[k] = b->qoff[k]; a->qlen[k] = b->qlen[k]; a->ioff[k] = b->ioff[k]; }
+    a->ioff[kBatchQueues] = b->ioff[kBatchQueues];
+    a->sync = b->sync;
+    a->nsteps = nsteps;
+    a->spin_limit = spin;
 }
 
 }  // namespace
@@ -1725,15 +1775,19 @@ int sacx_batch_create(int32_t n, const sacx_grid *grids, const sacx_params *para
     b->n = n;
     b->precision = grids[0].precision;
     b->stream = (hipStream_t)hip_stream;
-    HIPCHK(hipGetDevice(&b->device));
+    if (hipGetDevice(&b->device) != hipSuccess) { sacx_batch_destroy(b); return fail(SACX_EDEVICE, "no current device"); }
     char *ws = (char *)d_ws;
     b->tab = ws + P.off_tab;
-    b->gbeg = (long long *)(ws + P.off_gbeg);
-    b->ctr = (int *)(ws + P.off_ctr);
-    b->ctr_cap = kBatchCtr;
+    b->sync = (int *)(ws + P.off_sync);
     b->items = (BatchItem *)(ws + P.off_items);
+    b->qinst = (int *)(ws + P.off_qinst);
     b->items_cap = (int)batch_items_bound(n, grids);
     b->nt = b->precision == SACX_FP64 ? 128 : 256;
+    hipLaunchKernelGGL(k_zero_ints, dim3(8), dim3(256), 0, b->stream, b->sync, BATCH_SYNC0 + 2 * n);
+    if (hipGetLastError() != hipSuccess) {
+        sacx_batch_destroy(b);
+        return fail(SACX_EDEVICE, "clearing the batch's synchronisation words failed");
+    }
     for (int i = 0; i < n; ++i) {
         sacx_ctx *c = nullptr;
         rc = sacx_create(&grids[i], &params[i], ws + P.inst_off[i], P.inst_bytes[i], hip_stream, &c);
@@ -1793,17 +1847,37 @@ int sacx_batch_advance(sacx_batch *b, int32_t nsteps, int32_t sync) {
         if (rc) return rc;
         b->gen_built = gsum;
     }
-    const int per_launch = b->ctr_cap / 4;
+    int spin = kBatchSpinLimit;
+    if (const char *env = getenv("SACX_BATCH_SPIN_LIMIT")) spin = std::max(0, atoi(env));
+    // steps per launch: every queue index stays within an int
+    int qmax = 1;
+    for (int k = 0; k < kBatchQueues; ++k) qmax = std::max(qmax, b->qlen[k]);
+    const int per_launch = (int)std::max<int64_t>(1, std::min<int64_t>(4096, (INT32_MAX - 2LL * b->n) / (4LL * qmax)));
     for (int done = 0; done < nsteps; done += per_launch) {
         const int k = std::min(per_launch, nsteps - done);
-        hipLaunchKernelGGL(k_zero_ints, dim3(8), dim3(256), 0, b->stream, b->ctr, 4 * k);
+        // the queue counters, block counts and completion counters start at
+        // zero; the abort flag is sticky (a launch after an abandoned one
+        // does nothing)
+        hipLaunchKernelGGL(k_zero_ints, dim3(8), dim3(256), 0, b->stream, b->sync + BATCH_QUEUE0,
+                           BATCH_SYNC0 - BATCH_QUEUE0 + 2 * b->n);
         if (b->precision == SACX_FP64) {
-            BatchArgs<double> a{(const BatchInst<double> *)b->tab, b->n, b->items, b->nitems, b->gbeg, b->ctr, k};
+            BatchArgs<double> a;
+            batch_args(b, k, spin, &a);
             HIPCHK(launch_batch<double>(a, b->nt, b->blocks, b->stream));
         } else {
-            BatchArgs<float> a{(const BatchInst<float> *)b->tab, b->n, b->items, b->nitems, b->gbeg, b->ctr, k};
+            BatchArgs<float> a;
+            batch_args(b, k, spin, &a);
             HIPCHK(launch_batch<float>(a, b->nt, b->blocks, b->stream));
         }
+    }
+    if (sync) {
+        // a wait that exceeded its bound left the batch part-way through a
+        // launch: report it (the instance states are then undefined, and the
+        // flag stays set, so later launches of this batch do nothing)
+        int ab = 0;
+        HIPCHK(hipMemcpyAsync(&ab, b->sync + BATCH_ABORT, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+        HIPCHK(hipStreamSynchronize(b->stream));
+        if (ab) return fail(SACX_EDEVICE, "a batch dependency wait exceeded its bound; the instance states are undefined");
     }
     if (sync) {
         HIPCHK(hipStreamSynchronize(b->stream));

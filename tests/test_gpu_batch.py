@@ -112,11 +112,50 @@ def test_batch_64_mixed_workload(oracle_lib):
         s.advance(100)
         a, c = b[i].read_fields().cpu().numpy(), s.read_fields().cpu().numpy()
         assert np.array_equal(a, c), i
-    for i in (3, 35):
+    # FP32 against the FP64 oracle: two tubes and two boxes (the two smallest
+    # of each kind and instances 3 and 35).  Measured: tubes about 1e-6,
+    # boxes up to 8.7e-4 (the vortex's steepening fronts); guard 2e-3.
+    bw = sorted((i for i, p in enumerate(probs) if p.ny == 1), key=lambda i: probs[i].nx)[:2]
+    ot = sorted((i for i, p in enumerate(probs) if p.ny > 1), key=lambda i: probs[i].nx * probs[i].ny)[:2]
+    for i in sorted(set(bw + ot + [3, 35])):
         ora = oracle_lib.State(probs[i], form=oracle_lib.LOWSTORE)
         ora.run(100)
         got = b[i].read_fields().cpu().numpy()
         errs = [oracle_lib.rel_l2(got[k], ora.stacked()[k]) for k in range(6)]
         print(f"[batch] instance {i} ({probs[i].nx}x{probs[i].ny}) FP32 vs FP64 oracle rel-L2: "
               + " ".join(f"{e:.2e}" for e in errs), flush=True)
-        assert max(errs) < 1e-2
+        assert max(errs) <= 2e-3, (i, max(errs))
+
+
+def test_batch_advance_in_parts_equals_one_call():
+    """7 + 8 steps in two launches equal 15 steps of the single runs: a
+    launch closes its instances' last step, the next one begins from it."""
+    _torch()
+    from paper_1710_06423_amd import Batch, Solver, FP32
+    probs = _mixed(2, 2, seed=3)
+    b = Batch(probs, precision=FP32)
+    b.advance(7)
+    b.advance(8)
+    for i, p in enumerate(probs):
+        s = Solver.from_problem(p, precision=FP32)
+        s.advance(15)
+        assert np.array_equal(b[i].read_fields().cpu().numpy(), s.read_fields().cpu().numpy()), i
+        assert b[i].diagnostics()["steps"] == 15
+        s.close()
+    b.close()
+
+
+def test_batch_wait_bound_is_reported(monkeypatch):
+    """A dependency wait that exceeds its bound abandons the launch and the
+    host reports it.  The bound is forced to zero polls from the host, so
+    the first wait that is not already satisfied gives up; every block then
+    leaves the work queue and the kernel ends normally."""
+    _torch()
+    from paper_1710_06423_amd import Batch, FP32, sacx
+    monkeypatch.setenv("SACX_BATCH_SPIN_LIMIT", "0")
+    probs = _mixed(3, 3, seed=4)
+    b = Batch(probs, precision=FP32)
+    with pytest.raises(sacx.SacxError) as e:
+        b.advance(20)
+    assert e.value.code == sacx.EDEVICE and "bound" in str(e.value)
+    b.close()
