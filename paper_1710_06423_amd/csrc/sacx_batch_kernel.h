@@ -59,22 +59,25 @@ __device__ __forceinline__ int bwrap(int i, int n, int periodic) {
 
 // one piece of the ghost fill of an instance's stage input, by one block:
 // periodic images or zero-gradient copies of cells (every source is a cell,
-// corners included); the pieces split the instance's ghost cells evenly
+// corners included); the pieces split the instance's ghost cells evenly.
+// A tube (one row) fills only the ghost cells of its row: its tile reads
+// nothing else.
 template <typename real, int NT>
 __device__ void batch_inst_fill(const BatchInst<real> &I, int stage, int piece) {
     const int nx = I.L.nx, ny = I.L.ny, W = nx + 2 * G;
-    const int gc = 2 * G * W + 2 * G * ny;   // ghost cells per field
+    const int gy = I.oned ? 0 : 2 * G * W;   // ghost cells of the rows above and below, per field
+    const int gc = gy + 2 * G * ny;          // ghost cells per field
     const int g0 = piece * kBatchFillPiece, g1 = min(NF * gc, g0 + kBatchFillPiece);
     for (int g = g0 + (int)threadIdx.x; g < g1; g += NT) {
         const int f = g / gc;
         const int m = g - f * gc;
         int ci, rj;
-        if (m < 2 * G * W) {
+        if (m < gy) {
             const int rr = m / W;
             ci = m % W - G;
             rj = rr < G ? rr - G : ny + rr - G;
         } else {
-            const int m2 = m - 2 * G * W;
+            const int m2 = m - gy;
             rj = m2 / (2 * G);
             const int cc = m2 % (2 * G);
             ci = cc < G ? cc - G : nx + cc - G;

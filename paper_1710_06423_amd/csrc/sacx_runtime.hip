@@ -1563,9 +1563,11 @@ constexpr int kBatchSpinLimit = 1 << 20;
 constexpr size_t kInstBytes = sizeof(BatchInst<double>) > sizeof(BatchInst<float>) ? sizeof(BatchInst<double>)
                                                                                     : sizeof(BatchInst<float>);
 
-// ghost-fill pieces of one stage of a batched instance
+// ghost-fill pieces of one stage of a batched instance (a tube, one row
+// with one-row tiles, fills only the ghost cells of its row)
 int batch_fill_pieces(const sacx_grid &g) {
-    const int64_t cells = (int64_t)NF * (2LL * G * (g.nx + 2 * G) + 2LL * G * g.ny);
+    const bool oned = g.ny == 1 && g.nx >= 2;
+    const int64_t cells = (int64_t)NF * ((oned ? 0 : 2LL * G * (g.nx + 2 * G)) + 2LL * G * g.ny);
     return (int)((cells + kBatchFillPiece - 1) / kBatchFillPiece);
 }
 
