@@ -56,6 +56,10 @@ import numpy as np
 HBM_PEAK_GBS = 8000.0
 ROOT = os.path.dirname(os.path.abspath(__file__))
 METRIC = "Mcell-updates/s & % HBM roofline; plain vs FP32/batched/surrogate at equal error"
+# training data of the learned coefficient: seeded Orszag-Tang runs at 256^2
+# to 1024^2, snapshots every SUR_EVERY[side] steps up to t = 3
+SUR_SIDES = (256, 512, 1024)
+SUR_EVERY = {256: 10, 512: 10, 1024: 40}
 
 
 def log(*a):
@@ -239,7 +243,7 @@ def sub_surrogate(args, log_every=1000):
     from paper_1710_06423_amd import surrogate as sur
     from paper_1710_06423_amd.sacx import CHECK_FLUX
     t0 = time.time()
-    data = sur.generate(sides=(256, 384, 512), seeds=tuple(range(1, 9)), snap_every=10, t_end=3.0, log=lambda *a: None)
+    data = sur.generate(sides=SUR_SIDES, seeds=tuple(range(1, 9)), snap_every=SUR_EVERY, t_end=3.0, log=lambda *a: None)
     gen_s = time.time() - t0
     net = sur.Network(seed=0)
     t1 = time.time()
@@ -266,8 +270,9 @@ def sub_surrogate(args, log_every=1000):
             "fallback_tile_fraction": round(st["tiles_fallback"] / max(st["tiles_checked"], 1), 4),
             "err_used": float("%.3e" % st["err_used"]),
             "rel_l2_vs_plain_fp64": {names[k]: float("%.3e" % rel_l2(a[k], ref[k])) for k in range(6)},
-            "training": {"snapshots": int(sum(v.shape[0] for v in data.x.values())), "generate_s": round(gen_s, 1),
-                         "iterations": 6000, "train_s": round(train_s, 1)}}
+            "training": {"sides": list(SUR_SIDES), "snap_every": {str(k): v for k, v in SUR_EVERY.items()},
+                         "seeds": list(range(1, 9)), "snapshots": int(sum(v.shape[0] for v in data.x.values())),
+                         "generate_s": round(gen_s, 1), "iterations": 6000, "train_s": round(train_s, 1)}}
 
 
 def run_single(args):
@@ -597,7 +602,7 @@ def run_surrogate(args):
     from paper_1710_06423_amd.sacx import CHECK_FLUX
 
     t0 = time.time()
-    data = sur.generate(sides=(256, 384, 512), seeds=tuple(range(1, 9)), snap_every=10, t_end=3.0,
+    data = sur.generate(sides=SUR_SIDES, seeds=tuple(range(1, 9)), snap_every=SUR_EVERY, t_end=3.0,
                         max_snaps=args.max_snaps, log=log)
     log(f"[bench] data: {sum(v.shape[0] for v in data.x.values())} snapshots in {time.time() - t0:.1f} s")
     net = sur.Network(seed=0)
@@ -675,7 +680,8 @@ def run_surrogate(args):
     out = base_record(args, best["mcell_updates_s"], best["ms_per_step"], "f64", {
         "workload": f"orszag_tang_{n}x{n}_fp64_hd_learned_coefficient", "nx": n, "ny": n,
         "check": {"metric": "flux", "bound": args.bound, "tile": args.tile},
-        "training": {"sides": [256, 384, 512], "seeds": list(range(1, 9)), "snap_every": 10, "t_end": 3.0,
+        "training": {"sides": list(SUR_SIDES), "seeds": list(range(1, 9)),
+                     "snap_every": {str(k): v for k, v in SUR_EVERY.items()}, "t_end": 3.0,
                      "iterations": args.train_iters, "seconds": round(train_s, 1),
                      "loss_before": float("%.3e" % e0), "loss_after": float("%.3e" % e1)},
     })

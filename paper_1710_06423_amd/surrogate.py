@@ -141,10 +141,11 @@ def ot_solver(side: int, b0: float, precision=sx.FP64, device="cuda") -> "sx.Sol
 
 
 def generate(sides: Sequence[int] = (256, 384, 512), seeds: Sequence[int] = tuple(range(1, 9)),
-             snap_every: int = 10, t_end: float = 3.0, max_snaps: int = 0, precision=sx.FP64,
+             snap_every=10, t_end: float = 3.0, max_snaps: int = 0, precision=sx.FP64,
              norm: Optional[Sequence[float]] = None, device="cuda", log=None) -> Dataset:
     """Seeded Orszag-Tang runs (B0 scaled by U(0.5, 1.5) from each seed),
-    snapshots every `snap_every` steps until t_end."""
+    snapshots every `snap_every` steps until t_end (an int, or a dict from
+    side to interval: a 1024^2 snapshot takes about 100 MB)."""
     b0s = {s: float(np.random.default_rng(s).uniform(0.5, 1.5)) for s in seeds}
     if norm is None:
         probe = [ot_solver(min(sides), b0s[s], precision, device) for s in seeds[:2]]
@@ -157,6 +158,7 @@ def generate(sides: Sequence[int] = (256, 384, 512), seeds: Sequence[int] = tupl
     ys: Dict[int, List[torch.Tensor]] = {}
     ws: Dict[int, List[torch.Tensor]] = {}
     for side in sides:
+        every = snap_every[side] if isinstance(snap_every, dict) else snap_every
         for seed in seeds:
             s = ot_solver(side, b0s[seed], precision, device)
             k = 0
@@ -168,21 +170,22 @@ def generate(sides: Sequence[int] = (256, 384, 512), seeds: Sequence[int] = tupl
                 k += 1
                 if max_snaps and k >= max_snaps:
                     break
-                rc, done, t = s.advance_rc(snap_every, t_end=t_end)
+                rc, done, t = s.advance_rc(every, t_end=t_end)
                 if rc != sx.OK:
                     # the run left the physical range: the snapshots taken so far
                     # are of valid states; stop this run here
                     if log:
                         log(f"[data] side {side} seed {seed}: stopped at a non-physical state, t = {t:.3f}")
                     break
-                if done < snap_every or t >= t_end * (1 - 1e-12):
+                if done < every or t >= t_end * (1 - 1e-12):
                     break
             if log:
                 log(f"[data] side {side} seed {seed} b0x{b0s[seed]:.3f}: {k} snapshots, t = {s.diagnostics()['t']:.3f}")
             s.close()
     return Dataset(tuple(norm), {k: torch.stack(v) for k, v in xs.items()},
                    {k: torch.stack(v) for k, v in ys.items()}, {k: torch.stack(v) for k, v in ws.items()},
-                   {"sides": list(sides), "seeds": list(seeds), "snap_every": snap_every, "t_end": t_end,
+                   {"sides": list(sides), "seeds": list(seeds), "snap_every": snap_every if isinstance(snap_every, int)
+                    else {int(k): int(v) for k, v in snap_every.items()}, "t_end": t_end,
                     "b0": b0s})
 
 

@@ -265,8 +265,9 @@ def test_fp32_512_100_steps_error_growth(oracle_lib):
     """FP32 bulk against the FP64 oracle over 100 steps of OT 512^2 (t = 0.16,
     fifteen times the simulated time of the 8000^2 benchmark run).  The
     ratio coefficient amplifies the FP32 rounding as the run goes on; the
-    per-field relative L2 measured here is 5e-6 to 1.3e-5, guarded at 3e-5.
-    The 1e-5 budget of the benchmark workload is the slow 8000^2 test."""
+    per-field relative L2 measured here is 5e-6 to 1.3e-5, guarded at 1.6e-5.
+    The 1e-5 budget is the benchmark run's (t = 0.01 at 8000^2; the slow
+    8000^2 test), not this longer one's."""
     _torch()
     from paper_1710_06423_amd import Solver, FP32
     print("case: OT 512 fp32 100 steps", flush=True)
@@ -275,7 +276,7 @@ def test_fp32_512_100_steps_error_growth(oracle_lib):
     s.advance(100)
     out = s.read_fields().cpu().numpy()
     ora = oracle_run(oracle_lib, prob, 100)
-    assert_parity(oracle_lib, out, ora, tol=3e-5, label="OT-512 FP32 100 steps", exact=False)
+    assert_parity(oracle_lib, out, ora, tol=1.6e-5, label="OT-512 FP32 100 steps", exact=False)
 
 
 @pytest.mark.slow
