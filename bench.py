@@ -234,6 +234,21 @@ def sub_batch(args):
             "dtype": "f32 bulk, f64 dt and sums", "sampled_max_rel_l2_vs_oracle": errs}
 
 
+def all_fallback_run(sur, prob, norm, K, tile, bound, steps, warmup=2):
+    """Time a surrogate run whose network has zero weights, so that every
+    check falls back everywhere: (ms, fallback tile fraction)."""
+    import torch
+    from paper_1710_06423_amd import FP64, Solver
+    from paper_1710_06423_amd.sacx import CHECK_FLUX, CNN_NPARAM
+    zero = sur.Network(torch.zeros(CNN_NPARAM, dtype=torch.float32))
+    s = Solver.from_problem(prob, precision=FP64)
+    s.set_surrogate(zero.packed, norm, refresh_every=K, tile=tile, bound=bound, metric=CHECK_FLUX)
+    ms = timed_advance(s, steps, warmup)
+    st = s.hd_stats()
+    s.close()
+    return ms, round(st["tiles_fallback"] / max(st["tiles_checked"], 1), 4)
+
+
 def sub_surrogate(args, log_every=1000):
     """The learned coefficient on Orszag-Tang 2048^2, 500 steps, refresh
     every 16 steps, flux bound 0.05: trained on solver-generated data by the
@@ -262,11 +277,16 @@ def sub_surrogate(args, log_every=1000):
     st = s.hd_stats()
     a = s.read_fields()
     s.close()
+    # the same run with a network that is never kept (zero weights predict 2
+    # everywhere): what the refreshes and the check cost on their own
+    ms0, fb0 = all_fallback_run(sur, prob, data.norm, K, 16, bound, steps)
     names = ("rho", "mx", "my", "e", "bx", "by")
     return {"workload": f"orszag_tang_{n}x{n}_fp64_hd_learned_coefficient", "steps": steps, "refresh_every": K,
             "bound": bound, "check": "flux, 16^2 tiles",
             "mcell_updates_s": round(n * n * steps / (ms / 1e3) / 1e6, 1),
             "plain_mcell_updates_s": round(n * n * steps / (ms_plain / 1e3) / 1e6, 1),
+            "all_fallback_mcell_updates_s": round(n * n * steps / (ms0 / 1e3) / 1e6, 1),
+            "all_fallback_tile_fraction": fb0,
             "fallback_tile_fraction": round(st["tiles_fallback"] / max(st["tiles_checked"], 1), 4),
             "err_used": float("%.3e" % st["err_used"]),
             "rel_l2_vs_plain_fp64": {names[k]: float("%.3e" % rel_l2(a[k], ref[k])) for k in range(6)},
@@ -649,6 +669,13 @@ def run_surrogate(args):
         }
         log(f"[bench] K={K}: {runs[f'K{K}']}")
         s.close()
+        ms0, fb0 = all_fallback_run(sur, prob, data.norm, K, args.tile, args.bound, args.steps, args.warmup)
+        runs[f"K{K}_all_fallback"] = {
+            "mcell_updates_s": round(n * n * args.steps / (ms0 / 1e3) / 1e6, 1),
+            "ms_per_step": round(ms0 / args.steps, 4),
+            "fallback_tile_fraction": fb0,
+        }
+        log(f"[bench] K={K} zero network: {runs[f'K{K}_all_fallback']}")
     # the same with FP32 bulk arithmetic (the speed here comes from FP32; the
     # errors are against the FP64 plain run)
     from paper_1710_06423_amd import FP32

@@ -519,8 +519,8 @@ typedef struct sacx_hd_stats {
     double err_all;          /* max over every finite comparison */
 } sacx_hd_stats;
 
-/* Device bytes the surrogate needs for this context (ratio planes, network
- * input and two activation buffers). */
+/* Device bytes the surrogate needs for this context (ratio planes, the
+ * check's per-tile flags, network input and two activation buffers). */
 int sacx_surrogate_workspace_size(const sacx_ctx *ctx, size_t *bytes);
 
 /* Switch the surrogate on (caller-owned workspace, 256-byte aligned, valid
@@ -533,7 +533,10 @@ int sacx_hd_set_surrogate(sacx_ctx *ctx, const sacx_surrogate *cfg, void *d_ws, 
 int sacx_hd_clear_surrogate(sacx_ctx *ctx);
 
 /* Device address and row pitch (elements) of the surrogate's ratio planes
- * (plane stride pitch * ny).  Checked tiles that fell back hold -1. */
+ * (plane stride pitch * ny).  Checked tiles that fell back hold -1.  Until
+ * the next check the stages read the planes of the tiles the last check kept
+ * (values written there meanwhile are used) and no plane of a tile that fell
+ * back (those take the plain ratio whatever the planes hold). */
 int sacx_hd_ratio_buffer(sacx_ctx *ctx, float **d_r, int64_t *pitch);
 
 /* Surrogate counters since sacx_hd_set_surrogate (synchronises). */

@@ -140,6 +140,12 @@ struct StageArgs {
     const float *Rs;
     int64_t rs_plane;     // elements per plane
     int rs_pitch;         // elements per row
+    // per check tile (row-major, rs_ntx tiles of rs_tile x rs_tile cells per
+    // row): 1 where the last check kept the prediction, 0 where it fell back;
+    // the planes of a fallen-back tile are not read (its faces take the plain
+    // ratio, as its planes' -1 would give)
+    const unsigned char *Rk;
+    int rs_tile, rs_ntx;
 };
 
 // arguments of the ratio-field kernels (plain ratios of a state whose halo is
@@ -228,7 +234,7 @@ template <typename real>
 hipError_t launch_ratio_fields(const RatioArgs<real> &a, float *out, float *d1, int64_t pitch, hipStream_t s);
 template <typename real>
 hipError_t launch_hd_check(const RatioArgs<real> &a, float *rs, int64_t pitch, double bound, int tile, int metric,
-                           HdDevStats *st, hipStream_t s);
+                           HdDevStats *st, unsigned char *kept, hipStream_t s);
 struct InputNorm {
     float v[12];   // shift[6], scale[6]
 };

@@ -134,11 +134,12 @@ __global__ __launch_bounds__(256) void k_d1_max(RatioArgs<real> a, HdDevStats *s
 // e = |r - R_plain| |d1| / D (METRIC 1; d1 the face's first difference, D the
 // plane's largest |d1| over the domain, e = 0 when D = 0).  A tile falls
 // back when any value is not finite or has NOT(e <= bound); then the whole
-// tile of every plane is set to -1 (plain ratio).  Arithmetic in the working
-// precision.
+// tile of every plane is set to -1 (plain ratio).  kept[tile] records the
+// outcome (1 kept, 0 fell back) for the stage kernels, which read no plane
+// of a fallen-back tile.  Arithmetic in the working precision.
 template <typename real, int METRIC>
 __global__ __launch_bounds__(256) void k_hd_check(RatioArgs<real> a, float *rs, int64_t pitch, double bound,
-                                                  int tile, HdDevStats *st) {
+                                                  int tile, HdDevStats *st, unsigned char *kept) {
     __shared__ double s_err[4];
     __shared__ int s_bad[4];
     const int ntx = (a.L.nx + tile - 1) / tile;
@@ -176,6 +177,7 @@ __global__ __launch_bounds__(256) void k_hd_check(RatioArgs<real> a, float *rs, 
     const double et = fmax(fmax(s_err[0], s_err[1]), fmax(s_err[2], s_err[3]));
     const int bt = s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3];
     if (threadIdx.x == 0) {
+        kept[blockIdx.x] = bt ? 0 : 1;
         atomicMax(&st->err_all, (unsigned long long)__double_as_longlong(et));
         if (bt) atomicAdd(&st->tiles_fallback, 1ull);
         else atomicMax(&st->err_used, (unsigned long long)__double_as_longlong(et));
@@ -191,16 +193,16 @@ __global__ __launch_bounds__(256) void k_hd_check(RatioArgs<real> a, float *rs, 
 
 template <typename real>
 hipError_t launch_hd_check(const RatioArgs<real> &a, float *rs, int64_t pitch, double bound, int tile, int metric,
-                           HdDevStats *st, hipStream_t s) {
+                           HdDevStats *st, unsigned char *kept, hipStream_t s) {
     const int ntx = (a.L.nx + tile - 1) / tile, nty = (a.L.ny + tile - 1) / tile;
     if (metric == 1) {
         hipLaunchKernelGGL(k_check_reset, dim3(1), dim3(64), 0, s, st);
         const int64_t n = (int64_t)a.L.nx * a.L.ny;
         const int blocks = (int)std::min<int64_t>((n + 255) / 256, 2048);
         hipLaunchKernelGGL(k_d1_max<real>, dim3(blocks), dim3(256), 0, s, a, st);
-        hipLaunchKernelGGL((k_hd_check<real, 1>), dim3(ntx * nty), dim3(256), 0, s, a, rs, pitch, bound, tile, st);
+        hipLaunchKernelGGL((k_hd_check<real, 1>), dim3(ntx * nty), dim3(256), 0, s, a, rs, pitch, bound, tile, st, kept);
     } else {
-        hipLaunchKernelGGL((k_hd_check<real, 0>), dim3(ntx * nty), dim3(256), 0, s, a, rs, pitch, bound, tile, st);
+        hipLaunchKernelGGL((k_hd_check<real, 0>), dim3(ntx * nty), dim3(256), 0, s, a, rs, pitch, bound, tile, st, kept);
     }
     return hipGetLastError();
 }
@@ -236,9 +238,9 @@ hipError_t launch_cnn_inputs(const RatioArgs<real> &a, const InputNorm &norm, vo
 template hipError_t launch_ratio_fields<double>(const RatioArgs<double> &, float *, float *, int64_t, hipStream_t);
 template hipError_t launch_ratio_fields<float>(const RatioArgs<float> &, float *, float *, int64_t, hipStream_t);
 template hipError_t launch_hd_check<double>(const RatioArgs<double> &, float *, int64_t, double, int, int,
-                                            HdDevStats *, hipStream_t);
+                                            HdDevStats *, unsigned char *, hipStream_t);
 template hipError_t launch_hd_check<float>(const RatioArgs<float> &, float *, int64_t, double, int, int,
-                                           HdDevStats *, hipStream_t);
+                                           HdDevStats *, unsigned char *, hipStream_t);
 template hipError_t launch_cnn_inputs<double>(const RatioArgs<double> &, const InputNorm &, void *, hipStream_t);
 template hipError_t launch_cnn_inputs<float>(const RatioArgs<float> &, const InputNorm &, void *, hipStream_t);
 

@@ -91,6 +91,7 @@ struct sacx_ctx {
     bool sur_on;
     sacx_surrogate sur;
     float *sur_r;          // ratio planes
+    unsigned char *sur_k;  // per check tile: prediction kept (1) or fallen back (0)
     int64_t sur_pitch;
     void *sur_x, *sur_a1, *sur_a2;
     HdDevStats *sur_st;
@@ -659,6 +660,9 @@ StageArgs<real> stage_args(sacx_ctx *c) {
         a.Rs = c->sur_r;
         a.rs_pitch = (int)c->sur_pitch;
         a.rs_plane = c->sur_pitch * c->L.ny;
+        a.Rk = c->sur_k;
+        a.rs_tile = c->sur.tile;
+        a.rs_ntx = (c->L.nx + c->sur.tile - 1) / c->sur.tile;
     }
     return a;
 }
@@ -689,9 +693,9 @@ int sur_refresh(sacx_ctx *c) {
                                c->sur_pitch * ny, c->sur_pitch, c->stream));
     }
     HIPCHK(fp64 ? launch_hd_check<double>(ratio_args<double>(c), c->sur_r, c->sur_pitch, c->sur.bound, c->sur.tile,
-                                          c->sur.metric, c->sur_st, c->stream)
+                                          c->sur.metric, c->sur_st, c->sur_k, c->stream)
                 : launch_hd_check<float>(ratio_args<float>(c), c->sur_r, c->sur_pitch, c->sur.bound, c->sur.tile,
-                                         c->sur.metric, c->sur_st, c->stream));
+                                         c->sur.metric, c->sur_st, c->sur_k, c->stream));
     const int64_t ntx = (nx + c->sur.tile - 1) / c->sur.tile, nty = (ny + c->sur.tile - 1) / c->sur.tile;
     c->sur_refreshes += 1;
     c->sur_tiles_checked += ntx * nty;
@@ -849,6 +853,7 @@ int sacx_create(const sacx_grid *grid, const sacx_params *params, void *d_ws, si
     c->prof_on = false;
     c->sur_on = false;
     c->sur_r = nullptr;
+    c->sur_k = nullptr;
     c->ev_pool = new (std::nothrow) std::vector<hipEvent_t>();
     c->ev_marks = new (std::nothrow) std::vector<std::pair<int, std::pair<int, int>>>();
     if (!c->ev_pool || !c->ev_marks) {
@@ -1392,7 +1397,7 @@ __global__ void k_zero_stats(HdDevStats *st) {
 
 struct SurPlan {
     int64_t pitch;
-    size_t off_r, off_st, off_x, off_a1, off_a2, total;
+    size_t off_r, off_st, off_k, off_x, off_a1, off_a2, total;
 };
 
 SurPlan sur_plan(const sacx_ctx *c) {
@@ -1402,6 +1407,8 @@ SurPlan sur_plan(const sacx_ctx *c) {
     size_t o = 0;
     p.off_r = o;  o = round_up(o + (size_t)10 * p.pitch * ny * sizeof(float), kAlign);
     p.off_st = o; o = round_up(o + sizeof(HdDevStats), kAlign);
+    // one flag per check tile, sized for the smallest tile (one cell)
+    p.off_k = o;  o = round_up(o + (size_t)nx * ny, kAlign);
     p.off_x = o;  o = round_up(o + (size_t)nx * ny * 8 * 2, kAlign);
     p.off_a1 = o; o = round_up(o + (size_t)nx * ny * 32 * 2, kAlign);
     p.off_a2 = o; o = round_up(o + (size_t)nx * ny * 32 * 2, kAlign);
@@ -1452,6 +1459,7 @@ int sacx_hd_set_surrogate(sacx_ctx *ctx, const sacx_surrogate *cfg, void *d_ws, 
     ctx->sur_pitch = p.pitch;
     ctx->sur_r = (float *)(w + p.off_r);
     ctx->sur_st = (HdDevStats *)(w + p.off_st);
+    ctx->sur_k = (unsigned char *)(w + p.off_k);
     ctx->sur_x = w + p.off_x;
     ctx->sur_a1 = w + p.off_a1;
     ctx->sur_a2 = w + p.off_a2;
@@ -1460,6 +1468,10 @@ int sacx_hd_set_surrogate(sacx_ctx *ctx, const sacx_surrogate *cfg, void *d_ws, 
     ctx->sur_tiles_checked = 0;
     const int64_t nr = (int64_t)10 * p.pitch * ctx->L.ny;
     hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, ctx->stream, ctx->sur_r, nr, -1.0f);
+    // every tile flag 0 (fallen back) until the first check (its bytes as
+    // float zeros: the flag region is a whole number of 256-byte blocks)
+    const int64_t nk = (int64_t)(p.off_x - p.off_k) / 4;
+    hipLaunchKernelGGL(k_fill_f32, dim3(256), dim3(256), 0, ctx->stream, (float *)ctx->sur_k, nk, 0.0f);
     hipLaunchKernelGGL(k_zero_stats, dim3(1), dim3(64), 0, ctx->stream, ctx->sur_st);
     HIPCHK(hipGetLastError());
     ctx->sur_on = true;
@@ -1470,6 +1482,7 @@ int sacx_hd_clear_surrogate(sacx_ctx *ctx) {
     if (!ctx) return fail(SACX_EINVAL, "ctx must not be NULL");
     ctx->sur_on = false;
     ctx->sur_r = nullptr;
+    ctx->sur_k = nullptr;
     return SACX_OK;
 }
 

@@ -56,12 +56,12 @@ __global__ __launch_bounds__(NT, sizeof(real) == 4 ? 2 : 1) void k_stage(StageAr
 }
 
 // two threads per column (x and y roles), two waves per SIMD
-template <typename real, int NC, int STAGE, bool BG>
+template <typename real, int NC, int STAGE, bool BG, bool SUR = false>
 __global__ __launch_bounds__(2 * NC, 2) void k_stage_split(StageArgs<real> a) {
     __shared__ SplitLds<real, NC, BG> lds;
     int tx, ty;
     xcd_tile<4>(tx, ty);
-    stage_tile_split<real, NC, STAGE, BG>(a, tx, ty, lds);
+    stage_tile_split<real, NC, STAGE, BG, SUR>(a, tx, ty, lds);
 }
 
 template <typename real, int NT, int STAGE, bool HD>
@@ -81,8 +81,9 @@ static hipError_t launch_s(bool hd, bool bg, const StageArgs<real> &a, hipStream
     }
     dim3 grid((a.L.nx + TX - 1) / TX, (a.L.ny + a.ty - 1) / a.ty);
     if constexpr (std::is_same<real, double>::value) {
-        if (a.split && hd && !a.Rs) {
-            if (bg) hipLaunchKernelGGL((k_stage_split<real, NT, STAGE, true>), grid, dim3(2 * NT), 0, s, a);
+        if (a.split && hd && !(a.Rs && bg)) {
+            if (a.Rs) hipLaunchKernelGGL((k_stage_split<real, NT, STAGE, false, true>), grid, dim3(2 * NT), 0, s, a);
+            else if (bg) hipLaunchKernelGGL((k_stage_split<real, NT, STAGE, true>), grid, dim3(2 * NT), 0, s, a);
             else hipLaunchKernelGGL((k_stage_split<real, NT, STAGE, false>), grid, dim3(2 * NT), 0, s, a);
             return hipGetLastError();
         }

@@ -72,6 +72,58 @@ __device__ __forceinline__ real hd_ratio(real q0, real q1, real q2, real q3, rea
     return m > (real)0 ? n / m : (real)0;
 }
 
+// Learned coefficient: the periodic image of a row of faces in the ratio
+// planes, the check-tile flag of that row in column tile ckx, and its five
+// planes from plane0 in column cw -- or five -1 (plain ratios) where the
+// tile fell back; a wave none of whose lanes is in a kept tile issues no
+// plane load.  A row loop loads the planes it uses in the same iteration and
+// the flag one iteration ahead (a loaded value copied between registers
+// while its load is in flight would make the copy wait for it), and keeps
+// every load issued after the planes unconditional, so that the compiler's
+// count of the loads in flight when it waits for the planes stays exact
+// (with loads under a lane mask after them it would wait for all).
+// A row of faces as the planes see it: its periodic image j and, within
+// the check tiles, its tile row t and its row within that tile; set up with
+// one division and then stepped row by row without one (an integer division
+// per row would cost as much scalar issue as a sizeable part of the row's
+// arithmetic).
+struct SurRow {
+    int j, t, in;
+
+    template <typename real>
+    __device__ __forceinline__ void set(const StageArgs<real> &a, int row) {
+        j = row % a.L.ny;
+        j += j < 0 ? a.L.ny : 0;
+        t = j / a.rs_tile;
+        in = j - t * a.rs_tile;
+    }
+
+    template <typename real>
+    __device__ __forceinline__ void next(const StageArgs<real> &a) {
+        ++j;
+        ++in;
+        if (in == a.rs_tile) { in = 0; ++t; }
+        if (j == a.L.ny) { j = 0; t = 0; in = 0; }
+    }
+};
+
+template <typename real>
+__device__ __forceinline__ int sur_kept(const StageArgs<real> &a, const SurRow &w, int ckx) {
+    return a.Rk[w.t * a.rs_ntx + ckx];
+}
+
+template <typename real>
+__device__ __forceinline__ void sur_planes(const StageArgs<real> &a, const SurRow &w, int kept, int cw, int plane0,
+                                           float (&v)[5]) {
+    const float *p = a.Rs + plane0 * a.rs_plane + (int64_t)w.j * a.rs_pitch + cw;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) v[k] = -1.0f;
+    if (kept) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) v[k] = p[k * a.rs_plane];
+    }
+}
+
 template <typename real>
 struct Row6 {
     real v[NF];
@@ -137,8 +189,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
 
     const int64_t colofs = (int64_t)L.xoff + (colv ? c : L.nx + G - 1);
     const int rbeg = y0 - G, rend = y1 - 1 + G;
-    // surrogate: this column's periodic image in the ratio planes
+    // surrogate: this column's periodic image in the ratio planes, and its
+    // column of check tiles
     const int cw = SUR ? ((c % L.nx) + L.nx) % L.nx : 0;
+    const int ckx = SUR ? cw / a.rs_tile : 0;
 
     // ---------------- per-thread windows (column-local data) ----------------
     real qw[5][6];       // y-face set {rho~, eps~, v_x, v_y, B~_x}, rows r-5..r
@@ -186,11 +240,41 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
         for (int f = 0; f < NF; ++f) nxt.v[f] = a.S[0][ro + f * fs];
     }
 
+    // surrogate: the face rows of the iteration (x faces of row r-1, y faces
+    // (r-3)+1/2) and of the next one, and the tile flags of this
+    // iteration's faces (loaded one iteration ahead)
+    SurRow wx{}, wy{}, wxn{}, wyn{};
+    int fkx = 0, fky = 0;
+    if (SUR) {
+        wx.set(a, rbeg - 1);
+        wy.set(a, rbeg - 3);
+        fkx = sur_kept(a, wx, ckx);
+        fky = sur_kept(a, wy, ckx);
+    }
+
     for (int r = rbeg; r <= rend; ++r) {
         const int64_t ro = colofs + (int64_t)(r + G) * L.pitch;
+        // surrogate ratios of this iteration's faces: x faces of row r-1,
+        // y faces (r-3)+1/2, issued before the iteration's other loads
+        // (a wave none of whose lanes is in a kept tile takes the plain path)
+        float rsx[5], rsy[5];
+        bool wkx = false, wky = false;
+        if (SUR) {
+            wkx = __ballot(fkx) != 0;
+            wky = __ballot(fky) != 0;
+            if (wkx) sur_planes(a, wx, fkx, cw, 0, rsx);
+            if (wky) sur_planes(a, wy, fky, cw, 5, rsy);
+            wx.next(a);
+            wy.next(a);
+            fkx = sur_kept(a, wx, ckx);
+            fky = sur_kept(a, wy, ckx);
+        }
         const Row6<real> cur = nxt;
-        if (r < rend) {
-            const int64_t rn = ro + L.pitch;
+        // (with the surrogate every load of the iteration is unconditional,
+        // for an exact count of the loads in flight: past the last row the
+        // next-row load re-reads that row, unused)
+        if (SUR || r < rend) {
+            const int64_t rn = colofs + (int64_t)((SUR ? min(r + 1, rend) : r + 1) + G) * L.pitch;
 #pragma unroll
             for (int f = 0; f < NF; ++f) nxt.v[f] = a.S[0][rn + f * fs];
         }
@@ -212,24 +296,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
 #pragma unroll
             for (int f = 0; f < NF; ++f) lds.ps[ring][f][tid] = cur.v[f];
         }
-        if (outrow) {
+        if (SUR || outrow) {
+            // (with the surrogate, a thread without an output row reads a
+            // cell of its own column instead, unused)
+            const int64_t op = SUR && !outrow ? colofs + (int64_t)(max(j, y0) + G) * L.pitch : oo;
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
-                if (STAGE == 2 || STAGE == 3) pU.v[f] = a.U[0][oo + f * fs];
-                if (STAGE == 4) pU.v[f] = a.A[0][oo + f * fs];
+                if (STAGE == 2 || STAGE == 3) pU.v[f] = a.U[0][op + f * fs];
+                if (STAGE == 4) pU.v[f] = a.A[0][op + f * fs];
             }
-        }
-        // surrogate ratios of this iteration's faces: x faces of row r-1,
-        // y faces (r-3)+1/2 (periodic images)
-        float rsx[5], rsy[5];
-        if (SUR) {
-            int jx = (r - 1) % L.ny, jy = (r - 3) % L.ny;
-            jx += jx < 0 ? L.ny : 0;
-            jy += jy < 0 ? L.ny : 0;
-            const float *px_ = a.Rs + (int64_t)jx * a.rs_pitch + cw;
-            const float *py_ = a.Rs + 5 * a.rs_plane + (int64_t)jy * a.rs_pitch + cw;
-#pragma unroll
-            for (int k = 0; k < 5; ++k) { rsx[k] = px_[k * a.rs_plane]; rsy[k] = py_[k * a.rs_plane]; }
         }
         const int slot = r & 1, pslot = slot ^ 1;
         // ================= A: row r =================
@@ -342,7 +417,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
                 const int cl = qclass(k);
                 const real q2 = sh_q[pslot][k][tid], q3 = sh_q[pslot][k][tp1];
                 real R;
-                if (SUR && rsx[k] >= 0.0f)
+                if (SUR && wkx && rsx[k] >= 0.0f)
                     R = (real)rsx[k];
                 else
                     R = hd_ratio(sh_q[pslot][k][tm2], sh_q[pslot][k][tm1], q2, q3, sh_q[pslot][k][tp2],
@@ -359,7 +434,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
             for (int k = 0; k < 5; ++k) {
                 const int cl = qclass(k);
                 real R;
-                if (SUR && rsy[k] >= 0.0f)
+                if (SUR && wky && rsy[k] >= 0.0f)
                     R = (real)rsy[k];
                 else
                     R = hd_ratio(qw[k][0], qw[k][1], qw[k][2], qw[k][3], qw[k][4], qw[k][5]);

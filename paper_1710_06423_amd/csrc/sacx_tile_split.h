@@ -11,6 +11,10 @@
 // y-face fluxes) so that each role fits in 256 registers and two waves share
 // every SIMD; what one role needs from the other goes through LDS.
 //
+// With the learned coefficient (SUR), a face whose check tile was kept and
+// whose supplied ratio is >= 0 takes that value in place of the plain ratio,
+// exactly as in the one-thread tile.
+//
 // Block: 2*NC threads over NC columns (column t = tid mod NC, the first NC
 // threads are the x role).  Per iteration r (row r is the newest state row):
 //   phase 1  X: primitives and x fluxes of row r, published with the state
@@ -96,7 +100,7 @@ __device__ __forceinline__ int ring3(int r) { return (r + 3 * 4096) % 3; }
 
 // x role: primitives and x fluxes of the newest row, D_x F_x, compression,
 // x-face G and x-face fluxes
-template <typename real, int NC, int STAGE, bool BG>
+template <typename real, int NC, int STAGE, bool BG, bool SUR>
 __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCommon<real, NC> &m,
                                         SplitLds<real, NC, BG> &lds) {
     const real half = (real)0.5, two = (real)2, eight = (real)8, zero = (real)0;
@@ -145,11 +149,33 @@ __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCom
         }
     }
 
+    // surrogate: this column's periodic image in the ratio planes, its
+    // column of check tiles and the tile flag of the x faces of row r-1
+    // (loaded one iteration ahead)
+    const int cw = SUR ? ((m.c % L.nx) + L.nx) % L.nx : 0;
+    const int ckx = SUR ? cw / a.rs_tile : 0;
+    SurRow wx{};
+    int fk = 0;
+    if (SUR) {
+        wx.set(a, m.rbeg - 1);
+        fk = sur_kept(a, wx, ckx);
+    }
+
     for (int r = m.rbeg; r <= m.rend; ++r) {
         const int slot = r & 1, pslot = slot ^ 1;
         const int s1 = ring3(r - 1);              // ring slot of row r-1
         const int sy = (r - 3 + 2 * 4096) & 1;    // ring slot of face (r-3)+1/2
         const int syp = sy ^ 1;
+        // surrogate ratios of the x faces of row r-1 (used in phase 2); a
+        // wave none of whose lanes is in a kept tile takes the plain path
+        float rsx[5];
+        bool wk = false;
+        if (SUR) {
+            wk = __ballot(fk) != 0;
+            if (wk) sur_planes(a, wx, fk, cw, 0, rsx);
+            wx.next(a);
+            fk = sur_kept(a, wx, ckx);
+        }
         // ---------- phase 1: row r ----------
         const Row6<real> cur = n1;
         n1 = n2;
@@ -162,8 +188,11 @@ __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCom
 #pragma unroll
             for (int f = 0; f < NBG; ++f) g1[f] = g2[f];
         }
-        if (r + 2 <= m.rend) {
-            const int64_t rn = m.colofs + (int64_t)(r + 2 + G) * L.pitch;
+        // (with the surrogate the load is unconditional: past the last row
+        // it re-reads that row, unused)
+        if (SUR || r + 2 <= m.rend) {
+            const int rn_row = SUR ? min(r + 2, m.rend) : r + 2;
+            const int64_t rn = m.colofs + (int64_t)(rn_row + G) * L.pitch;
 #pragma unroll
             for (int f = 0; f < NF; ++f) n2.v[f] = a.S[0][rn + f * fs];
             if (BG) {
@@ -217,10 +246,27 @@ __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCom
         vyw[0] = vyw[1];
         vyw[1] = vy;
         real Rx[5];
+        if (SUR && wk) {
+            // a face takes its supplied value where it is >= 0; the plain
+            // ratios are computed only by waves with a lane that needs one
+            bool plain = false;
 #pragma unroll
-        for (int k = 0; k < 5; ++k)
-            Rx[k] = hd_ratio(lds.q[pslot][k][tm2], lds.q[pslot][k][tm1], lds.q[pslot][k][t], lds.q[pslot][k][tp1],
-                             lds.q[pslot][k][tp2], lds.q[pslot][k][tp3]);
+            for (int k = 0; k < 5; ++k) { Rx[k] = zero; plain = plain || !(rsx[k] >= 0.0f); }
+            if (plain) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k)
+                    Rx[k] = hd_ratio(lds.q[pslot][k][tm2], lds.q[pslot][k][tm1], lds.q[pslot][k][t],
+                                     lds.q[pslot][k][tp1], lds.q[pslot][k][tp2], lds.q[pslot][k][tp3]);
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+                if (rsx[k] >= 0.0f) Rx[k] = (real)rsx[k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 5; ++k)
+                Rx[k] = hd_ratio(lds.q[pslot][k][tm2], lds.q[pslot][k][tm1], lds.q[pslot][k][t],
+                                 lds.q[pslot][k][tp1], lds.q[pslot][k][tp2], lds.q[pslot][k][tp3]);
+        }
         __syncthreads();  // P2
 
         // ---------- phase 3: D_x F_x of row r, x-face G of row r-1, H_x at row r-3 ----------
@@ -350,7 +396,7 @@ __device__ __forceinline__ void split_output(const StageArgs<real> &a, const Spl
 
 // y role: y-face G, y fluxes, D_y F_y, the ideal L, y-face fluxes, and one
 // iteration later L(S) of the output row and the stage combine
-template <typename real, int NC, int STAGE, bool BG>
+template <typename real, int NC, int STAGE, bool BG, bool SUR>
 __device__ __forceinline__ void split_y(const StageArgs<real> &a, const SplitCommon<real, NC> &m,
                                         SplitLds<real, NC, BG> &lds, double &cx_t, double &cy_t, int &bad_t) {
     const real half = (real)0.5, two = (real)2, eight = (real)8, zero = (real)0;
@@ -377,17 +423,42 @@ __device__ __forceinline__ void split_y(const StageArgs<real> &a, const SplitCom
 #pragma unroll
     for (int f = 0; f < NF; ++f) pUa.v[f] = 0;
 
+    // surrogate: the tile flag of the y faces (r-3)+1/2 (loaded one
+    // iteration ahead)
+    const int cw = SUR ? ((m.c % L.nx) + L.nx) % L.nx : 0;
+    const int ckx = SUR ? cw / a.rs_tile : 0;
+    SurRow wy{};
+    int fy = 0;
+    if (SUR) {
+        wy.set(a, m.rbeg - 3);
+        fy = sur_kept(a, wy, ckx);
+    }
+
     for (int r = m.rbeg; r <= m.rend; ++r) {
         const int slot = r & 1;
         const int s2 = ring3(r - 2), s3 = ring3(r - 3);
         const int sy = (r - 3 + 2 * 4096) & 1;
+        // surrogate ratios of the y faces (r-3)+1/2 (used in phase 2); a
+        // wave none of whose lanes is in a kept tile takes the plain path
+        float rsy[5];
+        bool wk = false;
+        if (SUR) {
+            wk = __ballot(fy) != 0;
+            if (wk) sur_planes(a, wy, fy, cw, 5, rsy);
+            wy.next(a);
+            fy = sur_kept(a, wy, ckx);
+        }
         // ---------- phase 1: output row r-4, operands of row r-3 ----------
         if (r - 4 >= m.y0 && m.outcol)
             split_output<real, NC, STAGE, BG>(a, m, lds, r - 4, kia, hb, ha, pUa, cx_t, cy_t, bad_t);
         const int j = r - G;
+        const bool outrow = j >= m.y0 && m.outcol;
         Row6<real> pUb;
-        if (j >= m.y0 && m.outcol) {
-            const int64_t oo = (int64_t)L.xoff + m.c + (int64_t)(j + G) * L.pitch;
+        if (SUR || outrow) {
+            // (with the surrogate the load is unconditional: a thread without
+            // an output row reads a cell of its own column instead, unused)
+            const int64_t oo = SUR && !outrow ? m.colofs + (int64_t)(max(j, m.y0) + G) * L.pitch
+                                              : (int64_t)L.xoff + m.c + (int64_t)(j + G) * L.pitch;
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 if (STAGE == 2 || STAGE == 3) pUb.v[f] = a.U[0][oo + f * fs];
@@ -421,12 +492,33 @@ __device__ __forceinline__ void split_y(const StageArgs<real> &a, const SplitCom
         // s of rows r-3 and r-2
         const real sfy = fmax(lds.s[s3][t], lds.s[s2][t]);
         real gyn[5];
+        if (SUR && wk) {
+            // a face takes its supplied value where it is >= 0; the plain
+            // ratios are computed only by waves with a lane that needs one
+            real Ry[5];
+            bool plain = false;
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
-            const int cl = qclass(k);
-            const real R = hd_ratio(qw[k][0], qw[k][1], qw[k][2], qw[k][3], qw[k][4], qw[k][5]);
-            const real nu = m.ky2[cl] * R + (real)kc.kys[cl] * sfy;
-            gyn[k] = nu * (qw[k][3] - qw[k][2]) * m.idy;
+            for (int k = 0; k < 5; ++k) { Ry[k] = zero; plain = plain || !(rsy[k] >= 0.0f); }
+            if (plain) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k)
+                    Ry[k] = hd_ratio(qw[k][0], qw[k][1], qw[k][2], qw[k][3], qw[k][4], qw[k][5]);
+            }
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                if (rsy[k] >= 0.0f) Ry[k] = (real)rsy[k];
+                const int cl = qclass(k);
+                const real nu = m.ky2[cl] * Ry[k] + (real)kc.kys[cl] * sfy;
+                gyn[k] = nu * (qw[k][3] - qw[k][2]) * m.idy;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                const int cl = qclass(k);
+                const real R = hd_ratio(qw[k][0], qw[k][1], qw[k][2], qw[k][3], qw[k][4], qw[k][5]);
+                const real nu = m.ky2[cl] * R + (real)kc.kys[cl] * sfy;
+                gyn[k] = nu * (qw[k][3] - qw[k][2]) * m.idy;
+            }
         }
         lds.gy[0][sy][t] = gyn[QVX];
         lds.gy[1][sy][t] = gyn[QB];
@@ -515,7 +607,7 @@ __device__ __forceinline__ void split_y(const StageArgs<real> &a, const SplitCom
         split_output<real, NC, STAGE, BG>(a, m, lds, m.rend - G, kia, hb, ha, pUa, cx_t, cy_t, bad_t);
 }
 
-template <typename real, int NC, int STAGE, bool BG>
+template <typename real, int NC, int STAGE, bool BG, bool SUR = false>
 __device__ __forceinline__ void stage_tile_split(const StageArgs<real> &a, int tile_x, int tile_y,
                                                  SplitLds<real, NC, BG> &lds) {
     if (!a.sc->active) return;
@@ -528,9 +620,9 @@ __device__ __forceinline__ void stage_tile_split(const StageArgs<real> &a, int t
     double cx_t = 0.0, cy_t = 0.0;
     int bad_t = 0;
     if (xrole)
-        split_x<real, NC, STAGE, BG>(a, m, lds);
+        split_x<real, NC, STAGE, BG, SUR>(a, m, lds);
     else
-        split_y<real, NC, STAGE, BG>(a, m, lds, cx_t, cy_t, bad_t);
+        split_y<real, NC, STAGE, BG, SUR>(a, m, lds, cx_t, cy_t, bad_t);
 
     if (STAGE == 4) {
         // block reduction of the wave speeds, one atomic per block

@@ -237,6 +237,50 @@ def test_check_mask_matches_oracle(sx, metric):
     assert 0 < nf < mask.size
 
 
+@pytest.mark.parametrize("split,threads", [(True, 64), (True, 128), (True, 256), (False, 128), (False, 256)])
+def test_fallen_back_tiles_read_no_planes(sx, split, threads):
+    """One check leaves some tiles fallen back (planes -1) and the others
+    kept; the fallen-back tiles' planes are then
+    overwritten with positive values, which the stages must not read.  Eleven
+    more steps equal the oracle's supplied-ratio scheme on the planes as the
+    check left them, bit for bit, in the FP64 two-role tile at every block
+    width and in the one-thread tile."""
+    prob, ref = _pair(96, 70, 3)
+    rng = np.random.default_rng(21)
+    rnn = ref.ratio_fields().astype(np.float32)
+    tile = 20
+    for ty in range(4):
+        for tx in range(5):
+            sl = (slice(None), slice(ty * tile, (ty + 1) * tile), slice(tx * tile, (tx + 1) * tile))
+            if (tx + ty) % 2:
+                rnn[sl] += rng.normal(0, 0.03, size=rnn[sl].shape).astype(np.float32)
+            else:
+                rnn[sl] *= np.float32(1.0 + 1e-3)   # within the bound: kept
+    s = sx.Solver.from_problem(prob, device=DEV)
+    s.set_column_split(split)
+    s.set_launch(threads=threads)
+    s.advance(3)
+    s.set_surrogate(None, (0.0,) * 6 + (1.0,) * 6, refresh_every=10 ** 6, tile=tile, bound=0.01, metric=0)
+    s.ratio_buffer().copy_(torch.from_numpy(rnn))
+    s.advance(1)
+    left = s.ratio_buffer().cpu().numpy()
+    mask, nf, _, _ = oracle.hd_check(ref.cfg, ref.f, rnn, 0.01, tile, 0)
+    assert nf == 10, nf
+    buf = s.ratio_buffer()
+    for ty in range(4):
+        for tx in range(5):
+            if mask[ty, tx]:
+                buf[:, ty * tile:(ty + 1) * tile, tx * tile:(tx + 1) * tile] = 7.0
+    s.advance(11)
+    ref.advance_ext(12, left)
+    got = s.read_fields().cpu().numpy()
+    print(f"[surrogate tiles] split={split} threads={threads}: differing {int(np.sum(got != ref.stacked()))}",
+          flush=True)
+    assert np.array_equal(got, ref.stacked())
+    st = s.hd_stats()
+    assert st["refreshes"] == 1 and st["tiles_fallback"] == nf
+
+
 @pytest.mark.parametrize("weights,metric", [("zero", 0), ("nan", 0), ("nan", 1)])
 def test_bad_network_falls_back_everywhere(sx, sur, weights, metric):
     """Zeroed or corrupted weights: every tile falls back and the run is the
