@@ -157,12 +157,14 @@ struct RatioArgs {
     double gm1, igm1;
 };
 
-// device-side surrogate counters
+// device-side surrogate counters.  A check's blocks update one of kStatSlots
+// copies of each counter (by block index), so that thousands of blocks do
+// not contend for one word; the reader reduces the copies.
+constexpr int kStatSlots = 64;
 struct HdDevStats {
-    unsigned long long tiles_fallback;
-    unsigned long long err_used;   // IEEE bits of a non-negative double (max)
-    unsigned long long err_all;
-    unsigned long long pad;
+    unsigned long long tiles_fallback[kStatSlots];
+    unsigned long long err_used[kStatSlots];   // IEEE bits of a non-negative double (max)
+    unsigned long long err_all[kStatSlots];
     unsigned long long dmax[10];   // per plane max |first difference| of the current check
 };
 

@@ -125,7 +125,9 @@ __global__ __launch_bounds__(256) void k_d1_max(RatioArgs<real> a, HdDevStats *s
     if (threadIdx.x < 10) {
         const int k = threadIdx.x;
         const double v = fmax(fmax(red[0][k], red[1][k]), fmax(red[2][k], red[3][k]));
-        atomicMax(&st->dmax[k], (unsigned long long)__double_as_longlong(v));
+        const unsigned long long vb = (unsigned long long)__double_as_longlong(v);
+        if (vb > __hip_atomic_load(&st->dmax[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&st->dmax[k], vb);
     }
 }
 
@@ -137,15 +139,31 @@ __global__ __launch_bounds__(256) void k_d1_max(RatioArgs<real> a, HdDevStats *s
 // tile of every plane is set to -1 (plain ratio).  kept[tile] records the
 // outcome (1 kept, 0 fell back) for the stage kernels, which read no plane
 // of a fallen-back tile.  Arithmetic in the working precision.
+//
+// The tile is worked in sub-tiles of at most 256 cells (kCheckW x kCheckH
+// for the tile's side): the quantity sets of the sub-tile's cells and of
+// the apron its faces reach (two cells before, three after, in each
+// direction) are formed once into LDS, then each thread takes one cell's
+// ten faces from there.  The values are those of cell_ratios.
+__host__ __device__ constexpr int check_sub_w(int tile) { return tile < 64 ? tile : 64; }
+__host__ __device__ constexpr int check_sub_h(int tile) {
+    return (256 / check_sub_w(tile)) < tile ? (256 / check_sub_w(tile)) : tile;
+}
+// largest (w + 5) (h + 5) over every tile side (reached from side 64 on)
+constexpr int kCheckLds = 69 * 9;
+
 template <typename real, int METRIC>
 __global__ __launch_bounds__(256) void k_hd_check(RatioArgs<real> a, float *rs, int64_t pitch, double bound,
                                                   int tile, HdDevStats *st, unsigned char *kept) {
+    __shared__ real sq[6][kCheckLds];
     __shared__ double s_err[4];
     __shared__ int s_bad[4];
     const int ntx = (a.L.nx + tile - 1) / tile;
     const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
     const int i0 = tx * tile, j0 = ty * tile;
     const int wx = min(tile, a.L.nx - i0), wy = min(tile, a.L.ny - j0);
+    const int SW = check_sub_w(tile), SH = check_sub_h(tile);
+    const int LW = SW + 5;
     const int64_t plane = pitch * a.L.ny;
     const real b = (real)bound;
     real dm[10];
@@ -155,17 +173,56 @@ __global__ __launch_bounds__(256) void k_hd_check(RatioArgs<real> a, float *rs, 
     }
     double emax = 0.0;
     int bad = 0;
-    for (int c = threadIdx.x; c < wx * wy; c += 256) {
-        const int i = i0 + c % wx, j = j0 + c / wx;
-        real R[10], D[10];
-        cell_ratios(a, i, j, R, D);
+    for (int sj = 0; sj < wy; sj += SH) {
+        for (int si = 0; si < wx; si += SW) {
+            const int bi = i0 + si, bj = j0 + sj;               // sub-tile origin
+            const int cw = min(SW, wx - si), ch = min(SH, wy - sj);
+            const bool own = (int)threadIdx.x < cw * ch;
+            const int li = own ? threadIdx.x % cw : 0, lj = own ? threadIdx.x / cw : 0;
+            const int i = bi + li, j = bj + lj;
+            // this thread's plane values, issued before the quantity loads so
+            // that the two groups of loads are in flight together
+            float rv[10];
 #pragma unroll
-        for (int k = 0; k < 10; ++k) {
-            const float rv = rs[k * plane + (int64_t)j * pitch + i];
-            real e = fabs((real)rv - R[k]);
-            if (METRIC == 1) e = dm[k] > (real)0 ? (e * fabs(D[k])) / dm[k] : (real)0;
-            if (!isfinite(rv) || !(e <= b)) bad = 1;
-            if (isfinite(e)) emax = fmax(emax, (double)e);
+            for (int k = 0; k < 10; ++k) rv[k] = own ? rs[k * plane + (int64_t)j * pitch + i] : 0.0f;
+            __syncthreads();   // the previous sub-tile's reads are done
+            // quantity sets of the cells the faces use: the sub-tile's rows
+            // with the x apron, its columns with the y apron (LDS cell (ci, cj)
+            // is cell (bi - 2 + ci, bj - 2 + cj)); at most three per thread,
+            // their loads issued together
+            const int nc = LW * (ch + 5);
+#pragma unroll
+            for (int u = 0; u < (kCheckLds + 255) / 256; ++u) {
+                const int c = (int)threadIdx.x + 256 * u;
+                const int ci = c % LW, cj = c / LW;
+                const bool need = c < nc && ((cj >= 2 && cj < 2 + ch && ci < cw + 5) || (ci >= 2 && ci < 2 + cw));
+                if (need) {
+                    real q[6];
+                    cell_quantities(a, bi - 2 + ci, bj - 2 + cj, q);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) sq[k][c] = q[k];
+                }
+            }
+            __syncthreads();
+            if (own) {
+                const int cx = (lj + 2) * LW + li;   // x faces: row lj + 2, columns li .. li + 5
+                const int cy = lj * LW + li + 2;     // y faces: column li + 2, rows lj .. lj + 5
+#pragma unroll
+                for (int k = 0; k < 10; ++k) {
+                    // B~_y on x faces, B~_x on y faces
+                    const int kq = k < 5 ? k : (k == 9 ? 5 : k - 5);
+                    const real *p = sq[kq] + (k < 5 ? cx : cy);
+                    const int st_ = k < 5 ? 1 : LW;
+                    const real R = hd_ratio(p[0], p[st_], p[2 * st_], p[3 * st_], p[4 * st_], p[5 * st_]);
+                    real e = fabs((real)rv[k] - R);
+                    if (METRIC == 1) {
+                        const real D = p[3 * st_] - p[2 * st_];
+                        e = dm[k] > (real)0 ? (e * fabs(D)) / dm[k] : (real)0;
+                    }
+                    if (!isfinite(rv[k]) || !(e <= b)) bad = 1;
+                    if (isfinite(e)) emax = fmax(emax, (double)e);
+                }
+            }
         }
     }
     for (int off = 32; off > 0; off >>= 1) {
@@ -178,9 +235,15 @@ __global__ __launch_bounds__(256) void k_hd_check(RatioArgs<real> a, float *rs, 
     const int bt = s_bad[0] | s_bad[1] | s_bad[2] | s_bad[3];
     if (threadIdx.x == 0) {
         kept[blockIdx.x] = bt ? 0 : 1;
-        atomicMax(&st->err_all, (unsigned long long)__double_as_longlong(et));
-        if (bt) atomicAdd(&st->tiles_fallback, 1ull);
-        else atomicMax(&st->err_used, (unsigned long long)__double_as_longlong(et));
+        // this block's copy of the counters; a maximum is only sent when it
+        // may raise the copy (the atomic decides)
+        const int sl = blockIdx.x & (kStatSlots - 1);
+        const unsigned long long eb = (unsigned long long)__double_as_longlong(et);
+        if (eb > __hip_atomic_load(&st->err_all[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&st->err_all[sl], eb);
+        if (bt) atomicAdd(&st->tiles_fallback[sl], 1ull);
+        else if (eb > __hip_atomic_load(&st->err_used[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+            atomicMax(&st->err_used[sl], eb);
     }
     if (bt) {
         for (int c = threadIdx.x; c < wx * wy; c += 256) {

@@ -1392,7 +1392,7 @@ __global__ void k_fill_f32(float *p, int64_t n, float v) {
 __global__ void k_zero_stats(HdDevStats *st) {
     unsigned long long *p = (unsigned long long *)st;
     const int n = (int)(sizeof(HdDevStats) / sizeof(unsigned long long));
-    if (blockIdx.x == 0 && (int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) p[i] = 0ull;
 }
 
 struct SurPlan {
@@ -1504,10 +1504,18 @@ int sacx_hd_read_stats(sacx_ctx *ctx, sacx_hd_stats *out) {
     HIPCHK(hipStreamSynchronize(ctx->stream));
     out->refreshes = ctx->sur_refreshes;
     out->tiles_checked = ctx->sur_tiles_checked;
-    out->tiles_fallback = (int64_t)h.tiles_fallback;
+    // reduce the counters' copies (maxima of non-negative doubles are the
+    // maxima of their bit patterns)
+    unsigned long long nf = 0, bu = 0, ba = 0;
+    for (int k = 0; k < kStatSlots; ++k) {
+        nf += h.tiles_fallback[k];
+        bu = std::max(bu, h.err_used[k]);
+        ba = std::max(ba, h.err_all[k]);
+    }
+    out->tiles_fallback = (int64_t)nf;
     double eu, ea;
-    std::memcpy(&eu, &h.err_used, sizeof(eu));
-    std::memcpy(&ea, &h.err_all, sizeof(ea));
+    std::memcpy(&eu, &bu, sizeof(eu));
+    std::memcpy(&ea, &ba, sizeof(ea));
     out->err_used = eu;
     out->err_all = ea;
     return SACX_OK;

@@ -202,16 +202,19 @@ def test_supplied_ratios_bitexact(sx, gravity):
     assert st["refreshes"] == 1 and st["tiles_fallback"] == 0
 
 
-@pytest.mark.parametrize("metric", [0, 1])
-def test_check_mask_matches_oracle(sx, metric):
+@pytest.mark.parametrize("metric,tile", [(0, 20), (1, 20), (0, 1), (1, 7), (0, 70), (1, 70)])
+def test_check_mask_matches_oracle(sx, metric, tile):
+    """The check's fallback mask, counts and error maxima equal the oracle's
+    exactly, for check tiles of one cell, ragged tiles, tiles worked in
+    several sub-tiles and tiles wider than a sub-tile."""
     prob, ref = _pair(96, 70, 3)
     rng = np.random.default_rng(9)
     R = ref.ratio_fields().astype(np.float32)
     rnn = R.copy()
-    tile = 20
-    for ty in range(4):
-        for tx in range(5):
-            if rng.uniform() < 0.5:
+    nty, ntx = -(-70 // tile), -(-96 // tile)
+    for ty in range(nty):
+        for tx in range(ntx):
+            if rng.uniform() < 0.5 and (tx, ty) != (0, 0):   # tile (0, 0) stays kept
                 sl = (slice(None), slice(ty * tile, (ty + 1) * tile), slice(tx * tile, (tx + 1) * tile))
                 rnn[sl] += rng.normal(0, 0.03 if metric == 0 else 0.3, size=rnn[sl].shape).astype(np.float32)
     rnn[3, 65, 90] = np.nan
