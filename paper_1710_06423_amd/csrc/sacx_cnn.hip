@@ -132,20 +132,39 @@ struct ConvArgs {
     float *out;                  // final output planes
     int64_t out_img, out_plane, out_row;
     int n, h, w;
+    int rows;                    // output rows per block
 };
 
-// One wave computes 16 output pixels x (16 MB) channels per work item; the
-// waves of the grid stride over all items.
+// Row-streamed implicit GEMM: a block of 4 waves owns a strip of kStrip
+// output pixels (16 per wave) of one image over a.rows output rows.  The
+// input rows its taps reach -- the strip's pixels and one more on each side,
+// periodic -- pass through an LDS ring of 4 rows: each is loaded from memory
+// once per strip, while the row before it is being multiplied, and every
+// tap's B operand is a 16-byte LDS read.  One barrier per output row.
+constexpr int kStrip = 64;
+
 template <int CIN, int NCHUNK, int MB, int MODE>
 __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int kg = lane >> 4, px = lane & 15;
-    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int64_t nwaves = (int64_t)gridDim.x * 4;
-    const int wg = a.w >> 4;
-    const int64_t per_img = (int64_t)a.h * wg;
-    const int64_t items = (int64_t)a.n * per_img;
+    constexpr int LW = kStrip + 2;          // pixels of an LDS row
+    constexpr int VPP = CIN / 8;            // 16-byte vectors per pixel
+    constexpr int NV = LW * VPP;            // vectors per LDS row
+    constexpr int NLD = (NV + 255) / 256;   // row loads per thread
     constexpr int SIGN = MODE == MODE_BWD ? -1 : 1;
+    // (rows padded to whole loads per thread, so that every thread stores
+    // its loads unconditionally)
+    __shared__ u32x4 ring[4][NLD * 256];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int kg = lane >> 4, px = lane & 15;
+    const int strips = (a.w + kStrip - 1) / kStrip;
+    const int groups = (a.h + a.rows - 1) / a.rows;
+    int b = blockIdx.x;
+    const int img = b / (strips * groups);
+    b -= img * strips * groups;
+    const int gy = b / strips, sx = b - gy * strips;
+    const int x0 = sx * kStrip, y0 = gy * a.rows, y1 = min(y0 + a.rows, a.h);
+    const int x = x0 + 16 * wv + px;         // this lane's output pixel
+    const bool act = x0 + 16 * wv < a.w;     // the wave has output pixels (w is a multiple of 16)
+    const int64_t ibase = (int64_t)img * a.h;
 
     bf16x8 A[NCHUNK][MB];
 #pragma unroll
@@ -153,12 +172,45 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) A[q][mb] = as_bf(a.wa[(q * MB + mb) * 64 + lane]);
 
-    for (int64_t it = wave; it < items; it += nwaves) {
-        const int img = (int)(it / per_img);
-        const int rem = (int)(it - (int64_t)img * per_img);
-        const int y = rem / wg;
-        const int x = (rem - y * wg) * 16 + px;
-        const int64_t ibase = (int64_t)img * a.h;
+    // this thread's share of an LDS row: vector i = threadIdx.x + 256 u is
+    // part i % VPP of LDS pixel i / VPP, image column x0 - 1 + i / VPP
+    // (periodic); threads past the row re-load its last vector, unused
+    int64_t coff[NLD];
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+        const int i = min((int)threadIdx.x + 256 * u, NV - 1);
+        const int p = i / VPP;
+        const int xx = ((x0 - 1 + p) % a.w + a.w) % a.w;
+        coff[u] = (int64_t)xx * CIN + (i - p * VPP) * 8;
+    }
+    auto load_row = [&](int yy, u32x4 (&v)[NLD]) __attribute__((always_inline)) {
+        const int64_t rb = (ibase + wrapi(yy, a.h)) * a.w * CIN;
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) v[u] = *(const u32x4 *)(a.x + rb + coff[u]);
+    };
+    auto store_row = [&](int slot, const u32x4 (&v)[NLD]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) ring[slot][threadIdx.x + 256 * u] = v[u];
+    };
+    // this lane's biases (forward modes), read once: a global read in the
+    // row loop would make the wave wait for the rows in flight
+    float bias[MB][4];
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int o = mb * 16 + 4 * kg + e;
+            bias[mb][e] = MODE == MODE_BWD || (MODE == MODE_FINAL && o >= 10) ? 0.0f : a.bias[o];
+        }
+    // backward: the layer-input activation of the row's pixels (the ReLU
+    // mask), issued before the row loads that follow it
+    auto load_mask = [&](int y, u32x2 (&m)[MB]) __attribute__((always_inline)) {
+        const int64_t pix = (ibase + y) * a.w + (act ? x : 0);
+#pragma unroll
+        for (int mb = 0; mb < MB; ++mb) m[mb] = *(const u32x2 *)(a.mask + pix * AC + mb * 16 + 4 * kg);
+    };
+    auto mul_store = [&](int y, const u32x2 (&mk)[MB]) __attribute__((always_inline)) {
+        if (!act) return;
         f32x4 acc[MB];
 #pragma unroll
         for (int mb = 0; mb < MB; ++mb) acc[mb] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -168,9 +220,9 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
             const int t = k0 / CIN, c0 = k0 % CIN;
             u32x4 bv = u32x4{0u, 0u, 0u, 0u};
             if (t < 9) {
-                const int yy = wrapi(y + SIGN * (t / 3 - 1), a.h);
-                const int xx = wrapi(x + SIGN * (t % 3 - 1), a.w);
-                bv = *(const u32x4 *)(a.x + (((ibase + yy) * a.w + xx) * CIN + c0));
+                const int ry = y + SIGN * (t / 3 - 1);
+                const int lx = 16 * wv + px + 1 + SIGN * (t % 3 - 1);
+                bv = ring[(ry - y0 + 1) & 3][lx * VPP + c0 / 8];
             }
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb)
@@ -184,7 +236,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
                 const int o0 = mb * 16 + 4 * kg;
                 float v[4];
 #pragma unroll
-                for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[mb][e] + a.bias[o0 + e], 0.0f);
+                for (int e = 0; e < 4; ++e) v[e] = fmaxf(acc[mb][e] + bias[mb][e], 0.0f);
                 *(u32x2 *)(a.y + pix * AC + o0) = u32x2{pack2(v[0], v[1]), pack2(v[2], v[3])};
             }
         } else if (MODE == MODE_FINAL) {
@@ -192,7 +244,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
             for (int e = 0; e < 4; ++e) {
                 const int o = 4 * kg + e;
                 if (o < 10) {
-                    const float z = acc[0][e] + a.bias[o];
+                    const float z = acc[0][e] + bias[0][e];
                     a.out[img * a.out_img + o * a.out_plane + y * a.out_row + x] = 4.0f / (1.0f + expf(-z));
                 }
             }
@@ -200,7 +252,7 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
 #pragma unroll
             for (int mb = 0; mb < MB; ++mb) {
                 const int c0 = mb * 16 + 4 * kg;
-                const u32x2 m = *(const u32x2 *)(a.mask + pix * AC + c0);
+                const u32x2 m = mk[mb];
                 const unsigned short mh[4] = {(unsigned short)(m[0] & 0xffff), (unsigned short)(m[0] >> 16),
                                               (unsigned short)(m[1] & 0xffff), (unsigned short)(m[1] >> 16)};
                 float v[4];
@@ -209,6 +261,42 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs a) {
                 *(u32x2 *)(a.y + pix * AC + c0) = u32x2{pack2(v[0], v[1]), pack2(v[2], v[3])};
             }
         }
+    };
+
+    // input row r lives in slot (r - y0 + 1) & 3; rows y0-1, y0, y0+1 first.
+    // An output row y multiplies from the ring and stores its outputs, then
+    // issues the loads of row y+3 and stores row y+2, in flight since the
+    // previous output row: each row has a row of work to arrive.  The loop
+    // is unrolled over the two register sets so that neither is copied while
+    // its loads are in flight, and a row's loads come after the output
+    // stores, so that the wait for the row before it leaves them in flight.
+    // Past the strip's last row the loads re-read that row, unused.
+    u32x4 ra[NLD], rb[NLD];
+    {
+        u32x4 v0[NLD], v1[NLD], v2[NLD];
+        load_row(y0 - 1, v0);
+        load_row(y0, v1);
+        load_row(y0 + 1, v2);
+        load_row(min(y0 + 2, y1), ra);
+        store_row(0, v0);
+        store_row(1, v1);
+        store_row(2, v2);
+    }
+    __syncthreads();
+    u32x2 mk[MB];
+    for (int y = y0; y < y1; y += 2) {
+        if (MODE == MODE_BWD) load_mask(y, mk);
+        mul_store(y, mk);
+        load_row(min(y + 3, y1), rb);
+        // slot of row y+2 held row y-2, read by no one since the last barrier
+        store_row((y + 3 - y0) & 3, ra);
+        __syncthreads();
+        if (y + 1 >= y1) break;
+        if (MODE == MODE_BWD) load_mask(y + 1, mk);
+        mul_store(y + 1, mk);
+        load_row(min(y + 4, y1), ra);
+        store_row((y + 4 - y0) & 3, rb);
+        __syncthreads();
     }
 }
 
@@ -409,9 +497,12 @@ __global__ void k_adam(float *__restrict__ th, float *__restrict__ m, float *__r
 }
 
 // ------------------------------------------------------------- host side
-static int conv_blocks(int64_t items) {
-    const int64_t waves = std::min<int64_t>(items, 4096);
-    return (int)std::max<int64_t>(1, (waves + 3) / 4);
+// output rows per block: about 2048 blocks (a few per compute unit), at
+// least 4 rows (each strip re-reads two apron rows)
+static int conv_rows(int n, int h, int w) {
+    const int64_t strips = (int64_t)n * ((w + kStrip - 1) / kStrip);
+    const int64_t r = (strips * h + 2047) / 2048;
+    return (int)std::min<int64_t>(h, std::max<int64_t>(4, r));
 }
 
 static hipError_t launch_conv(int layer, int mode, const unsigned char *pk, const void *x, const void *mask,
@@ -425,7 +516,8 @@ static hipError_t launch_conv(int layer, int mode, const unsigned char *pk, cons
     a.out = out;
     a.out_img = oimg; a.out_plane = oplane; a.out_row = orow;
     a.n = n; a.h = h; a.w = w;
-    const int blocks = conv_blocks((int64_t)n * h * (w / 16));
+    a.rows = conv_rows(n, h, w);
+    const int blocks = n * ((w + kStrip - 1) / kStrip) * ((h + a.rows - 1) / a.rows);
     const u32x4 *v = (const u32x4 *)pk;
     if (mode == MODE_BWD) {
         if (layer == 3) { a.wa = v + VB3; k_conv<G3C, 5, 2, MODE_BWD><<<blocks, 256, 0, s>>>(a); }
