@@ -266,8 +266,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
             if (wky) sur_planes(a, wy, fky, cw, 5, rsy);
             wx.next(a);
             wy.next(a);
-            fkx = sur_kept(a, wx, ckx);
-            fky = sur_kept(a, wy, ckx);
+            // (reloaded when a face row enters a new row of check tiles)
+            if (wx.in == 0) fkx = sur_kept(a, wx, ckx);
+            if (wy.in == 0) fky = sur_kept(a, wy, ckx);
         }
         const Row6<real> cur = nxt;
         // (with the surrogate every load of the iteration is unconditional,

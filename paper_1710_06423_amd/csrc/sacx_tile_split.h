@@ -151,7 +151,8 @@ __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCom
 
     // surrogate: this column's periodic image in the ratio planes, its
     // column of check tiles and the tile flag of the x faces of row r-1
-    // (loaded one iteration ahead)
+    // (loaded one iteration ahead, when the row enters a new row of check
+    // tiles)
     const int cw = SUR ? ((m.c % L.nx) + L.nx) % L.nx : 0;
     const int ckx = SUR ? cw / a.rs_tile : 0;
     SurRow wx{};
@@ -174,7 +175,7 @@ __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCom
             wk = __ballot(fk) != 0;
             if (wk) sur_planes(a, wx, fk, cw, 0, rsx);
             wx.next(a);
-            fk = sur_kept(a, wx, ckx);
+            if (wx.in == 0) fk = sur_kept(a, wx, ckx);   // a new row of check tiles
         }
         // ---------- phase 1: row r ----------
         const Row6<real> cur = n1;
@@ -424,7 +425,7 @@ __device__ __forceinline__ void split_y(const StageArgs<real> &a, const SplitCom
     for (int f = 0; f < NF; ++f) pUa.v[f] = 0;
 
     // surrogate: the tile flag of the y faces (r-3)+1/2 (loaded one
-    // iteration ahead)
+    // iteration ahead, when the face row enters a new row of check tiles)
     const int cw = SUR ? ((m.c % L.nx) + L.nx) % L.nx : 0;
     const int ckx = SUR ? cw / a.rs_tile : 0;
     SurRow wy{};
@@ -446,7 +447,7 @@ __device__ __forceinline__ void split_y(const StageArgs<real> &a, const SplitCom
             wk = __ballot(fy) != 0;
             if (wk) sur_planes(a, wy, fy, cw, 5, rsy);
             wy.next(a);
-            fy = sur_kept(a, wy, ckx);
+            if (wy.in == 0) fy = sur_kept(a, wy, ckx);   // a new row of check tiles
         }
         // ---------- phase 1: output row r-4, operands of row r-3 ----------
         if (r - 4 >= m.y0 && m.outcol)
