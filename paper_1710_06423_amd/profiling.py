@@ -3,11 +3,15 @@
   python -m paper_1710_06423_amd.profiling stats  STATS_CSV BENCH_LOG OUT_MD TITLE COMMAND
   python -m paper_1710_06423_amd.profiling sq     COUNTER_CSV BENCH_LOG OUT_MD COMMAND
   python -m paper_1710_06423_amd.profiling table  STATS_CSV BENCH_LOG OUT_MD TITLE COMMAND [NOTE...]
+  python -m paper_1710_06423_amd.profiling select STATS_CSV BENCH_LOG OUT_MD TITLE PATTERN COMMAND [NOTE...]
   python -m paper_1710_06423_amd.profiling traffic FETCH_CSV WRITE_CSV CFETCH_CSV CWRITE_CSV COPY_BYTES
                                                   BENCH_LOG OUT_MD COMMANDS...
+  python -m paper_1710_06423_amd.profiling kernels SQ_CSV FETCH_CSV WRITE_CSV CFETCH_CSV CWRITE_CSV COPY_BYTES
+                                                  PATTERN BENCH_LOG OUT_MD TITLE COMMANDS...
 
 `stats` turns a --kernel-trace --stats kernel summary into a table and
 compares the mean stage-kernel launch with the bench's own HIP-event timing.
+`kernels` gives both, per kernel matching PATTERN, for any launch.
 `traffic` turns two --pmc passes (FETCH_SIZE, WRITE_SIZE, KiB per dispatch)
 over the stage kernel and the same two passes over a device copy of known
 size into HBM bytes per stage launch: each counter is divided by what it
@@ -158,11 +162,15 @@ def traffic_summary(fetch_csv: str, write_csv: str, cfetch_csv: str, cwrite_csv:
 
 
 def table_summary(stats_csv: str, bench_log: str, title: str, command: str, notes: List[str],
-                  top: int = 16) -> str:
-    """Any kernel trace as a table (the `top` kernels by GPU time), with the
-    bench line of the same run."""
+                  top: int = 16, pattern: Optional[str] = None) -> str:
+    """Any kernel trace as a table (the `top` kernels by GPU time, or every
+    kernel whose name matches `pattern`), with the bench line of the same
+    run."""
     rows = list(csv.DictReader(open(stats_csv)))
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    if pattern is not None:
+        rows = [r for r in rows if re.search(pattern, _short(r["Name"]))]
+        top = len(rows)
     b = _bench_line(bench_log)
     out = [f"# {title}", "", "Command (repository root on the GPU host):", "", "    " + command, ""]
     out += [n for n in notes] + ([""] if notes else [])
@@ -204,6 +212,45 @@ def sq_summary(counter_csv: str, bench_log: str, command: str) -> str:
     return "\n".join(lines) + "\n"
 
 
+def kernels_summary(sq_csv: str, fetch_csv: str, write_csv: str, cfetch_csv: str, cwrite_csv: str,
+                    copy_bytes: int, pattern: str, bench_log: str, title: str, commands: List[str],
+                    copy_pattern: str = "copyBuffer") -> str:
+    """Per kernel matching `pattern`: the instruction mix (the SQ counters of
+    `sq_summary`) and its HBM bytes per dispatch from FETCH_SIZE and
+    WRITE_SIZE, calibrated against a device copy of known size as in
+    `traffic_summary`, also per cell of the bench's grid."""
+    b = _bench_line(bench_log)
+    agg: Dict[str, Dict[str, float]] = {}
+    for r in csv.DictReader(open(sq_csv)):
+        name = _short(r["Kernel_Name"])
+        if not re.search(pattern, name):
+            continue
+        agg.setdefault(name, {}).setdefault(r["Counter_Name"], 0.0)
+        agg[name][r["Counter_Name"]] += float(r["Counter_Value"])
+    fetch = pmc_per_kernel(fetch_csv, "FETCH_SIZE")
+    write = pmc_per_kernel(write_csv, "WRITE_SIZE")
+    kf = _mean_of(pmc_per_kernel(cfetch_csv, "FETCH_SIZE"), copy_pattern) * 1024.0 / copy_bytes
+    kw = _mean_of(pmc_per_kernel(cwrite_csv, "WRITE_SIZE"), copy_pattern) * 1024.0 / copy_bytes
+    cfg = b["config"]
+    cells = cfg.get("nx", 1) * cfg.get("ny", 1) * cfg.get("nz", 1)
+    lines = [f"# {title}", "", "Commands (repository root on the GPU host), one counter set per run:", ""]
+    lines += ["    " + c for c in commands]
+    lines += ["", f"Copy calibration: {kf:.4f} (FETCH_SIZE) and {kw:.4f} (WRITE_SIZE) counter-KiB per KiB moved.",
+              f"Bench line of the fetch run: workload {cfg['workload']}, {b['value']} {b['unit']}.", "",
+              "| kernel | VALU / wave | LDS / wave | SALU / wave | VALU active / wave cycles | "
+              "waiting on counters / wave cycles | HBM read GB / dispatch | HBM written GB / dispatch | "
+              "HBM B / cell |", "|---|---|---|---|---|---|---|---|---|"]
+    for name, d in sorted(agg.items()):
+        w = d["SQ_WAVES"]
+        fb = sum(fetch.get(name, [0.0])) / max(len(fetch.get(name, [])), 1) * 1024.0 / kf
+        wb = sum(write.get(name, [0.0])) / max(len(write.get(name, [])), 1) * 1024.0 / kw
+        lines.append(f"| `{name}` | {d['SQ_INSTS_VALU'] / w:.0f} | {d['SQ_INSTS_LDS'] / w:.0f} | "
+                     f"{d['SQ_INSTS_SALU'] / w:.0f} | {d['SQ_ACTIVE_INST_VALU'] / d['SQ_WAVE_CYCLES']:.2f} | "
+                     f"{d['SQ_WAIT_INST_ANY'] / d['SQ_WAVE_CYCLES']:.2f} | {fb / 1e9:.3f} | {wb / 1e9:.3f} | "
+                     f"{(fb + wb) / cells:.0f} |")
+    return "\n".join(lines) + "\n"
+
+
 def read_traffic(path: str) -> Optional[Dict[str, float]]:
     """The traffic file's figures, or None when it is missing or was taken
     from other stage-kernel sources than the current ones."""
@@ -230,9 +277,18 @@ def main(argv: List[str]):
         text = table_summary(argv[1], argv[2], argv[4], argv[5], argv[6:])
         open(argv[3], "w").write(text)
         print(text)
+    elif argv and argv[0] == "select" and len(argv) >= 7:
+        text = table_summary(argv[1], argv[2], argv[4], argv[6], argv[7:], pattern=argv[5])
+        open(argv[3], "w").write(text)
+        print(text)
     elif argv and argv[0] == "sq" and len(argv) == 5:
         text = sq_summary(argv[1], argv[2], argv[4])
         open(argv[3], "w").write(text)
+        print(text)
+    elif argv and argv[0] == "kernels" and len(argv) >= 12:
+        text = kernels_summary(argv[1], argv[2], argv[3], argv[4], argv[5], int(argv[6]), argv[7], argv[8],
+                               argv[10], argv[11:])
+        open(argv[9], "w").write(text)
         print(text)
     elif argv and argv[0] == "traffic" and len(argv) >= 9:
         text = traffic_summary(argv[1], argv[2], argv[3], argv[4], int(argv[5]), argv[6], argv[8:])
