@@ -234,6 +234,21 @@ def sub_batch(args):
             "dtype": "f32 bulk, f64 dt and sums", "sampled_max_rel_l2_vs_oracle": errs}
 
 
+def phase_profile(s, steps=32):
+    """The library's own HIP-event timings (sacx_profile_*) over `steps` more
+    steps of a context: per step its stage kernels and halo fills, per
+    refresh of a learned coefficient the refresh (network inputs, network,
+    check).  Taken after the timed region; the events cost a little time."""
+    s.profile_enable(True)
+    s.advance(steps)
+    p = s.profile_read()
+    s.profile_enable(False)
+    return {"steps": steps, "stage_ms_per_step": round(sum(p["ms_stage"]) / steps, 4),
+            "halo_ms_per_step": round(p["ms_halo"] / steps, 4),
+            "refresh_ms": round(p["ms_surrogate"] / p["n_surrogate"], 4) if p["n_surrogate"] else None,
+            "refreshes": p["n_surrogate"]}
+
+
 def all_fallback_run(sur, prob, norm, K, tile, bound, steps, warmup=2):
     """Time a surrogate run whose network has zero weights, so that every
     check falls back everywhere: (ms, fallback tile fraction)."""
@@ -245,8 +260,9 @@ def all_fallback_run(sur, prob, norm, K, tile, bound, steps, warmup=2):
     s.set_surrogate(zero.packed, norm, refresh_every=K, tile=tile, bound=bound, metric=CHECK_FLUX)
     ms = timed_advance(s, steps, warmup)
     st = s.hd_stats()
+    prof = phase_profile(s)
     s.close()
-    return ms, round(st["tiles_fallback"] / max(st["tiles_checked"], 1), 4)
+    return ms, round(st["tiles_fallback"] / max(st["tiles_checked"], 1), 4), prof
 
 
 def sub_surrogate(args, log_every=1000):
@@ -276,10 +292,11 @@ def sub_surrogate(args, log_every=1000):
     ms = timed_advance(s, steps, 2)
     st = s.hd_stats()
     a = s.read_fields()
+    prof = phase_profile(s)
     s.close()
     # the same run with a network that is never kept (zero weights predict 2
     # everywhere): what the refreshes and the check cost on their own
-    ms0, fb0 = all_fallback_run(sur, prob, data.norm, K, 16, bound, steps)
+    ms0, fb0, prof0 = all_fallback_run(sur, prob, data.norm, K, 16, bound, steps)
     names = ("rho", "mx", "my", "e", "bx", "by")
     return {"workload": f"orszag_tang_{n}x{n}_fp64_hd_learned_coefficient", "steps": steps, "refresh_every": K,
             "bound": bound, "check": "flux, 16^2 tiles",
@@ -287,7 +304,9 @@ def sub_surrogate(args, log_every=1000):
             "plain_mcell_updates_s": round(n * n * steps / (ms_plain / 1e3) / 1e6, 1),
             "all_fallback_mcell_updates_s": round(n * n * steps / (ms0 / 1e3) / 1e6, 1),
             "all_fallback_tile_fraction": fb0,
+            "all_fallback_phases": prof0,
             "fallback_tile_fraction": round(st["tiles_fallback"] / max(st["tiles_checked"], 1), 4),
+            "phases": prof,
             "err_used": float("%.3e" % st["err_used"]),
             "rel_l2_vs_plain_fp64": {names[k]: float("%.3e" % rel_l2(a[k], ref[k])) for k in range(6)},
             "training": {"sides": list(SUR_SIDES), "snap_every": {str(k): v for k, v in SUR_EVERY.items()},
@@ -652,6 +671,7 @@ def run_surrogate(args):
     plain = Solver.from_problem(prob, precision=FP64)
     ms_plain = timed(plain)
     ref = plain.read_fields()
+    prof_plain = phase_profile(plain)
     names = ("rho", "mx", "my", "e", "bx", "by")
     runs = {}
     for K in (1, 4, 16):
@@ -666,14 +686,16 @@ def run_surrogate(args):
             "kept_tile_fraction": round(1 - st["tiles_fallback"] / st["tiles_checked"], 4),
             "err_used": float("%.3e" % st["err_used"]),
             "rel_l2_vs_plain": {names[k]: float("%.3e" % rel_l2(a[k], ref[k])) for k in range(6)},
+            "phases": phase_profile(s),
         }
         log(f"[bench] K={K}: {runs[f'K{K}']}")
         s.close()
-        ms0, fb0 = all_fallback_run(sur, prob, data.norm, K, args.tile, args.bound, args.steps, args.warmup)
+        ms0, fb0, prof0 = all_fallback_run(sur, prob, data.norm, K, args.tile, args.bound, args.steps, args.warmup)
         runs[f"K{K}_all_fallback"] = {
             "mcell_updates_s": round(n * n * args.steps / (ms0 / 1e3) / 1e6, 1),
             "ms_per_step": round(ms0 / args.steps, 4),
             "fallback_tile_fraction": fb0,
+            "phases": prof0,
         }
         log(f"[bench] K={K} zero network: {runs[f'K{K}_all_fallback']}")
     # the same with FP32 bulk arithmetic (the speed here comes from FP32; the
@@ -715,6 +737,7 @@ def run_surrogate(args):
     out["roofline"] = None
     out["cpu_baseline"] = None
     out["plain_mcell_updates_s"] = round(plain_v, 1)
+    out["plain_phases"] = prof_plain
     out["runs"] = runs
     print(json.dumps(out), flush=True)
 
