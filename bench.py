@@ -50,6 +50,7 @@ import math
 import os
 import sys
 import time
+from typing import Optional
 
 import numpy as np
 
@@ -152,6 +153,90 @@ def oracle_one_thread(n_sample: int):
     if r.returncode != 0:
         return {"error": r.stderr.strip()[-400:]}
     return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+W2_SAMPLE_STEPS = 10
+
+
+def run_oracle_workloads(args):
+    """The oracle on the two smaller workloads: Brio-Wu 800 to t = 0.1 in
+    full, and the first W2_SAMPLE_STEPS steps of Orszag-Tang 1024^2; on the
+    threads OpenMP was started with."""
+    import oracle
+    import workloads as W
+    out = {"threads": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), "nproc": os.cpu_count(),
+           "cpu": cpu_model()}
+    bw = W.brio_wu(800)
+    st = oracle.State(bw, form=oracle.LOWSTORE)
+    t0 = time.perf_counter()
+    done = st.run(100000, t_end=0.1)
+    sec = time.perf_counter() - t0
+    out["brio_wu_800"] = {"steps": done, "t": st.t, "seconds": round(sec, 3),
+                          "mcell_updates_s": round(800 * done / sec / 1e6, 3)}
+    ot = W.orszag_tang(1024)
+    st = oracle.State(ot, form=oracle.LOWSTORE)
+    t0 = time.perf_counter()
+    done = st.run(W2_SAMPLE_STEPS)
+    sec = time.perf_counter() - t0
+    out["orszag_tang_1024"] = {"steps": done, "seconds": round(sec, 3),
+                               "mcell_updates_s": round(1024 * 1024 * done / sec / 1e6, 3)}
+    print(json.dumps(out), flush=True)
+
+
+def oracle_workloads(threads: Optional[int]):
+    """run_oracle_workloads in a child process (OpenMP reads its thread count
+    when it starts), on `threads` threads or the inherited setting."""
+    import subprocess
+    env = dict(os.environ)
+    if threads is not None:
+        env["OMP_NUM_THREADS"] = str(threads)
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--mode", "oracle-workloads"],
+                       capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip()[-400:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def sub_workloads(args):
+    """Brio-Wu 800 to t = 0.1 and Orszag-Tang 1024^2 (200 steps) on the GPU,
+    FP64, beside the oracle's rates on the same workloads (all threads and one
+    thread, timed before the GPU was touched)."""
+    import workloads as W
+    from paper_1710_06423_amd import FP64, Solver
+    res = {}
+    bw = Solver.from_problem(W.brio_wu(800), precision=FP64)
+    bw.advance(2)
+    bw.close()
+    bw = Solver.from_problem(W.brio_wu(800), precision=FP64)
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, t = bw.advance(100000, t_end=0.1)
+    sec = time.perf_counter() - t0
+    bw.close()
+    res["brio_wu_800"] = {"steps": done, "t": t, "seconds": round(sec, 4),
+                          "mcell_updates_s": round(800 * done / sec / 1e6, 3),
+                          "note": "one 800-cell tube: launch-bound, timed on the host around the synchronising advance"}
+    ot = Solver.from_problem(W.orszag_tang(1024), precision=FP64)
+    ms = timed_advance(ot, 200, 2)
+    ot.close()
+    res["orszag_tang_1024"] = {"steps": 200, "ms_per_step": round(ms / 200, 4),
+                               "mcell_updates_s": round(1024 * 1024 * 200 / (ms / 1e3) / 1e6, 1)}
+    res["oracle_all_threads"] = args.cpu_workloads[0]
+    res["oracle_1thread"] = args.cpu_workloads[1]
+    res["oracle_note"] = (f"the oracle's Orszag-Tang 1024^2 rate is over its first {W2_SAMPLE_STEPS} steps; "
+                          "Brio-Wu 800 is the full run to t = 0.1")
+    return res
 
 
 def run_oracle_sample(args):
@@ -419,8 +504,11 @@ def run_single(args):
         fields = s.read_fields()
         s.close()
         subs = {}
-        for name, fn in (("fp32_8000", lambda: sub_fp32(args, fields, t_ref)), ("batch64", lambda: sub_batch(args)),
-                         ("learned_coefficient_2048_k16", lambda: sub_surrogate(args))):
+        subs_fns = [("fp32_8000", lambda: sub_fp32(args, fields, t_ref)), ("batch64", lambda: sub_batch(args)),
+                    ("learned_coefficient_2048_k16", lambda: sub_surrogate(args))]
+        if args.cpu_workloads is not None:
+            subs_fns.append(("smaller_workloads", lambda: sub_workloads(args)))
+        for name, fn in subs_fns:
             log(f"[bench] sub-record {name}")
             try:
                 subs[name] = fn()
@@ -845,7 +933,7 @@ def main():
     ap.add_argument("--steps", type=int, default=None, help="timed steps (default 100, surrogate 500)")
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--mode", choices=["single", "batch", "surrogate", "decomposed", "graph", "copy", "3d",
-                                       "oracle-sample"],
+                                       "oracle-sample", "oracle-workloads"],
                     default="single")
     ap.add_argument("--split", default="2x2", help="decomposed mode: subdomains along x and y, e.g. 2x2")
     ap.add_argument("--graph-steps", type=int, default=10, help="graph and decomposed modes: steps per captured graph")
@@ -866,6 +954,9 @@ def main():
     if args.mode == "oracle-sample":
         run_oracle_sample(args)
         return
+    if args.mode == "oracle-workloads":
+        run_oracle_workloads(args)
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs one GPU's subdomain only; --gpus {args.gpus} is not supported "
@@ -877,10 +968,13 @@ def main():
         args.n = {"surrogate": 2048, "graph": 1024, "3d": 512}.get(args.mode, 8000)
 
     args.one_thread = None
+    args.cpu_workloads = None
     if args.mode == "single" and not args.no_extras and args.cpu_sample > 0 and args.n == 8000:
         # before anything initialises the GPU
         log("[bench] oracle at one thread on a 1000^2 sub-block")
         args.one_thread = oracle_one_thread(1000)
+        log("[bench] oracle on Brio-Wu 800 and Orszag-Tang 1024^2, all threads and one thread")
+        args.cpu_workloads = (oracle_workloads(None), oracle_workloads(1))
     import torch
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
