@@ -72,20 +72,21 @@ __device__ __forceinline__ real hd_ratio(real q0, real q1, real q2, real q3, rea
     return m > (real)0 ? n / m : (real)0;
 }
 
-// Learned coefficient: the periodic image of a row of faces in the ratio
-// planes, the check-tile flag of that row in column tile ckx, and its five
-// planes from plane0 in column cw -- or five -1 (plain ratios) where the
-// tile fell back; a wave none of whose lanes is in a kept tile issues no
-// plane load.  A row loop loads the planes it uses in the same iteration and
-// the flag one iteration ahead (a loaded value copied between registers
-// while its load is in flight would make the copy wait for it), and keeps
-// every load issued after the planes unconditional, so that the compiler's
-// count of the loads in flight when it waits for the planes stays exact
-// (with loads under a lane mask after them it would wait for all).
-// A row of faces as the planes see it: its periodic image j and, within
-// the check tiles, its tile row t and its row within that tile; set up with
-// one division and then stepped row by row without one (an integer division
-// per row would cost as much scalar issue as a sizeable part of the row's
+// Learned coefficient in the row loops.  A lane holds the check-tile flag of
+// its column for the face row it works on, reloaded when the row enters a
+// new row of check tiles (the flag is loaded before the iteration that uses
+// it: a loaded value copied between registers while its load is in flight
+// would make the copy wait for it).  A wave none of whose lanes is in a kept
+// tile takes the plain path and loads no plane; otherwise each kept lane
+// loads its five planes in the iteration that uses them.  Every load issued
+// after the planes is unconditional, so that the compiler's count of the
+// loads in flight when it waits for the planes stays exact (with loads under
+// a lane mask after them it would wait for all of them).
+
+// A row of faces as the planes see it: its periodic image j and, within the
+// check tiles, its tile row t and its row within that tile; set up with one
+// division and then stepped row by row without one (an integer division per
+// row would cost as much scalar issue as a sizeable part of the row's
 // arithmetic).
 struct SurRow {
     int j, t, in;
@@ -107,11 +108,14 @@ struct SurRow {
     }
 };
 
+// the kept flag of row w's check tile in column of tiles ckx
 template <typename real>
 __device__ __forceinline__ int sur_kept(const StageArgs<real> &a, const SurRow &w, int ckx) {
     return a.Rk[w.t * a.rs_ntx + ckx];
 }
 
+// the five planes from plane0 of row w in column cw where kept, else five
+// -1 (the plain ratio)
 template <typename real>
 __device__ __forceinline__ void sur_planes(const StageArgs<real> &a, const SurRow &w, int kept, int cw, int plane0,
                                            float (&v)[5]) {
@@ -241,9 +245,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
     }
 
     // surrogate: the face rows of the iteration (x faces of row r-1, y faces
-    // (r-3)+1/2) and of the next one, and the tile flags of this
-    // iteration's faces (loaded one iteration ahead)
-    SurRow wx{}, wy{}, wxn{}, wyn{};
+    // (r-3)+1/2) and the tile flags of their check tiles
+    SurRow wx{}, wy{};
     int fkx = 0, fky = 0;
     if (SUR) {
         wx.set(a, rbeg - 1);
