@@ -297,13 +297,55 @@ __global__ __launch_bounds__(TX *TY, 2) void k3_faces(Face3Args a) {
 
 // ---------------------------------------------------------------- stage launch
 
-template <int TX, int TY>
+template <int TX, int TY, bool HD>
 struct StageLds3 {
     double pr[7][TY + 4][TX + 4];   // rho, v_x, v_y, v_z, B_x, B_y, B_z of plane r
     double fx[7][TY + 4][TX + 4];   // x fluxes of rho, m_x, m_y, m_z, e, B_y, B_z
     double fy[7][TY + 4][TX + 4];   // y fluxes of rho, m_x, m_y, m_z, e, B_x, B_z
+    // with hyper-diffusion, the face quantities the x- and y-face fluxes of
+    // plane r read, staged from the face arrays once per plane: element
+    // [.][j][i] is the face stored at (X0 - 1 + i, Y0 - 1 + j).  Each tile is
+    // filled 32 doubles at a time and padded to a whole number of those.
+    static constexpr int HX = HD ? TX : 0, HY = HD ? TY : 0;
+    static constexpr int pad32(int n) { return (n + 32) / 32 * 32 - n; }   // 1..32
+    static constexpr int NGX = NQF * (HY + 2) * (HX + 1), NGY = NQF * (HY + 1) * (HX + 2), NGZ = 4 * (HY + 2) * (HX + 2);
+    struct GzTile {
+        double v[4][HY + 2][HX + 2];     // G_z of v_x, B_x, v_y, B_y
+        double pad[pad32(NGZ)];
+    };
+    double gx[NQF][HY + 2][HX + 1];      // G_x, all seven, plane r
+    double gx_pad[pad32(NGX)];
+    double gy[NQF][HY + 1][HX + 2];      // G_y, all seven, plane r
+    double gy_pad[pad32(NGY)];
+    GzTile gz[2];                        // planes r-1 and r (by parity)
     double red[4][TX * TY / 64];
 };
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void glb_void;
+
+// Fill an LDS tile of N face quantities with loads that write LDS directly:
+// no registers are held, and the loads overlap whatever the block does until
+// its next barrier (which waits for them).  Each instruction of a wave moves
+// 32 doubles, lane l the (l & 1) half of element 32 c + l / 2; lanes past N
+// repeat the last element into the padding.  Element e, laid out [q][H][W],
+// is slot q of direction d (for the G_z tile, its q-th of v_x, B_x, v_y, B_y)
+// at (X0 - 1 + e % W, Y0 - 1 + (e / W) % H, k), clamped into the ghost layers.
+template <int N, int W, int H, bool ZSEL, int NWAVE>
+__device__ __forceinline__ void dma_tile(double *dst, const double *Gf, int64_t fs, const Layout3 &L, int d, int X0,
+                                         int Y0, int k, int wv, int lane) {
+    constexpr int NCH = (N + 31) / 32;
+    const uint32_t hw = (uint32_t)(lane & 1) * 4u;
+#pragma unroll 1
+    for (int c = wv; c < NCH; c += NWAVE) {
+        const int e = min(c * 32 + (lane >> 1), N - 1);
+        const int i = e % W, jq = e / W, j = jq % H, q = jq / H;
+        const int qs = ZSEL ? (q == 0 ? GVX : (q == 1 ? GB1 : (q == 2 ? GVY : GB2))) : q;
+        const int gx = clampi(X0 - 1 + i, -G, L.nx + G - 1), gy = clampi(Y0 - 1 + j, -G, L.ny + G - 1);
+        const char *src = (const char *)(Gf + (int64_t)(NQF * d + qs) * fs) + (L.off(gx, gy, k) + hw);
+        __builtin_amdgcn_global_load_lds((glb_void *)src, (lds_void *)(dst + c * 32), 4, 0, 0);
+    }
+}
 
 // the eight face fluxes of one face from its seven G values, the cross-term
 // means A4 of the two other directions (first, second in x, y, z order) and
@@ -345,7 +387,7 @@ __device__ __forceinline__ double a4(const double *g, uint32_t c0, uint32_t c1, 
 
 template <int STAGE, bool HD, int TX, int TY>
 __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
-    __shared__ StageLds3<TX, TY> lds;
+    __shared__ StageLds3<TX, TY, HD> lds;
     constexpr int BX = TX + 4, BY = TY + 4;
     constexpr int NFRAME = BX * BY - TX * TY;
     Dev3 *sc = a.sc;
@@ -359,6 +401,7 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
     const int zb = (blk / (a.ntx * a.nty)) * a.tz;
     const int ze = min(zb + a.tz, L.nz);
     const int tid = threadIdx.x, tx = tid % TX, ty = tid / TX;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
     const int x = X0 + tx, y = Y0 + ty;
     const bool colv = x < L.nx && y < L.ny;
     const int xc = min(x, L.nx - 1), yc = min(y, L.ny - 1);   // column clamped into the cells
@@ -395,6 +438,21 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
     const uint32_t sy = (uint32_t)L.pitch * 8u, sz = (uint32_t)(L.plane * 8);   // byte strides
 
     for (int r = zb - 4; r < ze; ++r) {
+        const bool body = r >= zb;   // plane r is an output plane of this block
+        if (HD) {
+            // ---- the face quantities of plane r that the x- and y-face
+            // fluxes read, into LDS while the state of the plane is loaded
+            // (G_z also for the plane before the first output plane); the
+            // previous plane's closing barrier has freed the tiles
+            using Lds = StageLds3<TX, TY, HD>;
+            constexpr int NW = TX * TY / 64;
+            if (body) {
+                dma_tile<Lds::NGX, TX + 1, TY + 2, false, NW>(&lds.gx[0][0][0], Gf, fs, L, 0, X0, Y0, r, wv, lane);
+                dma_tile<Lds::NGY, TX + 2, TY + 1, false, NW>(&lds.gy[0][0][0], Gf, fs, L, 1, X0, Y0, r, wv, lane);
+            }
+            if (r >= zb - 1)
+                dma_tile<Lds::NGZ, TX + 2, TY + 2, true, NW>(&lds.gz[r & 1].v[0][0][0], Gf, fs, L, 2, X0, Y0, r, wv, lane);
+        }
         // ---- own column, plane r+2: state, primitives, z fluxes
         double pn[7], fzn[7];
         {
@@ -421,7 +479,6 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
             fzn[5] = uz * bx_ - bz_ * ux;
             fzn[6] = uz * by_ - bz_ * uy;
         }
-        const bool body = r >= zb;   // plane r is an output plane of this block
         // ---- P1: plane r over the tile and its apron -> primitives, x and y fluxes in LDS
         double so[NF3];   // own cell's stage input (the combine's pointwise operand)
         if (body) {
@@ -546,23 +603,27 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
                 // keeps the G loads of later faces from being hoisted into
                 // the registers of earlier ones)
                 double ah[NF3], bh[NF3];
+                const int zc = r & 1, zp = zc ^ 1;   // G_z slots of planes r and r-1
 #pragma unroll 1
                 for (int side = 0; side < 2; ++side) {
-                    const int xx = x - 1 + side;          // face between xx and xx + 1
-                    const int lb = bx - 1 + side;         // LDS column of xx
+                    const int lb = bx - 1 + side;         // box column of the face's left cell xx = x - 1 + side
+                    const int i = tx + side;              // staged column of xx
                     double g[NQF];
-                    const uint32_t c = L.off(xx, y, r);
 #pragma unroll
-                    for (int q = 0; q < NQF; ++q) g[q] = ldo(garr(0, q), c);
+                    for (int q = 0; q < NQF; ++q) g[q] = lds.gx[q][ty + 1][i];
                     double v1 = 0.0, b1 = 0.0, v2 = 0.0, b2 = 0.0;
                     if (cross) {
-                        // y faces around the x face (G of v_x, B_x), then z faces
-                        const uint32_t c00 = c - sy, c01 = c, c10 = c + 8u - sy, c11 = c + 8u;
-                        v1 = a4(garr(1, GVX), c00, c01, c10, c11);
-                        b1 = a4(garr(1, GB1), c00, c01, c10, c11);
-                        const uint32_t d00 = c - sz, d01 = c, d10 = c + 8u - sz, d11 = c + 8u;
-                        v2 = a4(garr(2, GVX), d00, d01, d10, d11);
-                        b2 = a4(garr(2, GB1), d00, d01, d10, d11);
+                        // y faces around the x face (G of v_x, B_x): (xx, y-1), (xx, y),
+                        // (xx+1, y-1), (xx+1, y); then z faces: (xx, r-1), (xx, r),
+                        // (xx+1, r-1), (xx+1, r)
+                        v1 = ((lds.gy[GVX][ty][i] + lds.gy[GVX][ty + 1][i]) +
+                              (lds.gy[GVX][ty][i + 1] + lds.gy[GVX][ty + 1][i + 1])) * 0.25;
+                        b1 = ((lds.gy[GB1][ty][i] + lds.gy[GB1][ty + 1][i]) +
+                              (lds.gy[GB1][ty][i + 1] + lds.gy[GB1][ty + 1][i + 1])) * 0.25;
+                        v2 = ((lds.gz[zp].v[0][ty + 1][i] + lds.gz[zc].v[0][ty + 1][i]) +
+                              (lds.gz[zp].v[0][ty + 1][i + 1] + lds.gz[zc].v[0][ty + 1][i + 1])) * 0.25;
+                        b2 = ((lds.gz[zp].v[1][ty + 1][i] + lds.gz[zc].v[1][ty + 1][i]) +
+                              (lds.gz[zp].v[1][ty + 1][i + 1] + lds.gz[zc].v[1][ty + 1][i + 1])) * 0.25;
                     }
                     const double rf = half * (lds.pr[0][by][lb] + lds.pr[0][by][lb + 1]);
                     double vf[3], bf[3];
@@ -578,21 +639,24 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
                 }
 #pragma unroll 1
                 for (int side = 0; side < 2; ++side) {
-                    const int yy = y - 1 + side;
-                    const int lb = by - 1 + side;
+                    const int lb = by - 1 + side;         // box row of the face's lower cell yy = y - 1 + side
+                    const int j = ty + side;              // staged row of yy
                     double g[NQF];
-                    const uint32_t c = L.off(x, yy, r);
 #pragma unroll
-                    for (int q = 0; q < NQF; ++q) g[q] = ldo(garr(1, q), c);
+                    for (int q = 0; q < NQF; ++q) g[q] = lds.gy[q][j][tx + 1];
                     double v1 = 0.0, b1 = 0.0, v2 = 0.0, b2 = 0.0;
                     if (cross) {
-                        // x faces around the y face (G of v_y, B_y), then z faces
-                        const uint32_t c00 = c - 8u, c01 = c, c10 = c - 8u + sy, c11 = c + sy;
-                        v1 = a4(garr(0, GVY), c00, c01, c10, c11);
-                        b1 = a4(garr(0, GB1), c00, c01, c10, c11);
-                        const uint32_t d00 = c - sz, d01 = c, d10 = c + sy - sz, d11 = c + sy;
-                        v2 = a4(garr(2, GVY), d00, d01, d10, d11);
-                        b2 = a4(garr(2, GB2), d00, d01, d10, d11);
+                        // x faces around the y face (G of v_y, B_y): (x-1, yy), (x, yy),
+                        // (x-1, yy+1), (x, yy+1); then z faces: (yy, r-1), (yy, r),
+                        // (yy+1, r-1), (yy+1, r)
+                        v1 = ((lds.gx[GVY][j][tx] + lds.gx[GVY][j][tx + 1]) +
+                              (lds.gx[GVY][j + 1][tx] + lds.gx[GVY][j + 1][tx + 1])) * 0.25;
+                        b1 = ((lds.gx[GB1][j][tx] + lds.gx[GB1][j][tx + 1]) +
+                              (lds.gx[GB1][j + 1][tx] + lds.gx[GB1][j + 1][tx + 1])) * 0.25;
+                        v2 = ((lds.gz[zp].v[2][j][tx + 1] + lds.gz[zc].v[2][j][tx + 1]) +
+                              (lds.gz[zp].v[2][j + 1][tx + 1] + lds.gz[zc].v[2][j + 1][tx + 1])) * 0.25;
+                        b2 = ((lds.gz[zp].v[3][j][tx + 1] + lds.gz[zc].v[3][j][tx + 1]) +
+                              (lds.gz[zp].v[3][j + 1][tx + 1] + lds.gz[zc].v[3][j + 1][tx + 1])) * 0.25;
                     }
                     const double rf = half * (lds.pr[0][lb][bx] + lds.pr[0][lb + 1][bx]);
                     double vf[3], bf[3];
