@@ -538,6 +538,22 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
         }
         __syncthreads();
 
+        // the combine's stored operand of the own cell (U at stages 2 and 3,
+        // A at stage 4).  With hyper-diffusion its eight loads go out here,
+        // together and beside the own column's loads, rather than each behind
+        // the previous output store (which may alias it); columns past the
+        // last cell and planes before the first output plane read a cell of
+        // the block and discard it.  Without, they stay at the stores: there
+        // the registers to hold them would cost the build its second wave per
+        // SIMD.
+        const double *usrc = STAGE == 4 ? a.A : a.U;
+        double uo[NF3];
+        if (STAGE > 1 && HD) {
+            const uint32_t ou = L.off(xc, yc, max(r, zb));
+#pragma unroll
+            for (int f = 0; f < NF3; ++f) uo[f] = ldo(usrc + f * fs, ou);
+        }
+
         // ---- P2: H_z on the face r+1/2 (planes r, r+1 of the own column)
         FaceFlux hz;
 #pragma unroll
@@ -674,24 +690,25 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
                 for (int f = 0; f < NF3; ++f) K[f] = K[f] + ((ah[f] + bh[f]) + (hz.h[f] - hzp[f]) * kc.ih[2]);
             }
             const uint32_t oo = L.off(x, y, r);
+            auto uop = [&](int f) __attribute__((always_inline)) { return HD ? uo[f] : ldo(usrc + f * fs, oo); };
             if (STAGE == 1) {
 #pragma unroll
                 for (int f = 0; f < NF3; ++f) sto(a.out1 + f * fs, oo, so[f] + hdt * K[f]);
             } else if (STAGE == 2) {
 #pragma unroll
                 for (int f = 0; f < NF3; ++f) {
-                    const double u = ldo(a.U + f * fs, oo), sv = so[f];
+                    const double u = uop(f), sv = so[f];
                     sto(a.out1 + f * fs, oo, u + hdt * K[f]);
                     sto(a.out2 + f * fs, oo, (u + u) + ((sv - u) + dt * K[f]));
                 }
             } else if (STAGE == 3) {
 #pragma unroll
-                for (int f = 0; f < NF3; ++f) sto(a.out1 + f * fs, oo, ldo(a.U + f * fs, oo) + dt * K[f]);
+                for (int f = 0; f < NF3; ++f) sto(a.out1 + f * fs, oo, uop(f) + dt * K[f]);
             } else {
                 double un[NF3];
 #pragma unroll
                 for (int f = 0; f < NF3; ++f) {
-                    const double av = ldo(a.A + f * fs, oo), sv = so[f];
+                    const double av = uop(f), sv = so[f];
                     un[f] = (sv + (av - (sv + sv)) * kc.third) + dt6 * K[f];
                     sto(a.out1 + f * fs, oo, un[f]);
                 }
