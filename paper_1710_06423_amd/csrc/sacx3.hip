@@ -179,6 +179,13 @@ __global__ __launch_bounds__(TX *TY, 2) void k3_faces(Face3Args a) {
     const bool yf = colv && y <= L.ny - 1;   // owns a y face
     const double gm1 = kc.gm1, igm1 = kc.igm1;
     const double half = 0.5, zero = 0.0;
+    // the step's coefficients, read once: read where they are used, each
+    // would be read again behind the previous face store (which may alias it)
+    double kd2[3][4];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) kd2[d][c] = sc->kd2[d][c];
 
     double w[NQF][6];   // z-face set rho~, eps~, v_x, v_y, v_z, B_x, B_y of planes r-5..r
 #pragma unroll
@@ -254,7 +261,7 @@ __global__ __launch_bounds__(TX *TY, 2) void k3_faces(Face3Args a) {
                                  q4 = row[tx + 4], q5 = row[tx + 5];
                     const double R = sacx::hd_ratio(q0, q1, q2, q3, q4, q5);
                     const int cl = gclass(q);
-                    const double nu = sc->kd2[0][cl] * R + kc.kds[0][cl] * sf;
+                    const double nu = kd2[0][cl] * R + kc.kds[0][cl] * sf;
                     sto(a.Gf + (0 * NQF + q) * fs, o, (nu * (q3 - q2)) * kc.ih[0]);
                 }
             }
@@ -270,7 +277,7 @@ __global__ __launch_bounds__(TX *TY, 2) void k3_faces(Face3Args a) {
                                  q4 = lds.q[pslot][src[q]][ty + 4][bx], q5 = lds.q[pslot][src[q]][ty + 5][bx];
                     const double R = sacx::hd_ratio(q0, q1, q2, q3, q4, q5);
                     const int cl = gclass(q);
-                    const double nu = sc->kd2[1][cl] * R + kc.kds[1][cl] * sf;
+                    const double nu = kd2[1][cl] * R + kc.kds[1][cl] * sf;
                     sto(a.Gf + (1 * NQF + q) * fs, o, (nu * (q3 - q2)) * kc.ih[1]);
                 }
             }
@@ -283,7 +290,7 @@ __global__ __launch_bounds__(TX *TY, 2) void k3_faces(Face3Args a) {
             for (int q = 0; q < NQF; ++q) {
                 const double R = sacx::hd_ratio(w[q][0], w[q][1], w[q][2], w[q][3], w[q][4], w[q][5]);
                 const int cl = gclass(q);
-                const double nu = sc->kd2[2][cl] * R + kc.kds[2][cl] * sf;
+                const double nu = kd2[2][cl] * R + kc.kds[2][cl] * sf;
                 sto(a.Gf + (2 * NQF + q) * fs, o, (nu * (w[q][3] - w[q][2])) * kc.ih[2]);
             }
         }
