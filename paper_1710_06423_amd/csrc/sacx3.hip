@@ -311,46 +311,50 @@ struct StageLds3 {
     double fy[7][TY + 4][TX + 4];   // y fluxes of rho, m_x, m_y, m_z, e, B_x, B_z
     // with hyper-diffusion, the face quantities the x- and y-face fluxes of
     // plane r read, staged from the face arrays once per plane: element
-    // [.][j][i] is the face stored at (X0 - 1 + i, Y0 - 1 + j).  Each tile is
-    // filled 32 doubles at a time and padded to a whole number of those.
-    static constexpr int HX = HD ? TX : 0, HY = HD ? TY : 0;
-    static constexpr int pad32(int n) { return (n + 32) / 32 * 32 - n; }   // 1..32
-    static constexpr int NGX = NQF * (HY + 2) * (HX + 1), NGY = NQF * (HY + 1) * (HX + 2), NGZ = 4 * (HY + 2) * (HX + 2);
+    // [.][j][i] is the face stored at (X0 - 2 + i, Y0 - 1 + j).  Rows are
+    // GW = TX + 4 doubles, filled as 16-byte pairs from an even x, 128
+    // doubles per wave instruction; each tile is padded to whole instructions.
+    static constexpr int HX = HD ? TX : 0, HY = HD ? TY : 0, GW = HD ? TX + 4 : 2;
+    static constexpr int fill128(int rows) { return (rows * GW + 127) / 128 * 128; }
     struct GzTile {
-        double v[4][HY + 2][HX + 2];     // G_z of v_x, B_x, v_y, B_y
-        double pad[pad32(NGZ)];
+        alignas(16) double v[4][HY + 2][GW];   // G_z of v_x, B_x, v_y, B_y
+        double pad[fill128(4 * (HY + 2)) - 4 * (HY + 2) * GW + 2];
     };
-    double gx[NQF][HY + 2][HX + 1];      // G_x, all seven, plane r
-    double gx_pad[pad32(NGX)];
-    double gy[NQF][HY + 1][HX + 2];      // G_y, all seven, plane r
-    double gy_pad[pad32(NGY)];
-    GzTile gz[2];                        // planes r-1 and r (by parity)
+    alignas(16) double gx[NQF][HY + 2][GW];    // G_x, all seven, plane r
+    double gx_pad[fill128(NQF * (HY + 2)) - NQF * (HY + 2) * GW + 2];
+    alignas(16) double gy[NQF][HY + 1][GW];    // G_y, all seven, plane r
+    double gy_pad[fill128(NQF * (HY + 1)) - NQF * (HY + 1) * GW + 2];
+    GzTile gz[2];                              // planes r-1 and r (by parity)
     double red[4][TX * TY / 64];
 };
 
 typedef __attribute__((address_space(3))) void lds_void;
 typedef __attribute__((address_space(1))) void glb_void;
 
-// Fill an LDS tile of N face quantities with loads that write LDS directly:
-// no registers are held, and the loads overlap whatever the block does until
-// its next barrier (which waits for them).  Each instruction of a wave moves
-// 32 doubles, lane l the (l & 1) half of element 32 c + l / 2; lanes past N
-// repeat the last element into the padding.  Element e, laid out [q][H][W],
-// is slot q of direction d (for the G_z tile, its q-th of v_x, B_x, v_y, B_y)
-// at (X0 - 1 + e % W, Y0 - 1 + (e / W) % H, k), clamped into the ghost layers.
-template <int N, int W, int H, bool ZSEL, int NWAVE>
+// Fill an LDS tile of face quantities with loads that write LDS directly: no
+// registers are held, and the loads overlap whatever the block does until its
+// next barrier (which waits for them).  The tile holds NQ quantities x H rows
+// x GW columns; row j of quantity q is slot q of direction d (for the G_z
+// tile, its q-th of v_x, B_x, v_y, B_y) at y = Y0 - 1 + j, x = X0 - 2 ..
+// X0 - 3 + GW, plane k.  Lane l of a wave instruction moves the pair p =
+// 64 c + l of the tile (two doubles, 16-byte aligned in both memories: x is
+// even and column 0 of every row is on a 256-byte boundary); lanes past the
+// tile repeat its last pair into the padding.  Positions past the ghost
+// layers read whatever follows in the array (a later row or plane: staged
+// planes end at n_z - 1 and three ghost planes follow); no output reads them.
+template <int NQ, int H, int GW, bool ZSEL, int NWAVE>
 __device__ __forceinline__ void dma_tile(double *dst, const double *Gf, int64_t fs, const Layout3 &L, int d, int X0,
                                          int Y0, int k, int wv, int lane) {
-    constexpr int NCH = (N + 31) / 32;
-    const uint32_t hw = (uint32_t)(lane & 1) * 4u;
+    constexpr int PR = GW / 2, NP = NQ * H * PR, NCH = (NP + 63) / 64;
+    static_assert(GW % 2 == 0, "rows are filled in pairs");
 #pragma unroll 1
     for (int c = wv; c < NCH; c += NWAVE) {
-        const int e = min(c * 32 + (lane >> 1), N - 1);
-        const int i = e % W, jq = e / W, j = jq % H, q = jq / H;
+        const int p = min(c * 64 + lane, NP - 1);
+        const int row = p / PR, pr = p - row * PR;
+        const int q = row / H, j = row - q * H;
         const int qs = ZSEL ? (q == 0 ? GVX : (q == 1 ? GB1 : (q == 2 ? GVY : GB2))) : q;
-        const int gx = clampi(X0 - 1 + i, -G, L.nx + G - 1), gy = clampi(Y0 - 1 + j, -G, L.ny + G - 1);
-        const char *src = (const char *)(Gf + (int64_t)(NQF * d + qs) * fs) + (L.off(gx, gy, k) + hw);
-        __builtin_amdgcn_global_load_lds((glb_void *)src, (lds_void *)(dst + c * 32), 4, 0, 0);
+        const char *src = (const char *)(Gf + (int64_t)(NQF * d + qs) * fs) + L.off(X0 - 2 + 2 * pr, Y0 - 1 + j, k);
+        __builtin_amdgcn_global_load_lds((glb_void *)src, (lds_void *)(dst + c * 128), 16, 0, 0);
     }
 }
 
@@ -451,14 +455,13 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
             // fluxes read, into LDS while the state of the plane is loaded
             // (G_z also for the plane before the first output plane); the
             // previous plane's closing barrier has freed the tiles
-            using Lds = StageLds3<TX, TY, HD>;
-            constexpr int NW = TX * TY / 64;
+            constexpr int NW = TX * TY / 64, GW = StageLds3<TX, TY, HD>::GW;
             if (body) {
-                dma_tile<Lds::NGX, TX + 1, TY + 2, false, NW>(&lds.gx[0][0][0], Gf, fs, L, 0, X0, Y0, r, wv, lane);
-                dma_tile<Lds::NGY, TX + 2, TY + 1, false, NW>(&lds.gy[0][0][0], Gf, fs, L, 1, X0, Y0, r, wv, lane);
+                dma_tile<NQF, TY + 2, GW, false, NW>(&lds.gx[0][0][0], Gf, fs, L, 0, X0, Y0, r, wv, lane);
+                dma_tile<NQF, TY + 1, GW, false, NW>(&lds.gy[0][0][0], Gf, fs, L, 1, X0, Y0, r, wv, lane);
             }
             if (r >= zb - 1)
-                dma_tile<Lds::NGZ, TX + 2, TY + 2, true, NW>(&lds.gz[r & 1].v[0][0][0], Gf, fs, L, 2, X0, Y0, r, wv, lane);
+                dma_tile<4, TY + 2, GW, true, NW>(&lds.gz[r & 1].v[0][0][0], Gf, fs, L, 2, X0, Y0, r, wv, lane);
         }
         // ---- own column, plane r+2: state, primitives, z fluxes
         double pn[7], fzn[7];
@@ -630,7 +633,7 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
 #pragma unroll 1
                 for (int side = 0; side < 2; ++side) {
                     const int lb = bx - 1 + side;         // box column of the face's left cell xx = x - 1 + side
-                    const int i = tx + side;              // staged column of xx
+                    const int i = tx + side + 1;          // staged column of xx
                     double g[NQF];
 #pragma unroll
                     for (int q = 0; q < NQF; ++q) g[q] = lds.gx[q][ty + 1][i];
@@ -666,20 +669,20 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
                     const int j = ty + side;              // staged row of yy
                     double g[NQF];
 #pragma unroll
-                    for (int q = 0; q < NQF; ++q) g[q] = lds.gy[q][j][tx + 1];
+                    for (int q = 0; q < NQF; ++q) g[q] = lds.gy[q][j][tx + 2];
                     double v1 = 0.0, b1 = 0.0, v2 = 0.0, b2 = 0.0;
                     if (cross) {
                         // x faces around the y face (G of v_y, B_y): (x-1, yy), (x, yy),
                         // (x-1, yy+1), (x, yy+1); then z faces: (yy, r-1), (yy, r),
                         // (yy+1, r-1), (yy+1, r)
-                        v1 = ((lds.gx[GVY][j][tx] + lds.gx[GVY][j][tx + 1]) +
-                              (lds.gx[GVY][j + 1][tx] + lds.gx[GVY][j + 1][tx + 1])) * 0.25;
-                        b1 = ((lds.gx[GB1][j][tx] + lds.gx[GB1][j][tx + 1]) +
-                              (lds.gx[GB1][j + 1][tx] + lds.gx[GB1][j + 1][tx + 1])) * 0.25;
-                        v2 = ((lds.gz[zp].v[2][j][tx + 1] + lds.gz[zc].v[2][j][tx + 1]) +
-                              (lds.gz[zp].v[2][j + 1][tx + 1] + lds.gz[zc].v[2][j + 1][tx + 1])) * 0.25;
-                        b2 = ((lds.gz[zp].v[3][j][tx + 1] + lds.gz[zc].v[3][j][tx + 1]) +
-                              (lds.gz[zp].v[3][j + 1][tx + 1] + lds.gz[zc].v[3][j + 1][tx + 1])) * 0.25;
+                        v1 = ((lds.gx[GVY][j][tx + 1] + lds.gx[GVY][j][tx + 2]) +
+                              (lds.gx[GVY][j + 1][tx + 1] + lds.gx[GVY][j + 1][tx + 2])) * 0.25;
+                        b1 = ((lds.gx[GB1][j][tx + 1] + lds.gx[GB1][j][tx + 2]) +
+                              (lds.gx[GB1][j + 1][tx + 1] + lds.gx[GB1][j + 1][tx + 2])) * 0.25;
+                        v2 = ((lds.gz[zp].v[2][j][tx + 2] + lds.gz[zc].v[2][j][tx + 2]) +
+                              (lds.gz[zp].v[2][j + 1][tx + 2] + lds.gz[zc].v[2][j + 1][tx + 2])) * 0.25;
+                        b2 = ((lds.gz[zp].v[3][j][tx + 2] + lds.gz[zc].v[3][j][tx + 2]) +
+                              (lds.gz[zp].v[3][j + 1][tx + 2] + lds.gz[zc].v[3][j + 1][tx + 2])) * 0.25;
                     }
                     const double rf = half * (lds.pr[0][lb][bx] + lds.pr[0][lb + 1][bx]);
                     double vf[3], bf[3];
