@@ -13,7 +13,7 @@
  * on the thread count.
  *
  * What is computed (paper section 2 and our reading of what it defers to the
- * SAC/SMAUG papers; every reading is listed in the design notes):
+ * SAC/SMAUG papers):
  *
  *  - ideal compressible MHD in conservative form (section 2, the governing
  *    equations), with the closure p_t = p_k + B^2/2,

@@ -20,12 +20,14 @@
 //              face fluxes H_d (hyper-viscous stress, hyper-resistive e.m.f.,
 //              the energy they carry) from the stored G and their divergence,
 //              then the storage-saving RK4 combine; stage 4 also reduces the
-//              wave speeds of the new state.
+//              wave speeds of the new state.  The G that the x- and y-face
+//              fluxes of a plane read are staged in LDS tiles by loads that
+//              write LDS directly, issued before the plane's state loads.
 //
 // Splitting the stage in two moves the 21 face quantities through HBM (a
-// fused 3-D kernel would need the z windows of both launches in one thread),
-// so a stage moves about three times the algorithmic bytes; the design notes
-// give the figures.
+// fused 3-D kernel would need the z windows of both launches in one thread):
+// as laid out, about 592 B per cell and stage against the 192 B of the
+// stage's own state accesses.
 //
 // Arithmetic: every value is the IEEE operation sequence of the scheme's
 // definition in its storage-saving arrangement (divisions by grid constants
