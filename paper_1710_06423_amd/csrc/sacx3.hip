@@ -394,10 +394,6 @@ __device__ __forceinline__ FaceFlux face_flux(const double (&g)[NQF], double a4v
     return H;
 }
 
-__device__ __forceinline__ double a4(const double *g, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3) {
-    return ((ldo(g, c0) + ldo(g, c1)) + (ldo(g, c2) + ldo(g, c3))) * 0.25;
-}
-
 template <int STAGE, bool HD, int TX, int TY>
 __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
     __shared__ StageLds3<TX, TY, HD> lds;
@@ -450,6 +446,51 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
     const int cx = min(x, L.nx + G - 1), cy = min(y, L.ny + G - 1);
     const uint32_t sy = (uint32_t)L.pitch * 8u, sz = (uint32_t)(L.plane * 8);   // byte strides
 
+    // The own column's loads that a plane consumes after its tile work (its
+    // state two planes ahead, the G of H_z and, at stages 2-4, the combine's
+    // stored operand) are issued one plane early, as soon as the previous
+    // plane has consumed its own, into registers consumed in place: they
+    // land during that plane's x and y terms, and no barrier waits for them
+    // before the next plane's tile barrier.  Past the block's last plane
+    // they read ghost planes, unused.
+    const double *usrc = STAGE == 4 ? a.A : a.U;
+    double psn[NF3];                 // state of the own column, plane r+2
+    double puo[NF3];                 // the combine's stored operand of the own cell, plane r
+    double pgz[NQF];                 // G_z of the own column's face r+1/2
+    double pgc[4][4];                // G_x(v_z), G_x(B_z), G_y(v_z), G_y(B_z) around that face
+    auto prefetch = [&](int rr) __attribute__((always_inline)) {
+        const uint32_t o = L.off(cx, cy, rr + 2);
+#pragma unroll
+        for (int f = 0; f < NF3; ++f) psn[f] = ldo(a.S + f * fs, o);
+        if (STAGE > 1 && HD) {
+            // columns past the last cell and planes before the first output
+            // plane read a cell of the block and discard it
+            const uint32_t ou = L.off(xc, yc, max(rr, zb));
+#pragma unroll
+            for (int f = 0; f < NF3; ++f) puo[f] = ldo(usrc + f * fs, ou);
+        }
+        if (HD) {
+            const uint32_t c = L.off(xc, yc, max(rr, zb - 1));
+#pragma unroll
+            for (int q = 0; q < NQF; ++q) pgz[q] = ldo(garr(2, q), c);
+            if (cross) {
+                // x faces around the z face, then y faces: (-1, r), (0, r),
+                // (-1, r+1), (0, r+1) relative to the own column
+                const uint32_t c00 = c - 8u, c01 = c, c10 = c - 8u + sz, c11 = c + sz;
+                const uint32_t d00 = c - sy, d01 = c, d10 = c - sy + sz, d11 = c + sz;
+                pgc[0][0] = ldo(garr(0, GVZ), c00); pgc[0][1] = ldo(garr(0, GVZ), c01);
+                pgc[0][2] = ldo(garr(0, GVZ), c10); pgc[0][3] = ldo(garr(0, GVZ), c11);
+                pgc[1][0] = ldo(garr(0, GB2), c00); pgc[1][1] = ldo(garr(0, GB2), c01);
+                pgc[1][2] = ldo(garr(0, GB2), c10); pgc[1][3] = ldo(garr(0, GB2), c11);
+                pgc[2][0] = ldo(garr(1, GVZ), d00); pgc[2][1] = ldo(garr(1, GVZ), d01);
+                pgc[2][2] = ldo(garr(1, GVZ), d10); pgc[2][3] = ldo(garr(1, GVZ), d11);
+                pgc[3][0] = ldo(garr(1, GB2), d00); pgc[3][1] = ldo(garr(1, GB2), d01);
+                pgc[3][2] = ldo(garr(1, GB2), d10); pgc[3][3] = ldo(garr(1, GB2), d11);
+            }
+        }
+    };
+    prefetch(zb - 4);
+
     for (int r = zb - 4; r < ze; ++r) {
         const bool body = r >= zb;   // plane r is an output plane of this block
         if (HD) {
@@ -464,32 +505,6 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
             }
             if (r >= zb - 1)
                 dma_tile<4, TY + 2, GW, true, NW>(&lds.gz[r & 1].v[0][0][0], Gf, fs, L, 2, X0, Y0, r, wv, lane);
-        }
-        // ---- own column, plane r+2: state, primitives, z fluxes
-        double pn[7], fzn[7];
-        {
-            const uint32_t o = L.off(cx, cy, r + 2);
-            double sn[NF3];
-#pragma unroll
-            for (int f = 0; f < NF3; ++f) sn[f] = ldo(a.S + f * fs, o);
-            const double rt = sn[FR], mx = sn[FMX], my = sn[FMY], mz = sn[FMZ], et = sn[FE];
-            const double bx_ = sn[FBX], by_ = sn[FBY], bz_ = sn[FBZ];
-            const double ir = 1.0 / rt;
-            const double ux = mx * ir, uy = my * ir, uz = mz * ir;
-            const double kin = half * ((mx * ux + my * uy) + mz * uz);
-            const double b2 = (bx_ * bx_ + by_ * by_) + bz_ * bz_;
-            const double pk = gm1 * ((et - kin) - half * b2);
-            const double pt = pk + half * b2;
-            const double bv = (bx_ * ux + by_ * uy) + bz_ * uz;
-            const double ef = et + pt;
-            pn[0] = rt; pn[1] = ux; pn[2] = uy; pn[3] = uz; pn[4] = bx_; pn[5] = by_; pn[6] = bz_;
-            fzn[0] = mz;
-            fzn[1] = uz * mx - bz_ * bx_;
-            fzn[2] = uz * my - bz_ * by_;
-            fzn[3] = (uz * mz - bz_ * bz_) + pt;
-            fzn[4] = uz * ef - bz_ * bv;
-            fzn[5] = uz * bx_ - bz_ * ux;
-            fzn[6] = uz * by_ - bz_ * uy;
         }
         // ---- P1: plane r over the tile and its apron -> primitives, x and y fluxes in LDS
         double so[NF3];   // own cell's stage input (the combine's pointwise operand)
@@ -550,20 +565,28 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
         }
         __syncthreads();
 
-        // the combine's stored operand of the own cell (U at stages 2 and 3,
-        // A at stage 4).  With hyper-diffusion its eight loads go out here,
-        // together and beside the own column's loads, rather than each behind
-        // the previous output store (which may alias it); columns past the
-        // last cell and planes before the first output plane read a cell of
-        // the block and discard it.  Without, they stay at the stores: there
-        // the registers to hold them would cost the build its second wave per
-        // SIMD.
-        const double *usrc = STAGE == 4 ? a.A : a.U;
-        double uo[NF3];
-        if (STAGE > 1 && HD) {
-            const uint32_t ou = L.off(xc, yc, max(r, zb));
-#pragma unroll
-            for (int f = 0; f < NF3; ++f) uo[f] = ldo(usrc + f * fs, ou);
+        // ---- own column, plane r+2: state, primitives, z fluxes
+        double pn[7], fzn[7];
+        {
+            const double *sn = psn;
+            const double rt = sn[FR], mx = sn[FMX], my = sn[FMY], mz = sn[FMZ], et = sn[FE];
+            const double bx_ = sn[FBX], by_ = sn[FBY], bz_ = sn[FBZ];
+            const double ir = 1.0 / rt;
+            const double ux = mx * ir, uy = my * ir, uz = mz * ir;
+            const double kin = half * ((mx * ux + my * uy) + mz * uz);
+            const double b2 = (bx_ * bx_ + by_ * by_) + bz_ * bz_;
+            const double pk = gm1 * ((et - kin) - half * b2);
+            const double pt = pk + half * b2;
+            const double bv = (bx_ * ux + by_ * uy) + bz_ * uz;
+            const double ef = et + pt;
+            pn[0] = rt; pn[1] = ux; pn[2] = uy; pn[3] = uz; pn[4] = bx_; pn[5] = by_; pn[6] = bz_;
+            fzn[0] = mz;
+            fzn[1] = uz * mx - bz_ * bx_;
+            fzn[2] = uz * my - bz_ * by_;
+            fzn[3] = (uz * mz - bz_ * bz_) + pt;
+            fzn[4] = uz * ef - bz_ * bv;
+            fzn[5] = uz * bx_ - bz_ * ux;
+            fzn[6] = uz * by_ - bz_ * uy;
         }
 
         // ---- P2: H_z on the face r+1/2 (planes r, r+1 of the own column)
@@ -571,19 +594,13 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
 #pragma unroll
         for (int f = 0; f < NF3; ++f) hz.h[f] = 0.0;
         if (HD && r >= zb - 1) {
-            double g[NQF];
-            const uint32_t c = L.off(xc, yc, r);
-#pragma unroll
-            for (int q = 0; q < NQF; ++q) g[q] = ldo(garr(2, q), c);
             double v1 = 0.0, b1 = 0.0, v2 = 0.0, b2 = 0.0;
             if (cross) {
-                // x faces around the z face (G of v_z, B_z), then y faces
-                const uint32_t c00 = c - 8u, c01 = c, c10 = c - 8u + sz, c11 = c + sz;
-                v1 = a4(garr(0, GVZ), c00, c01, c10, c11);
-                b1 = a4(garr(0, GB2), c00, c01, c10, c11);
-                const uint32_t d00 = c - sy, d01 = c, d10 = c - sy + sz, d11 = c + sz;
-                v2 = a4(garr(1, GVZ), d00, d01, d10, d11);
-                b2 = a4(garr(1, GB2), d00, d01, d10, d11);
+                // means of the four x faces (G of v_z, B_z), then y faces
+                v1 = ((pgc[0][0] + pgc[0][1]) + (pgc[0][2] + pgc[0][3])) * 0.25;
+                b1 = ((pgc[1][0] + pgc[1][1]) + (pgc[1][2] + pgc[1][3])) * 0.25;
+                v2 = ((pgc[2][0] + pgc[2][1]) + (pgc[2][2] + pgc[2][3])) * 0.25;
+                b2 = ((pgc[3][0] + pgc[3][1]) + (pgc[3][2] + pgc[3][3])) * 0.25;
             }
             const double rf = half * (pq[0][0] + pq[1][0]);
             double vf[3], bf[3];
@@ -592,8 +609,15 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
                 vf[k] = half * (pq[0][1 + k] + pq[1][1 + k]);
                 bf[k] = half * (pq[0][4 + k] + pq[1][4 + k]);
             }
-            hz = face_flux<2>(g, v1, b1, v2, b2, rf, vf, bf);
+            hz = face_flux<2>(pgz, v1, b1, v2, b2, rf, vf, bf);
         }
+        // the combine operand leaves the prefetch registers (its loads are
+        // complete: the barrier above waited for them), which then take the
+        // next plane's loads for the whole of this plane's x and y terms
+        double uo[NF3];
+#pragma unroll
+        for (int f = 0; f < NF3; ++f) uo[f] = puo[f];
+        prefetch(r + 1);
         __builtin_amdgcn_sched_barrier(0);
 
         // ---- P3: x and y terms of plane r and its output
