@@ -280,11 +280,13 @@ def sub_fp32(args, ref_fields, t_ref):
 
 def sub_batch(args):
     """64 mixed instances in one persistent launch (FP32, autotuned tiles),
-    100 steps; sampled instances against the FP64 oracle."""
+    100 steps; beside it the same instances run one at a time in FP64 (rate,
+    and every instance's error against its FP64 run), and sampled instances
+    against the FP64 oracle."""
     import torch
     import oracle
     import workloads as W
-    from paper_1710_06423_amd import FP32, Batch
+    from paper_1710_06423_amd import FP32, FP64, Batch, Solver
     from paper_1710_06423_amd.autotune import tune_batch
     probs = W.batch_instances(seed=0)
     cells = sum(p.nx * p.ny for p in probs)
@@ -301,6 +303,22 @@ def sub_batch(args):
     e1.record(b.stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    value = cells * steps / (ms / 1e3) / 1e6
+    # the same instances one at a time in FP64 (each its own context and launches)
+    seq_ms, worst = 0.0, 0.0
+    for i, p in enumerate(probs):
+        s = Solver.from_problem(p, precision=FP64)
+        torch.cuda.synchronize()
+        a0, a1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a0.record(s.stream)
+        s.advance(steps, sync=False)
+        a1.record(s.stream)
+        torch.cuda.synchronize()
+        seq_ms += a0.elapsed_time(a1)
+        x, y = b[i].read_fields(torch.float64), s.read_fields(torch.float64)
+        worst = max(worst, max(rel_l2(x[k], y[k]) for k in range(6)))
+        s.close()
+    seq = cells * steps / (seq_ms / 1e3) / 1e6
     # sampled against the oracle: the two smallest tubes and the two smallest boxes
     bw = sorted((i for i, p in enumerate(probs) if p.ny == 1), key=lambda i: probs[i].nx)[:2]
     ot = sorted((i for i, p in enumerate(probs) if p.ny > 1), key=lambda i: probs[i].nx * probs[i].ny)[:2]
@@ -314,9 +332,11 @@ def sub_batch(args):
         errs[f"{'briowu' if probs[i].ny == 1 else 'orszag_tang'}_{probs[i].nx}x{probs[i].ny}"] = float(
             "%.3e" % max(oracle.rel_l2(got[k], want[k]) for k in range(6)))
     b.close()
-    return {"mcell_updates_s": round(cells * steps / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms / steps, 4),
+    return {"mcell_updates_s": round(value, 1), "ms_per_step": round(ms / steps, 4),
             "instances": len(probs), "cells": cells, "steps": steps, "tiles": {"threads": t, "rows2d": r},
-            "dtype": "f32 bulk, f64 dt and sums", "sampled_max_rel_l2_vs_oracle": errs}
+            "dtype": "f32 bulk, f64 dt and sums",
+            "one_at_a_time_fp64_mcell_updates_s": round(seq, 1), "speedup_vs_one_at_a_time_fp64": round(value / seq, 2),
+            "max_rel_l2_vs_one_at_a_time_fp64": float("%.3e" % worst), "sampled_max_rel_l2_vs_oracle": errs}
 
 
 def phase_profile(s, steps=32):
