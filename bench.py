@@ -547,7 +547,8 @@ def run_single(args):
         s.close()
         subs = {}
         subs_fns = [("fp32_8000", lambda: sub_fp32(args, fields, t_ref)), ("batch64", lambda: sub_batch(args)),
-                    ("learned_coefficient_2048_k16", lambda: sub_surrogate(args))]
+                    ("learned_coefficient_2048_k16", lambda: sub_surrogate(args)),
+                    ("orszag_tang_3d_512", lambda: sub_3d(args))]
         if args.cpu_workloads is not None:
             subs_fns.append(("smaller_workloads", lambda: sub_workloads(args)))
         for name, fn in subs_fns:
@@ -870,6 +871,32 @@ def run_surrogate(args):
     out["plain_phases"] = prof_plain
     out["runs"] = runs
     print(json.dumps(out), flush=True)
+
+
+def sub_3d(args, n=512, steps=5, warmup=2):
+    """The 3-D scheme on Orszag-Tang carried into z at n^3, FP64, hyper-
+    diffusion on: its rate and algorithmic HBM fraction over `steps` steps."""
+    import torch
+    import workloads as W
+    from paper_1710_06423_amd.sacx3 import Solver3
+    s = Solver3.from_problem(W.orszag_tang_3d(n), cfl=0.3)
+    s.advance(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.advance(steps, sync=False)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    d = s.diagnostics()
+    s.close()
+    if d["nonphys"] or d["steps"] != warmup + steps:
+        raise RuntimeError(f"3-D run failed: {d}")
+    alg = 12 * 8 * 8
+    return {"workload": f"orszag_tang_3d_{n}^3_fp64_hd", "steps": steps,
+            "mcell_updates_s": round(n ** 3 * steps / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms / steps, 3),
+            "roofline_frac_algorithmic": round(alg * n ** 3 / (ms / steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "parity": "bit-identical to the 3-D oracle (GPU tests)"}
 
 
 def run_3d(args):
