@@ -611,12 +611,15 @@ __global__ __launch_bounds__(TX *TY, 1) void k3_stage(Stage3Args a) {
             }
             hz = face_flux<2>(pgz, v1, b1, v2, b2, rf, vf, bf);
         }
-        // the combine operand leaves the prefetch registers (its loads are
-        // complete: the barrier above waited for them), which then take the
-        // next plane's loads for the whole of this plane's x and y terms
+        // the combine operand leaves the prefetch registers (with
+        // hyper-diffusion its loads are complete: the barrier above waited
+        // for the tile fill issued after them), which then take the next
+        // plane's loads for the whole of this plane's x and y terms
         double uo[NF3];
+        if (STAGE > 1 && HD) {
 #pragma unroll
-        for (int f = 0; f < NF3; ++f) uo[f] = puo[f];
+            for (int f = 0; f < NF3; ++f) uo[f] = puo[f];
+        }
         prefetch(r + 1);
         __builtin_amdgcn_sched_barrier(0);
 
