@@ -78,24 +78,32 @@ __device__ __forceinline__ real hd_ratio(real q0, real q1, real q2, real q3, rea
     return m > (real)0 ? n / m : (real)0;
 }
 
-// FP32: the quotient through the hardware reciprocal (within about 1 ulp)
-// instead of a correctly rounded division, which takes about nine
-// instructions.  The ratio is at most 4 (each third difference is a sum of
-// first differences with weights 1, 2, 1), and the clamp keeps that bound
-// where m is subnormal and small enough for its reciprocal to overflow.
-template <>
-__device__ __forceinline__ float hd_ratio<float>(float q0, float q1, float q2, float q3, float q4, float q5) {
-    float n, m;
-    hd_ratio_terms(q0, q1, q2, q3, q4, q5, n, m);
-    return m > 0.0f ? fminf(n * __builtin_amdgcn_rcpf(m), 4.0f) : 0.0f;
+// The stage tiles' FP32 forms without a background (FAST): the quotient
+// through the hardware reciprocal (within about 1 ulp) instead of a correctly
+// rounded division, which takes about nine instructions.  The ratio is at
+// most 4 (each third difference is a sum of first differences with weights
+// 1, 2, 1), and the clamp keeps that bound where m is subnormal and small
+// enough for its reciprocal to overflow.  FP64, and FP32 with a background
+// (whose registers the shorter code would overflow into scratch), divide.
+template <typename real, bool FAST>
+__device__ __forceinline__ real hd_ratio_t(real q0, real q1, real q2, real q3, real q4, real q5) {
+    if constexpr (FAST && sizeof(real) == 4) {
+        real n, m;
+        hd_ratio_terms(q0, q1, q2, q3, q4, q5, n, m);
+        return m > 0.0f ? fminf(n * __builtin_amdgcn_rcpf(m), 4.0f) : 0.0f;
+    } else {
+        return hd_ratio(q0, q1, q2, q3, q4, q5);
+    }
 }
 
-// 1/x: correctly rounded in FP64; in FP32 the hardware reciprocal (within
-// about 1 ulp; x is a density, positive and normal)
-template <typename real>
-__device__ __forceinline__ real recip(real x) { return (real)1 / x; }
-template <>
-__device__ __forceinline__ float recip<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+// 1/x, the same way (x is a density, positive and normal)
+template <typename real, bool FAST>
+__device__ __forceinline__ real recip_t(real x) {
+    if constexpr (FAST && sizeof(real) == 4)
+        return __builtin_amdgcn_rcpf(x);
+    else
+        return (real)1 / x;
+}
 
 // Learned coefficient in the row loops.  A lane holds the check-tile flag of
 // its column for the face row it works on, reloaded when the row enters a
@@ -341,7 +349,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
         real rb = 0, eb = 0, bxb = 0, byb = 0;
         if (BG) { rb = a.BG[0][ro]; eb = a.BG[0][ro + 1 * fs]; bxb = a.BG[0][ro + 2 * fs]; byb = a.BG[0][ro + 3 * fs]; }
         const real rho = rb + rt;
-        const real irho = recip(rho);
+        const real irho = recip_t<real, !BG>(rho);
         const real vx = mx * irho, vy = my * irho;
         const real kin = half * (mx * vx + my * vy);
         const real bbdot = bxb * bxt + byb * byt;
@@ -449,7 +457,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
                 if (SUR && wkx && rsx[k] >= 0.0f)
                     R = (real)rsx[k];
                 else
-                    R = hd_ratio(sh_q[pslot][k][tm2], sh_q[pslot][k][tm1], q2, q3, sh_q[pslot][k][tp2],
+                    R = hd_ratio_t<real, !BG>(sh_q[pslot][k][tm2], sh_q[pslot][k][tm1], q2, q3, sh_q[pslot][k][tp2],
                                  sh_q[pslot][k][tp3]);
                 const real nu = kx2[cl] * R + (real)kc.kxs[cl] * sfx;
                 gxn[k] = nu * (q3 - q2) * idx;
@@ -466,7 +474,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<real> &a, int tile_x,
                 if (SUR && wky && rsy[k] >= 0.0f)
                     R = (real)rsy[k];
                 else
-                    R = hd_ratio(qw[k][0], qw[k][1], qw[k][2], qw[k][3], qw[k][4], qw[k][5]);
+                    R = hd_ratio_t<real, !BG>(qw[k][0], qw[k][1], qw[k][2], qw[k][3], qw[k][4], qw[k][5]);
                 const real nu = ky2[cl] * R + (real)kc.kys[cl] * sfy;
                 gyn[k] = nu * (qw[k][3] - qw[k][2]) * idy;
             }
@@ -676,7 +684,7 @@ __device__ __forceinline__ void stage_tile_1d(const StageArgs<real> &a, int tile
     }
     const real rt = a.S[0][ro], mx = a.S[1][ro], my = a.S[2][ro], et = a.S[3][ro], bxt = a.S[4][ro], byt = a.S[5][ro];
     const real rho = zero + rt;
-    const real irho = recip(rho);
+    const real irho = recip_t<real, true>(rho);
     const real vx = mx * irho, vy = my * irho;
     const real kin = half * (mx * vx + my * vy);
     const real bbdot = zero * bxt + zero * byt;
@@ -734,7 +742,7 @@ __device__ __forceinline__ void stage_tile_1d(const StageArgs<real> &a, int tile
             const int cl = qclass(k);
             const real q0 = sh_q[k][tm2], q1 = sh_q[k][tm1], q2 = sh_q[k][tid];
             const real q3 = sh_q[k][tp1], q4 = sh_q[k][tp2], q5 = sh_q[k][tp3];
-            const real R = hd_ratio(q0, q1, q2, q3, q4, q5);
+            const real R = hd_ratio_t<real, true>(q0, q1, q2, q3, q4, q5);
             const real nu = kx2[cl] * R + (real)kc.kxs[cl] * sfx;
             gx[k] = nu * (q3 - q2) * idx;
         }
