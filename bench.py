@@ -1037,7 +1037,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs one GPU's subdomain only; --gpus {args.gpus} is not supported "
-              f"(multi-GPU halo exchange is a design note, not part of this build).", file=sys.stderr)
+              f"(the halo exchange between GPUs is not implemented).", file=sys.stderr)
         sys.exit(2)
     if args.steps is None:
         args.steps = 500 if args.mode == "surrogate" else 100
