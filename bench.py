@@ -893,10 +893,22 @@ def sub_3d(args, n=512, steps=5, warmup=2):
     if d["nonphys"] or d["steps"] != warmup + steps:
         raise RuntimeError(f"3-D run failed: {d}")
     alg = 12 * 8 * 8
-    return {"workload": f"orszag_tang_3d_{n}^3_fp64_hd", "steps": steps,
-            "mcell_updates_s": round(n ** 3 * steps / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms / steps, 3),
-            "roofline_frac_algorithmic": round(alg * n ** 3 / (ms / steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "parity": "bit-identical to the 3-D oracle (GPU tests)"}
+    out = {"workload": f"orszag_tang_3d_{n}^3_fp64_hd", "steps": steps,
+           "mcell_updates_s": round(n ** 3 * steps / (ms / 1e3) / 1e6, 1), "ms_per_step": round(ms / steps, 3),
+           "roofline_frac_algorithmic": round(alg * n ** 3 / (ms / steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+           "parity": "bit-identical to the 3-D oracle (GPU tests)"}
+    # the 3-D oracle beside it: one step of the same problem at a small size
+    from oracle import oracle3d as O3
+    O3.build(force=False)
+    m = 64
+    st = O3.State3(W.orszag_tang_3d(m), form=O3.LOWSTORE)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    st.run(1)
+    sec = time.perf_counter() - t0
+    out["oracle"] = {"mcell_updates_s": round(m ** 3 / sec / 1e6, 3), "threads": threads,
+                     "sample": f"one RK4 step (HD on) of orszag_tang_3d at {m}^3: {sec:.2f} s"}
+    return out
 
 
 def run_3d(args):
