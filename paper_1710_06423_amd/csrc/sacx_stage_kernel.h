@@ -1,7 +1,8 @@
 // sacx_stage_kernel.h -- the fused RK stage kernel and its launchers, as
 // templates; each precision is instantiated in its own translation unit
-// (sacx_stage.hip: FP64, built without contraction for bit-exact results;
-// sacx_stage32.hip: FP32 bulk arithmetic).
+// (sacx_stage.hip: FP64, built without contraction for bit-exact results,
+// with the two-role FP64 tile in sacx_stage_split.hip; sacx_stage32.hip:
+// FP32 bulk arithmetic).
 #pragma once
 
 #include <type_traits>
@@ -70,6 +71,13 @@ __global__ __launch_bounds__(NT) void k_stage_1d(StageArgs<real> a) {
     stage_tile_1d<real, NT, STAGE, HD>(a, blockIdx.x, lds);
 }
 
+// The two-role FP64 tile is compiled in a unit of its own
+// (sacx_stage_split.hip), with a scheduling strategy that suits it but not
+// the one-thread tile: these launch and size its kernels there.
+hipError_t launch_split_fp64(int stage, int nc, bool bg, bool sur, dim3 grid, const StageArgs<double> &a,
+                             hipStream_t s);
+hipError_t split_blocks_per_cu_fp64(int nc, bool bg, int *blocks);
+
 template <typename real, int NT, int STAGE>
 static hipError_t launch_s(bool hd, bool bg, const StageArgs<real> &a, hipStream_t s) {
     constexpr int TX = NT - 2 * G;
@@ -81,12 +89,7 @@ static hipError_t launch_s(bool hd, bool bg, const StageArgs<real> &a, hipStream
     }
     dim3 grid((a.L.nx + TX - 1) / TX, (a.L.ny + a.ty - 1) / a.ty);
     if constexpr (std::is_same<real, double>::value) {
-        if (a.split && hd && !(a.Rs && bg)) {
-            if (a.Rs) hipLaunchKernelGGL((k_stage_split<real, NT, STAGE, false, true>), grid, dim3(2 * NT), 0, s, a);
-            else if (bg) hipLaunchKernelGGL((k_stage_split<real, NT, STAGE, true>), grid, dim3(2 * NT), 0, s, a);
-            else hipLaunchKernelGGL((k_stage_split<real, NT, STAGE, false>), grid, dim3(2 * NT), 0, s, a);
-            return hipGetLastError();
-        }
+        if (a.split && hd && !(a.Rs && bg)) return launch_split_fp64(STAGE, NT, bg, a.Rs != nullptr, grid, a, s);
     }
     if (a.Rs && hd && !bg) {
         hipLaunchKernelGGL((k_stage<real, NT, STAGE, true, false, true>), grid, dim3(NT), 0, s, a);
@@ -114,9 +117,7 @@ static hipError_t launch_nt(int stage, bool hd, bool bg, const StageArgs<real> &
 template <typename real, int NT>
 static hipError_t blocks_per_cu_nt(bool hd, bool bg, bool split, int *blocks) {
     if constexpr (std::is_same<real, double>::value) {
-        if (split && hd)
-            return bg ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage_split<real, NT, 1, true>, 2 * NT, 0)
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage_split<real, NT, 1, false>, 2 * NT, 0);
+        if (split && hd) return split_blocks_per_cu_fp64(NT, bg, blocks);
     }
     if (hd && bg) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage<real, NT, 1, true, true>, NT, 0);
     if (hd) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks, k_stage<real, NT, 1, true, false>, NT, 0);

@@ -32,7 +32,7 @@ from typing import Dict, List, Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 STAGE_SOURCES = ("csrc/sacx_tile.h", "csrc/sacx_tile_split.h", "csrc/sacx_stage_kernel.h", "csrc/sacx_stage.hip",
-                 "csrc/sacx_internal.h")
+                 "csrc/sacx_stage_split.hip", "csrc/sacx_internal.h", "build.py")
 
 
 def code_text(src: str) -> str:
