@@ -43,9 +43,19 @@ FLAGS = [
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, CONTRACT.get(src, "-ffp-contract=off"), *SCHED.get(src, []), "-c", os.path.join(CSRC, src),
-           "-o", obj]
-    r = subprocess.run(cmd, capture_output=True, text=True)
+
+    def run(sched):
+        cmd = [HIPCC, *FLAGS, CONTRACT.get(src, "-ffp-contract=off"), *sched, "-c", os.path.join(CSRC, src),
+               "-o", obj]
+        return subprocess.run(cmd, capture_output=True, text=True)
+
+    r = run(SCHED.get(src, []))
+    if r.returncode != 0 and src in SCHED:
+        # the non-default scheduler is a speed choice only: a compiler that
+        # rejects it (or fails under it) builds the unit with the default one
+        sys.stderr.write(f"hipcc failed for {src} with {' '.join(SCHED[src])}; "
+                         "building it with the default scheduler\n")
+        r = run([])
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError(f"hipcc failed for {src}")

@@ -32,7 +32,17 @@ from typing import Dict, List, Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 STAGE_SOURCES = ("csrc/sacx_tile.h", "csrc/sacx_tile_split.h", "csrc/sacx_stage_kernel.h", "csrc/sacx_stage.hip",
-                 "csrc/sacx_stage_split.hip", "csrc/sacx_internal.h", "build.py")
+                 "csrc/sacx_stage_split.hip", "csrc/sacx_internal.h")
+STAGE_UNITS = ("sacx_stage.hip", "sacx_stage_split.hip")
+
+
+def stage_build_settings() -> str:
+    """The compiler settings of the stage kernel's units (target, flags,
+    contraction rule, scheduler), without the machine's include paths."""
+    from . import build as B
+    flags = [f for f in B.FLAGS if not os.path.isabs(f)]
+    per_unit = [(u, B.CONTRACT.get(u, "-ffp-contract=off"), list(B.SCHED.get(u, []))) for u in STAGE_UNITS]
+    return repr((B.ARCH, flags, per_unit))
 
 
 def code_text(src: str) -> str:
@@ -62,8 +72,9 @@ def code_text(src: str) -> str:
 
 
 def stage_source_hash(read=None) -> str:
-    """Hash of the stage kernel's code (comments and layout excluded).
-    `read(rel)` returns a source's text (default: the working tree)."""
+    """Hash of the stage kernel's code (comments and layout excluded) and of
+    the settings its units are compiled with.  `read(rel)` returns a source's
+    text (default: the working tree)."""
     h = hashlib.sha256()
     for rel in STAGE_SOURCES:
         if read is None:
@@ -72,6 +83,7 @@ def stage_source_hash(read=None) -> str:
         else:
             text = read(rel)
         h.update(code_text(text).encode())
+    h.update(stage_build_settings().encode())
     return h.hexdigest()[:16]
 
 
