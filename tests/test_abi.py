@@ -101,6 +101,7 @@ def test_workspace_size_arithmetic(sx):
 
 @pytest.mark.parametrize("bad", [
     dict(nx=0), dict(ny=-3), dict(nx=1, ny=1), dict(x1=0.0), dict(precision=7), dict(background_on=2),
+    dict(nx=(1 << 24) + 1, ny=2), dict(nx=2, ny=(1 << 24) + 1), dict(nx=1 << 17, ny=(1 << 17) + 1),
 ])
 def test_invalid_grids_rejected(sx, bad):
     kw = dict(nx=16, ny=16, x0=0.0, x1=1.0, y0=0.0, y1=1.0, precision=0, background_on=0)
@@ -109,6 +110,15 @@ def test_invalid_grids_rejected(sx, bad):
     with pytest.raises(sx.SacxError) as e:
         sx.workspace_size(g, sx.make_params(5 / 3))
     assert e.value.code == sx.EINVAL
+
+
+@pytest.mark.parametrize("nx, ny", [(1 << 24, 2), (2, 1 << 24), (1 << 17, 1 << 17)])
+def test_largest_grids_accepted(sx, nx, ny):
+    """The size limits themselves (a side of 2^24 cells, 2^34 cells in all)
+    are accepted, and the workspace size is computed without overflow."""
+    g = sx.make_grid(nx, ny, 0, 1, 0, 1)
+    b = sx.workspace_size(g, sx.make_params(5 / 3))
+    assert b >= 4 * 6 * (nx + 6) * (ny + 6) * 8
 
 
 @pytest.mark.parametrize("bad", [dict(gamma=1.0), dict(cfl=0.0), dict(c2=(-1, 0, 0, 0)), dict(cshk=(0, float("nan"), 0, 0)),
