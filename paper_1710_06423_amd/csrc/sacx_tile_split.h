@@ -98,11 +98,43 @@ struct SplitCommon {
 __device__ __forceinline__ int ring5(int r) { return (r + 5 * 4096) % 5; }
 __device__ __forceinline__ int ring3(int r) { return (r + 3 * 4096) % 3; }
 
+// Wave speeds of one cell of the new state (stage 4): the running maxima of
+// |v_d| + c_f, and the non-physical flag.  Without a background the x role
+// evaluates it (the y role leaves the new state in the state ring's slot of
+// that row, which no one reads again before the x role refills it five rows
+// later): the y role's first phase is the longest of the row otherwise.
+template <typename real, int NC>
+__device__ __forceinline__ void new_state_speeds(const SplitCommon<real, NC> &m, const real (&un)[6], real rb0,
+                                                 real eb0, real bxb0, real byb0, double &cx_t, double &cy_t,
+                                                 int &bad_t) {
+    const real half = (real)0.5;
+    const real r0 = rb0 + un[0];
+    const real ir0 = (real)1 / r0;
+    const real ux = un[1] * ir0, uy = un[2] * ir0;
+    const real kn = half * (un[1] * ux + un[2] * uy);
+    const real bbd = bxb0 * un[4] + byb0 * un[5];
+    const real b2t = un[4] * un[4] + un[5] * un[5];
+    const real pkt = m.gm1 * (((un[3] - kn) - bbd) - half * b2t);
+    const real b2b = bxb0 * bxb0 + byb0 * byb0;
+    const real pkb = m.gm1 * (eb0 - half * b2b);
+    const real pkk = pkb + pkt;
+    const real bxx = bxb0 + un[4], byy = byb0 + un[5];
+    const real cf = sqrt((m.gamma * pkk + (bxx * bxx + byy * byy)) * ir0);
+    const bool fin = isfinite(un[0]) && isfinite(un[1]) && isfinite(un[2]) && isfinite(un[3]) &&
+                     isfinite(un[4]) && isfinite(un[5]) && isfinite(cf);
+    if (!(r0 > (real)0) || !(pkk > (real)0) || !fin) {
+        bad_t = 1;
+    } else {
+        cx_t = fmax(cx_t, (double)(fabs(ux) + cf));
+        cy_t = fmax(cy_t, (double)(fabs(uy) + cf));
+    }
+}
+
 // x role: primitives and x fluxes of the newest row, D_x F_x, compression,
 // x-face G and x-face fluxes
 template <typename real, int NC, int STAGE, bool BG, bool SUR>
 __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCommon<real, NC> &m,
-                                        SplitLds<real, NC, BG> &lds) {
+                                        SplitLds<real, NC, BG> &lds, double &cx_t, double &cy_t, int &bad_t) {
     const real half = (real)0.5, two = (real)2, eight = (real)8, zero = (real)0;
     const Layout L = a.L;
     const int64_t fs = a.fstride;
@@ -202,6 +234,13 @@ __device__ __forceinline__ void split_x(const StageArgs<real> &a, const SplitCom
             }
         }
         const int pr = ring5(r);
+        if (STAGE == 4 && !BG && r - 5 >= m.y0 && m.outcol) {
+            // the slot of row r holds the new state of output row r-5
+            real un[6];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) un[f] = lds.ps[pr][f][t];
+            new_state_speeds<real, NC>(m, un, zero, zero, zero, zero, cx_t, cy_t, bad_t);
+        }
 #pragma unroll
         for (int f = 0; f < NF; ++f) lds.ps[pr][f][t] = cur.v[f];
         const real rt = cur.v[0], mx = cur.v[1], my = cur.v[2], et = cur.v[3], bxt = cur.v[4], byt = cur.v[5];
@@ -369,28 +408,15 @@ __device__ __forceinline__ void split_output(const StageArgs<real> &a, const Spl
             un[f] = (s + (av - (s + s)) * m.third) + m.dt6 * K[f];
             a.out1[0][oo + f * fs] = un[f];
         }
-        // wave speeds of the new state (next step's dt and c_max)
-        real rb0 = 0, eb0 = 0, bxb0 = 0, byb0 = 0;
-        if (BG) { rb0 = a.BG[0][oo]; eb0 = a.BG[0][oo + 1 * fs]; bxb0 = a.BG[0][oo + 2 * fs]; byb0 = a.BG[0][oo + 3 * fs]; }
-        const real r0 = rb0 + un[0];
-        const real ir0 = (real)1 / r0;
-        const real ux = un[1] * ir0, uy = un[2] * ir0;
-        const real kn = half * (un[1] * ux + un[2] * uy);
-        const real bbd = bxb0 * un[4] + byb0 * un[5];
-        const real b2t = un[4] * un[4] + un[5] * un[5];
-        const real pkt = m.gm1 * (((un[3] - kn) - bbd) - half * b2t);
-        const real b2b = bxb0 * bxb0 + byb0 * byb0;
-        const real pkb = m.gm1 * (eb0 - half * b2b);
-        const real pkk = pkb + pkt;
-        const real bxx = bxb0 + un[4], byy = byb0 + un[5];
-        const real cf = sqrt((m.gamma * pkk + (bxx * bxx + byy * byy)) * ir0);
-        const bool fin = isfinite(un[0]) && isfinite(un[1]) && isfinite(un[2]) && isfinite(un[3]) &&
-                         isfinite(un[4]) && isfinite(un[5]) && isfinite(cf);
-        if (!(r0 > (real)0) || !(pkk > (real)0) || !fin) {
-            bad_t = 1;
+        // wave speeds of the new state (next step's dt and c_max): here with
+        // a background, else by the x role from the state ring
+        if (BG) {
+            const real rb0 = a.BG[0][oo], eb0 = a.BG[0][oo + 1 * fs], bxb0 = a.BG[0][oo + 2 * fs],
+                       byb0 = a.BG[0][oo + 3 * fs];
+            new_state_speeds<real, NC>(m, un, rb0, eb0, bxb0, byb0, cx_t, cy_t, bad_t);
         } else {
-            cx_t = fmax(cx_t, (double)(fabs(ux) + cf));
-            cy_t = fmax(cy_t, (double)(fabs(uy) + cf));
+#pragma unroll
+            for (int f = 0; f < NF; ++f) lds.ps[pj][f][t] = un[f];
         }
     }
 }
@@ -621,10 +647,28 @@ __device__ __forceinline__ void stage_tile_split(const StageArgs<real> &a, int t
     double cx_t = 0.0, cy_t = 0.0;
     int bad_t = 0;
     if (xrole)
-        split_x<real, NC, STAGE, BG, SUR>(a, m, lds);
+        split_x<real, NC, STAGE, BG, SUR>(a, m, lds, cx_t, cy_t, bad_t);
     else
         split_y<real, NC, STAGE, BG, SUR>(a, m, lds, cx_t, cy_t, bad_t);
 
+    if (STAGE == 4 && !BG) {
+        // the new state of the last two output rows (rend-4, rend-3), left
+        // in the ring by the y role's last iteration and its final row
+        __syncthreads();
+        if (xrole) {
+#pragma unroll
+            for (int k = 4; k >= 3; --k) {
+                const int jj = m.rend - k;
+                if (jj >= m.y0 && m.outcol) {
+                    const int pj = ring5(jj);
+                    real un[6];
+#pragma unroll
+                    for (int f = 0; f < NF; ++f) un[f] = lds.ps[pj][f][m.t];
+                    new_state_speeds<real, NC>(m, un, (real)0, (real)0, (real)0, (real)0, cx_t, cy_t, bad_t);
+                }
+            }
+        }
+    }
     if (STAGE == 4) {
         // block reduction of the wave speeds, one atomic per block
         auto &red = lds.red;
