@@ -382,13 +382,14 @@ def test_launch_shape_does_not_change_results(oracle_lib, shape):
     assert_parity(oracle_lib, s.read_fields().cpu().numpy(), ora, label=f"launch {shape}")
 
 
-@pytest.mark.parametrize("shape", [(64, 7), (128, 256), (256, 33)])
+@pytest.mark.parametrize("shape", [(64, 7), (128, 256), (256, 33), (128, 1), (64, 2), (256, 3), (128, 4)])
 @pytest.mark.parametrize("cross,background", [(True, False), (False, False), (True, True)])
 def test_column_split_matches_one_thread_tiles(shape, cross, background):
     """The two-threads-per-column tile (x and y roles) and the one-thread tile
     give the same bits over every stage of several steps (time step included),
-    for block widths and strip heights that leave ragged tiles and strips, on
-    mixed open and periodic boundaries; with a background and gravity too."""
+    for block widths and strip heights that leave ragged tiles and strips
+    (down to strips of one to four rows, shorter than the warm-up), on mixed
+    open and periodic boundaries; with a background and gravity too."""
     torch = _torch()
     from paper_1710_06423_amd import Solver
     print(f"case: split vs one-thread {shape} cross={cross} background={background}", flush=True)
